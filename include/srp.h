@@ -1,0 +1,194 @@
+/*
+ * srp.h — C ABI of the MI355X (gfx950) ray-traced solar-radiation-pressure
+ * library.
+ *
+ * The library evaluates the SRP force and torque on a triangulated,
+ * articulated spacecraft by casting a uniform grid of parallel sun-direction
+ * rays over the mesh's projected footprint (one independent ray per pixel of
+ * a discretised image plane, Sec. 4.3 of the paper), finding each ray's first
+ * hit (self-shadowing, Sec. 1), applying the absorbed / specular / diffuse
+ * momentum-transfer law of the hit facet's material, following specular
+ * secondary rays iteratively (Sec. 4.3), and reducing everything on the GPU to
+ * a total force and torque (GPU-side reduction, Sec. 4.3 and Sec. 7.2).
+ * Articulated solar panels follow the paper's rooted kinematic tree
+ * G = (N, E, L) with edge labels (pivot, axes, intervals) (Sec. 4.4.1) and the
+ * clamp-to-interval rule of the panel update (Sec. 4.4.2).
+ *
+ * Conventions for every entry point:
+ *   - Return value: SRP_OK (0) or a negative SRP_ERR_* code; srp_last_error()
+ *     then gives a thread-local, human-readable message.  On error no output
+ *     is written except where stated.
+ *   - Units: metres, radians, N/m^2 for pressure; forces in N, torques in N m.
+ *   - Frames: everything is in the spacecraft body frame (rest pose for the
+ *     mesh and the tree).
+ *   - Ownership: inputs are copied during the call; the caller keeps its
+ *     buffers.  Opaque handles are owned by the library until destroyed.
+ *   - Device: the library uses the HIP device current at srp_build_scene;
+ *     a scene's calls are ordered on the stream given (or the null stream).
+ *     Calls on one scene must not overlap from several host threads.
+ *   - Precision: rays, traversal and intersection in FP32; every sum of
+ *     force, torque and gradient contributions in FP64.
+ */
+#ifndef SRP_MI355X_H
+#define SRP_MI355X_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SRP_OK 0
+#define SRP_ERR_ARG -1     /* invalid argument (null pointer, range, topology, shape) */
+#define SRP_ERR_OOM -2     /* host or device allocation failed */
+#define SRP_ERR_DEVICE -3  /* a HIP runtime call failed; message has its text */
+#define SRP_ERR_DEPTH -4   /* a hierarchy deeper than the traversal stack */
+
+/* srp_eval_params.flags */
+#define SRP_F_COUNT 1u     /* also count box and triangle tests (slower kernel variant) */
+
+#define SRP_MAX_N 8192     /* largest ray grid side */
+#define SRP_MAX_BOUNCES 4  /* largest number of secondary generations */
+#define SRP_MAX_NODES 128  /* largest number of tree nodes */
+#define SRP_MAX_MATS 64    /* largest number of materials */
+
+typedef struct srp_scene srp_scene;
+
+/* Optical coefficients of one material: rho_s specular, rho_d diffuse,
+ * rho_a = 1 - rho_s - rho_d absorbed (Sec. 5.1 table of spacecraft models).
+ * Valid when rho_s >= 0, rho_d >= 0, rho_s + rho_d <= 1. */
+typedef struct {
+    double rho_s, rho_d;
+} srp_material;
+
+/* One node of the kinematic tree (Sec. 4.4.1): a rigid group of mesh parts.
+ * Node 0 is the root (parent = -1, n_axes = 0); every other node's parent has
+ * a smaller index.  The edge from the parent carries the label (p, A, I):
+ * pivot p, unit axes axis[0..n_axes-1] and intervals [lo, hi] (radians), all in
+ * the rest-pose body frame.  The node's world transform is
+ *   M = M_parent * T(p) * R(axis[0], th0) * ... * R(axis[k-1], th_{k-1}) * T(-p). */
+typedef struct {
+    int32_t parent;
+    int32_t is_panel;      /* 1 if the node is a solar panel (Sec. 4.4.1 flag t_n) */
+    double pivot[3];
+    int32_t n_axes;        /* 0..3 */
+    int32_t reserved;
+    double axis[3][3];
+    double lo[3], hi[3];
+} srp_node;
+
+/* Per-evaluation parameters. */
+typedef struct {
+    double sun_dir[3];     /* spacecraft -> Sun, body frame; finite, nonzero, any length */
+    double pressure;       /* N/m^2 at the spacecraft (caller scales P0 (AU/r)^2) */
+    int32_t n;             /* ray grid N (N x N rays), 1..SRP_MAX_N */
+    int32_t bounces;       /* specular secondary generations B, 0..SRP_MAX_BOUNCES */
+    double ref[3];         /* torque reference point, body frame */
+    uint32_t flags;        /* SRP_F_* */
+    uint32_t reserved;
+} srp_eval_params;
+
+/* Result of one evaluation.  n_box_tests / n_tri_tests are filled only with
+ * SRP_F_COUNT (else 0). */
+typedef struct {
+    double force[3];
+    double torque[3];
+    int64_t n_rays;            /* primary rays cast (N^2) */
+    int64_t n_hits;            /* primary rays that hit */
+    int64_t n_secondary;       /* secondary rays spawned */
+    int64_t n_secondary_hits;  /* secondary rays that hit */
+    int64_t n_box_tests;       /* ray-box tests (SRP_F_COUNT) */
+    int64_t n_tri_tests;       /* ray-triangle tests (SRP_F_COUNT) */
+    uint32_t status;           /* 0, or SRP_STATUS_* bits (the evaluation is then invalid) */
+    uint32_t reserved;
+} srp_result;
+
+/* srp_result.status bits */
+#define SRP_STATUS_STACK 1u   /* a traversal stack overflowed (cannot happen for scenes
+                                 accepted by srp_build_scene; reported, never silent) */
+
+/* One item of a batch.  Items may use different scenes, grid sizes, bounce
+ * counts and angles. */
+typedef struct {
+    srp_scene *scene;
+    const double *angles;  /* host, scene's n_dof values; NULL = scene's current angles */
+    srp_eval_params p;
+} srp_batch_item;
+
+/* Build a scene: mesh (rest pose), per-triangle material and node, material
+ * table and kinematic tree (Sec. 4.4.1; the triangles of a node form its mesh
+ * parts O_n and every triangle belongs to exactly one node).
+ *   verts:  n_verts x 3 (double);  tris: n_tris x 3 vertex indices;
+ *   tri_material, tri_node: n_tris each;  mats: n_mats;  nodes: n_nodes.
+ * Builds one bounding-volume hierarchy per node in rest-pose coordinates and
+ * uploads everything to the current device; all angles start at 0 (clamped).
+ * Errors: SRP_ERR_ARG for null pointers, out-of-range indices, invalid
+ * coefficients, a tree whose parent indices are not increasing from a single
+ * root, n_axes outside 0..3 or a root with axes, n_nodes > SRP_MAX_NODES,
+ * n_mats > SRP_MAX_MATS, non-finite coordinates; SRP_ERR_OOM; SRP_ERR_DEPTH if
+ * a hierarchy cannot be kept within the traversal stack; SRP_ERR_DEVICE.
+ * *out is set only on success. */
+int srp_build_scene(const double *verts, int64_t n_verts, const int32_t *tris, int64_t n_tris,
+                    const int32_t *tri_material, const int32_t *tri_node,
+                    const srp_material *mats, int32_t n_mats,
+                    const srp_node *nodes, int32_t n_nodes, srp_scene **out);
+
+/* Release a scene and its device memory (waits for its pending work).
+ * NULL is accepted and ignored. */
+int srp_destroy_scene(srp_scene *scene);
+
+/* Number of hinge degrees of freedom (sum of n_axes), or a negative error. */
+int32_t srp_scene_n_dof(const srp_scene *scene);
+
+/* Replace the material table (same count).  Cheap; for coefficient fitting. */
+int srp_set_materials(srp_scene *scene, const srp_material *mats, int32_t n_mats);
+
+/* Set the hinge angles (Sec. 4.4.2): angles[n_dof] in node order, then axis
+ * order; each is clamped to its interval (not an error).  Only the per-node
+ * instance transforms and the top-level hierarchy over the nodes are rebuilt;
+ * the per-node hierarchies are untouched.  Returns the number of clamped
+ * angles (>= 0) on success.  Errors: SRP_ERR_ARG (null, n_dof mismatch,
+ * non-finite angle). */
+int srp_set_panel_angles(srp_scene *scene, const double *angles, int32_t n_dof);
+
+/* One evaluation at the scene's current angles; blocks until the result is
+ * on the host.  Optional per-ray records (host buffers, may be NULL):
+ *   hit_ids: N*N*(B+1) int32, pixel p = j*N + i (row j, column i) major,
+ *            generation minor; the original triangle index or -1;
+ *   hit_t:   same layout, ray parameter of the hit (0 where none).
+ * Errors: SRP_ERR_ARG (null scene/params/out, N or B out of range,
+ * non-finite or zero sun_dir, non-finite pressure/ref), SRP_ERR_DEVICE. */
+int srp_eval(srp_scene *scene, const srp_eval_params *params, srp_result *out,
+             int32_t *hit_ids, float *hit_t);
+
+/* A batch of evaluations in one persistent launch (plus a window pass and a
+ * fixed-order reduction).  out_dev: device array of n_items srp_result,
+ * written in stream order on hip_stream (a hipStream_t; NULL = null stream).
+ * The call returns once the work is queued; host inputs may be reused then.
+ * Results are bitwise independent of scheduling.  Errors as srp_eval, checked
+ * for every item before anything is queued. */
+int srp_eval_batch(const srp_batch_item *items, int64_t n_items, srp_result *out_dev,
+                   void *hip_stream);
+
+/* One evaluation plus the gradient of the force at fixed visibility (hit
+ * triangles of every generation, window, pixel area and ray origins frozen):
+ *   dF_drho_s: n_mats x 3, dF_drho_d: n_mats x 3, dF_dtheta: n_dof x 3 (host).
+ * dF_dtheta is with respect to the clamped angles.  Any gradient pointer may
+ * be NULL.  Blocks until the results are on the host.  Errors as srp_eval. */
+int srp_eval_grad(srp_scene *scene, const srp_eval_params *params, srp_result *out,
+                  double *dF_drho_s, double *dF_drho_d, double *dF_dtheta);
+
+/* Batched form of srp_eval_grad.  grad_dev: device array, item k's gradients
+ * at grad_dev + k*grad_stride doubles, laid out as rho_s (M x 3), rho_d
+ * (M x 3), theta (J x 3) with that item's M and J; grad_stride must be at
+ * least 3*(2M+J) for every item.  Stream-ordered like srp_eval_batch. */
+int srp_eval_grad_batch(const srp_batch_item *items, int64_t n_items, srp_result *out_dev,
+                        double *grad_dev, int64_t grad_stride, void *hip_stream);
+
+/* Thread-local message of the last error ("" if none). */
+const char *srp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

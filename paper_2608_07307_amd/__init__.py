@@ -1,0 +1,186 @@
+"""MI355X-native ray-traced solar-radiation-pressure (SRP) library.
+
+Python binding of the C ABI in include/srp.h.  Every step of an evaluation
+runs in the gfx950 kernels of libsrp_mi355x.so; this module only marshals
+arguments (numpy arrays, torch device tensors and HIP streams).  There is no
+CPU fallback: without the built library every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib as L
+from ._lib import RESULT_DTYPE, SRP_F_COUNT, SrpError  # noqa: F401
+
+__all__ = ["Scene", "params", "eval", "eval_grad", "eval_batch", "eval_grad_batch",
+           "SrpError", "RESULT_DTYPE"]
+
+
+def _load():
+    return L.load()
+
+
+def params(sun_dir, n, bounces=0, pressure=1.0, ref=(0.0, 0.0, 0.0), count=False):
+    p = L.srp_eval_params()
+    p.sun_dir[:] = [float(x) for x in sun_dir]
+    p.pressure = float(pressure)
+    p.n = int(n)
+    p.bounces = int(bounces)
+    p.ref[:] = [float(x) for x in ref]
+    p.flags = L.SRP_F_COUNT if count else 0
+    return p
+
+
+class Scene:
+    """A scene built by srp_build_scene from mesh, materials and tree arrays.
+
+    `mesh` is any object with the attributes verts (V,3), tris (T,3),
+    tri_mat (T,), tri_node (T,), mats (M,2), parent, is_panel, pivot,
+    n_axes, axes (K,3,3), lo, hi (K,3)."""
+
+    def __init__(self, mesh):
+        lib = _load()
+        verts = np.ascontiguousarray(mesh.verts, dtype=np.float64)
+        tris = np.ascontiguousarray(mesh.tris, dtype=np.int32)
+        tm = np.ascontiguousarray(mesh.tri_mat, dtype=np.int32)
+        tn = np.ascontiguousarray(mesh.tri_node, dtype=np.int32)
+        mats = (L.srp_material * len(mesh.mats))(*[L.srp_material(float(a), float(b)) for a, b in mesh.mats])
+        K = len(mesh.parent)
+        nodes = (L.srp_node * K)()
+        for k in range(K):
+            nd = nodes[k]
+            nd.parent = int(mesh.parent[k])
+            nd.is_panel = int(mesh.is_panel[k])
+            nd.pivot[:] = [float(x) for x in mesh.pivot[k]]
+            nd.n_axes = int(mesh.n_axes[k])
+            for a in range(3):
+                nd.axis[a][:] = [float(x) for x in mesh.axes[k][a]]
+            nd.lo[:] = [float(x) for x in mesh.lo[k]]
+            nd.hi[:] = [float(x) for x in mesh.hi[k]]
+        h = C.c_void_p()
+        L.check(lib.srp_build_scene(L.ptr(verts), verts.shape[0], L.ptr(tris), tris.shape[0],
+                                    L.ptr(tm), L.ptr(tn), mats, len(mesh.mats), nodes, K,
+                                    C.byref(h)))
+        self.handle = h
+        self.n_dof = int(lib.srp_scene_n_dof(h))
+        self.n_mats = len(mesh.mats)
+        self.n_nodes = K
+        self.n_tris = tris.shape[0]
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and L._lib is not None:
+            L._lib.srp_destroy_scene(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_angles(self, angles) -> int:
+        a = np.ascontiguousarray(angles, dtype=np.float64).reshape(-1)
+        return L.check(_load().srp_set_panel_angles(self.handle, L.ptr(a) if a.size else None, a.size))
+
+    def set_materials(self, mats):
+        m = np.asarray(mats, dtype=np.float64).reshape(-1, 2)
+        arr = (L.srp_material * len(m))(*[L.srp_material(float(a), float(b)) for a, b in m])
+        L.check(_load().srp_set_materials(self.handle, arr, len(m)))
+
+
+def _result_dict(r) -> dict:
+    return dict(force=np.array(r.force[:]), torque=np.array(r.torque[:]), n_rays=r.n_rays,
+                n_hits=r.n_hits, n_secondary=r.n_secondary, n_secondary_hits=r.n_secondary_hits,
+                n_box_tests=r.n_box_tests, n_tri_tests=r.n_tri_tests, status=r.status)
+
+
+def eval(scene: Scene, sun_dir, n, bounces=0, pressure=1.0, ref=(0, 0, 0), count=False,
+         record=False) -> dict:
+    """srp_eval at the scene's current angles.  With record=True the result
+    also holds ids (N*N, B+1) int32 and ts (N*N, B+1) float32."""
+    lib = _load()
+    p = params(sun_dir, n, bounces, pressure, ref, count)
+    r = L.srp_result()
+    ids = ts = None
+    if record:
+        ids = np.empty((n * n, bounces + 1), np.int32)
+        ts = np.empty((n * n, bounces + 1), np.float32)
+    L.check(lib.srp_eval(scene.handle, C.byref(p), C.byref(r), L.ptr(ids), L.ptr(ts)))
+    out = _result_dict(r)
+    if record:
+        out["ids"], out["ts"] = ids, ts
+    return out
+
+
+def eval_grad(scene: Scene, sun_dir, n, bounces=0, pressure=1.0, ref=(0, 0, 0)) -> dict:
+    """srp_eval_grad: result plus dF/drho_s (M,3), dF/drho_d (M,3), dF/dtheta (J,3)."""
+    lib = _load()
+    p = params(sun_dir, n, bounces, pressure, ref)
+    r = L.srp_result()
+    gs = np.zeros((scene.n_mats, 3))
+    gd = np.zeros((scene.n_mats, 3))
+    gt = np.zeros((max(scene.n_dof, 1), 3))
+    L.check(lib.srp_eval_grad(scene.handle, C.byref(p), C.byref(r), L.ptr(gs), L.ptr(gd), L.ptr(gt)))
+    out = _result_dict(r)
+    out.update(rho_s=gs, rho_d=gd, theta=gt[: scene.n_dof])
+    return out
+
+
+def _items(entries):
+    """entries: list of (scene, angles or None, params)."""
+    arr = (L.srp_batch_item * len(entries))()
+    keep = []
+    for k, (sc, ang, p) in enumerate(entries):
+        arr[k].scene = sc.handle
+        if ang is not None:
+            a = np.ascontiguousarray(ang, dtype=np.float64).reshape(-1)
+            if a.size != sc.n_dof:
+                raise ValueError("angles length differs from the scene's n_dof")
+            keep.append(a)
+            arr[k].angles = a.ctypes.data if a.size else None
+        else:
+            arr[k].angles = None
+        arr[k].p = p
+    return arr, keep
+
+
+def eval_batch(entries, out=None, stream=None):
+    """srp_eval_batch.  entries: list of (scene, angles or None, params).
+    Returns a uint8 device tensor of len(entries) srp_result records (use
+    results_to_numpy to read it); stream-ordered on `stream` (torch stream)."""
+    import torch
+    lib = _load()
+    n = len(entries)
+    if out is None:
+        out = torch.empty(n * RESULT_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+    s = stream if stream is not None else torch.cuda.current_stream()
+    arr, keep = _items(entries)
+    L.check(lib.srp_eval_batch(arr, n, C.c_void_p(out.data_ptr()), C.c_void_p(s.cuda_stream)))
+    return out
+
+
+def eval_grad_batch(entries, out=None, grad=None, stream=None):
+    """srp_eval_grad_batch.  Returns (results uint8 tensor, gradients float64
+    tensor (n, stride)) with stride = max over entries of 3*(2M+J)."""
+    import torch
+    lib = _load()
+    n = len(entries)
+    stride = max(3 * (2 * sc.n_mats + sc.n_dof) for sc, _, _ in entries)
+    if out is None:
+        out = torch.empty(n * RESULT_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+    if grad is None:
+        grad = torch.zeros((n, stride), dtype=torch.float64, device="cuda")
+    s = stream if stream is not None else torch.cuda.current_stream()
+    arr, keep = _items(entries)
+    L.check(lib.srp_eval_grad_batch(arr, n, C.c_void_p(out.data_ptr()),
+                                    C.c_void_p(grad.data_ptr()), grad.shape[1],
+                                    C.c_void_p(s.cuda_stream)))
+    return out, grad
+
+
+def results_to_numpy(t) -> np.ndarray:
+    """Structured array (RESULT_DTYPE) from a results tensor."""
+    b = t.detach().cpu().numpy().tobytes()
+    return np.frombuffer(b, dtype=RESULT_DTYPE)

@@ -1,0 +1,106 @@
+"""ctypes declarations of the C ABI in include/srp.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsrp_mi355x.so")
+
+SRP_OK, SRP_ERR_ARG, SRP_ERR_OOM, SRP_ERR_DEVICE, SRP_ERR_DEPTH = 0, -1, -2, -3, -4
+SRP_F_COUNT = 1
+SRP_MAX_N, SRP_MAX_BOUNCES, SRP_MAX_NODES, SRP_MAX_MATS = 8192, 4, 128, 64
+
+EXPORTS = [
+    "srp_build_scene", "srp_destroy_scene", "srp_scene_n_dof", "srp_set_materials",
+    "srp_set_panel_angles", "srp_eval", "srp_eval_batch", "srp_eval_grad",
+    "srp_eval_grad_batch", "srp_last_error",
+]
+
+
+class srp_material(C.Structure):
+    _fields_ = [("rho_s", C.c_double), ("rho_d", C.c_double)]
+
+
+class srp_node(C.Structure):
+    _fields_ = [("parent", C.c_int32), ("is_panel", C.c_int32), ("pivot", C.c_double * 3),
+                ("n_axes", C.c_int32), ("reserved", C.c_int32), ("axis", (C.c_double * 3) * 3),
+                ("lo", C.c_double * 3), ("hi", C.c_double * 3)]
+
+
+class srp_eval_params(C.Structure):
+    _fields_ = [("sun_dir", C.c_double * 3), ("pressure", C.c_double), ("n", C.c_int32),
+                ("bounces", C.c_int32), ("ref", C.c_double * 3), ("flags", C.c_uint32),
+                ("reserved", C.c_uint32)]
+
+
+class srp_result(C.Structure):
+    _fields_ = [("force", C.c_double * 3), ("torque", C.c_double * 3), ("n_rays", C.c_int64),
+                ("n_hits", C.c_int64), ("n_secondary", C.c_int64),
+                ("n_secondary_hits", C.c_int64), ("n_box_tests", C.c_int64),
+                ("n_tri_tests", C.c_int64), ("status", C.c_uint32), ("reserved", C.c_uint32)]
+
+
+class srp_batch_item(C.Structure):
+    _fields_ = [("scene", C.c_void_p), ("angles", C.c_void_p), ("p", srp_eval_params)]
+
+
+RESULT_DTYPE = np.dtype([("force", "<f8", 3), ("torque", "<f8", 3), ("n_rays", "<i8"),
+                         ("n_hits", "<i8"), ("n_secondary", "<i8"), ("n_secondary_hits", "<i8"),
+                         ("n_box_tests", "<i8"), ("n_tri_tests", "<i8"), ("status", "<u4"),
+                         ("reserved", "<u4")])
+assert RESULT_DTYPE.itemsize == C.sizeof(srp_result)
+
+_lib = None
+
+
+def load(path: str | None = None):
+    """Loads the library.  torch is imported first so that the library binds
+    to the HIP runtime torch already loaded (one runtime per process)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    import torch  # noqa: F401  (must precede the library: shared HIP runtime)
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(f"{p} is missing: build it with `python -m paper_2608_07307_amd.build` "
+                           "(there is no CPU fallback)")
+    lib = C.CDLL(p)
+    V, I32, I64 = C.c_void_p, C.c_int32, C.c_int64
+    lib.srp_build_scene.argtypes = [V, I64, V, I64, V, V, V, I32, V, I32, C.POINTER(V)]
+    lib.srp_destroy_scene.argtypes = [V]
+    lib.srp_scene_n_dof.argtypes = [V]
+    lib.srp_scene_n_dof.restype = I32
+    lib.srp_set_materials.argtypes = [V, V, I32]
+    lib.srp_set_panel_angles.argtypes = [V, V, I32]
+    lib.srp_eval.argtypes = [V, C.POINTER(srp_eval_params), C.POINTER(srp_result), V, V]
+    lib.srp_eval_batch.argtypes = [V, I64, V, V]
+    lib.srp_eval_grad.argtypes = [V, C.POINTER(srp_eval_params), C.POINTER(srp_result), V, V, V]
+    lib.srp_eval_grad_batch.argtypes = [V, I64, V, V, I64, V]
+    lib.srp_last_error.restype = C.c_char_p
+    for f in ("srp_build_scene", "srp_destroy_scene", "srp_set_materials",
+              "srp_set_panel_angles", "srp_eval", "srp_eval_batch", "srp_eval_grad",
+              "srp_eval_grad_batch"):
+        getattr(lib, f).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+class SrpError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"srp error {code}: {msg}")
+        self.code = code
+
+
+def check(rc: int) -> int:
+    if rc < 0:
+        raise SrpError(rc, _lib.srp_last_error().decode())
+    return rc
+
+
+def ptr(a) -> C.c_void_p | None:
+    if a is None:
+        return None
+    return C.c_void_p(a.ctypes.data)

@@ -1,0 +1,70 @@
+// Host-side scene and articulation structures of the SRP library.
+#pragma once
+#include <string>
+#include <vector>
+
+#include "srp.h"
+#include "srp_internal.h"
+
+namespace srp {
+
+// One kinematic-tree node (Sec. 4.4.1) plus its bottom-level hierarchy.
+struct NodeInfo {
+    int32_t parent = -1;
+    int32_t is_panel = 0;
+    double pivot[3] = {0, 0, 0};
+    int32_t n_axes = 0;
+    double axis[3][3] = {{0}};
+    double lo[3] = {0}, hi[3] = {0};
+    int32_t dof_offset = 0;
+    uint32_t blas_root = REF_NONE;   // REF_NONE when the node has no triangles
+    int32_t blas_depth = 0;
+    double blo[3] = {0}, bhi[3] = {0};  // padded rest-pose bounds of the node's triangles
+};
+
+// Host image of one articulation slot (see srp_internal.h for the layout).
+struct SlotHost {
+    std::vector<Inst> inst;
+    std::vector<BNode> tlas;
+    uint32_t root_ref = REF_NONE;
+    int tlas_depth = 0;
+    std::vector<double> xf;        // K x 12: R (row-major) then t
+    std::vector<double> axw;       // J x 3
+    std::vector<int32_t> dof_node; // J
+    int n_clamped = 0;
+};
+
+struct SlotLayout {
+    size_t inst, tlas, xf, axw, dof_node, bytes;
+};
+SlotLayout slot_layout(int n_nodes, int n_tlas, int n_dof);
+void slot_pack(const SlotHost &s, const SlotLayout &L, char *dst);
+
+struct SceneHost {
+    int32_t n_nodes = 0, n_mats = 0, n_dof = 0;
+    int64_t n_tris = 0;
+    std::vector<NodeInfo> nodes;
+    std::vector<float> mats;        // 2 per material
+    std::vector<TriRec> tris;       // leaf order
+    std::vector<BNode> blas;
+    std::vector<WPoint> wpts;
+    std::vector<int32_t> parent;
+    double pad = 0;                 // box padding (metres)
+    int max_blas_depth = 0;
+};
+
+// Validates the inputs and builds the host image.  Returns SRP_OK or an
+// error code with a message in *err.
+int scene_build(const double *verts, int64_t n_verts, const int32_t *tris, int64_t n_tris,
+                const int32_t *tri_material, const int32_t *tri_node, const srp_material *mats,
+                int32_t n_mats, const srp_node *nodes, int32_t n_nodes, SceneHost *out,
+                std::string *err);
+
+int validate_materials(const srp_material *mats, int32_t n_mats, std::string *err);
+
+// Composes the node transforms for `angles` (NULL = all zero), clamping each
+// angle to its interval (Sec. 4.4.2 step 4), and builds the instances, the
+// top-level hierarchy and the world hinge axes.
+int slot_build(const SceneHost &S, const double *angles, SlotHost *out, std::string *err);
+
+}  // namespace srp

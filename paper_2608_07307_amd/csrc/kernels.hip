@@ -1,0 +1,673 @@
+// gfx950 kernels of the ray-traced SRP library.
+//
+//   k_window  per evaluation, the tight projected window of the articulated
+//             mesh (FP64 bounds of every (vertex, node) point on the image
+//             axes u, v and the photon direction d), merged across blocks with
+//             order-preserving 64-bit atomic min.
+//   k_trace   persistent: blocks pull chunks (16 x 16*rpt pixels of one
+//             evaluation) from an atomic counter; one ray per lane, an 8x8
+//             pixel patch per wave; two-level traversal (top level over the
+//             kinematic-tree nodes, rigid instance transform, bottom level in
+//             rest-pose coordinates) with a per-lane stack in LDS; watertight
+//             FP32 triangle test; momentum law at each hit; specular secondary
+//             rays iteratively; FP64 per-lane sums, wave butterfly, fixed
+//             block order, one partial per chunk (no floating-point atomics,
+//             so results do not depend on scheduling).  The GRAD variant also
+//             differentiates each ray's hit chain at fixed visibility.
+//   k_reduce  per evaluation, sums its chunk partials in chunk order, scales by
+//             P * A_pix and writes the srp_result (and the gradients).
+//
+// The per-pixel structure, the iterative secondary rays and the GPU-side
+// reduction follow Sec. 4.3 of the paper; the articulation follows Sec. 4.4.
+#include <float.h>
+
+#include "srp.h"
+#include "srp_internal.h"
+
+namespace srp {
+
+namespace {
+
+constexpr float T_INF = 3.0e38f;
+constexpr int WAVE = 64;
+constexpr int MAX_CHAIN = SRP_MAX_BOUNCES + 1;
+
+__device__ __forceinline__ float safe_inv(float x) {
+    // reciprocal of a direction component, finite for zero components
+    float ax = fabsf(x) < 1e-30f ? copysignf(1e-30f, x) : x;
+    return 1.0f / ax;
+}
+
+// An orthonormal basis (bx, by) orthogonal to unit d (Duff et al., JCGT 2017).
+__device__ __forceinline__ void onb(const float d[3], float bx[3], float by[3]) {
+    float s = copysignf(1.0f, d[2]);
+    float a = -1.0f / (s + d[2]);
+    float b = d[0] * d[1] * a;
+    bx[0] = 1.0f + s * d[0] * d[0] * a;
+    bx[1] = s * b;
+    bx[2] = -s * d[0];
+    by[0] = b;
+    by[1] = s + d[1] * d[1] * a;
+    by[2] = -d[1];
+}
+
+// Ray state in one frame: slab-test constants and the watertight-test frame
+// (x, y axes orthogonal to the direction, z = direction, offsets = axes . o).
+struct Frame {
+    float ix, iy, iz;      // 1 / d
+    float oix, oiy, oiz;   // o / d
+    float mx[3], my[3], mz[3];
+    float cx, cy, cz;
+};
+
+__device__ __forceinline__ void frame_setup(const float o[3], const float d[3], Frame &F) {
+    F.ix = safe_inv(d[0]);
+    F.iy = safe_inv(d[1]);
+    F.iz = safe_inv(d[2]);
+    F.oix = o[0] * F.ix;
+    F.oiy = o[1] * F.iy;
+    F.oiz = o[2] * F.iz;
+    onb(d, F.mx, F.my);
+    F.mz[0] = d[0]; F.mz[1] = d[1]; F.mz[2] = d[2];
+    F.cx = F.mx[0] * o[0] + F.mx[1] * o[1] + F.mx[2] * o[2];
+    F.cy = F.my[0] * o[0] + F.my[1] * o[1] + F.my[2] * o[2];
+    F.cz = F.mz[0] * o[0] + F.mz[1] * o[1] + F.mz[2] * o[2];
+}
+
+// Slab test of one box against [tmin, tmax]; returns entry distance or +inf.
+__device__ __forceinline__ float box_enter(float lx, float ly, float lz, float hx, float hy, float hz,
+                                           float ix, float iy, float iz, float oix, float oiy, float oiz,
+                                           float tmin, float tmax) {
+    float t0x = fmaf(lx, ix, -oix), t1x = fmaf(hx, ix, -oix);
+    float t0y = fmaf(ly, iy, -oiy), t1y = fmaf(hy, iy, -oiy);
+    float t0z = fmaf(lz, iz, -oiz), t1z = fmaf(hz, iz, -oiz);
+    float tn = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), tmin));
+    float tf = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fminf(fmaxf(t0z, t1z), tmax));
+    return tn <= tf ? tn : T_INF;
+}
+
+__device__ __forceinline__ float xf_dot(const float m[3], float c, const float v[3]) {
+    return fmaf(m[0], v[0], fmaf(m[1], v[1], fmaf(m[2], v[2], -c)));
+}
+
+// Watertight ray/triangle test in the ray frame: 2-D edge functions of the
+// projected corners (products rounded separately, so a shared edge gets the
+// exact negated value in both triangles: no ray passes between them), then
+// the hit distance.  Returns t or a negative value for a miss.
+__device__ __forceinline__ float tri_hit(const Frame &F, const float a[3], const float b[3], const float c[3]) {
+#pragma clang fp contract(off)
+    float ax = xf_dot(F.mx, F.cx, a), ay = xf_dot(F.my, F.cy, a);
+    float bx = xf_dot(F.mx, F.cx, b), by = xf_dot(F.my, F.cy, b);
+    float cx = xf_dot(F.mx, F.cx, c), cy = xf_dot(F.my, F.cy, c);
+    float U = cx * by - cy * bx;
+    float V = ax * cy - ay * cx;
+    float W = bx * ay - by * ax;
+    float mn = fminf(fminf(U, V), W), mx = fmaxf(fmaxf(U, V), W);
+    if (mn < 0.0f && mx > 0.0f) return -1.0f;
+    float det = U + V + W;
+    if (det == 0.0f) return -1.0f;
+    float az = xf_dot(F.mz, F.cz, a), bz = xf_dot(F.mz, F.cz, b), cz = xf_dot(F.mz, F.cz, c);
+    float T = U * az + V * bz + W * cz;
+    return T / det;
+}
+
+struct Hit {
+    float t;
+    int32_t tri;    // leaf-order index into the scene's triangle records
+    int32_t inst;
+    int32_t id;     // original triangle index
+};
+
+template <bool COUNT>
+__device__ bool trace_closest(const EvalDesc &D, const float o[3], const float d[3], float tmin,
+                              int32_t exclude_id, uint32_t *stack, Hit &h, uint32_t &nbox, uint32_t &ntri) {
+    h.t = T_INF;
+    h.tri = -1;
+    h.inst = -1;
+    h.id = 0x7FFFFFFF;
+    uint32_t ref = D.root_ref;
+    if (ref == REF_NONE) return true;
+    // world frame (top level)
+    const float wix = safe_inv(d[0]), wiy = safe_inv(d[1]), wiz = safe_inv(d[2]);
+    const float woix = o[0] * wix, woiy = o[1] * wiy, woiz = o[2] * wiz;
+    float ix = wix, iy = wiy, iz = wiz, oix = woix, oiy = woiy, oiz = woiz;
+    Frame F;
+    int inst = -1;
+    int sp = 0;
+    for (;;) {
+        uint32_t ty = ref_type(ref);
+        if (ty == REF_BLAS_NODE || ty == REF_TLAS_NODE) {
+            const BNode *nb = (ty == REF_TLAS_NODE ? D.tlas : D.blas) + ref_index(ref);
+            const float4 *q = reinterpret_cast<const float4 *>(nb);
+            float4 A = q[0], B = q[1], C = q[2];
+            uint4 R = reinterpret_cast<const uint4 *>(nb)[3];
+            float t0 = box_enter(A.x, A.y, A.z, A.w, B.x, B.y, ix, iy, iz, oix, oiy, oiz, tmin, h.t);
+            float t1 = box_enter(B.z, B.w, C.x, C.y, C.z, C.w, ix, iy, iz, oix, oiy, oiz, tmin, h.t);
+            if (COUNT) nbox += 2;
+            bool h0 = t0 != T_INF, h1 = t1 != T_INF;
+            if (h0 && h1) {
+                uint32_t nr = t0 <= t1 ? R.x : R.y, fr = t0 <= t1 ? R.y : R.x;
+                if (sp >= STACK_DEPTH) return false;
+                stack[sp * BLOCK] = fr;
+                ++sp;
+                ref = nr;
+                continue;
+            }
+            if (h0) { ref = R.x; continue; }
+            if (h1) { ref = R.y; continue; }
+        } else if (ty == REF_BLAS_LEAF) {
+            uint32_t p = ref_index(ref);
+            uint32_t first = p >> 3, cnt = (p & 7u) + 1u;
+            for (uint32_t k = 0; k < cnt; ++k) {
+                const float4 *q = reinterpret_cast<const float4 *>(D.tris + first + k);
+                float4 A = q[0], B = q[1], C = q[2];
+                int32_t id = __float_as_int(A.w);
+                if (COUNT) ntri++;
+                if (id == exclude_id) continue;
+                float va[3] = {A.x, A.y, A.z}, vb[3] = {B.x, B.y, B.z}, vc[3] = {C.x, C.y, C.z};
+                float t = tri_hit(F, va, vb, vc);
+                if (t > tmin && (t < h.t || (t == h.t && id < h.id))) {
+                    h.t = t;
+                    h.tri = (int32_t)(first + k);
+                    h.inst = inst;
+                    h.id = id;
+                }
+            }
+        } else {
+            // top-level leaf: enter the instance (rigid transform; t is preserved)
+            inst = (int)ref_index(ref);
+            const Inst &I = D.inst[inst];
+            float r0 = o[0] - I.t[0], r1 = o[1] - I.t[1], r2 = o[2] - I.t[2];
+            float lo[3], ld[3];
+            lo[0] = I.R[0] * r0 + I.R[3] * r1 + I.R[6] * r2;
+            lo[1] = I.R[1] * r0 + I.R[4] * r1 + I.R[7] * r2;
+            lo[2] = I.R[2] * r0 + I.R[5] * r1 + I.R[8] * r2;
+            ld[0] = I.R[0] * d[0] + I.R[3] * d[1] + I.R[6] * d[2];
+            ld[1] = I.R[1] * d[0] + I.R[4] * d[1] + I.R[7] * d[2];
+            ld[2] = I.R[2] * d[0] + I.R[5] * d[1] + I.R[8] * d[2];
+            frame_setup(lo, ld, F);
+            ix = F.ix; iy = F.iy; iz = F.iz;
+            oix = F.oix; oiy = F.oiy; oiz = F.oiz;
+            if (sp >= STACK_DEPTH) return false;
+            stack[sp * BLOCK] = REF_EXIT;
+            ++sp;
+            ref = I.root;
+            continue;
+        }
+        // pop
+        for (;;) {
+            if (sp == 0) return true;
+            --sp;
+            ref = stack[sp * BLOCK];
+            if (ref != REF_EXIT) break;
+            ix = wix; iy = wiy; iz = wiz;
+            oix = woix; oiy = woiy; oiz = woiz;
+            inst = -1;
+        }
+    }
+}
+
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m, WAVE);
+    return x;
+}
+
+// Per-hit record kept for the fixed-visibility adjoint of one ray chain.
+struct ChainHit {
+    float n[3], d[3];
+    float c, w, rs, rd;
+    int32_t mat, node;
+};
+
+// Adds per-lane vectors into per-wave LDS accumulators acc[key * stride + 0..n),
+// one wave-wide FP64 sum per distinct key (keys processed lowest lane first).
+__device__ void wave_scatter_add(double *acc, int key, bool active, const float *vals, int n, int stride) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    uint64_t pending = __ballot(active);
+    while (pending) {
+        int leader = __ffsll((unsigned long long)pending) - 1;
+        int k = __shfl(key, leader, WAVE);
+        bool sel = active && key == k;
+        uint64_t m = __ballot(sel);
+        for (int c = 0; c < n; ++c) {
+            double s = wave_sum(sel ? (double)vals[c] : 0.0);
+            if (lane == c) acc[k * stride + c] += s;
+        }
+        pending &= ~m;
+    }
+}
+
+// 3x3 helpers (row-major)
+__device__ __forceinline__ void m3_zero(float *M) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) M[i] = 0.0f;
+}
+
+template <bool COUNT, bool GRAD>
+__global__ __launch_bounds__(BLOCK) void k_trace(const EvalDesc *__restrict__ descs,
+                                                 const int64_t *__restrict__ chunk_base, int n_evals,
+                                                 const uint64_t *__restrict__ win, uint32_t *counter,
+                                                 int64_t total_chunks, ChunkOut *__restrict__ chunks,
+                                                 uint64_t *__restrict__ counts) {
+    extern __shared__ char smem[];
+    uint32_t *stack = reinterpret_cast<uint32_t *>(smem) + threadIdx.x;   // entry s at [s * BLOCK]
+    double *gacc = reinterpret_cast<double *>(smem + sizeof(uint32_t) * STACK_DEPTH * BLOCK);
+    __shared__ uint32_t s_chunk;
+    __shared__ double s_red[BLOCK / WAVE][8];
+    __shared__ uint32_t s_cnt[BLOCK / WAVE][6];
+
+    const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid >> 6;
+
+    for (;;) {
+        if (tid == 0) s_chunk = atomicAdd(counter, 1u);
+        __syncthreads();
+        const int64_t c = s_chunk;
+        __syncthreads();
+        if (c >= total_chunks) break;
+
+        // evaluation owning chunk c (chunk_base is increasing; chunk_base[n_evals] = total)
+        int lo = 0, hi = n_evals - 1;
+        while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (chunk_base[mid] <= c) lo = mid; else hi = mid - 1;
+        }
+        const EvalDesc &D = descs[lo];
+        const int64_t kc = c - D.chunk_base;
+        const int N = D.n;
+
+        // window -> ray grid (FP64 -> FP32 constants)
+        const uint64_t *W = win + (size_t)lo * WIN_STRIDE;
+        const double umin = dec_f64(W[0]), umax = -dec_f64(W[1]);
+        const double vmin = dec_f64(W[2]), vmax = -dec_f64(W[3]), hmin = dec_f64(W[4]);
+        const double wu = umax - umin, wv_ = vmax - vmin;
+        const bool empty = !(wu * wv_ > 0.0) || !(wu < INFINITY) || !(wv_ < INFINITY) ||
+                           D.root_ref == REF_NONE;
+        const double L = fmax(wu, wv_);
+        const double h0 = hmin - 1e-3 * L - 1e-3;
+        const double du = wu / N, dv = wv_ / N;
+        float o0[3], su[3], sv[3], dd[3];
+        for (int k = 0; k < 3; ++k) {
+            o0[k] = (float)((umin + 0.5 * du) * D.u[k] + (vmin + 0.5 * dv) * D.v[k] + h0 * D.d[k]);
+            su[k] = (float)(du * D.u[k]);
+            sv[k] = (float)(dv * D.v[k]);
+            dd[k] = (float)D.d[k];
+        }
+        const float tmin2 = (float)(1e-6 * L);
+
+        const int cy = (int)(kc / D.tiles_x), cx = (int)(kc % D.tiles_x);
+        const int px = cx * TILE + (wv & 1) * 8 + (lane & 7);
+        const int py0 = cy * TILE * D.rpt + (wv >> 1) * 8 + (lane >> 3);
+        const int B = D.bounces;
+
+        double acc[6] = {0, 0, 0, 0, 0, 0};
+        uint32_t n_hit = 0, n_sec = 0, n_sec_hit = 0, nbox = 0, ntri = 0, status = 0;
+        double *gw = nullptr;
+        int gK = D.n_nodes, gM = D.n_mats;
+        if (GRAD) {
+            gw = gacc + (size_t)wv * D.grad_n;
+            for (int i = lane; i < D.grad_n; i += WAVE) gw[i] = 0.0;
+        }
+
+        for (int r = 0; r < D.rpt; ++r) {
+            const int py = py0 + r * TILE;
+            const bool valid = !empty && px < N && py < N;
+            ChainHit chain[GRAD ? MAX_CHAIN : 1];
+            int K = 0;
+            if (valid) {
+                float o[3], d[3];
+                for (int k = 0; k < 3; ++k) {
+                    o[k] = fmaf((float)py, sv[k], fmaf((float)px, su[k], o0[k]));
+                    d[k] = dd[k];
+                }
+                float w = 1.0f, tmin = 0.0f;
+                int32_t excl = -1;
+                const int64_t pix = (int64_t)py * N + px;
+                for (int gen = 0; gen <= B; ++gen) {
+                    Hit h;
+                    if (!trace_closest<COUNT>(D, o, d, tmin, excl, stack, h, nbox, ntri)) {
+                        status |= SRP_STATUS_STACK;
+                        break;
+                    }
+                    if (D.hit_ids) {
+                        D.hit_ids[pix * (B + 1) + gen] = h.tri >= 0 ? h.id : -1;
+                        D.hit_t[pix * (B + 1) + gen] = h.tri >= 0 ? h.t : 0.0f;
+                    }
+                    if (h.tri < 0) break;
+                    if (gen == 0) n_hit++; else n_sec_hit++;
+                    const TriRec &T = D.tris[h.tri];
+                    const Inst &I = D.inst[h.inst];
+                    float e1[3] = {T.v1[0] - T.v0[0], T.v1[1] - T.v0[1], T.v1[2] - T.v0[2]};
+                    float e2[3] = {T.v2[0] - T.v0[0], T.v2[1] - T.v0[1], T.v2[2] - T.v0[2]};
+                    float nl[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+                                   e1[0] * e2[1] - e1[1] * e2[0]};
+                    float n[3];
+                    for (int k = 0; k < 3; ++k) n[k] = I.R[3 * k] * nl[0] + I.R[3 * k + 1] * nl[1] + I.R[3 * k + 2] * nl[2];
+                    float inv = rsqrtf(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+                    float nd = (n[0] * d[0] + n[1] * d[1] + n[2] * d[2]) * inv;
+                    if (nd > 0.0f) inv = -inv;
+                    for (int k = 0; k < 3; ++k) n[k] *= inv;
+                    const float cth = -(n[0] * d[0] + n[1] * d[1] + n[2] * d[2]);
+                    const float rs = D.mats[2 * T.mat], rd = D.mats[2 * T.mat + 1];
+                    const float a = w * (1.0f - rs), b = -2.0f * w * (rs * cth + rd * (1.0f / 3.0f));
+                    float f[3], x[3], rr[3];
+                    for (int k = 0; k < 3; ++k) {
+                        f[k] = a * d[k] + b * n[k];
+                        x[k] = fmaf(h.t, d[k], o[k]);
+                        rr[k] = x[k] - (float)D.ref[k];
+                    }
+                    acc[0] += (double)f[0];
+                    acc[1] += (double)f[1];
+                    acc[2] += (double)f[2];
+                    acc[3] += (double)(rr[1] * f[2] - rr[2] * f[1]);
+                    acc[4] += (double)(rr[2] * f[0] - rr[0] * f[2]);
+                    acc[5] += (double)(rr[0] * f[1] - rr[1] * f[0]);
+                    if (GRAD) {
+                        ChainHit &ch = chain[K];
+                        for (int k = 0; k < 3; ++k) { ch.n[k] = n[k]; ch.d[k] = d[k]; }
+                        ch.c = cth; ch.w = w; ch.rs = rs; ch.rd = rd;
+                        ch.mat = T.mat; ch.node = T.node;
+                    }
+                    ++K;
+                    if (gen == B || !(rs > 0.0f)) break;
+                    for (int k = 0; k < 3; ++k) {
+                        o[k] = x[k];
+                        d[k] = fmaf(2.0f * cth, n[k], d[k]);
+                    }
+                    w *= rs;
+                    tmin = tmin2;
+                    excl = T.id;
+                    n_sec++;
+                }
+            }
+            if (GRAD) {
+                // Reverse sweep over the chain at fixed visibility.
+                //   A  = d(sum of later contributions)/d(incoming direction)   (3x3)
+                //   Tn = later contributions divided by the weight after this hit
+                int Kmax = K;
+                for (int m = 32; m >= 1; m >>= 1) Kmax = max(Kmax, __shfl_xor(Kmax, m, WAVE));
+                float A[9], Tn[3] = {0, 0, 0};
+                m3_zero(A);
+                for (int k = Kmax - 1; k >= 0; --k) {
+                    const bool act = k < K;
+                    float Hm[9], gmat[6];
+                    int node = 0, mat = 0;
+                    if (act) {
+                        const ChainHit ch = chain[k];
+                        const float *n = ch.n, *d = ch.d;
+                        const float w = ch.w, rs = ch.rs, rd = ch.rd, cc = ch.c;
+                        const float sc = rs * cc + rd * (1.0f / 3.0f);
+                        // material terms
+                        for (int i = 0; i < 3; ++i) {
+                            gmat[i] = w * (-d[i] - 2.0f * cc * n[i] + Tn[i]);
+                            gmat[3 + i] = w * (-2.0f / 3.0f) * n[i];
+                        }
+                        // G = dF/dn (explicit) + A (2c I - 2 n d^T)
+                        float G[9];
+                        for (int i = 0; i < 3; ++i)
+                            for (int j = 0; j < 3; ++j) {
+                                float e = w * (2.0f * rs * n[i] * d[j] - (i == j ? 2.0f * sc : 0.0f));
+                                float an = A[3 * i] * n[0] + A[3 * i + 1] * n[1] + A[3 * i + 2] * n[2];
+                                e += 2.0f * cc * A[3 * i + j] - 2.0f * an * d[j];
+                                G[3 * i + j] = e;
+                            }
+                        // H = -G [n]x
+                        for (int i = 0; i < 3; ++i) {
+                            const float g0 = G[3 * i], g1 = G[3 * i + 1], g2 = G[3 * i + 2];
+                            Hm[3 * i + 0] = -(g1 * n[2] - g2 * n[1]);
+                            Hm[3 * i + 1] = -(g2 * n[0] - g0 * n[2]);
+                            Hm[3 * i + 2] = -(g0 * n[1] - g1 * n[0]);
+                        }
+                        // A <- dF_k/dd + A (I - 2 n n^T);  Tn <- f_k + rs Tn
+                        float An[3];
+                        for (int i = 0; i < 3; ++i) An[i] = A[3 * i] * n[0] + A[3 * i + 1] * n[1] + A[3 * i + 2] * n[2];
+                        for (int i = 0; i < 3; ++i)
+                            for (int j = 0; j < 3; ++j)
+                                A[3 * i + j] = A[3 * i + j] - 2.0f * An[i] * n[j] +
+                                               w * ((i == j ? 1.0f - rs : 0.0f) + 2.0f * rs * n[i] * n[j]);
+                        for (int i = 0; i < 3; ++i) Tn[i] = (1.0f - rs) * d[i] - 2.0f * sc * n[i] + rs * Tn[i];
+                        node = ch.node;
+                        mat = ch.mat;
+                    }
+                    wave_scatter_add(gw, node, act, Hm, 9, 9);
+                    wave_scatter_add(gw + 9 * gK, mat, act, gmat, 6, 6);
+                }
+            }
+        }
+
+        // block reduction of the chunk's sums (fixed order)
+        for (int k = 0; k < 6; ++k) {
+            double s = wave_sum(acc[k]);
+            if (lane == 0) s_red[wv][k] = s;
+        }
+        uint32_t cnts[6] = {n_hit, n_sec, n_sec_hit, nbox, ntri, status};
+        for (int k = 0; k < 6; ++k) {
+            uint32_t s = cnts[k];
+            for (int m = 32; m >= 1; m >>= 1) s = (k == 5) ? (s | __shfl_xor(s, m, WAVE)) : (s + __shfl_xor(s, m, WAVE));
+            if (lane == 0) s_cnt[wv][k] = s;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            ChunkOut co;
+            for (int k = 0; k < 6; ++k) {
+                double s = s_red[0][k];
+                for (int w2 = 1; w2 < BLOCK / WAVE; ++w2) s += s_red[w2][k];
+                co.f[k] = s;
+            }
+            uint32_t cs[6] = {0, 0, 0, 0, 0, 0};
+            for (int w2 = 0; w2 < BLOCK / WAVE; ++w2)
+                for (int k = 0; k < 6; ++k) cs[k] = (k == 5) ? (cs[k] | s_cnt[w2][k]) : (cs[k] + s_cnt[w2][k]);
+            co.hits = cs[0];
+            co.sec = cs[1];
+            co.sec_hits = cs[2];
+            co.flags = cs[5];
+            chunks[c] = co;
+            if (COUNT) {
+                counts[2 * c] = cs[3];
+                counts[2 * c + 1] = cs[4];
+            }
+        }
+        if (GRAD) {
+            __syncthreads();
+            double *dst = D.grad_part + (size_t)kc * D.grad_n;
+            for (int i = tid; i < D.grad_n; i += BLOCK) {
+                double s = gacc[i];
+                for (int w2 = 1; w2 < BLOCK / WAVE; ++w2) s += gacc[(size_t)w2 * D.grad_n + i];
+                dst[i] = s;
+            }
+            (void)gM;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_window(const EvalDesc *__restrict__ descs, uint64_t *win) {
+    const EvalDesc &D = descs[blockIdx.y];
+    double mn[5] = {INFINITY, INFINITY, INFINITY, INFINITY, INFINITY};
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < D.n_wpts;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const WPoint p = D.wpts[i];
+        const double *X = D.xf + 12 * p.node;
+        double x = X[0] * p.x + X[1] * p.y + X[2] * p.z + X[9];
+        double y = X[3] * p.x + X[4] * p.y + X[5] * p.z + X[10];
+        double z = X[6] * p.x + X[7] * p.y + X[8] * p.z + X[11];
+        double a = x * D.u[0] + y * D.u[1] + z * D.u[2];
+        double b = x * D.v[0] + y * D.v[1] + z * D.v[2];
+        double h = x * D.d[0] + y * D.d[1] + z * D.d[2];
+        mn[0] = fmin(mn[0], a);
+        mn[1] = fmin(mn[1], -a);
+        mn[2] = fmin(mn[2], b);
+        mn[3] = fmin(mn[3], -b);
+        mn[4] = fmin(mn[4], h);
+    }
+    __shared__ double s[256 / WAVE][5];
+    const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x >> 6;
+    for (int k = 0; k < 5; ++k) {
+        double x = mn[k];
+        for (int m = 32; m >= 1; m >>= 1) x = fmin(x, __shfl_xor(x, m, WAVE));
+        if (lane == 0) s[wv][k] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x < 5) {
+        double x = s[0][threadIdx.x];
+        for (int w = 1; w < (int)(blockDim.x / WAVE); ++w) x = fmin(x, s[w][threadIdx.x]);
+        if (x != INFINITY) atomicMin((unsigned long long *)(win + (size_t)blockIdx.y * WIN_STRIDE + threadIdx.x),
+                                     (unsigned long long)enc_f64(x));
+    }
+}
+
+template <bool COUNT, bool GRAD>
+__global__ __launch_bounds__(256) void k_reduce(const EvalDesc *__restrict__ descs,
+                                                const int64_t *__restrict__ chunk_base,
+                                                const uint64_t *__restrict__ win,
+                                                const ChunkOut *__restrict__ chunks,
+                                                const uint64_t *__restrict__ counts, srp_result *out) {
+    const int e = blockIdx.x, tid = threadIdx.x;
+    const EvalDesc &D = descs[e];
+    const int64_t c0 = chunk_base[e], c1 = chunk_base[e + 1];
+    double f[6] = {0, 0, 0, 0, 0, 0};
+    uint64_t cn[5] = {0, 0, 0, 0, 0};
+    uint32_t st = 0;
+    for (int64_t c = c0 + tid; c < c1; c += blockDim.x) {
+        const ChunkOut &co = chunks[c];
+        for (int k = 0; k < 6; ++k) f[k] += co.f[k];
+        cn[0] += co.hits;
+        cn[1] += co.sec;
+        cn[2] += co.sec_hits;
+        st |= co.flags;
+        if (COUNT) { cn[3] += counts[2 * c]; cn[4] += counts[2 * c + 1]; }
+    }
+    __shared__ double sf[256][6];
+    __shared__ unsigned long long sc[256][5];
+    __shared__ uint32_t ss[256];
+    for (int k = 0; k < 6; ++k) sf[tid][k] = f[k];
+    for (int k = 0; k < 5; ++k) sc[tid][k] = cn[k];
+    ss[tid] = st;
+    __syncthreads();
+    for (int s = 128; s >= 1; s >>= 1) {
+        if (tid < s) {
+            for (int k = 0; k < 6; ++k) sf[tid][k] += sf[tid + s][k];
+            for (int k = 0; k < 5; ++k) sc[tid][k] += sc[tid + s][k];
+            ss[tid] |= ss[tid + s];
+        }
+        __syncthreads();
+    }
+    const uint64_t *W = win + (size_t)e * WIN_STRIDE;
+    const double umin = dec_f64(W[0]), umax = -dec_f64(W[1]);
+    const double vmin = dec_f64(W[2]), vmax = -dec_f64(W[3]);
+    const double wu = umax - umin, wv = vmax - vmin;
+    const bool empty = !(wu * wv > 0.0) || !(wu < INFINITY) || !(wv < INFINITY) || D.root_ref == REF_NONE;
+    const double scale = empty ? 0.0 : D.pressure * (wu * wv / ((double)D.n * (double)D.n));
+    if (tid == 0) {
+        srp_result r;
+        for (int k = 0; k < 3; ++k) {
+            r.force[k] = scale * sf[0][k];
+            r.torque[k] = scale * sf[0][3 + k];
+        }
+        r.n_rays = (int64_t)D.n * D.n;
+        r.n_hits = (int64_t)sc[0][0];
+        r.n_secondary = (int64_t)sc[0][1];
+        r.n_secondary_hits = (int64_t)sc[0][2];
+        r.n_box_tests = COUNT ? (int64_t)sc[0][3] : 0;
+        r.n_tri_tests = COUNT ? (int64_t)sc[0][4] : 0;
+        r.status = ss[0];
+        r.reserved = 0;
+        out[e] = r;
+    }
+    if (GRAD) {
+        // sum chunk partials per component (fixed chunk order), then assemble
+        const int G = D.grad_n, K = D.n_nodes, M = D.n_mats, J = D.n_dof;
+        __shared__ double sg[MAX_GRAD_SLOTS];
+        for (int i = tid; i < G; i += blockDim.x) {
+            double s = 0.0;
+            for (int64_t c = 0; c < D.n_chunks; ++c) s += D.grad_part[(size_t)c * G + i];
+            sg[i] = s;
+        }
+        __syncthreads();
+        double *g = D.grad_out;
+        if (g) {
+            // rho_s (M x 3), rho_d (M x 3)
+            for (int i = tid; i < 6 * M; i += blockDim.x) {
+                int m = i / 6, k = i % 6;
+                double v = scale * sg[9 * K + i];
+                if (k < 3) g[3 * m + k] = v;
+                else g[3 * M + 3 * m + (k - 3)] = v;
+            }
+            // theta: (sum of S_q over the subtree of the joint's node) * world axis
+            for (int j = tid; j < J; j += blockDim.x) {
+                const int p = D.dof_node[j];
+                double S[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+                for (int q = 0; q < K; ++q) {
+                    int a = q;
+                    while (a > p) a = D.parent[a];
+                    if (a != p) continue;
+                    for (int i = 0; i < 9; ++i) S[i] += sg[9 * q + i];
+                }
+                const double *ax = D.axw + 3 * j;
+                for (int i = 0; i < 3; ++i)
+                    g[6 * M + 3 * j + i] = scale * (S[3 * i] * ax[0] + S[3 * i + 1] * ax[1] + S[3 * i + 2] * ax[2]);
+            }
+        }
+    }
+}
+
+int check(hipError_t e) { return e == hipSuccess ? 0 : (int)e; }
+
+}  // namespace
+
+int launch_window(const EvalDesc *d_desc, int n_evals, int blocks_x, uint64_t *d_win, void *stream) {
+    if (n_evals <= 0) return 0;
+    hipLaunchKernelGGL(k_window, dim3(blocks_x, n_evals), dim3(256), 0, (hipStream_t)stream, d_desc, d_win);
+    return check(hipGetLastError());
+}
+
+int launch_trace(const EvalDesc *d_desc, const int64_t *d_chunk_base, int n_evals, const uint64_t *d_win,
+                 uint32_t *d_counter, int64_t total_chunks, ChunkOut *d_chunks, uint64_t *d_counts, bool count,
+                 bool grad, int grid_blocks, int lds_grad_doubles, void *stream) {
+    if (total_chunks <= 0) return 0;
+    size_t lds = sizeof(uint32_t) * STACK_DEPTH * BLOCK + (grad ? sizeof(double) * (BLOCK / 64) * lds_grad_doubles : 0);
+    hipStream_t s = (hipStream_t)stream;
+    if (count && grad)
+        hipLaunchKernelGGL((k_trace<true, true>), dim3(grid_blocks), dim3(BLOCK), lds, s, d_desc, d_chunk_base,
+                           n_evals, d_win, d_counter, total_chunks, d_chunks, d_counts);
+    else if (count)
+        hipLaunchKernelGGL((k_trace<true, false>), dim3(grid_blocks), dim3(BLOCK), lds, s, d_desc, d_chunk_base,
+                           n_evals, d_win, d_counter, total_chunks, d_chunks, d_counts);
+    else if (grad)
+        hipLaunchKernelGGL((k_trace<false, true>), dim3(grid_blocks), dim3(BLOCK), lds, s, d_desc, d_chunk_base,
+                           n_evals, d_win, d_counter, total_chunks, d_chunks, d_counts);
+    else
+        hipLaunchKernelGGL((k_trace<false, false>), dim3(grid_blocks), dim3(BLOCK), lds, s, d_desc, d_chunk_base,
+                           n_evals, d_win, d_counter, total_chunks, d_chunks, d_counts);
+    return check(hipGetLastError());
+}
+
+int launch_reduce(const EvalDesc *d_desc, const int64_t *d_chunk_base, int n_evals, const uint64_t *d_win,
+                  const ChunkOut *d_chunks, const uint64_t *d_counts, bool count, bool grad, void *d_out,
+                  void *stream) {
+    if (n_evals <= 0) return 0;
+    hipStream_t s = (hipStream_t)stream;
+    srp_result *out = (srp_result *)d_out;
+    if (count && grad)
+        hipLaunchKernelGGL((k_reduce<true, true>), dim3(n_evals), dim3(256), 0, s, d_desc, d_chunk_base, d_win, d_chunks, d_counts, out);
+    else if (count)
+        hipLaunchKernelGGL((k_reduce<true, false>), dim3(n_evals), dim3(256), 0, s, d_desc, d_chunk_base, d_win, d_chunks, d_counts, out);
+    else if (grad)
+        hipLaunchKernelGGL((k_reduce<false, true>), dim3(n_evals), dim3(256), 0, s, d_desc, d_chunk_base, d_win, d_chunks, d_counts, out);
+    else
+        hipLaunchKernelGGL((k_reduce<false, false>), dim3(n_evals), dim3(256), 0, s, d_desc, d_chunk_base, d_win, d_chunks, d_counts, out);
+    return check(hipGetLastError());
+}
+
+int trace_blocks_per_cu(bool count, bool grad, int lds_grad_doubles) {
+    size_t lds = sizeof(uint32_t) * STACK_DEPTH * BLOCK + (grad ? sizeof(double) * (BLOCK / 64) * lds_grad_doubles : 0);
+    int nb = 0;
+    hipError_t e;
+    if (count && grad) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_trace<true, true>, BLOCK, lds);
+    else if (count) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_trace<true, false>, BLOCK, lds);
+    else if (grad) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_trace<false, true>, BLOCK, lds);
+    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_trace<false, false>, BLOCK, lds);
+    if (e != hipSuccess || nb < 1) nb = 1;
+    return nb;
+}
+
+}  // namespace srp

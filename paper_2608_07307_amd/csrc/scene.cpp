@@ -1,0 +1,483 @@
+// Scene construction on the host: input validation, one bounding-volume
+// hierarchy per kinematic-tree node in rest-pose coordinates, the window
+// point set, and the per-angle articulation slot (instance transforms and a
+// top-level hierarchy over the nodes).
+//
+// The paper moves the triangles of each articulated subtree on the CPU before
+// every evaluation (Sec. 4.4.2, step 5).  Here each node's triangles stay in
+// their rest pose inside their own hierarchy; a hinge rotation only changes
+// the node's rigid transform, so an angle update rebuilds nothing but a
+// top-level hierarchy of at most SRP_MAX_NODES boxes.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "host.h"
+
+namespace srp {
+
+namespace {
+
+constexpr int BINS = 16;
+constexpr double C_TRAV = 0.6;  // cost of a node visit (two box tests) relative to a triangle test
+
+struct Prim {
+    float lo[3], hi[3];
+    float c[3];
+    int32_t tri;
+};
+
+struct Box {
+    float lo[3], hi[3];
+    Box() {
+        for (int a = 0; a < 3; ++a) { lo[a] = INFINITY; hi[a] = -INFINITY; }
+    }
+    void grow(const Box &b) {
+        for (int a = 0; a < 3; ++a) { lo[a] = std::min(lo[a], b.lo[a]); hi[a] = std::max(hi[a], b.hi[a]); }
+    }
+    void grow(const float *p) {
+        for (int a = 0; a < 3; ++a) { lo[a] = std::min(lo[a], p[a]); hi[a] = std::max(hi[a], p[a]); }
+    }
+    double area() const {
+        double dx = (double)hi[0] - lo[0], dy = (double)hi[1] - lo[1], dz = (double)hi[2] - lo[2];
+        if (!(dx >= 0) || !(dy >= 0) || !(dz >= 0)) return 0;
+        return 2.0 * (dx * dy + dy * dz + dz * dx);
+    }
+};
+
+int ceil_log2(int64_t x) {
+    int k = 0;
+    while ((int64_t(1) << k) < x) ++k;
+    return k;
+}
+
+struct BlasBuilder {
+    std::vector<Prim> &P;
+    const std::vector<TriRec> &rec;   // by original triangle index
+    std::vector<BNode> &nodes;
+    std::vector<TriRec> &out;
+    float pad;
+    int max_depth = 0;
+    bool depth_error = false;
+
+    uint32_t leaf(int b, int e) {
+        uint32_t first = (uint32_t)out.size();
+        for (int k = b; k < e; ++k) out.push_back(rec[P[k].tri]);
+        return make_ref(REF_BLAS_LEAF, (first << 3) | (uint32_t)(e - b - 1));
+    }
+
+    // Builds prims [b, e) at `depth` internal levels below the root; returns its
+    // reference and writes its (unpadded) bounds.
+    uint32_t build(int b, int e, int depth, Box &bounds) {
+        Box cb;
+        bounds = Box();
+        for (int k = b; k < e; ++k) {
+            Box pb;
+            std::memcpy(pb.lo, P[k].lo, sizeof pb.lo);
+            std::memcpy(pb.hi, P[k].hi, sizeof pb.hi);
+            bounds.grow(pb);
+            cb.grow(P[k].c);
+        }
+        int n = e - b;
+        if (n <= 1) return leaf(b, e);
+        int remaining = BLAS_MAX_DEPTH - depth;                // internal levels still allowed
+        int needed = ceil_log2((n + LEAF_MAX - 1) / LEAF_MAX); // levels a balanced split needs
+        if (needed > remaining) { depth_error = true; return leaf(b, std::min(e, b + LEAF_MAX)); }
+
+        int split = -1, axis = -1;
+        double best = INFINITY;
+        bool sah = remaining > needed + 1;
+        double leaf_cost = n;
+        if (sah) {
+            double pa = bounds.area();
+            for (int a = 0; a < 3; ++a) {
+                double ext = (double)cb.hi[a] - cb.lo[a];
+                if (!(ext > 0)) continue;
+                Box bb[BINS];
+                int cnt[BINS] = {0};
+                double scale = BINS / ext;
+                for (int k = b; k < e; ++k) {
+                    int bi = std::min(BINS - 1, (int)((P[k].c[a] - cb.lo[a]) * scale));
+                    Box pb;
+                    std::memcpy(pb.lo, P[k].lo, sizeof pb.lo);
+                    std::memcpy(pb.hi, P[k].hi, sizeof pb.hi);
+                    bb[bi].grow(pb);
+                    cnt[bi]++;
+                }
+                double la[BINS], ra[BINS];
+                int lc[BINS], rc[BINS];
+                Box acc;
+                int c = 0;
+                for (int i = 0; i < BINS; ++i) { acc.grow(bb[i]); c += cnt[i]; la[i] = acc.area(); lc[i] = c; }
+                acc = Box();
+                c = 0;
+                for (int i = BINS - 1; i >= 0; --i) { acc.grow(bb[i]); c += cnt[i]; ra[i] = acc.area(); rc[i] = c; }
+                for (int i = 0; i < BINS - 1; ++i) {
+                    if (lc[i] == 0 || rc[i + 1] == 0) continue;
+                    double cost = C_TRAV + (pa > 0 ? (la[i] * lc[i] + ra[i + 1] * rc[i + 1]) / pa : n);
+                    if (cost < best) { best = cost; split = i; axis = a; }
+                }
+            }
+            if (n <= LEAF_MAX && leaf_cost <= best) return leaf(b, e);
+        } else if (n <= LEAF_MAX && n <= 4) {
+            return leaf(b, e);
+        }
+
+        int mid;
+        if (split >= 0) {
+            double ext = (double)cb.hi[axis] - cb.lo[axis];
+            double scale = BINS / ext;
+            float lo = cb.lo[axis];
+            auto it = std::partition(P.begin() + b, P.begin() + e, [&](const Prim &p) {
+                return std::min(BINS - 1, (int)((p.c[axis] - lo) * scale)) <= split;
+            });
+            mid = (int)(it - P.begin());
+        } else {
+            // object median along the widest centroid axis (or by index when all coincide)
+            int a = 0;
+            for (int k = 1; k < 3; ++k)
+                if ((double)cb.hi[k] - cb.lo[k] > (double)cb.hi[a] - cb.lo[a]) a = k;
+            mid = b + n / 2;
+            std::nth_element(P.begin() + b, P.begin() + mid, P.begin() + e, [&](const Prim &x, const Prim &y) {
+                return x.c[a] < y.c[a] || (x.c[a] == y.c[a] && x.tri < y.tri);
+            });
+        }
+        if (mid <= b || mid >= e) mid = b + n / 2;
+
+        uint32_t me = (uint32_t)nodes.size();
+        nodes.push_back(BNode{});
+        max_depth = std::max(max_depth, depth + 1);
+        Box lb, rb;
+        uint32_t l = build(b, mid, depth + 1, lb);
+        uint32_t r = build(mid, e, depth + 1, rb);
+        BNode &nd = nodes[me];
+        for (int a = 0; a < 3; ++a) {
+            nd.lo0[a] = lb.lo[a] - pad; nd.hi0[a] = lb.hi[a] + pad;
+            nd.lo1[a] = rb.lo[a] - pad; nd.hi1[a] = rb.hi[a] + pad;
+        }
+        nd.ref0 = l;
+        nd.ref1 = r;
+        return make_ref(REF_BLAS_NODE, me);
+    }
+};
+
+void rot_axis_angle(const double *a_in, double th, double *R) {
+    double n = std::sqrt(a_in[0] * a_in[0] + a_in[1] * a_in[1] + a_in[2] * a_in[2]);
+    double x = a_in[0] / n, y = a_in[1] / n, z = a_in[2] / n;
+    double c = std::cos(th), s = std::sin(th), C = 1 - c;
+    double M[9] = {c + x * x * C,     x * y * C - z * s, x * z * C + y * s,
+                   y * x * C + z * s, c + y * y * C,     y * z * C - x * s,
+                   z * x * C - y * s, z * y * C + x * s, c + z * z * C};
+    std::memcpy(R, M, sizeof M);
+}
+
+void mat3_mul(const double *A, const double *B, double *C) {
+    double T[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) T[3 * i + j] = A[3 * i] * B[j] + A[3 * i + 1] * B[3 + j] + A[3 * i + 2] * B[6 + j];
+    std::memcpy(C, T, sizeof T);
+}
+
+void mat3_vec(const double *A, const double *x, double *y) {
+    double t[3];
+    for (int i = 0; i < 3; ++i) t[i] = A[3 * i] * x[0] + A[3 * i + 1] * x[1] + A[3 * i + 2] * x[2];
+    std::memcpy(y, t, sizeof t);
+}
+
+bool finite3(const double *v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
+
+}  // namespace
+
+int validate_materials(const srp_material *mats, int32_t n_mats, std::string *err) {
+    if (!mats || n_mats < 1 || n_mats > SRP_MAX_MATS) {
+        *err = "materials: need 1.." + std::to_string(SRP_MAX_MATS) + " entries";
+        return SRP_ERR_ARG;
+    }
+    for (int32_t m = 0; m < n_mats; ++m) {
+        double s = mats[m].rho_s, d = mats[m].rho_d;
+        if (!(s >= 0 && d >= 0 && s + d <= 1.0 + 1e-12) || !std::isfinite(s) || !std::isfinite(d)) {
+            *err = "material " + std::to_string(m) + ": need rho_s >= 0, rho_d >= 0, rho_s + rho_d <= 1";
+            return SRP_ERR_ARG;
+        }
+    }
+    return SRP_OK;
+}
+
+int scene_build(const double *verts, int64_t n_verts, const int32_t *tris, int64_t n_tris,
+                const int32_t *tri_material, const int32_t *tri_node, const srp_material *mats,
+                int32_t n_mats, const srp_node *nodes, int32_t n_nodes, SceneHost *S,
+                std::string *err) {
+    if ((n_verts > 0 && !verts) || (n_tris > 0 && (!tris || !tri_material || !tri_node)) || !nodes ||
+        n_verts < 0 || n_tris < 0) {
+        *err = "srp_build_scene: null or negative-size input";
+        return SRP_ERR_ARG;
+    }
+    if (n_tris >= (int64_t(1) << 27)) { *err = "srp_build_scene: too many triangles"; return SRP_ERR_ARG; }
+    if (n_nodes < 1 || n_nodes > SRP_MAX_NODES) {
+        *err = "srp_build_scene: need 1.." + std::to_string(SRP_MAX_NODES) + " nodes";
+        return SRP_ERR_ARG;
+    }
+    int rc = validate_materials(mats, n_mats, err);
+    if (rc) return rc;
+    if (nodes[0].parent != -1 || nodes[0].n_axes != 0) {
+        *err = "srp_build_scene: node 0 must be the root (parent -1, no axes)";
+        return SRP_ERR_ARG;
+    }
+    S->nodes.assign(n_nodes, NodeInfo{});
+    S->parent.assign(n_nodes, -1);
+    int32_t dof = 0;
+    for (int32_t k = 0; k < n_nodes; ++k) {
+        const srp_node &in = nodes[k];
+        NodeInfo &o = S->nodes[k];
+        if (k > 0 && (in.parent < 0 || in.parent >= k)) {
+            *err = "node " + std::to_string(k) + ": parent must be in [0, k) (single root, topological order)";
+            return SRP_ERR_ARG;
+        }
+        if (in.n_axes < 0 || in.n_axes > 3) { *err = "node " + std::to_string(k) + ": n_axes must be 0..3"; return SRP_ERR_ARG; }
+        o.parent = in.parent;
+        o.is_panel = in.is_panel;
+        o.n_axes = in.n_axes;
+        o.dof_offset = dof;
+        dof += in.n_axes;
+        if (!finite3(in.pivot)) { *err = "node " + std::to_string(k) + ": non-finite pivot"; return SRP_ERR_ARG; }
+        std::memcpy(o.pivot, in.pivot, sizeof o.pivot);
+        for (int a = 0; a < in.n_axes; ++a) {
+            double nrm = std::sqrt(in.axis[a][0] * in.axis[a][0] + in.axis[a][1] * in.axis[a][1] + in.axis[a][2] * in.axis[a][2]);
+            if (!(nrm > 0) || !std::isfinite(nrm) || !(in.lo[a] <= in.hi[a]) || !std::isfinite(in.lo[a]) ||
+                !std::isfinite(in.hi[a])) {
+                *err = "node " + std::to_string(k) + ": invalid axis or interval";
+                return SRP_ERR_ARG;
+            }
+            for (int c = 0; c < 3; ++c) o.axis[a][c] = in.axis[a][c] / nrm;
+            o.lo[a] = in.lo[a];
+            o.hi[a] = in.hi[a];
+        }
+        S->parent[k] = in.parent;
+    }
+    S->n_nodes = n_nodes;
+    S->n_dof = dof;
+    S->n_mats = n_mats;
+    S->n_tris = n_tris;
+    S->mats.resize(2 * n_mats);
+    for (int m = 0; m < n_mats; ++m) { S->mats[2 * m] = (float)mats[m].rho_s; S->mats[2 * m + 1] = (float)mats[m].rho_d; }
+
+    // triangles: validate, FP32 records, per-node lists, scene scale
+    std::vector<TriRec> rec(n_tris);
+    std::vector<std::vector<int32_t>> per_node(n_nodes);
+    double scale = 0;
+    for (int64_t t = 0; t < n_tris; ++t) {
+        for (int c = 0; c < 3; ++c) {
+            int32_t vi = tris[3 * t + c];
+            if (vi < 0 || vi >= n_verts) { *err = "triangle " + std::to_string(t) + ": vertex index out of range"; return SRP_ERR_ARG; }
+            if (!finite3(verts + 3 * (int64_t)vi)) { *err = "non-finite vertex"; return SRP_ERR_ARG; }
+        }
+        if (tri_material[t] < 0 || tri_material[t] >= n_mats) { *err = "triangle " + std::to_string(t) + ": material out of range"; return SRP_ERR_ARG; }
+        if (tri_node[t] < 0 || tri_node[t] >= n_nodes) { *err = "triangle " + std::to_string(t) + ": node out of range"; return SRP_ERR_ARG; }
+        TriRec &r = rec[t];
+        const double *p0 = verts + 3 * (int64_t)tris[3 * t];
+        const double *p1 = verts + 3 * (int64_t)tris[3 * t + 1];
+        const double *p2 = verts + 3 * (int64_t)tris[3 * t + 2];
+        for (int a = 0; a < 3; ++a) {
+            r.v0[a] = (float)p0[a]; r.v1[a] = (float)p1[a]; r.v2[a] = (float)p2[a];
+            scale = std::max(scale, std::max(std::fabs(p0[a]), std::max(std::fabs(p1[a]), std::fabs(p2[a]))));
+        }
+        r.id = (int32_t)t;
+        r.mat = tri_material[t];
+        r.node = tri_node[t];
+        per_node[tri_node[t]].push_back((int32_t)t);
+    }
+    S->pad = 4e-6 * scale + 1e-9;
+
+    // one hierarchy per node
+    S->tris.clear();
+    S->tris.reserve(n_tris);
+    S->blas.clear();
+    S->max_blas_depth = 0;
+    for (int32_t k = 0; k < n_nodes; ++k) {
+        NodeInfo &o = S->nodes[k];
+        const auto &lst = per_node[k];
+        if (lst.empty()) { o.blas_root = REF_NONE; continue; }
+        std::vector<Prim> P(lst.size());
+        for (size_t i = 0; i < lst.size(); ++i) {
+            const TriRec &r = rec[lst[i]];
+            Prim &p = P[i];
+            for (int a = 0; a < 3; ++a) {
+                p.lo[a] = std::min(r.v0[a], std::min(r.v1[a], r.v2[a]));
+                p.hi[a] = std::max(r.v0[a], std::max(r.v1[a], r.v2[a]));
+                p.c[a] = 0.5f * (p.lo[a] + p.hi[a]);
+            }
+            p.tri = lst[i];
+        }
+        BlasBuilder B{P, rec, S->blas, S->tris, (float)S->pad};
+        Box root;
+        o.blas_root = B.build(0, (int)P.size(), 0, root);
+        if (B.depth_error) {
+            *err = "node " + std::to_string(k) + ": hierarchy exceeds the traversal stack";
+            return SRP_ERR_DEPTH;
+        }
+        o.blas_depth = B.max_depth;
+        S->max_blas_depth = std::max(S->max_blas_depth, B.max_depth);
+        for (int a = 0; a < 3; ++a) { o.blo[a] = (double)root.lo[a] - S->pad; o.bhi[a] = (double)root.hi[a] + S->pad; }
+    }
+    if ((int64_t)S->blas.size() >= (int64_t(1) << 30)) { *err = "srp_build_scene: hierarchy too large"; return SRP_ERR_ARG; }
+
+    // window points: distinct (vertex, node) pairs used by triangles
+    std::vector<std::pair<int32_t, int32_t>> vn;
+    vn.reserve(3 * n_tris);
+    for (int64_t t = 0; t < n_tris; ++t)
+        for (int c = 0; c < 3; ++c) vn.emplace_back(tri_node[t], tris[3 * t + c]);
+    std::sort(vn.begin(), vn.end());
+    vn.erase(std::unique(vn.begin(), vn.end()), vn.end());
+    S->wpts.resize(vn.size());
+    for (size_t i = 0; i < vn.size(); ++i) {
+        const double *p = verts + 3 * (int64_t)vn[i].second;
+        S->wpts[i] = WPoint{p[0], p[1], p[2], vn[i].first, 0};
+    }
+    return SRP_OK;
+}
+
+SlotLayout slot_layout(int n_nodes, int n_tlas, int n_dof) {
+    auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+    SlotLayout L;
+    L.inst = 0;
+    L.tlas = al(L.inst + sizeof(Inst) * (size_t)n_nodes);
+    L.xf = al(L.tlas + sizeof(BNode) * (size_t)std::max(n_tlas, 1));
+    L.axw = al(L.xf + sizeof(double) * 12 * (size_t)n_nodes);
+    L.dof_node = al(L.axw + sizeof(double) * 3 * (size_t)std::max(n_dof, 1));
+    L.bytes = al(L.dof_node + sizeof(int32_t) * (size_t)std::max(n_dof, 1));
+    return L;
+}
+
+void slot_pack(const SlotHost &s, const SlotLayout &L, char *dst) {
+    std::memcpy(dst + L.inst, s.inst.data(), sizeof(Inst) * s.inst.size());
+    if (!s.tlas.empty()) std::memcpy(dst + L.tlas, s.tlas.data(), sizeof(BNode) * s.tlas.size());
+    std::memcpy(dst + L.xf, s.xf.data(), sizeof(double) * s.xf.size());
+    if (!s.axw.empty()) std::memcpy(dst + L.axw, s.axw.data(), sizeof(double) * s.axw.size());
+    if (!s.dof_node.empty()) std::memcpy(dst + L.dof_node, s.dof_node.data(), sizeof(int32_t) * s.dof_node.size());
+}
+
+namespace {
+struct TItem {
+    float lo[3], hi[3];
+    double c[3];
+    int32_t inst;
+};
+
+uint32_t tlas_build(std::vector<TItem> &it, int b, int e, std::vector<BNode> &nodes, int depth, int &maxd,
+                    float lo[3], float hi[3]) {
+    for (int a = 0; a < 3; ++a) { lo[a] = INFINITY; hi[a] = -INFINITY; }
+    for (int k = b; k < e; ++k)
+        for (int a = 0; a < 3; ++a) { lo[a] = std::min(lo[a], it[k].lo[a]); hi[a] = std::max(hi[a], it[k].hi[a]); }
+    if (e - b == 1) return make_ref(REF_TLAS_LEAF, (uint32_t)it[b].inst);
+    double clo[3] = {INFINITY, INFINITY, INFINITY}, chi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int k = b; k < e; ++k)
+        for (int a = 0; a < 3; ++a) { clo[a] = std::min(clo[a], it[k].c[a]); chi[a] = std::max(chi[a], it[k].c[a]); }
+    int ax = 0;
+    for (int a = 1; a < 3; ++a)
+        if (chi[a] - clo[a] > chi[ax] - clo[ax]) ax = a;
+    int mid = b + (e - b) / 2;
+    std::nth_element(it.begin() + b, it.begin() + mid, it.begin() + e, [&](const TItem &x, const TItem &y) {
+        return x.c[ax] < y.c[ax] || (x.c[ax] == y.c[ax] && x.inst < y.inst);
+    });
+    uint32_t me = (uint32_t)nodes.size();
+    nodes.push_back(BNode{});
+    maxd = std::max(maxd, depth + 1);
+    float llo[3], lhi[3], rlo[3], rhi[3];
+    uint32_t l = tlas_build(it, b, mid, nodes, depth + 1, maxd, llo, lhi);
+    uint32_t r = tlas_build(it, mid, e, nodes, depth + 1, maxd, rlo, rhi);
+    BNode &n = nodes[me];
+    for (int a = 0; a < 3; ++a) { n.lo0[a] = llo[a]; n.hi0[a] = lhi[a]; n.lo1[a] = rlo[a]; n.hi1[a] = rhi[a]; }
+    n.ref0 = l;
+    n.ref1 = r;
+    return make_ref(REF_TLAS_NODE, me);
+}
+}  // namespace
+
+int slot_build(const SceneHost &S, const double *angles, SlotHost *out, std::string *err) {
+    const int K = S.n_nodes, J = S.n_dof;
+    out->inst.assign(K, Inst{});
+    out->xf.assign(12 * (size_t)K, 0.0);
+    out->axw.assign(3 * (size_t)J, 0.0);
+    out->dof_node.assign(J, 0);
+    out->tlas.clear();
+    out->n_clamped = 0;
+    for (int k = 0; k < K; ++k) {
+        const NodeInfo &nd = S.nodes[k];
+        double *X = &out->xf[12 * (size_t)k];
+        if (k == 0) {
+            double I[12] = {1, 0, 0, 0, 1, 0, 0, 0, 1, 0, 0, 0};
+            std::memcpy(X, I, sizeof I);
+        } else {
+            const double *Pm = &out->xf[12 * (size_t)nd.parent];
+            double prefix[9];
+            std::memcpy(prefix, Pm, sizeof prefix);   // R_parent * R(a_0) ... R(a_{j-1})
+            double Rl[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+            for (int a = 0; a < nd.n_axes; ++a) {
+                int j = nd.dof_offset + a;
+                double th = angles ? angles[j] : 0.0;
+                if (!std::isfinite(th)) { *err = "non-finite hinge angle"; return SRP_ERR_ARG; }
+                if (th < nd.lo[a]) { th = nd.lo[a]; out->n_clamped++; }
+                if (th > nd.hi[a]) { th = nd.hi[a]; out->n_clamped++; }
+                mat3_vec(prefix, nd.axis[a], &out->axw[3 * (size_t)j]);
+                out->dof_node[j] = k;
+                double Ra[9];
+                rot_axis_angle(nd.axis[a], th, Ra);
+                mat3_mul(Rl, Ra, Rl);
+                mat3_mul(prefix, Ra, prefix);
+            }
+            // local: x -> Rl (x - p) + p ; world: R_par * local + t_par
+            double Rp[3], tl[3], tw[3];
+            mat3_vec(Rl, nd.pivot, Rp);
+            for (int c = 0; c < 3; ++c) tl[c] = nd.pivot[c] - Rp[c];
+            mat3_vec(Pm, tl, tw);
+            mat3_mul(Pm, Rl, X);
+            for (int c = 0; c < 3; ++c) X[9 + c] = tw[c] + Pm[9 + c];
+        }
+        Inst &I = out->inst[k];
+        for (int c = 0; c < 9; ++c) I.R[c] = (float)X[c];
+        for (int c = 0; c < 3; ++c) I.t[c] = (float)X[9 + c];
+        I.root = nd.blas_root;
+        I.node = k;
+    }
+    // top-level hierarchy over the non-empty nodes' world boxes
+    std::vector<TItem> items;
+    for (int k = 0; k < K; ++k) {
+        const NodeInfo &nd = S.nodes[k];
+        if (nd.blas_root == REF_NONE) continue;
+        const double *X = &out->xf[12 * (size_t)k];
+        double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        for (int c = 0; c < 8; ++c) {
+            double p[3] = {(c & 1) ? nd.bhi[0] : nd.blo[0], (c & 2) ? nd.bhi[1] : nd.blo[1], (c & 4) ? nd.bhi[2] : nd.blo[2]};
+            double w[3];
+            mat3_vec(X, p, w);
+            for (int a = 0; a < 3; ++a) {
+                w[a] += X[9 + a];
+                lo[a] = std::min(lo[a], w[a]);
+                hi[a] = std::max(hi[a], w[a]);
+            }
+        }
+        TItem ti;
+        for (int a = 0; a < 3; ++a) {
+            ti.lo[a] = std::nextafter((float)(lo[a] - S.pad), -INFINITY);
+            ti.hi[a] = std::nextafter((float)(hi[a] + S.pad), INFINITY);
+            ti.c[a] = 0.5 * (lo[a] + hi[a]);
+        }
+        ti.inst = k;
+        items.push_back(ti);
+    }
+    out->tlas_depth = 0;
+    if (items.empty()) {
+        out->root_ref = REF_NONE;
+    } else {
+        float lo[3], hi[3];
+        out->root_ref = tlas_build(items, 0, (int)items.size(), out->tlas, 0, out->tlas_depth, lo, hi);
+    }
+    if (out->tlas_depth + 1 + S.max_blas_depth > STACK_DEPTH) {
+        *err = "hierarchy depth exceeds the traversal stack";
+        return SRP_ERR_DEPTH;
+    }
+    return SRP_OK;
+}
+
+}  // namespace srp

@@ -1,0 +1,151 @@
+// Internal data layout shared by the host runtime and the gfx950 kernels.
+//
+// Device memory of a scene (built once, Sec. 4.4.1: one rigid node = one
+// bottom-level hierarchy in rest-pose coordinates):
+//   TriRec  tris[T]   triangles in leaf order, 48 B each (3 corners + ids)
+//   BNode   blas[..]  binary hierarchy nodes of all tree nodes, 64 B each
+//   float2  mats[M]   (rho_s, rho_d)
+//   WPoint  wpts[..]  distinct (vertex, tree node) pairs, for the window pass
+// Device memory of an articulation slot (one per distinct hinge-angle vector,
+// Sec. 4.4.2 steps 1, 4, 5 as rigid instance transforms):
+//   Inst    inst[K]   local->world transform + bottom-level root, 64 B each
+//   BNode   tlas[..]  top-level hierarchy over the instances' world boxes
+//   double  xf[K][12] FP64 transforms (window pass)
+//   double  axw[J][3] world-frame hinge axes (gradient)
+//   int32   dof_node[J]
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace srp {
+
+// ---- references stored in hierarchy nodes and on the traversal stack ----
+// bits 31..30 type; BLAS leaf payload = (first_tri << 3) | (count - 1).
+constexpr uint32_t REF_BLAS_NODE = 0u;
+constexpr uint32_t REF_BLAS_LEAF = 1u;
+constexpr uint32_t REF_TLAS_NODE = 2u;
+constexpr uint32_t REF_TLAS_LEAF = 3u;
+constexpr uint32_t REF_EXIT = 0xFFFFFFFEu;  // stack marker: leave the current instance
+constexpr uint32_t REF_NONE = 0xFFFFFFFFu;
+constexpr int LEAF_MAX = 8;
+constexpr int STACK_DEPTH = 32;             // per-lane traversal stack entries (LDS)
+constexpr int BLAS_MAX_DEPTH = 24;          // internal nodes on any root-to-leaf path
+constexpr int TLAS_MAX_DEPTH = 7;           // <= 128 instances, median split
+constexpr int BLOCK = 256;                  // threads per block of the trace kernel
+constexpr int TILE = 16;                    // a chunk is TILE columns x (TILE * rpt) rows
+constexpr int MAX_GRAD_SLOTS = 960;         // doubles per wave for gradient partials (LDS <= 64 KB)
+
+#define SRP_HD __host__ __device__
+
+SRP_HD inline uint32_t make_ref(uint32_t type, uint32_t idx) { return (type << 30) | idx; }
+SRP_HD inline uint32_t ref_type(uint32_t r) { return r >> 30; }
+SRP_HD inline uint32_t ref_index(uint32_t r) { return r & 0x3FFFFFFFu; }
+
+struct alignas(64) BNode {
+    float lo0[3], hi0[3];
+    float lo1[3], hi1[3];
+    uint32_t ref0, ref1;
+    uint32_t pad0, pad1;
+};
+static_assert(sizeof(BNode) == 64, "BNode is one 64-byte line");
+
+struct alignas(16) TriRec {
+    float v0[3];
+    int32_t id;     // original triangle index
+    float v1[3];
+    int32_t mat;
+    float v2[3];
+    int32_t node;
+};
+static_assert(sizeof(TriRec) == 48, "TriRec is 48 bytes");
+
+struct alignas(64) Inst {
+    float R[9];       // local -> world rotation, row-major
+    float t[3];       // local -> world translation
+    uint32_t root;    // bottom-level root reference
+    int32_t node;
+    float pad[2];
+};
+static_assert(sizeof(Inst) == 64, "Inst is 64 bytes");
+
+struct alignas(32) WPoint {
+    double x, y, z;
+    int32_t node;
+    int32_t pad;
+};
+
+// Per-chunk partial sums (unscaled: multiply by P * A_pix).
+struct alignas(64) ChunkOut {
+    double f[6];        // force (3), torque (3)
+    uint32_t hits, sec, sec_hits, flags;
+};
+
+// One evaluation, as the kernels see it.
+struct alignas(64) EvalDesc {
+    // scene
+    const TriRec *tris;
+    const BNode *blas;
+    const float *mats;       // 2 floats per material
+    const WPoint *wpts;
+    int64_t n_wpts;
+    // articulation slot
+    const Inst *inst;
+    const BNode *tlas;
+    const double *xf;        // K x 12
+    const double *axw;       // J x 3
+    const int32_t *dof_node; // J
+    const int32_t *parent;   // K (device copy of the tree)
+    uint32_t root_ref;
+    int32_t n_nodes, n_mats, n_dof;
+    // parameters (basis in FP64 from the host)
+    double u[3], v[3], d[3];
+    double pressure;
+    double ref[3];
+    int32_t n, bounces;
+    uint32_t flags;
+    int32_t tiles_x;
+    int32_t rpt;            // rows of tiles per chunk (rays per thread)
+    int32_t grad_n;         // doubles per chunk gradient partial (0 = no gradient)
+    int64_t chunk_base;     // first chunk of this evaluation
+    int64_t n_chunks;
+    // optional outputs
+    int32_t *hit_ids;       // N*N*(B+1) or null
+    float *hit_t;
+    double *grad_part;      // n_chunks x grad_n (gradient partials)
+    double *grad_out;       // 3*(2M+J) final gradient or null
+};
+
+// Order-preserving map of doubles to unsigned 64-bit integers (for
+// atomic min/max of the window bounds).
+SRP_HD inline uint64_t enc_f64(double x) {
+    union { double d; uint64_t u; } c;
+    c.d = x;
+    return (c.u >> 63) ? ~c.u : (c.u | 0x8000000000000000ull);
+}
+SRP_HD inline double dec_f64(uint64_t e) {
+    union { double d; uint64_t u; } c;
+    c.u = (e >> 63) ? (e & 0x7FFFFFFFFFFFFFFFull) : ~e;
+    return c.d;
+}
+
+// window slots per evaluation: enc(umin), enc(-umax), enc(vmin), enc(-vmax), enc(hmin)
+constexpr int WIN_STRIDE = 8;
+
+struct LaunchCfg {
+    int rpt;              // rays per thread (tile rows per chunk)
+    int blocks_per_cu;    // persistent grid factor
+};
+
+// Kernel launchers (kernels.hip)
+int launch_window(const EvalDesc *d_desc, int n_evals, int blocks_x, uint64_t *d_win, void *stream);
+int launch_trace(const EvalDesc *d_desc, const int64_t *d_chunk_base, int n_evals,
+                 const uint64_t *d_win, uint32_t *d_counter, int64_t total_chunks,
+                 ChunkOut *d_chunks, uint64_t *d_counts, bool count, bool grad, int grid_blocks,
+                 int lds_grad_doubles, void *stream);
+int launch_reduce(const EvalDesc *d_desc, const int64_t *d_chunk_base, int n_evals,
+                  const uint64_t *d_win, const ChunkOut *d_chunks, const uint64_t *d_counts,
+                  bool count, bool grad, void *d_out, void *stream);
+// Resident blocks per compute unit of the trace kernel variant.
+int trace_blocks_per_cu(bool count, bool grad, int lds_grad_doubles);
+
+}  // namespace srp

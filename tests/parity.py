@@ -1,0 +1,109 @@
+"""Helpers shared by the GPU parity tests: compare the library with the FP64
+oracle on the same seeded inputs.
+
+Primary first-hit ids must agree exactly except for rays in the edge band:
+a ray whose image-plane distance to an edge of either candidate triangle is at
+most 1e-6 L, or whose distances to the two candidates' planes differ by at
+most 1e-6 L (L = the larger window side).  FP32 and FP64 may legitimately pick
+different triangles there.  Forces must agree to 1e-5 relative; the
+visibility-matched force (the oracle's FP64 physics re-shaded on the GPU's
+hit ids) must agree to 1e-5 even when a silhouette ray flips.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle
+
+EDGE_BAND = 1e-6
+F_TOL = 1e-5
+
+
+def pixel_uv(grid, n, pix):
+    i = pix % n
+    j = pix // n
+    a = grid["umin"] + (i + 0.5) * grid["wu"] / n
+    b = grid["vmin"] + (j + 0.5) * grid["wv"] / n
+    return a, b
+
+
+def _seg_dist(p, a, b):
+    ab = b - a
+    t = np.clip(((p - a) * ab).sum(-1) / np.maximum((ab * ab).sum(-1), 1e-300), 0, 1)
+    q = a + t[..., None] * ab
+    return np.linalg.norm(p - q, axis=-1)
+
+
+def _edge_dist(world, grid, tri, uv):
+    """Image-plane distance from points uv (k,2) to the edges of triangles tri (k,)."""
+    W = world[tri]                                  # (k,3,3)
+    P = np.stack([W @ grid["u"], W @ grid["v"]], -1)  # (k,3,2)
+    d = np.stack([_seg_dist(uv, P[:, 0], P[:, 1]), _seg_dist(uv, P[:, 1], P[:, 2]),
+                  _seg_dist(uv, P[:, 2], P[:, 0])], -1)
+    return d.min(-1)
+
+
+def _plane_t(world, grid, tri, n, pix):
+    a, b = pixel_uv(grid, n, pix)
+    o = a[:, None] * grid["u"] + b[:, None] * grid["v"] + grid["h0"] * grid["d"]
+    W = world[tri]
+    nrm = np.cross(W[:, 1] - W[:, 0], W[:, 2] - W[:, 0])
+    den = nrm @ grid["d"]
+    with np.errstate(divide="ignore", invalid="ignore"):
+        return ((W[:, 0] - o) * nrm).sum(-1) / den
+
+
+def classify_primary(mesh, angles, grid, n, ids_orc, ids_gpu):
+    """Returns (n_mismatch, n_mismatch_outside_band, band_fraction_of_rays)."""
+    ids_orc = np.asarray(ids_orc).reshape(-1)
+    ids_gpu = np.asarray(ids_gpu).reshape(-1)
+    mism = np.nonzero(ids_orc != ids_gpu)[0]
+    if mism.size == 0:
+        return 0, 0, 0.0
+    world = oracle.articulate(mesh, angles)
+    L = grid["L"]
+    a, b = pixel_uv(grid, n, mism)
+    uv = np.stack([a, b], -1)
+    band = np.zeros(mism.size, bool)
+    for ids in (ids_orc, ids_gpu):
+        t = ids[mism]
+        ok = t >= 0
+        if ok.any():
+            band[ok] |= _edge_dist(world, grid, t[ok], uv[ok]) <= EDGE_BAND * L
+    both = (ids_orc[mism] >= 0) & (ids_gpu[mism] >= 0)
+    if both.any():
+        pa = _plane_t(world, grid, ids_orc[mism][both], n, mism[both])
+        pb = _plane_t(world, grid, ids_gpu[mism][both], n, mism[both])
+        band[both] |= np.abs(pa - pb) <= EDGE_BAND * L
+    return int(mism.size), int((~band).sum()), float(band.sum()) / ids_orc.size
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300))
+
+
+def torque_err(t_gpu, t_orc, f_orc, L):
+    """Torque error scaled as |dtau| / (|tau| + L |F|) (tau may vanish by symmetry)."""
+    return float(np.linalg.norm(np.asarray(t_gpu) - t_orc) /
+                 max(np.linalg.norm(t_orc) + L * np.linalg.norm(f_orc), 1e-300))
+
+
+def compare_eval(mesh, angles, sun, n, bounces, gpu, orc, pressure=1.0):
+    """Full-grid comparison.  gpu: dict from paper_2608_07307_amd.eval(record=True);
+    orc: oracle.OracleResult with record=True.  Returns a report dict."""
+    grid = orc.grid
+    rep = {}
+    rep["f_err"] = rel(gpu["force"], orc.force)
+    rep["t_err"] = torque_err(gpu["torque"], orc.torque, orc.force, grid["L"])
+    m, out_band, frac = classify_primary(mesh, angles, grid, n, orc.ids[:, 0], gpu["ids"][:, 0])
+    rep.update(primary_mismatch=m, primary_outside_band=out_band, edge_band_fraction=frac)
+    if bounces:
+        sec_o, sec_g = orc.ids[:, 1:], gpu["ids"][:, 1:]
+        valid = (sec_o >= 0) | (sec_g >= 0)
+        rep["secondary_match_fraction"] = float((sec_o == sec_g)[valid].mean()) if valid.any() else 1.0
+    vm = oracle.shade_frozen(mesh, sun, n, bounces, grid, gpu["ids"], pressure=pressure,
+                             angles=angles)
+    rep["f_err_vis_matched"] = rel(gpu["force"], vm.force)
+    rep["t_err_vis_matched"] = torque_err(gpu["torque"], vm.torque, vm.force, grid["L"])
+    rep["hits_gpu"], rep["hits_orc"] = int(gpu["n_hits"]), int(orc.n_hits)
+    return rep
