@@ -1,0 +1,204 @@
+#!/usr/bin/env python
+"""Benchmark of the ray-traced SRP hot path on one MI355X.
+
+Workload: the seeded procedural ~50k-triangle spacecraft (49,644 triangles,
+9 tree nodes, 8 hinge DOF, 6 materials), 1024 x 1024 rays per evaluation,
+2 specular bounces.  One step = one pass of the whole hot path over one
+batch: per-item hinge angles (articulation slots), window pass, persistent
+trace with the fixed-visibility adjoint, fixed-order reduction; i.e.
+srp_eval_grad_batch over `--batch` attitudes (Fibonacci sun directions, root
+hinges drawn in [-90, 90] deg).  Inputs are resident on the device before
+the timed region; results and gradients stay on the device.
+
+Also measured (reported beside the headline value): the same batch forward
+only (srp_eval_batch), and the plain path (srp_set_panel_angles + srp_eval
+per item, a host round trip per evaluation, as a propagator stage does).
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_LANE_OPS = 256 * 64 * 2.4e9     # CUs x lanes x clock: one VALU lane-op per lane per cycle
+BOX_OPS, TRI_OPS = 10, 30             # algorithmic lane-ops per ray-box / ray-triangle test
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--batch", type=int, default=64)
+    ap.add_argument("--n", type=int, default=1024)
+    ap.add_argument("--bounces", type=int, default=2)
+    ap.add_argument("--plain", type=int, default=16, help="evaluations timed on the plain path")
+    ap.add_argument("--cpu-samples", type=int, default=2, help="batch items the oracle times (0: skip)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU: this SRP path has no multi-GPU mode "
+              "(batches shard with no collective; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2608_07307_amd as srp
+    import synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)  # noqa: E731
+
+    mesh = synth.procedural_spacecraft(seed=2)
+    scene = srp.Scene(mesh)
+    B, N, E = args.bounces, args.n, args.batch
+    dirs = synth.fibonacci_dirs(E)
+    rng = np.random.default_rng(1002)
+    angles = np.zeros((E, mesh.n_dof))
+    roots = [0, mesh.n_dof // 2]                      # the two wing root hinges
+    angles[:, roots] = rng.uniform(-np.pi / 2, np.pi / 2, size=(E, 2))
+    entries = [(scene, angles[k], srp.params(dirs[k], N, B)) for k in range(E)]
+    stride = 3 * (2 * mesh.n_mats + mesh.n_dof)
+    out = torch.empty(E * srp.RESULT_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+    grad = torch.zeros((E, stride), dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+    log(f"workload: T={mesh.n_tris} N={N} B={B} batch={E}")
+
+    # algorithmic work of one launch: box and triangle tests (counting variant, same inputs)
+    cnt_entries = [(scene, angles[k], srp.params(dirs[k], N, B, count=True)) for k in range(E)]
+    cres = srp.results_to_numpy(srp.eval_batch(cnt_entries))
+    n_box, n_tri = int(cres["n_box_tests"].sum()), int(cres["n_tri_tests"].sum())
+    rays_primary = int(cres["n_rays"].sum())
+    rays_total = rays_primary + int(cres["n_secondary"].sum())
+    work = BOX_OPS * n_box + TRI_OPS * n_tri
+    log(f"counts per batch: box {n_box:.3e} tri {n_tri:.3e} rays {rays_total:.3e} "
+        f"(tests/ray {(n_box + n_tri) / rays_total:.1f})")
+
+    # headline: batched forward + adjoint
+    for _ in range(args.warmup):
+        srp.eval_grad_batch(entries, out, grad, stream)
+    torch.cuda.synchronize()
+    srp.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        srp.eval_grad_batch(entries, out, grad, stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    trace_ms, launches = srp.profile_read()
+    srp.profile(False)
+    dt = (t1 - t0) / args.steps
+    res = srp.results_to_numpy(out)
+    assert (res["status"] == 0).all()
+    value = E / dt
+    kern_s = trace_ms / 1e3 / max(launches, 1)
+    log(f"batched+adjoint: {dt * 1e3:.3f} ms/step, {value:.1f} evals/s, trace kernel {kern_s * 1e3:.3f} ms")
+
+    # batched forward only
+    for _ in range(args.warmup):
+        srp.eval_batch(entries, out, stream)
+    torch.cuda.synchronize()
+    srp.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        srp.eval_batch(entries, out, stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    fwd_ms, fwd_launches = srp.profile_read()
+    srp.profile(False)
+    fwd_dt = (t1 - t0) / args.steps
+    fwd = srp.results_to_numpy(out)
+    log(f"batched forward: {fwd_dt * 1e3:.3f} ms/step, {E / fwd_dt:.1f} evals/s")
+
+    # plain: set angles + blocking eval per item
+    P = min(args.plain, E)
+    for k in range(min(2, P)):
+        scene.set_angles(angles[k])
+        srp.eval(scene, dirs[k], N, bounces=B)
+    t0 = time.perf_counter()
+    plain_f = []
+    for k in range(P):
+        scene.set_angles(angles[k])
+        plain_f.append(srp.eval(scene, dirs[k], N, bounces=B)["force"])
+    t1 = time.perf_counter()
+    plain_eps = P / (t1 - t0)
+    log(f"plain: {plain_eps:.1f} evals/s")
+    for k in range(P):
+        assert np.array_equal(plain_f[k], fwd[k]["force"]), "plain and batched results differ"
+
+    # oracle on a bounded sample (CPU baseline and parity of the sampled items)
+    cpu = None
+    parity = None
+    if args.cpu_samples > 0:
+        import oracle
+        errs = []
+        t0 = time.perf_counter()
+        for k in range(args.cpu_samples):
+            o = oracle.eval_srp(mesh, dirs[k], N, bounces=B, angles=angles[k], record=True)
+            oracle.fd_gradients(mesh, dirs[k], N, B, o.grid, o.ids, angles=angles[k])
+            errs.append(float(np.linalg.norm(res[k]["force"] - o.force) / np.linalg.norm(o.force)))
+        t1 = time.perf_counter()
+        cpu = {"value": round(args.cpu_samples / (t1 - t0), 4), "unit": "evals/s",
+               "cores": oracle.threads(), "kind": "oracle",
+               "sample": f"{args.cpu_samples} of the {E} batch items: FP64 forward (oracle BVH) + "
+                         f"central-difference gradient ({2 * (2 * mesh.n_mats + mesh.n_dof)} "
+                         f"fixed-visibility re-shades), {N}x{N} rays, B={B}"}
+        parity = {"max_rel_force_err": max(errs), "items_checked": args.cpu_samples}
+        log(f"oracle: {cpu['value']} evals/s on {cpu['cores']} threads; parity {max(errs):.2e}")
+
+    achieved = work / kern_s / 1e12
+    peak = PEAK_LANE_OPS / 1e12
+    line = {
+        "metric": "SRP evals/sec and Grays/s at 1024^2 rays, batched+adjoint vs plain, at 1e-5 rel force err",
+        "value": round(value, 3),
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(dt * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"procedural ~50k-triangle spacecraft ({mesh.n_tris} tris, 9 nodes, 8 DOF, "
+                        f"6 materials), {N}x{N} rays, {B} bounces, batch of {E} attitudes, "
+                        f"forward + fixed-visibility adjoint per step",
+            "batch": E, "n": N, "bounces": B, "triangles": mesh.n_tris,
+        },
+        "grays_per_s": round(rays_total * args.steps / (dt * args.steps) / 1e9, 4),
+        "grays_per_s_primary": round(rays_primary / dt / 1e9, 4),
+        "batched_forward_evals_per_s": round(E / fwd_dt, 3),
+        "batched_forward_grays_per_s": round(rays_total / fwd_dt / 1e9, 4),
+        "plain_evals_per_s": round(plain_eps, 3),
+        "parity": parity,
+        "roofline": {
+            "bound": "alu",
+            "achieved": round(achieved, 4),
+            "peak": round(peak, 4),
+            "unit": "Tlane-op/s",
+            "frac": round(achieved / peak, 4),
+            "traffic": None,
+            "kernel": "k_trace<GRAD> (forward + adjoint)",
+            "work_per_launch": {"box_tests": n_box, "tri_tests": n_tri,
+                                "lane_ops": work, "ops_per_box": BOX_OPS, "ops_per_tri": TRI_OPS},
+            "kernel_ms": round(kern_s * 1e3, 4),
+            "forward_kernel_ms": round(fwd_ms / max(fwd_launches, 1), 4),
+        },
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

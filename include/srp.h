@@ -185,6 +185,14 @@ int srp_eval_grad(srp_scene *scene, const srp_eval_params *params, srp_result *o
 int srp_eval_grad_batch(const srp_batch_item *items, int64_t n_items, srp_result *out_dev,
                         double *grad_dev, int64_t grad_stride, void *hip_stream);
 
+/* Measurement hook (not part of an evaluation): srp_profile(1) starts timing
+ * every trace-kernel launch with a pair of HIP events recorded on the launch
+ * stream, srp_profile(0) stops; both reset the totals.  srp_profile_read waits
+ * for the recorded launches and returns the summed kernel time (ms) and the
+ * launch count since the last reset. */
+int srp_profile(int enable);
+int srp_profile_read(double *trace_ms, int64_t *launches);
+
 /* Thread-local message of the last error ("" if none). */
 const char *srp_last_error(void);
 

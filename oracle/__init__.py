@@ -17,4 +17,5 @@ from .core import (  # noqa: F401
     shade_frozen,
     fd_gradients,
     OracleResult,
+    threads,
 )

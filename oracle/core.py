@@ -62,6 +62,7 @@ def _load():
         _lib.orc_grid_of.argtypes = [P, P, P, P]
         _lib.orc_articulate.argtypes = [P, P, P]
         _lib.orc_node_transforms.argtypes = [P, P, P]
+        _lib.orc_threads.restype = C.c_int32
         for f in ("orc_eval", "orc_shade_frozen", "orc_grid_of", "orc_articulate",
                   "orc_node_transforms"):
             getattr(_lib, f).restype = C.c_int
@@ -149,6 +150,11 @@ def eval_srp(scene, sun_dir, n, bounces=0, pressure=1.0, ref=(0, 0, 0), angles=N
         raise ValueError(f"oracle eval failed ({rc})")
     return OracleResult(np.array(out.force[:]), np.array(out.torque[:]), out.n_rays, out.n_hits,
                         out.n_secondary, out.n_secondary_hits, _grid_dict(out.grid), ids, ts)
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's pixel loops use."""
+    return int(_load().orc_threads())
 
 
 def grid_of(scene, sun_dir, n, angles=None) -> dict:

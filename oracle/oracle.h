@@ -48,6 +48,7 @@ typedef struct {
     orc_grid grid;
 } orc_result;
 
+int32_t orc_threads(void);
 int orc_validate(const orc_scene *S);
 int32_t orc_n_dof(const orc_scene *S);
 int orc_node_transforms(const orc_scene *S, const double *angles, double *xf /* nn x 12 */);

@@ -184,3 +184,15 @@ def results_to_numpy(t) -> np.ndarray:
     """Structured array (RESULT_DTYPE) from a results tensor."""
     b = t.detach().cpu().numpy().tobytes()
     return np.frombuffer(b, dtype=RESULT_DTYPE)
+
+
+def profile(enable: bool):
+    """Start (True) or stop (False) timing trace-kernel launches; resets totals."""
+    L.check(_load().srp_profile(1 if enable else 0))
+
+
+def profile_read():
+    """(summed trace-kernel milliseconds, launch count) since the last reset."""
+    ms, n = C.c_double(), C.c_int64()
+    L.check(_load().srp_profile_read(C.byref(ms), C.byref(n)))
+    return ms.value, n.value

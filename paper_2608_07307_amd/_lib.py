@@ -16,7 +16,7 @@ SRP_MAX_N, SRP_MAX_BOUNCES, SRP_MAX_NODES, SRP_MAX_MATS = 8192, 4, 128, 64
 EXPORTS = [
     "srp_build_scene", "srp_destroy_scene", "srp_scene_n_dof", "srp_set_materials",
     "srp_set_panel_angles", "srp_eval", "srp_eval_batch", "srp_eval_grad",
-    "srp_eval_grad_batch", "srp_last_error",
+    "srp_eval_grad_batch", "srp_last_error", "srp_profile", "srp_profile_read",
 ]
 
 
@@ -80,9 +80,11 @@ def load(path: str | None = None):
     lib.srp_eval_grad.argtypes = [V, C.POINTER(srp_eval_params), C.POINTER(srp_result), V, V, V]
     lib.srp_eval_grad_batch.argtypes = [V, I64, V, V, I64, V]
     lib.srp_last_error.restype = C.c_char_p
+    lib.srp_profile.argtypes = [C.c_int]
+    lib.srp_profile_read.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     for f in ("srp_build_scene", "srp_destroy_scene", "srp_set_materials",
               "srp_set_panel_angles", "srp_eval", "srp_eval_batch", "srp_eval_grad",
-              "srp_eval_grad_batch"):
+              "srp_eval_grad_batch", "srp_profile", "srp_profile_read"):
         getattr(lib, f).restype = C.c_int
     _lib = lib
     return lib

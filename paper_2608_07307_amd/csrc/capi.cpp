@@ -65,6 +65,40 @@ struct Workspace {
 };
 Workspace g_ws;
 
+// Optional timing of the trace-kernel launches (HIP events on the launch stream).
+struct Profile {
+    bool on = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pairs;   // recorded, not yet read
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
+    double ms = 0;
+    int64_t launches = 0;
+};
+Profile g_prof;
+
+int prof_event_pair(std::pair<hipEvent_t, hipEvent_t> *p) {
+    if (!g_prof.pool.empty()) {
+        *p = g_prof.pool.back();
+        g_prof.pool.pop_back();
+        return SRP_OK;
+    }
+    HIPCHK(hipEventCreate(&p->first));
+    HIPCHK(hipEventCreate(&p->second));
+    return SRP_OK;
+}
+
+int prof_collect() {
+    for (auto &pr : g_prof.pairs) {
+        HIPCHK(hipEventSynchronize(pr.second));
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, pr.first, pr.second));
+        g_prof.ms += ms;
+        g_prof.launches++;
+        g_prof.pool.push_back(pr);
+    }
+    g_prof.pairs.clear();
+    return SRP_OK;
+}
+
 int ws_init() {
     if (g_ws.init) return SRP_OK;
     HIPCHK(hipGetDevice(&g_ws.device));
@@ -318,9 +352,18 @@ int run_batch(const srp_batch_item *items, int64_t n, bool grad, const BatchOut 
     if (e) return fail(SRP_ERR_DEVICE, std::string("window kernel: ") + hipGetErrorString((hipError_t)e));
     int bpc = trace_blocks_per_cu(count, grad, max_grad_n);
     int64_t grid = std::min<int64_t>(total_chunks, (int64_t)g_ws.n_cu * bpc);
+    std::pair<hipEvent_t, hipEvent_t> ev{};
+    if (g_prof.on) {
+        if ((rc = prof_event_pair(&ev))) return rc;
+        HIPCHK(hipEventRecord(ev.first, stream));
+    }
     e = launch_trace(d_desc, d_base, (int)n, d_win, d_counter, total_chunks, d_chunks, d_counts, count, grad,
                      (int)std::max<int64_t>(grid, 1), max_grad_n, stream);
     if (e) return fail(SRP_ERR_DEVICE, std::string("trace kernel: ") + hipGetErrorString((hipError_t)e));
+    if (g_prof.on) {
+        HIPCHK(hipEventRecord(ev.second, stream));
+        g_prof.pairs.push_back(ev);
+    }
     e = launch_reduce(d_desc, d_base, (int)n, d_win, d_chunks, d_counts, count, grad, bo.d_out, stream);
     if (e) return fail(SRP_ERR_DEVICE, std::string("reduce kernel: ") + hipGetErrorString((hipError_t)e));
     HIPCHK(hipEventRecord(g_ws.done, stream));
@@ -562,6 +605,28 @@ int srp_eval_grad(srp_scene *scene, const srp_eval_params *params, srp_result *o
     if (dF_drho_d) std::memcpy(dF_drho_d, g.data() + 3 * M, sizeof(double) * 3 * M);
     if (dF_dtheta) std::memcpy(dF_dtheta, g.data() + 6 * M, sizeof(double) * 3 * J);
     if (out->status & SRP_STATUS_STACK) return fail(SRP_ERR_DEPTH, "traversal stack overflow");
+    return SRP_OK;
+}
+
+int srp_profile(int enable) {
+    g_err.clear();
+    std::lock_guard<std::mutex> lk(g_ws.mu);
+    int rc = prof_collect();
+    if (rc) return rc;
+    g_prof.on = enable != 0;
+    g_prof.ms = 0;
+    g_prof.launches = 0;
+    return SRP_OK;
+}
+
+int srp_profile_read(double *trace_ms, int64_t *launches) {
+    g_err.clear();
+    if (!trace_ms || !launches) return fail(SRP_ERR_ARG, "null output");
+    std::lock_guard<std::mutex> lk(g_ws.mu);
+    int rc = prof_collect();
+    if (rc) return rc;
+    *trace_ms = g_prof.ms;
+    *launches = g_prof.launches;
     return SRP_OK;
 }
 

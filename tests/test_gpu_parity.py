@@ -95,3 +95,137 @@ def test_procedural_reduced(srp):
         _show(f"procedural 256 B=2 seed={seed}", rep)
         _check(rep)
         assert rep["secondary_match_fraction"] > 0.999
+
+
+def test_articulated_equals_prerotated(srp):
+    """Instance-transformed panels give the evaluation of the same mesh
+    supplied with pre-rotated vertices (the paper's CPU geometry update,
+    Sec. 4.4.2 step 5): ids equal outside the edge band, forces to 1e-5."""
+    mesh = synth.procedural_sized(21, 6000)
+    ang = np.linspace(-1.2, 1.0, mesh.n_dof)
+    sc = srp.Scene(mesh)
+    sc.set_angles(ang)
+    static = synth.merge_static(mesh, oracle.articulate(mesh, ang))
+    st = srp.Scene(static)
+    for seed in (2101, 2102, 2103):
+        sun = synth.random_dirs(seed)[0]
+        a = srp.eval(sc, sun, 192, bounces=2, record=True)
+        b = srp.eval(st, sun, 192, bounces=2, record=True)
+        o = oracle.eval_srp(mesh, sun, 192, bounces=2, angles=ang, record=True)
+        rep = compare_eval(mesh, ang, sun, 192, 2, a, o)
+        rep_b = compare_eval(static, None, sun, 192, 2, b, o)
+        _show(f"articulated seed={seed}", rep)
+        _show(f"pre-rotated seed={seed}", rep_b)
+        _check(rep)
+        _check(rep_b)
+        assert rel(a["force"], b["force"]) <= F_TOL
+
+
+def test_batch_matches_single_and_is_deterministic(srp):
+    """A batch with mixed scenes, grid sizes, bounce counts and angles gives
+    bitwise the per-item srp_eval results, and repeated runs are bitwise
+    identical (fixed-order reduction, no floating-point atomics)."""
+    import torch
+    m1, m2 = synth.box_wing(), synth.procedural_sized(22, 4000)
+    s1, s2 = srp.Scene(m1), srp.Scene(m2)
+    entries, singles = [], []
+    for k in range(12):
+        sc, m = (s1, m1) if k % 3 == 0 else (s2, m2)
+        ang = np.full(m.n_dof, 0.1 * (k % 4) - 0.15)
+        n = [64, 100, 128, 37][k % 4]
+        B = k % 3
+        sun = synth.random_dirs(2200 + k)[0]
+        entries.append((sc, ang, srp.params(sun, n, B)))
+        sc.set_angles(ang)
+        singles.append(srp.eval(sc, sun, n, bounces=B))
+    out = srp.results_to_numpy(srp.eval_batch(entries))
+    out2 = srp.results_to_numpy(srp.eval_batch(entries))
+    torch.cuda.synchronize()
+    for k, s in enumerate(singles):
+        assert np.array_equal(out[k]["force"], s["force"]), k
+        assert np.array_equal(out[k]["torque"], s["torque"]), k
+        assert out[k]["n_hits"] == s["n_hits"] and out[k]["n_secondary_hits"] == s["n_secondary_hits"]
+    assert out.tobytes() == out2.tobytes()
+
+
+@pytest.mark.parametrize("n", [1, 2, 17, 100, 257])
+def test_ragged_and_tiny_grids(srp, n):
+    """Grid sizes that are not multiples of the 16-pixel tile, down to one ray."""
+    mesh = synth.box_wing()
+    sc = srp.Scene(mesh)
+    sun = synth.random_dirs(2300 + n)[0]
+    g = srp.eval(sc, sun, n, bounces=1, record=True)
+    o = oracle.eval_srp(mesh, sun, n, bounces=1, record=True)
+    rep = compare_eval(mesh, None, sun, n, 1, g, o)
+    _show(f"ragged n={n}", rep)
+    assert rep["primary_outside_band"] == 0 and rep["f_err_vis_matched"] <= F_TOL
+    assert g["n_rays"] == n * n
+
+
+def test_degenerate_cases(srp):
+    """Edge-on plate (zero-area window): zero force, no hit.  A zero-area
+    triangle is never hit.  Invalid parameters are errors."""
+    plate = synth.plate((0, 0, 0), (1, 0, 0), (0, 1, 0))
+    sc = srp.Scene(plate)
+    g = srp.eval(sc, (1, 0, 0), 32, bounces=1)
+    assert g["n_hits"] == 0 and not np.any(g["force"]) and not np.any(g["torque"])
+    base = synth.plate((-1, -1, 0), (2, 0, 0), (0, 2, 0), rho=(0.3, 0.3))
+    degen = np.array([[[-0.5, 0.0, 0.5], [0.5, 0.0, 0.5], [0.5, 0.0, 0.5]]])
+    with_d = synth.merge_static(base, np.concatenate([base.verts[base.tris], degen]),
+                                tri_mat=np.zeros(3, np.int32))
+    a = srp.eval(srp.Scene(base), (0, 0, 1), 50, bounces=1)
+    b = srp.eval(srp.Scene(with_d), (0, 0, 1), 50, bounces=1)
+    assert np.array_equal(a["force"], b["force"]) and a["n_hits"] == b["n_hits"] == 2500
+    for bad in (dict(n=0), dict(n=9000), dict(bounces=5), dict(sun_dir=(0, 0, 0)),
+                dict(sun_dir=(np.nan, 0, 1))):
+        kw = dict(sun_dir=(0, 0, 1), n=8, bounces=0)
+        kw.update(bad)
+        with pytest.raises(srp.SrpError):
+            srp.eval(sc, kw["sun_dir"], kw["n"], bounces=kw["bounces"])
+    with pytest.raises(srp.SrpError):
+        srp.Scene(synth.box_wing()).set_angles([0.1])
+
+
+@pytest.mark.parametrize("maker,n,B", [
+    (lambda: synth.box_wing(), 96, 1),
+    (lambda: synth.procedural_sized(23, 3000), 128, 2),
+])
+def test_adjoint_matches_finite_differences(srp, maker, n, B):
+    """Hand-written adjoint (fixed visibility) against FP64 central finite
+    differences (h = 1e-4) of the oracle's re-shade on the GPU-recorded hits."""
+    mesh = maker()
+    ang = np.linspace(-0.5, 0.7, mesh.n_dof)
+    sc = srp.Scene(mesh)
+    sc.set_angles(ang)
+    for seed in (2401, 2402):
+        sun = synth.random_dirs(seed)[0]
+        g = srp.eval_grad(sc, sun, n, bounces=B, pressure=2.0)
+        rec = srp.eval(sc, sun, n, bounces=B, pressure=2.0, record=True)
+        grid = oracle.grid_of(mesh, sun, n, angles=ang)
+        fd = oracle.fd_gradients(mesh, sun, n, B, grid, rec["ids"], pressure=2.0, angles=ang)
+        scale = max(np.abs(fd["rho_s"]).max(), np.abs(fd["rho_d"]).max(), np.abs(fd["theta"]).max())
+        for key in ("rho_s", "rho_d", "theta"):
+            err = np.abs(g[key] - fd[key]).max() / scale
+            print(f"adjoint {mesh.name} seed={seed} {key}: max err / max |grad| = {err:.2e}", flush=True)
+            assert err <= 1e-4, (key, g[key], fd[key])
+        assert np.array_equal(g["force"], rec["force"])
+
+
+def test_uneven_batch_small(srp):
+    """Uneven batch (scenes of 1k..20k triangles, grids 64..320, random
+    angles, 1 bounce) in one launch; every item against the oracle."""
+    specs = synth.uneven_batch_specs(seed=4, n=8)
+    entries, meshes = [], []
+    for k, s in enumerate(specs):
+        m = synth.procedural_sized(s["seed"], min(s["target_tris"], 20000))
+        ang = np.zeros(m.n_dof)
+        ang[0], ang[m.n_dof // 2] = s["root_angles"]
+        n = max(64, s["n"] // 6)
+        entries.append((srp.Scene(m), ang, srp.params(s["sun_dir"], n, 1)))
+        meshes.append((m, ang, s["sun_dir"], n))
+    out = srp.results_to_numpy(srp.eval_batch(entries))
+    for k, (m, ang, sun, n) in enumerate(meshes):
+        o = oracle.eval_srp(m, sun, n, bounces=1, angles=ang)
+        e = rel(out[k]["force"], o.force)
+        print(f"uneven item {k}: T={m.n_tris} n={n} rel F err {e:.2e}", flush=True)
+        assert e <= 1e-4   # strict parity incl. any silhouette flip at these small grids
