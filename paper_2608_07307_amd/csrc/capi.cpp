@@ -338,7 +338,8 @@ int run_batch(const srp_batch_item *items, int64_t n, bool grad, const BatchOut 
         D.hit_t = (n == 1) ? bo.d_hit_t : nullptr;
     }
 
-    HIPCHK(hipStreamWaitEvent(stream, g_ws.done, 0));
+    // the previous batch has completed (ws_wait above), so the staging
+    // buffer and the workspace are free on every stream
     HIPCHK(hipMemcpyAsync(Dv, H, stage_bytes, hipMemcpyHostToDevice, stream));
     const EvalDesc *d_desc = reinterpret_cast<const EvalDesc *>(Dv + o_desc);
     const int64_t *d_base = reinterpret_cast<const int64_t *>(Dv + o_base);

@@ -23,189 +23,14 @@
 
 #include "srp.h"
 #include "srp_internal.h"
+#include "trace.h"
 
 namespace srp {
 
 namespace {
 
-constexpr float T_INF = 3.0e38f;
 constexpr int WAVE = 64;
 constexpr int MAX_CHAIN = SRP_MAX_BOUNCES + 1;
-
-__device__ __forceinline__ float safe_inv(float x) {
-    // reciprocal of a direction component, finite for zero components
-    float ax = fabsf(x) < 1e-30f ? copysignf(1e-30f, x) : x;
-    return 1.0f / ax;
-}
-
-// An orthonormal basis (bx, by) orthogonal to unit d (Duff et al., JCGT 2017).
-__device__ __forceinline__ void onb(const float d[3], float bx[3], float by[3]) {
-    float s = copysignf(1.0f, d[2]);
-    float a = -1.0f / (s + d[2]);
-    float b = d[0] * d[1] * a;
-    bx[0] = 1.0f + s * d[0] * d[0] * a;
-    bx[1] = s * b;
-    bx[2] = -s * d[0];
-    by[0] = b;
-    by[1] = s + d[1] * d[1] * a;
-    by[2] = -d[1];
-}
-
-// Ray state in one frame: slab-test constants and the watertight-test frame
-// (x, y axes orthogonal to the direction, z = direction, offsets = axes . o).
-struct Frame {
-    float ix, iy, iz;      // 1 / d
-    float oix, oiy, oiz;   // o / d
-    float mx[3], my[3], mz[3];
-    float cx, cy, cz;
-};
-
-__device__ __forceinline__ void frame_setup(const float o[3], const float d[3], Frame &F) {
-    F.ix = safe_inv(d[0]);
-    F.iy = safe_inv(d[1]);
-    F.iz = safe_inv(d[2]);
-    F.oix = o[0] * F.ix;
-    F.oiy = o[1] * F.iy;
-    F.oiz = o[2] * F.iz;
-    onb(d, F.mx, F.my);
-    F.mz[0] = d[0]; F.mz[1] = d[1]; F.mz[2] = d[2];
-    F.cx = F.mx[0] * o[0] + F.mx[1] * o[1] + F.mx[2] * o[2];
-    F.cy = F.my[0] * o[0] + F.my[1] * o[1] + F.my[2] * o[2];
-    F.cz = F.mz[0] * o[0] + F.mz[1] * o[1] + F.mz[2] * o[2];
-}
-
-// Slab test of one box against [tmin, tmax]; returns entry distance or +inf.
-__device__ __forceinline__ float box_enter(float lx, float ly, float lz, float hx, float hy, float hz,
-                                           float ix, float iy, float iz, float oix, float oiy, float oiz,
-                                           float tmin, float tmax) {
-    float t0x = fmaf(lx, ix, -oix), t1x = fmaf(hx, ix, -oix);
-    float t0y = fmaf(ly, iy, -oiy), t1y = fmaf(hy, iy, -oiy);
-    float t0z = fmaf(lz, iz, -oiz), t1z = fmaf(hz, iz, -oiz);
-    float tn = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), tmin));
-    float tf = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fminf(fmaxf(t0z, t1z), tmax));
-    return tn <= tf ? tn : T_INF;
-}
-
-__device__ __forceinline__ float xf_dot(const float m[3], float c, const float v[3]) {
-    return fmaf(m[0], v[0], fmaf(m[1], v[1], fmaf(m[2], v[2], -c)));
-}
-
-// Watertight ray/triangle test in the ray frame: 2-D edge functions of the
-// projected corners (products rounded separately, so a shared edge gets the
-// exact negated value in both triangles: no ray passes between them), then
-// the hit distance.  Returns t or a negative value for a miss.
-__device__ __forceinline__ float tri_hit(const Frame &F, const float a[3], const float b[3], const float c[3]) {
-#pragma clang fp contract(off)
-    float ax = xf_dot(F.mx, F.cx, a), ay = xf_dot(F.my, F.cy, a);
-    float bx = xf_dot(F.mx, F.cx, b), by = xf_dot(F.my, F.cy, b);
-    float cx = xf_dot(F.mx, F.cx, c), cy = xf_dot(F.my, F.cy, c);
-    float U = cx * by - cy * bx;
-    float V = ax * cy - ay * cx;
-    float W = bx * ay - by * ax;
-    float mn = fminf(fminf(U, V), W), mx = fmaxf(fmaxf(U, V), W);
-    if (mn < 0.0f && mx > 0.0f) return -1.0f;
-    float det = U + V + W;
-    if (det == 0.0f) return -1.0f;
-    float az = xf_dot(F.mz, F.cz, a), bz = xf_dot(F.mz, F.cz, b), cz = xf_dot(F.mz, F.cz, c);
-    float T = U * az + V * bz + W * cz;
-    return T / det;
-}
-
-struct Hit {
-    float t;
-    int32_t tri;    // leaf-order index into the scene's triangle records
-    int32_t inst;
-    int32_t id;     // original triangle index
-};
-
-template <bool COUNT>
-__device__ bool trace_closest(const EvalDesc &D, const float o[3], const float d[3], float tmin,
-                              int32_t exclude_id, uint32_t *stack, Hit &h, uint32_t &nbox, uint32_t &ntri) {
-    h.t = T_INF;
-    h.tri = -1;
-    h.inst = -1;
-    h.id = 0x7FFFFFFF;
-    uint32_t ref = D.root_ref;
-    if (ref == REF_NONE) return true;
-    // world frame (top level)
-    const float wix = safe_inv(d[0]), wiy = safe_inv(d[1]), wiz = safe_inv(d[2]);
-    const float woix = o[0] * wix, woiy = o[1] * wiy, woiz = o[2] * wiz;
-    float ix = wix, iy = wiy, iz = wiz, oix = woix, oiy = woiy, oiz = woiz;
-    Frame F;
-    int inst = -1;
-    int sp = 0;
-    for (;;) {
-        uint32_t ty = ref_type(ref);
-        if (ty == REF_BLAS_NODE || ty == REF_TLAS_NODE) {
-            const BNode *nb = (ty == REF_TLAS_NODE ? D.tlas : D.blas) + ref_index(ref);
-            const float4 *q = reinterpret_cast<const float4 *>(nb);
-            float4 A = q[0], B = q[1], C = q[2];
-            uint4 R = reinterpret_cast<const uint4 *>(nb)[3];
-            float t0 = box_enter(A.x, A.y, A.z, A.w, B.x, B.y, ix, iy, iz, oix, oiy, oiz, tmin, h.t);
-            float t1 = box_enter(B.z, B.w, C.x, C.y, C.z, C.w, ix, iy, iz, oix, oiy, oiz, tmin, h.t);
-            if (COUNT) nbox += 2;
-            bool h0 = t0 != T_INF, h1 = t1 != T_INF;
-            if (h0 && h1) {
-                uint32_t nr = t0 <= t1 ? R.x : R.y, fr = t0 <= t1 ? R.y : R.x;
-                if (sp >= STACK_DEPTH) return false;
-                stack[sp * BLOCK] = fr;
-                ++sp;
-                ref = nr;
-                continue;
-            }
-            if (h0) { ref = R.x; continue; }
-            if (h1) { ref = R.y; continue; }
-        } else if (ty == REF_BLAS_LEAF) {
-            uint32_t p = ref_index(ref);
-            uint32_t first = p >> 3, cnt = (p & 7u) + 1u;
-            for (uint32_t k = 0; k < cnt; ++k) {
-                const float4 *q = reinterpret_cast<const float4 *>(D.tris + first + k);
-                float4 A = q[0], B = q[1], C = q[2];
-                int32_t id = __float_as_int(A.w);
-                if (COUNT) ntri++;
-                if (id == exclude_id) continue;
-                float va[3] = {A.x, A.y, A.z}, vb[3] = {B.x, B.y, B.z}, vc[3] = {C.x, C.y, C.z};
-                float t = tri_hit(F, va, vb, vc);
-                if (t > tmin && (t < h.t || (t == h.t && id < h.id))) {
-                    h.t = t;
-                    h.tri = (int32_t)(first + k);
-                    h.inst = inst;
-                    h.id = id;
-                }
-            }
-        } else {
-            // top-level leaf: enter the instance (rigid transform; t is preserved)
-            inst = (int)ref_index(ref);
-            const Inst &I = D.inst[inst];
-            float r0 = o[0] - I.t[0], r1 = o[1] - I.t[1], r2 = o[2] - I.t[2];
-            float lo[3], ld[3];
-            lo[0] = I.R[0] * r0 + I.R[3] * r1 + I.R[6] * r2;
-            lo[1] = I.R[1] * r0 + I.R[4] * r1 + I.R[7] * r2;
-            lo[2] = I.R[2] * r0 + I.R[5] * r1 + I.R[8] * r2;
-            ld[0] = I.R[0] * d[0] + I.R[3] * d[1] + I.R[6] * d[2];
-            ld[1] = I.R[1] * d[0] + I.R[4] * d[1] + I.R[7] * d[2];
-            ld[2] = I.R[2] * d[0] + I.R[5] * d[1] + I.R[8] * d[2];
-            frame_setup(lo, ld, F);
-            ix = F.ix; iy = F.iy; iz = F.iz;
-            oix = F.oix; oiy = F.oiy; oiz = F.oiz;
-            if (sp >= STACK_DEPTH) return false;
-            stack[sp * BLOCK] = REF_EXIT;
-            ++sp;
-            ref = I.root;
-            continue;
-        }
-        // pop
-        for (;;) {
-            if (sp == 0) return true;
-            --sp;
-            ref = stack[sp * BLOCK];
-            if (ref != REF_EXIT) break;
-            ix = wix; iy = wiy; iz = wiz;
-            oix = woix; oiy = woiy; oiz = woiz;
-            inst = -1;
-        }
-    }
-}
 
 __device__ __forceinline__ double wave_sum(double x) {
 #pragma unroll
@@ -325,7 +150,7 @@ __global__ __launch_bounds__(BLOCK) void k_trace(const EvalDesc *__restrict__ de
                 const int64_t pix = (int64_t)py * N + px;
                 for (int gen = 0; gen <= B; ++gen) {
                     Hit h;
-                    if (!trace_closest<COUNT>(D, o, d, tmin, excl, stack, h, nbox, ntri)) {
+                    if (!trace_closest<COUNT>(D, o, d, tmin, excl, stack, BLOCK, h, nbox, ntri)) {
                         status |= SRP_STATUS_STACK;
                         break;
                     }
@@ -480,11 +305,15 @@ __global__ __launch_bounds__(BLOCK) void k_trace(const EvalDesc *__restrict__ de
     }
 }
 
-__global__ __launch_bounds__(256) void k_window(const EvalDesc *__restrict__ descs, uint64_t *win) {
+constexpr int WBLOCK = 256;   // threads per block of the window and reduce kernels
+
+// Loop strides use compile-time block sizes and an explicit grid-width
+// argument, so termination never depends on runtime-filled dispatch values.
+__global__ __launch_bounds__(WBLOCK) void k_window(const EvalDesc *__restrict__ descs, uint64_t *win, int blocks_x) {
     const EvalDesc &D = descs[blockIdx.y];
     double mn[5] = {INFINITY, INFINITY, INFINITY, INFINITY, INFINITY};
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < D.n_wpts;
-         i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t stride = (int64_t)blocks_x * WBLOCK;
+    for (int64_t i = (int64_t)blockIdx.x * WBLOCK + threadIdx.x; i < D.n_wpts; i += stride) {
         const WPoint p = D.wpts[i];
         const double *X = D.xf + 12 * p.node;
         double x = X[0] * p.x + X[1] * p.y + X[2] * p.z + X[9];
@@ -499,7 +328,7 @@ __global__ __launch_bounds__(256) void k_window(const EvalDesc *__restrict__ des
         mn[3] = fmin(mn[3], -b);
         mn[4] = fmin(mn[4], h);
     }
-    __shared__ double s[256 / WAVE][5];
+    __shared__ double s[WBLOCK / WAVE][5];
     const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x >> 6;
     for (int k = 0; k < 5; ++k) {
         double x = mn[k];
@@ -509,14 +338,14 @@ __global__ __launch_bounds__(256) void k_window(const EvalDesc *__restrict__ des
     __syncthreads();
     if (threadIdx.x < 5) {
         double x = s[0][threadIdx.x];
-        for (int w = 1; w < (int)(blockDim.x / WAVE); ++w) x = fmin(x, s[w][threadIdx.x]);
+        for (int w = 1; w < WBLOCK / WAVE; ++w) x = fmin(x, s[w][threadIdx.x]);
         if (x != INFINITY) atomicMin((unsigned long long *)(win + (size_t)blockIdx.y * WIN_STRIDE + threadIdx.x),
                                      (unsigned long long)enc_f64(x));
     }
 }
 
 template <bool COUNT, bool GRAD>
-__global__ __launch_bounds__(256) void k_reduce(const EvalDesc *__restrict__ descs,
+__global__ __launch_bounds__(WBLOCK) void k_reduce(const EvalDesc *__restrict__ descs,
                                                 const int64_t *__restrict__ chunk_base,
                                                 const uint64_t *__restrict__ win,
                                                 const ChunkOut *__restrict__ chunks,
@@ -527,7 +356,7 @@ __global__ __launch_bounds__(256) void k_reduce(const EvalDesc *__restrict__ des
     double f[6] = {0, 0, 0, 0, 0, 0};
     uint64_t cn[5] = {0, 0, 0, 0, 0};
     uint32_t st = 0;
-    for (int64_t c = c0 + tid; c < c1; c += blockDim.x) {
+    for (int64_t c = c0 + tid; c < c1; c += WBLOCK) {
         const ChunkOut &co = chunks[c];
         for (int k = 0; k < 6; ++k) f[k] += co.f[k];
         cn[0] += co.hits;
@@ -577,7 +406,7 @@ __global__ __launch_bounds__(256) void k_reduce(const EvalDesc *__restrict__ des
         // sum chunk partials per component (fixed chunk order), then assemble
         const int G = D.grad_n, K = D.n_nodes, M = D.n_mats, J = D.n_dof;
         __shared__ double sg[MAX_GRAD_SLOTS];
-        for (int i = tid; i < G; i += blockDim.x) {
+        for (int i = tid; i < G; i += WBLOCK) {
             double s = 0.0;
             for (int64_t c = 0; c < D.n_chunks; ++c) s += D.grad_part[(size_t)c * G + i];
             sg[i] = s;
@@ -586,14 +415,14 @@ __global__ __launch_bounds__(256) void k_reduce(const EvalDesc *__restrict__ des
         double *g = D.grad_out;
         if (g) {
             // rho_s (M x 3), rho_d (M x 3)
-            for (int i = tid; i < 6 * M; i += blockDim.x) {
+            for (int i = tid; i < 6 * M; i += WBLOCK) {
                 int m = i / 6, k = i % 6;
                 double v = scale * sg[9 * K + i];
                 if (k < 3) g[3 * m + k] = v;
                 else g[3 * M + 3 * m + (k - 3)] = v;
             }
             // theta: (sum of S_q over the subtree of the joint's node) * world axis
-            for (int j = tid; j < J; j += blockDim.x) {
+            for (int j = tid; j < J; j += WBLOCK) {
                 const int p = D.dof_node[j];
                 double S[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
                 for (int q = 0; q < K; ++q) {
@@ -616,7 +445,7 @@ int check(hipError_t e) { return e == hipSuccess ? 0 : (int)e; }
 
 int launch_window(const EvalDesc *d_desc, int n_evals, int blocks_x, uint64_t *d_win, void *stream) {
     if (n_evals <= 0) return 0;
-    hipLaunchKernelGGL(k_window, dim3(blocks_x, n_evals), dim3(256), 0, (hipStream_t)stream, d_desc, d_win);
+    hipLaunchKernelGGL(k_window, dim3(blocks_x, n_evals), dim3(WBLOCK), 0, (hipStream_t)stream, d_desc, d_win, blocks_x);
     return check(hipGetLastError());
 }
 
@@ -648,13 +477,13 @@ int launch_reduce(const EvalDesc *d_desc, const int64_t *d_chunk_base, int n_eva
     hipStream_t s = (hipStream_t)stream;
     srp_result *out = (srp_result *)d_out;
     if (count && grad)
-        hipLaunchKernelGGL((k_reduce<true, true>), dim3(n_evals), dim3(256), 0, s, d_desc, d_chunk_base, d_win, d_chunks, d_counts, out);
+        hipLaunchKernelGGL((k_reduce<true, true>), dim3(n_evals), dim3(WBLOCK), 0, s, d_desc, d_chunk_base, d_win, d_chunks, d_counts, out);
     else if (count)
-        hipLaunchKernelGGL((k_reduce<true, false>), dim3(n_evals), dim3(256), 0, s, d_desc, d_chunk_base, d_win, d_chunks, d_counts, out);
+        hipLaunchKernelGGL((k_reduce<true, false>), dim3(n_evals), dim3(WBLOCK), 0, s, d_desc, d_chunk_base, d_win, d_chunks, d_counts, out);
     else if (grad)
-        hipLaunchKernelGGL((k_reduce<false, true>), dim3(n_evals), dim3(256), 0, s, d_desc, d_chunk_base, d_win, d_chunks, d_counts, out);
+        hipLaunchKernelGGL((k_reduce<false, true>), dim3(n_evals), dim3(WBLOCK), 0, s, d_desc, d_chunk_base, d_win, d_chunks, d_counts, out);
     else
-        hipLaunchKernelGGL((k_reduce<false, false>), dim3(n_evals), dim3(256), 0, s, d_desc, d_chunk_base, d_win, d_chunks, d_counts, out);
+        hipLaunchKernelGGL((k_reduce<false, false>), dim3(n_evals), dim3(WBLOCK), 0, s, d_desc, d_chunk_base, d_win, d_chunks, d_counts, out);
     return check(hipGetLastError());
 }
 

@@ -1,0 +1,208 @@
+// Ray traversal and intersection shared by the gfx950 kernels and a host
+// build of the same code (used to check the traversal on the CPU).
+//
+// trace_closest: closest hit of one ray in a two-level hierarchy (top level
+// over the kinematic-tree nodes in world coordinates; per node a bottom level
+// in rest-pose coordinates entered through the node's rigid transform, which
+// preserves the ray parameter t), with a per-lane stack whose entries are
+// STACK_DEPTH apart by `stride` words.
+#pragma once
+#include <math.h>
+#include <stdint.h>
+
+#include "srp_internal.h"
+
+namespace srp {
+
+constexpr float T_INF = 3.0e38f;
+SRP_HD inline float safe_inv(float x) {
+    // reciprocal of a direction component, finite for zero components
+    float ax = fabsf(x) < 1e-30f ? copysignf(1e-30f, x) : x;
+    return 1.0f / ax;
+}
+
+// An orthonormal basis (bx, by) orthogonal to unit d (Duff et al., JCGT 2017).
+SRP_HD inline void onb(const float d[3], float bx[3], float by[3]) {
+    float s = copysignf(1.0f, d[2]);
+    float a = -1.0f / (s + d[2]);
+    float b = d[0] * d[1] * a;
+    bx[0] = 1.0f + s * d[0] * d[0] * a;
+    bx[1] = s * b;
+    bx[2] = -s * d[0];
+    by[0] = b;
+    by[1] = s + d[1] * d[1] * a;
+    by[2] = -d[1];
+}
+
+// Ray state in one frame: slab-test constants and the watertight-test frame
+// (x, y axes orthogonal to the direction, z = direction, offsets = axes . o).
+struct Frame {
+    float ix, iy, iz;      // 1 / d
+    float oix, oiy, oiz;   // o / d
+    float mx[3], my[3], mz[3];
+    float cx, cy, cz;
+};
+
+SRP_HD inline void frame_setup(const float o[3], const float d[3], Frame &F) {
+    F.ix = safe_inv(d[0]);
+    F.iy = safe_inv(d[1]);
+    F.iz = safe_inv(d[2]);
+    F.oix = o[0] * F.ix;
+    F.oiy = o[1] * F.iy;
+    F.oiz = o[2] * F.iz;
+    onb(d, F.mx, F.my);
+    F.mz[0] = d[0]; F.mz[1] = d[1]; F.mz[2] = d[2];
+    F.cx = F.mx[0] * o[0] + F.mx[1] * o[1] + F.mx[2] * o[2];
+    F.cy = F.my[0] * o[0] + F.my[1] * o[1] + F.my[2] * o[2];
+    F.cz = F.mz[0] * o[0] + F.mz[1] * o[1] + F.mz[2] * o[2];
+}
+
+// Slab test of one box against [tmin, tmax]; returns entry distance or +inf.
+SRP_HD inline float box_enter(float lx, float ly, float lz, float hx, float hy, float hz,
+                                           float ix, float iy, float iz, float oix, float oiy, float oiz,
+                                           float tmin, float tmax) {
+    float t0x = fmaf(lx, ix, -oix), t1x = fmaf(hx, ix, -oix);
+    float t0y = fmaf(ly, iy, -oiy), t1y = fmaf(hy, iy, -oiy);
+    float t0z = fmaf(lz, iz, -oiz), t1z = fmaf(hz, iz, -oiz);
+    float tn = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), tmin));
+    float tf = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fminf(fmaxf(t0z, t1z), tmax));
+    return tn <= tf ? tn : T_INF;
+}
+
+SRP_HD inline float xf_dot(const float m[3], float c, const float v[3]) {
+    return fmaf(m[0], v[0], fmaf(m[1], v[1], fmaf(m[2], v[2], -c)));
+}
+
+// Watertight ray/triangle test in the ray frame: 2-D edge functions of the
+// projected corners (products rounded separately, so a shared edge gets the
+// exact negated value in both triangles: no ray passes between them), then
+// the hit distance.  Returns t or a negative value for a miss.
+SRP_HD inline float tri_hit(const Frame &F, const float a[3], const float b[3], const float c[3]) {
+#pragma clang fp contract(off)
+    float ax = xf_dot(F.mx, F.cx, a), ay = xf_dot(F.my, F.cy, a);
+    float bx = xf_dot(F.mx, F.cx, b), by = xf_dot(F.my, F.cy, b);
+    float cx = xf_dot(F.mx, F.cx, c), cy = xf_dot(F.my, F.cy, c);
+    float U = cx * by - cy * bx;
+    float V = ax * cy - ay * cx;
+    float W = bx * ay - by * ax;
+    float mn = fminf(fminf(U, V), W), mx = fmaxf(fmaxf(U, V), W);
+    if (mn < 0.0f && mx > 0.0f) return -1.0f;
+    float det = U + V + W;
+    if (det == 0.0f) return -1.0f;
+    float az = xf_dot(F.mz, F.cz, a), bz = xf_dot(F.mz, F.cz, b), cz = xf_dot(F.mz, F.cz, c);
+    float T = U * az + V * bz + W * cz;
+    return T / det;
+}
+
+SRP_HD inline int32_t f2i(float x) {
+    union { float f; int32_t i; } u;
+    u.f = x;
+    return u.i;
+}
+
+struct Hit {
+    float t;
+    int32_t tri;    // leaf-order index into the scene's triangle records
+    int32_t inst;
+    int32_t id;     // original triangle index
+};
+
+// Hard bound on the nodes and leaves one ray may visit: far above what any
+// hierarchy accepted by the builder needs (each node is visited at most once),
+// so reaching it means corrupted data and the ray reports an error instead of
+// looping.
+constexpr uint32_t MAX_VISITS = 1u << 22;
+
+template <bool COUNT>
+SRP_HD inline bool trace_closest(const EvalDesc &D, const float o[3], const float d[3], float tmin,
+                                 int32_t exclude_id, uint32_t *stack, int stride, Hit &h, uint32_t &nbox,
+                                 uint32_t &ntri, uint32_t *steps = nullptr) {
+    h.t = T_INF;
+    h.tri = -1;
+    h.inst = -1;
+    h.id = 0x7FFFFFFF;
+    uint32_t ref = D.root_ref;
+    if (ref == REF_NONE) return true;
+    // world frame (top level)
+    const float wix = safe_inv(d[0]), wiy = safe_inv(d[1]), wiz = safe_inv(d[2]);
+    const float woix = o[0] * wix, woiy = o[1] * wiy, woiz = o[2] * wiz;
+    float ix = wix, iy = wiy, iz = wiz, oix = woix, oiy = woiy, oiz = woiz;
+    Frame F;
+    int inst = -1;
+    int sp = 0;
+    for (uint32_t visit = 0;; ++visit) {
+        if (visit >= MAX_VISITS) return false;
+        if (steps) ++*steps;
+        uint32_t ty = ref_type(ref);
+        if (ty == REF_BLAS_NODE || ty == REF_TLAS_NODE) {
+            const BNode *nb = (ty == REF_TLAS_NODE ? D.tlas : D.blas) + ref_index(ref);
+            const float4 *q = reinterpret_cast<const float4 *>(nb);
+            float4 A = q[0], B = q[1], C = q[2];
+            uint4 R = reinterpret_cast<const uint4 *>(nb)[3];
+            float t0 = box_enter(A.x, A.y, A.z, A.w, B.x, B.y, ix, iy, iz, oix, oiy, oiz, tmin, h.t);
+            float t1 = box_enter(B.z, B.w, C.x, C.y, C.z, C.w, ix, iy, iz, oix, oiy, oiz, tmin, h.t);
+            if (COUNT) nbox += 2;
+            bool h0 = t0 != T_INF, h1 = t1 != T_INF;
+            if (h0 && h1) {
+                uint32_t nr = t0 <= t1 ? R.x : R.y, fr = t0 <= t1 ? R.y : R.x;
+                if (sp >= STACK_DEPTH) return false;
+                stack[sp * stride] = fr;
+                ++sp;
+                ref = nr;
+                continue;
+            }
+            if (h0) { ref = R.x; continue; }
+            if (h1) { ref = R.y; continue; }
+        } else if (ty == REF_BLAS_LEAF) {
+            uint32_t p = ref_index(ref);
+            uint32_t first = p >> 3, cnt = (p & 7u) + 1u;
+            for (uint32_t k = 0; k < cnt; ++k) {
+                const float4 *q = reinterpret_cast<const float4 *>(D.tris + first + k);
+                float4 A = q[0], B = q[1], C = q[2];
+                int32_t id = f2i(A.w);
+                if (COUNT) ntri++;
+                if (id == exclude_id) continue;
+                float va[3] = {A.x, A.y, A.z}, vb[3] = {B.x, B.y, B.z}, vc[3] = {C.x, C.y, C.z};
+                float t = tri_hit(F, va, vb, vc);
+                if (t > tmin && (t < h.t || (t == h.t && id < h.id))) {
+                    h.t = t;
+                    h.tri = (int32_t)(first + k);
+                    h.inst = inst;
+                    h.id = id;
+                }
+            }
+        } else {
+            // top-level leaf: enter the instance (rigid transform; t is preserved)
+            inst = (int)ref_index(ref);
+            const Inst &I = D.inst[inst];
+            float r0 = o[0] - I.t[0], r1 = o[1] - I.t[1], r2 = o[2] - I.t[2];
+            float lo[3], ld[3];
+            lo[0] = I.R[0] * r0 + I.R[3] * r1 + I.R[6] * r2;
+            lo[1] = I.R[1] * r0 + I.R[4] * r1 + I.R[7] * r2;
+            lo[2] = I.R[2] * r0 + I.R[5] * r1 + I.R[8] * r2;
+            ld[0] = I.R[0] * d[0] + I.R[3] * d[1] + I.R[6] * d[2];
+            ld[1] = I.R[1] * d[0] + I.R[4] * d[1] + I.R[7] * d[2];
+            ld[2] = I.R[2] * d[0] + I.R[5] * d[1] + I.R[8] * d[2];
+            frame_setup(lo, ld, F);
+            ix = F.ix; iy = F.iy; iz = F.iz;
+            oix = F.oix; oiy = F.oiy; oiz = F.oiz;
+            if (sp >= STACK_DEPTH) return false;
+            stack[sp * stride] = REF_EXIT;
+            ++sp;
+            ref = I.root;
+            continue;
+        }
+        // pop
+        for (;;) {
+            if (sp == 0) return true;
+            --sp;
+            ref = stack[sp * stride];
+            if (ref != REF_EXIT) break;
+            ix = wix; iy = wiy; iz = wiz;
+            oix = woix; oiy = woiy; oiz = woiz;
+            inst = -1;
+        }
+    }
+}
+
+}  // namespace srp
