@@ -253,7 +253,7 @@ int run_batch(const srp_batch_item *items, int64_t n, bool grad, const BatchOut 
         slot_of.emplace(key, item_slot[k]);
     }
 
-    // staging layout (uploaded): descs | chunk_base | win | counter | slots
+    // staging layout (uploaded): descs | chunk_base | win | (spare) | slots
     size_t o_desc = 0;
     size_t o_base = align_up(o_desc + sizeof(EvalDesc) * n);
     size_t o_win = align_up(o_base + sizeof(int64_t) * (n + 1));
@@ -344,7 +344,6 @@ int run_batch(const srp_batch_item *items, int64_t n, bool grad, const BatchOut 
     const EvalDesc *d_desc = reinterpret_cast<const EvalDesc *>(Dv + o_desc);
     const int64_t *d_base = reinterpret_cast<const int64_t *>(Dv + o_base);
     uint64_t *d_win = reinterpret_cast<uint64_t *>(Dv + o_win);
-    uint32_t *d_counter = reinterpret_cast<uint32_t *>(Dv + o_cnt);
     ChunkOut *d_chunks = reinterpret_cast<ChunkOut *>(Dv + o_chunks);
     uint64_t *d_counts = count ? reinterpret_cast<uint64_t *>(Dv + o_counts) : nullptr;
 
@@ -358,7 +357,7 @@ int run_batch(const srp_batch_item *items, int64_t n, bool grad, const BatchOut 
         if ((rc = prof_event_pair(&ev))) return rc;
         HIPCHK(hipEventRecord(ev.first, stream));
     }
-    e = launch_trace(d_desc, d_base, (int)n, d_win, d_counter, total_chunks, d_chunks, d_counts, count, grad,
+    e = launch_trace(d_desc, d_base, (int)n, d_win, total_chunks, d_chunks, d_counts, count, grad,
                      (int)std::max<int64_t>(grid, 1), max_grad_n, stream);
     if (e) return fail(SRP_ERR_DEVICE, std::string("trace kernel: ") + hipGetErrorString((hipError_t)e));
     if (g_prof.on) {

@@ -4,8 +4,8 @@
 //             mesh (FP64 bounds of every (vertex, node) point on the image
 //             axes u, v and the photon direction d), merged across blocks with
 //             order-preserving 64-bit atomic min.
-//   k_trace   persistent: blocks pull chunks (16 x 16*rpt pixels of one
-//             evaluation) from an atomic counter; one ray per lane, an 8x8
+//   k_trace   persistent: blocks walk the chunks (16 x 16*rpt pixels of one
+//             evaluation) with a uniform grid stride; one ray per lane, an 8x8
 //             pixel patch per wave; two-level traversal (top level over the
 //             kinematic-tree nodes, rigid instance transform, bottom level in
 //             rest-pose coordinates) with a per-lane stack in LDS; watertight
@@ -72,24 +72,23 @@ __device__ __forceinline__ void m3_zero(float *M) {
 template <bool COUNT, bool GRAD>
 __global__ __launch_bounds__(BLOCK) void k_trace(const EvalDesc *__restrict__ descs,
                                                  const int64_t *__restrict__ chunk_base, int n_evals,
-                                                 const uint64_t *__restrict__ win, uint32_t *counter,
+                                                 const uint64_t *__restrict__ win, int grid_blocks,
                                                  int64_t total_chunks, ChunkOut *__restrict__ chunks,
                                                  uint64_t *__restrict__ counts) {
     extern __shared__ char smem[];
     uint32_t *stack = reinterpret_cast<uint32_t *>(smem) + threadIdx.x;   // entry s at [s * BLOCK]
     double *gacc = reinterpret_cast<double *>(smem + sizeof(uint32_t) * STACK_DEPTH * BLOCK);
-    __shared__ uint32_t s_chunk;
     __shared__ double s_red[BLOCK / WAVE][8];
     __shared__ uint32_t s_cnt[BLOCK / WAVE][6];
 
     const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid >> 6;
 
-    for (;;) {
-        if (tid == 0) s_chunk = atomicAdd(counter, 1u);
-        __syncthreads();
-        const int64_t c = s_chunk;
-        __syncthreads();
-        if (c >= total_chunks) break;
+    // Persistent blocks walk the chunks with a uniform grid stride: the loop
+    // control is identical for every thread, so the block barriers below never
+    // sit under divergent control flow (a per-block atomic work counter read
+    // back through LDS did, and its loop was restructured so that the lane
+    // doing the atomic left the loop the other lanes kept re-entering).
+    for (int64_t c = blockIdx.x; c < total_chunks; c += grid_blocks) {
 
         // evaluation owning chunk c (chunk_base is increasing; chunk_base[n_evals] = total)
         int lo = 0, hi = n_evals - 1;
@@ -302,6 +301,7 @@ __global__ __launch_bounds__(BLOCK) void k_trace(const EvalDesc *__restrict__ de
             }
             (void)gM;
         }
+        __syncthreads();   // s_red, s_cnt and gacc are reused by the next chunk
     }
 }
 
@@ -450,23 +450,23 @@ int launch_window(const EvalDesc *d_desc, int n_evals, int blocks_x, uint64_t *d
 }
 
 int launch_trace(const EvalDesc *d_desc, const int64_t *d_chunk_base, int n_evals, const uint64_t *d_win,
-                 uint32_t *d_counter, int64_t total_chunks, ChunkOut *d_chunks, uint64_t *d_counts, bool count,
-                 bool grad, int grid_blocks, int lds_grad_doubles, void *stream) {
+                 int64_t total_chunks, ChunkOut *d_chunks, uint64_t *d_counts, bool count, bool grad,
+                 int grid_blocks, int lds_grad_doubles, void *stream) {
     if (total_chunks <= 0) return 0;
     size_t lds = sizeof(uint32_t) * STACK_DEPTH * BLOCK + (grad ? sizeof(double) * (BLOCK / 64) * lds_grad_doubles : 0);
     hipStream_t s = (hipStream_t)stream;
     if (count && grad)
         hipLaunchKernelGGL((k_trace<true, true>), dim3(grid_blocks), dim3(BLOCK), lds, s, d_desc, d_chunk_base,
-                           n_evals, d_win, d_counter, total_chunks, d_chunks, d_counts);
+                           n_evals, d_win, grid_blocks, total_chunks, d_chunks, d_counts);
     else if (count)
         hipLaunchKernelGGL((k_trace<true, false>), dim3(grid_blocks), dim3(BLOCK), lds, s, d_desc, d_chunk_base,
-                           n_evals, d_win, d_counter, total_chunks, d_chunks, d_counts);
+                           n_evals, d_win, grid_blocks, total_chunks, d_chunks, d_counts);
     else if (grad)
         hipLaunchKernelGGL((k_trace<false, true>), dim3(grid_blocks), dim3(BLOCK), lds, s, d_desc, d_chunk_base,
-                           n_evals, d_win, d_counter, total_chunks, d_chunks, d_counts);
+                           n_evals, d_win, grid_blocks, total_chunks, d_chunks, d_counts);
     else
         hipLaunchKernelGGL((k_trace<false, false>), dim3(grid_blocks), dim3(BLOCK), lds, s, d_desc, d_chunk_base,
-                           n_evals, d_win, d_counter, total_chunks, d_chunks, d_counts);
+                           n_evals, d_win, grid_blocks, total_chunks, d_chunks, d_counts);
     return check(hipGetLastError());
 }
 

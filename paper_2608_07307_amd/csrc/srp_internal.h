@@ -177,8 +177,8 @@ struct LaunchCfg {
 // Kernel launchers (kernels.hip)
 int launch_window(const EvalDesc *d_desc, int n_evals, int blocks_x, uint64_t *d_win, void *stream);
 int launch_trace(const EvalDesc *d_desc, const int64_t *d_chunk_base, int n_evals,
-                 const uint64_t *d_win, uint32_t *d_counter, int64_t total_chunks,
-                 ChunkOut *d_chunks, uint64_t *d_counts, bool count, bool grad, int grid_blocks,
+                 const uint64_t *d_win, int64_t total_chunks, ChunkOut *d_chunks,
+                 uint64_t *d_counts, bool count, bool grad, int grid_blocks,
                  int lds_grad_doubles, void *stream);
 int launch_reduce(const EvalDesc *d_desc, const int64_t *d_chunk_base, int n_evals,
                   const uint64_t *d_win, const ChunkOut *d_chunks, const uint64_t *d_counts,
