@@ -135,9 +135,17 @@ __global__ __launch_bounds__(BLOCK) void k_trace(const EvalDesc *__restrict__ de
 
         for (int r = 0; r < D.rpt; ++r) {
             const int py = py0 + r * TILE;
-            const bool valid = !empty && px < N && py < N;
+            const bool inside = px < N && py < N;
+            const bool valid = !empty && inside;
             ChainHit chain[GRAD ? MAX_CHAIN : 1];
             int K = 0;
+            if (inside && D.hit_ids) {   // generations a chain does not reach stay "no hit"
+                const int64_t pix = (int64_t)py * N + px;
+                for (int gen = 0; gen <= B; ++gen) {
+                    D.hit_ids[pix * (B + 1) + gen] = -1;
+                    D.hit_t[pix * (B + 1) + gen] = 0.0f;
+                }
+            }
             if (valid) {
                 float o[3], d[3];
                 for (int k = 0; k < 3; ++k) {

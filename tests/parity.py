@@ -101,6 +101,7 @@ def compare_eval(mesh, angles, sun, n, bounces, gpu, orc, pressure=1.0):
         sec_o, sec_g = orc.ids[:, 1:], gpu["ids"][:, 1:]
         valid = (sec_o >= 0) | (sec_g >= 0)
         rep["secondary_match_fraction"] = float((sec_o == sec_g)[valid].mean()) if valid.any() else 1.0
+        rep["secondary_mismatch"] = int((sec_o != sec_g)[valid].sum())
     vm = oracle.shade_frozen(mesh, sun, n, bounces, grid, gpu["ids"], pressure=pressure,
                              angles=angles)
     rep["f_err_vis_matched"] = rel(gpu["force"], vm.force)

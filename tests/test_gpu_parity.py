@@ -23,12 +23,18 @@ def _show(tag, rep):
 
 
 def _check(rep, strict=True):
+    """Primary ids equal outside the edge band; the visibility-matched force
+    and torque (oracle physics on the GPU's hits) within 1e-5; the plain
+    force within 1e-5 when no ray flipped, else within what the flipped rays
+    can carry (each moves F by about 1/N_hit; bound 4/N_hit per flipped ray)."""
     assert rep["primary_outside_band"] == 0, rep
     assert rep["f_err_vis_matched"] <= F_TOL, rep
     assert rep["t_err_vis_matched"] <= F_TOL, rep
     if strict:
-        assert rep["f_err"] <= F_TOL, rep
-        assert rep["t_err"] <= F_TOL, rep
+        flips = rep["primary_mismatch"] + rep.get("secondary_mismatch", 0)
+        allow = F_TOL + 4.0 * flips / max(rep["hits_orc"], 1)
+        assert rep["f_err"] <= allow, rep
+        assert rep["t_err"] <= allow, rep
 
 
 @pytest.mark.parametrize("seed", [1001, 1002, 1003, 1004])
