@@ -185,6 +185,55 @@ int srp_eval_grad(srp_scene *scene, const srp_eval_params *params, srp_result *o
 int srp_eval_grad_batch(const srp_batch_item *items, int64_t n_items, srp_result *out_dev,
                         double *grad_dev, int64_t grad_stride, void *hip_stream);
 
+/* ---- orbit propagation (Sec. 3) and panel sun tracking (Sec. 4.4.2) ---- */
+
+/* Sun tracking of the wing roots (panel nodes whose parent is not a panel),
+ * the panel-update steps 2-4: for each of the node's axes, outer to inner,
+ * the angle that turns the node's rest-pose area-weighted normal as close as
+ * possible to the Sun direction (either face, the smaller rotation), clamped
+ * to the interval.  Other angles are returned unchanged.  angles: in/out, n_dof
+ * values.  Host only.  Errors: SRP_ERR_ARG (null, n_dof mismatch, zero or
+ * non-finite sun_dir). */
+int srp_sun_tracking_angles(const srp_scene *scene, const double *sun_dir, double *angles, int32_t n_dof);
+
+/* Acceleration callback for srp_rk4: a(t, r, v) into a[3]; returns 0 or a
+ * negative error code that aborts the integration. */
+typedef int (*srp_accel_fn)(double t, const double *r, const double *v, double *a, void *user);
+
+/* Classical fixed-step fourth-order Runge-Kutta for y = [r; v],
+ * y' = [v; a(t, r, v)] (Sec. 3 equations of motion).  traj: caller-owned,
+ * (n_steps + 1) x 7 doubles per row (t, r, v), row 0 = the initial state.
+ * Host only.  Errors: SRP_ERR_ARG, or the callback's code. */
+int srp_rk4(const double *y0, double t0, double h, int64_t n_steps, srp_accel_fn accel, void *user,
+            double *traj);
+
+typedef struct {
+    double mu;          /* gravitational parameter of the central body (Sun), m^3/s^2 */
+    double mass;        /* spacecraft mass, kg */
+    double p_ref;       /* radiation pressure at distance r_ref, N/m^2 */
+    double r_ref;       /* m */
+    int32_t n;          /* SRP ray grid N */
+    int32_t bounces;    /* SRP secondary generations */
+    int32_t track_sun;  /* 1: wing roots track the Sun (srp_sun_tracking_angles) every stage */
+    int32_t reserved;
+    double ref[3];      /* torque reference point */
+} srp_orbit_params;
+
+typedef struct {
+    int64_t n_evals;      /* SRP evaluations (4 per step) */
+    double srp_seconds;   /* host wall time spent in them */
+} srp_prop_stats;
+
+/* Heliocentric two-body + ray-traced SRP propagation with RK4 (one SRP
+ * evaluation per stage, Sec. 3): the Sun is at the origin, the attitude is
+ * inertially fixed (body frame = inertial frame, Sec. 5.1), the Sun direction
+ * of a stage is -r/|r| and its pressure p_ref (r_ref/|r|)^2; a = -mu r/|r|^3 +
+ * F/mass.  angles0: initial hinge angles (NULL = zeros); y0: r (m), v (m/s);
+ * traj as srp_rk4.  Leaves the scene at the last stage's angles.  Errors as
+ * srp_eval, SRP_ERR_ARG for invalid orbit parameters. */
+int srp_propagate(srp_scene *scene, const srp_orbit_params *op, const double *angles0, const double *y0,
+                  double t0, double h, int64_t n_steps, double *traj, srp_prop_stats *stats);
+
 /* Measurement hook (not part of an evaluation): srp_profile(1) starts timing
  * every trace-kernel launch with a pair of HIP events recorded on the launch
  * stream, srp_profile(0) stops; both reset the totals.  srp_profile_read waits

@@ -196,3 +196,51 @@ def profile_read():
     ms, n = C.c_double(), C.c_int64()
     L.check(_load().srp_profile_read(C.byref(ms), C.byref(n)))
     return ms.value, n.value
+
+
+def sun_tracking_angles(scene: Scene, sun_dir, angles=None) -> np.ndarray:
+    """srp_sun_tracking_angles: wing roots turned towards the Sun (host)."""
+    a = np.zeros(scene.n_dof) if angles is None else np.array(angles, dtype=np.float64)
+    s = np.ascontiguousarray(sun_dir, dtype=np.float64)
+    L.check(_load().srp_sun_tracking_angles(scene.handle, L.ptr(s), L.ptr(a) if a.size else None,
+                                            a.size))
+    return a
+
+
+def rk4(y0, t0, h, n_steps, accel) -> np.ndarray:
+    """srp_rk4 with a Python acceleration accel(t, r, v) -> a (host only)."""
+    err = []
+
+    def cb(t, r, v, a, _):
+        try:
+            out = accel(t, np.ctypeslib.as_array(r, (3,)).copy(), np.ctypeslib.as_array(v, (3,)).copy())
+            for i in range(3):
+                a[i] = float(out[i])
+            return 0
+        except Exception as e:  # reported after the call
+            err.append(e)
+            return -1
+
+    f = L.ACCEL_FN(cb)
+    y = np.ascontiguousarray(y0, dtype=np.float64)
+    traj = np.zeros((n_steps + 1, 7))
+    rc = _load().srp_rk4(L.ptr(y), float(t0), float(h), int(n_steps), f, None, L.ptr(traj))
+    if err:
+        raise err[0]
+    L.check(rc)
+    return traj
+
+
+def propagate(scene: Scene, y0, t0, h, n_steps, mu, mass, p_ref, r_ref, n, bounces=0,
+              track_sun=False, angles0=None, ref=(0.0, 0.0, 0.0)):
+    """srp_propagate: heliocentric two-body + ray-traced SRP, RK4, one GPU
+    evaluation per stage.  Returns (traj (n_steps+1, 7), stats dict)."""
+    op = L.srp_orbit_params(float(mu), float(mass), float(p_ref), float(r_ref), int(n), int(bounces),
+                            1 if track_sun else 0, 0, (C.c_double * 3)(*ref))
+    y = np.ascontiguousarray(y0, dtype=np.float64)
+    a0 = None if angles0 is None else np.ascontiguousarray(angles0, dtype=np.float64)
+    traj = np.zeros((n_steps + 1, 7))
+    st = L.srp_prop_stats()
+    L.check(_load().srp_propagate(scene.handle, C.byref(op), L.ptr(a0) if a0 is not None and a0.size else None,
+                                  L.ptr(y), float(t0), float(h), int(n_steps), L.ptr(traj), C.byref(st)))
+    return traj, dict(n_evals=st.n_evals, srp_seconds=st.srp_seconds)

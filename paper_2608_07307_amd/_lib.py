@@ -17,6 +17,7 @@ EXPORTS = [
     "srp_build_scene", "srp_destroy_scene", "srp_scene_n_dof", "srp_set_materials",
     "srp_set_panel_angles", "srp_eval", "srp_eval_batch", "srp_eval_grad",
     "srp_eval_grad_batch", "srp_last_error", "srp_profile", "srp_profile_read",
+    "srp_sun_tracking_angles", "srp_rk4", "srp_propagate",
 ]
 
 
@@ -46,6 +47,19 @@ class srp_result(C.Structure):
 class srp_batch_item(C.Structure):
     _fields_ = [("scene", C.c_void_p), ("angles", C.c_void_p), ("p", srp_eval_params)]
 
+
+class srp_orbit_params(C.Structure):
+    _fields_ = [("mu", C.c_double), ("mass", C.c_double), ("p_ref", C.c_double),
+                ("r_ref", C.c_double), ("n", C.c_int32), ("bounces", C.c_int32),
+                ("track_sun", C.c_int32), ("reserved", C.c_int32), ("ref", C.c_double * 3)]
+
+
+class srp_prop_stats(C.Structure):
+    _fields_ = [("n_evals", C.c_int64), ("srp_seconds", C.c_double)]
+
+
+ACCEL_FN = C.CFUNCTYPE(C.c_int, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                       C.POINTER(C.c_double), C.c_void_p)
 
 RESULT_DTYPE = np.dtype([("force", "<f8", 3), ("torque", "<f8", 3), ("n_rays", "<i8"),
                          ("n_hits", "<i8"), ("n_secondary", "<i8"), ("n_secondary_hits", "<i8"),
@@ -81,10 +95,15 @@ def load(path: str | None = None):
     lib.srp_eval_grad_batch.argtypes = [V, I64, V, V, I64, V]
     lib.srp_last_error.restype = C.c_char_p
     lib.srp_profile.argtypes = [C.c_int]
+    lib.srp_sun_tracking_angles.argtypes = [V, V, V, I32]
+    lib.srp_rk4.argtypes = [V, C.c_double, C.c_double, I64, ACCEL_FN, V, V]
+    lib.srp_propagate.argtypes = [V, C.POINTER(srp_orbit_params), V, V, C.c_double, C.c_double, I64, V,
+                                  C.POINTER(srp_prop_stats)]
     lib.srp_profile_read.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     for f in ("srp_build_scene", "srp_destroy_scene", "srp_set_materials",
               "srp_set_panel_angles", "srp_eval", "srp_eval_batch", "srp_eval_grad",
-              "srp_eval_grad_batch", "srp_profile", "srp_profile_read"):
+              "srp_eval_grad_batch", "srp_profile", "srp_profile_read",
+              "srp_sun_tracking_angles", "srp_rk4", "srp_propagate"):
         getattr(lib, f).restype = C.c_int
     _lib = lib
     return lib

@@ -403,6 +403,15 @@ int dev_upload(T **dst, const std::vector<T> &src) {
 
 }  // namespace
 
+namespace srp {
+const SceneHost &scene_host(const srp_scene *sc) { return sc->h; }
+int scene_rest_normal(const srp_scene *sc, int node, double n0[3]) {
+    for (int a = 0; a < 3; ++a) n0[a] = sc->h.nodes[node].n0[a];
+    return SRP_OK;
+}
+void set_error(const std::string &msg) { g_err = msg; }
+}  // namespace srp
+
 extern "C" {
 
 const char *srp_last_error(void) { return g_err.c_str(); }

@@ -20,6 +20,7 @@ struct NodeInfo {
     uint32_t blas_root = REF_NONE;   // REF_NONE when the node has no triangles
     int32_t blas_depth = 0;
     double blo[3] = {0}, bhi[3] = {0};  // padded rest-pose bounds of the node's triangles
+    double n0[3] = {0, 0, 0};           // area-weighted rest-pose normal (unit, or 0 if none)
 };
 
 // Host image of one articulation slot (see srp_internal.h for the layout).

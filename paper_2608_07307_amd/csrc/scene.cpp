@@ -286,8 +286,18 @@ int scene_build(const double *verts, int64_t n_verts, const int32_t *tris, int64
         r.mat = tri_material[t];
         r.node = tri_node[t];
         per_node[tri_node[t]].push_back((int32_t)t);
+        double e1[3], e2[3];
+        for (int a = 0; a < 3; ++a) { e1[a] = p1[a] - p0[a]; e2[a] = p2[a] - p0[a]; }
+        double *nn = S->nodes[tri_node[t]].n0;
+        nn[0] += e1[1] * e2[2] - e1[2] * e2[1];
+        nn[1] += e1[2] * e2[0] - e1[0] * e2[2];
+        nn[2] += e1[0] * e2[1] - e1[1] * e2[0];
     }
     S->pad = 4e-6 * scale + 1e-9;
+    for (auto &nd : S->nodes) {
+        double l = std::sqrt(nd.n0[0] * nd.n0[0] + nd.n0[1] * nd.n0[1] + nd.n0[2] * nd.n0[2]);
+        for (int a = 0; a < 3; ++a) nd.n0[a] = l > 0 ? nd.n0[a] / l : 0.0;
+    }
 
     // one hierarchy per node
     S->tris.clear();
