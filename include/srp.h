@@ -185,6 +185,43 @@ int srp_eval_grad(srp_scene *scene, const srp_eval_params *params, srp_result *o
 int srp_eval_grad_batch(const srp_batch_item *items, int64_t n_items, srp_result *out_dev,
                         double *grad_dev, int64_t grad_stride, void *hip_stream);
 
+/* ---- captured launches, schedules and the autotuner ---- */
+
+#define SRP_PLAN_GRAD 1   /* plan / autotune flag: forward + fixed-visibility adjoint */
+
+/* A plan captures one batch launch (staging upload, window pass, persistent
+ * trace, reduction) in a HIP graph for repeated replays, e.g. the chunks of a
+ * precomputed table or the stages of many propagations.  The items fix the
+ * layout: scenes, grid sizes, bounce counts, flags and the number of distinct
+ * angle vectors; srp_plan_update may change Sun directions, pressures,
+ * references and angle values (a changed layout is recaptured).  out_dev
+ * (n_items srp_result) and, with SRP_PLAN_GRAD, grad_dev (as
+ * srp_eval_grad_batch) are device buffers that must outlive the plan.  Items
+ * with NULL angles read the scene's current angles at launch time: do not
+ * change them while a launch is in flight.  Errors as srp_eval_batch,
+ * SRP_ERR_DEVICE for graph capture failures. */
+typedef struct srp_plan srp_plan;
+int srp_plan_create(const srp_batch_item *items, int64_t n_items, int32_t flags, srp_result *out_dev,
+                    double *grad_dev, int64_t grad_stride, srp_plan **out);
+int srp_plan_update(srp_plan *plan, const srp_batch_item *items, int64_t n_items);
+int srp_plan_launch(srp_plan *plan, void *hip_stream);   /* stream-ordered; returns once queued */
+int srp_plan_destroy(srp_plan *plan);
+
+/* Launch schedule of batched evaluations: 16x16-pixel tiles per work chunk
+ * (rays per thread) and resident blocks per compute unit of the persistent
+ * grid; 0 = automatic (autotuned value for the batch's size class if any,
+ * else a heuristic).  Forces and torques do not depend on the schedule (every
+ * tile keeps its own partial sum); gradients are deterministic per schedule. */
+int srp_set_schedule(int32_t tiles_per_chunk, int32_t blocks_per_cu);
+
+/* Times the batch under candidate schedules (tiles per chunk 1..16, full and
+ * half occupancy) and keeps the fastest for batches of the same size class
+ * (total primary rays to a power of two, bounce count, gradient flag).
+ * Outputs the choice and its time (ms); any output pointer may be NULL.
+ * Blocks.  Errors as srp_eval_batch. */
+int srp_autotune(const srp_batch_item *items, int64_t n_items, int32_t flags, int32_t *tiles_per_chunk,
+                 int32_t *blocks_per_cu, double *best_ms);
+
 /* ---- orbit propagation (Sec. 3) and panel sun tracking (Sec. 4.4.2) ---- */
 
 /* Sun tracking of the wing roots (panel nodes whose parent is not a panel),

@@ -244,3 +244,57 @@ def propagate(scene: Scene, y0, t0, h, n_steps, mu, mass, p_ref, r_ref, n, bounc
     L.check(_load().srp_propagate(scene.handle, C.byref(op), L.ptr(a0) if a0 is not None and a0.size else None,
                                   L.ptr(y), float(t0), float(h), int(n_steps), L.ptr(traj), C.byref(st)))
     return traj, dict(n_evals=st.n_evals, srp_seconds=st.srp_seconds)
+
+
+def set_schedule(tiles_per_chunk=0, blocks_per_cu=0):
+    """srp_set_schedule (0 = automatic)."""
+    L.check(_load().srp_set_schedule(int(tiles_per_chunk), int(blocks_per_cu)))
+
+
+def autotune(entries, grad=False):
+    """srp_autotune over a batch; returns (tiles_per_chunk, blocks_per_cu, ms)."""
+    arr, keep = _items(entries)
+    r, b, ms = C.c_int32(), C.c_int32(), C.c_double()
+    L.check(_load().srp_autotune(arr, len(entries), L.SRP_PLAN_GRAD if grad else 0, C.byref(r),
+                                 C.byref(b), C.byref(ms)))
+    return r.value, b.value, ms.value
+
+
+class Plan:
+    """srp_plan: a captured batch launch replayed with new per-item values."""
+
+    def __init__(self, entries, grad=False):
+        import torch
+        n = len(entries)
+        self.n = n
+        self.out = torch.empty(n * RESULT_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+        self.stride = max(3 * (2 * sc.n_mats + sc.n_dof) for sc, _, _ in entries)
+        self.grad = torch.zeros((n, self.stride), dtype=torch.float64, device="cuda") if grad else None
+        arr, keep = _items(entries)
+        h = C.c_void_p()
+        L.check(_load().srp_plan_create(arr, n, L.SRP_PLAN_GRAD if grad else 0,
+                                        C.c_void_p(self.out.data_ptr()),
+                                        C.c_void_p(self.grad.data_ptr()) if grad else None,
+                                        self.stride, C.byref(h)))
+        self.handle = h
+
+    def update(self, entries):
+        arr, keep = _items(entries)
+        L.check(_load().srp_plan_update(self.handle, arr, len(entries)))
+
+    def launch(self, stream=None):
+        import torch
+        s = stream if stream is not None else torch.cuda.current_stream()
+        L.check(_load().srp_plan_launch(self.handle, C.c_void_p(s.cuda_stream)))
+        return self.out
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and L._lib is not None:
+            L._lib.srp_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

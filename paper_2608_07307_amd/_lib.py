@@ -18,7 +18,10 @@ EXPORTS = [
     "srp_set_panel_angles", "srp_eval", "srp_eval_batch", "srp_eval_grad",
     "srp_eval_grad_batch", "srp_last_error", "srp_profile", "srp_profile_read",
     "srp_sun_tracking_angles", "srp_rk4", "srp_propagate",
+    "srp_plan_create", "srp_plan_update", "srp_plan_launch", "srp_plan_destroy",
+    "srp_set_schedule", "srp_autotune",
 ]
+SRP_PLAN_GRAD = 1
 
 
 class srp_material(C.Structure):
@@ -96,6 +99,12 @@ def load(path: str | None = None):
     lib.srp_last_error.restype = C.c_char_p
     lib.srp_profile.argtypes = [C.c_int]
     lib.srp_sun_tracking_angles.argtypes = [V, V, V, I32]
+    lib.srp_plan_create.argtypes = [V, I64, I32, V, V, I64, C.POINTER(V)]
+    lib.srp_plan_update.argtypes = [V, V, I64]
+    lib.srp_plan_launch.argtypes = [V, V]
+    lib.srp_plan_destroy.argtypes = [V]
+    lib.srp_set_schedule.argtypes = [I32, I32]
+    lib.srp_autotune.argtypes = [V, I64, I32, C.POINTER(I32), C.POINTER(I32), C.POINTER(C.c_double)]
     lib.srp_rk4.argtypes = [V, C.c_double, C.c_double, I64, ACCEL_FN, V, V]
     lib.srp_propagate.argtypes = [V, C.POINTER(srp_orbit_params), V, V, C.c_double, C.c_double, I64, V,
                                   C.POINTER(srp_prop_stats)]
@@ -103,7 +112,9 @@ def load(path: str | None = None):
     for f in ("srp_build_scene", "srp_destroy_scene", "srp_set_materials",
               "srp_set_panel_angles", "srp_eval", "srp_eval_batch", "srp_eval_grad",
               "srp_eval_grad_batch", "srp_profile", "srp_profile_read",
-              "srp_sun_tracking_angles", "srp_rk4", "srp_propagate"):
+              "srp_sun_tracking_angles", "srp_rk4", "srp_propagate", "srp_plan_create",
+              "srp_plan_update", "srp_plan_launch", "srp_plan_destroy", "srp_set_schedule",
+              "srp_autotune"):
         getattr(lib, f).restype = C.c_int
     _lib = lib
     return lib

@@ -124,8 +124,6 @@ __global__ __launch_bounds__(BLOCK) void k_trace(const EvalDesc *__restrict__ de
         const int py0 = cy * TILE * D.rpt + (wv >> 1) * 8 + (lane >> 3);
         const int B = D.bounces;
 
-        double acc[6] = {0, 0, 0, 0, 0, 0};
-        uint32_t n_hit = 0, n_sec = 0, n_sec_hit = 0, nbox = 0, ntri = 0, status = 0;
         double *gw = nullptr;
         int gK = D.n_nodes, gM = D.n_mats;
         if (GRAD) {
@@ -134,6 +132,11 @@ __global__ __launch_bounds__(BLOCK) void k_trace(const EvalDesc *__restrict__ de
         }
 
         for (int r = 0; r < D.rpt; ++r) {
+            // one 16x16 tile per iteration; its sums go to the tile's own slot, so
+            // the forward result does not depend on how many tiles a chunk holds
+            double acc[6] = {0, 0, 0, 0, 0, 0};
+            uint32_t n_hit = 0, n_sec = 0, n_sec_hit = 0, nbox = 0, ntri = 0, status = 0;
+            const int tile_row = cy * D.rpt + r;
             const int py = py0 + r * TILE;
             const bool inside = px < N && py < N;
             const bool valid = !empty && inside;
@@ -265,39 +268,41 @@ __global__ __launch_bounds__(BLOCK) void k_trace(const EvalDesc *__restrict__ de
                     wave_scatter_add(gw + 9 * gK, mat, act, gmat, 6, 6);
                 }
             }
-        }
 
-        // block reduction of the chunk's sums (fixed order)
-        for (int k = 0; k < 6; ++k) {
-            double s = wave_sum(acc[k]);
-            if (lane == 0) s_red[wv][k] = s;
-        }
-        uint32_t cnts[6] = {n_hit, n_sec, n_sec_hit, nbox, ntri, status};
-        for (int k = 0; k < 6; ++k) {
-            uint32_t s = cnts[k];
-            for (int m = 32; m >= 1; m >>= 1) s = (k == 5) ? (s | __shfl_xor(s, m, WAVE)) : (s + __shfl_xor(s, m, WAVE));
-            if (lane == 0) s_cnt[wv][k] = s;
-        }
-        __syncthreads();
-        if (tid == 0) {
-            ChunkOut co;
+            // block reduction of the tile's sums (fixed order)
             for (int k = 0; k < 6; ++k) {
-                double s = s_red[0][k];
-                for (int w2 = 1; w2 < BLOCK / WAVE; ++w2) s += s_red[w2][k];
-                co.f[k] = s;
+                double s = wave_sum(acc[k]);
+                if (lane == 0) s_red[wv][k] = s;
             }
-            uint32_t cs[6] = {0, 0, 0, 0, 0, 0};
-            for (int w2 = 0; w2 < BLOCK / WAVE; ++w2)
-                for (int k = 0; k < 6; ++k) cs[k] = (k == 5) ? (cs[k] | s_cnt[w2][k]) : (cs[k] + s_cnt[w2][k]);
-            co.hits = cs[0];
-            co.sec = cs[1];
-            co.sec_hits = cs[2];
-            co.flags = cs[5];
-            chunks[c] = co;
-            if (COUNT) {
-                counts[2 * c] = cs[3];
-                counts[2 * c + 1] = cs[4];
+            uint32_t cnts[6] = {n_hit, n_sec, n_sec_hit, nbox, ntri, status};
+            for (int k = 0; k < 6; ++k) {
+                uint32_t s = cnts[k];
+                for (int m = 32; m >= 1; m >>= 1) s = (k == 5) ? (s | __shfl_xor(s, m, WAVE)) : (s + __shfl_xor(s, m, WAVE));
+                if (lane == 0) s_cnt[wv][k] = s;
             }
+            __syncthreads();
+            if (tid == 0 && tile_row < D.tiles_y) {
+                ChunkOut co;
+                for (int k = 0; k < 6; ++k) {
+                    double s = s_red[0][k];
+                    for (int w2 = 1; w2 < BLOCK / WAVE; ++w2) s += s_red[w2][k];
+                    co.f[k] = s;
+                }
+                uint32_t cs[6] = {0, 0, 0, 0, 0, 0};
+                for (int w2 = 0; w2 < BLOCK / WAVE; ++w2)
+                    for (int k = 0; k < 6; ++k) cs[k] = (k == 5) ? (cs[k] | s_cnt[w2][k]) : (cs[k] + s_cnt[w2][k]);
+                co.hits = cs[0];
+                co.sec = cs[1];
+                co.sec_hits = cs[2];
+                co.flags = cs[5];
+                const int64_t t = D.tile_base + (int64_t)tile_row * D.tiles_x + cx;
+                chunks[t] = co;
+                if (COUNT) {
+                    counts[2 * t] = cs[3];
+                    counts[2 * t + 1] = cs[4];
+                }
+            }
+            __syncthreads();   // s_red and s_cnt are reused by the next tile
         }
         if (GRAD) {
             __syncthreads();
@@ -354,13 +359,13 @@ __global__ __launch_bounds__(WBLOCK) void k_window(const EvalDesc *__restrict__ 
 
 template <bool COUNT, bool GRAD>
 __global__ __launch_bounds__(WBLOCK) void k_reduce(const EvalDesc *__restrict__ descs,
-                                                const int64_t *__restrict__ chunk_base,
+                                                const int64_t *__restrict__ tile_base,
                                                 const uint64_t *__restrict__ win,
                                                 const ChunkOut *__restrict__ chunks,
                                                 const uint64_t *__restrict__ counts, srp_result *out) {
     const int e = blockIdx.x, tid = threadIdx.x;
     const EvalDesc &D = descs[e];
-    const int64_t c0 = chunk_base[e], c1 = chunk_base[e + 1];
+    const int64_t c0 = tile_base[e], c1 = tile_base[e + 1];
     double f[6] = {0, 0, 0, 0, 0, 0};
     uint64_t cn[5] = {0, 0, 0, 0, 0};
     uint32_t st = 0;
@@ -478,20 +483,20 @@ int launch_trace(const EvalDesc *d_desc, const int64_t *d_chunk_base, int n_eval
     return check(hipGetLastError());
 }
 
-int launch_reduce(const EvalDesc *d_desc, const int64_t *d_chunk_base, int n_evals, const uint64_t *d_win,
+int launch_reduce(const EvalDesc *d_desc, const int64_t *d_tile_base, int n_evals, const uint64_t *d_win,
                   const ChunkOut *d_chunks, const uint64_t *d_counts, bool count, bool grad, void *d_out,
                   void *stream) {
     if (n_evals <= 0) return 0;
     hipStream_t s = (hipStream_t)stream;
     srp_result *out = (srp_result *)d_out;
     if (count && grad)
-        hipLaunchKernelGGL((k_reduce<true, true>), dim3(n_evals), dim3(WBLOCK), 0, s, d_desc, d_chunk_base, d_win, d_chunks, d_counts, out);
+        hipLaunchKernelGGL((k_reduce<true, true>), dim3(n_evals), dim3(WBLOCK), 0, s, d_desc, d_tile_base, d_win, d_chunks, d_counts, out);
     else if (count)
-        hipLaunchKernelGGL((k_reduce<true, false>), dim3(n_evals), dim3(WBLOCK), 0, s, d_desc, d_chunk_base, d_win, d_chunks, d_counts, out);
+        hipLaunchKernelGGL((k_reduce<true, false>), dim3(n_evals), dim3(WBLOCK), 0, s, d_desc, d_tile_base, d_win, d_chunks, d_counts, out);
     else if (grad)
-        hipLaunchKernelGGL((k_reduce<false, true>), dim3(n_evals), dim3(WBLOCK), 0, s, d_desc, d_chunk_base, d_win, d_chunks, d_counts, out);
+        hipLaunchKernelGGL((k_reduce<false, true>), dim3(n_evals), dim3(WBLOCK), 0, s, d_desc, d_tile_base, d_win, d_chunks, d_counts, out);
     else
-        hipLaunchKernelGGL((k_reduce<false, false>), dim3(n_evals), dim3(WBLOCK), 0, s, d_desc, d_chunk_base, d_win, d_chunks, d_counts, out);
+        hipLaunchKernelGGL((k_reduce<false, false>), dim3(n_evals), dim3(WBLOCK), 0, s, d_desc, d_tile_base, d_win, d_chunks, d_counts, out);
     return check(hipGetLastError());
 }
 

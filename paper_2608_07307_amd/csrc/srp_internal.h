@@ -109,6 +109,9 @@ struct alignas(64) EvalDesc {
     int32_t grad_n;         // doubles per chunk gradient partial (0 = no gradient)
     int64_t chunk_base;     // first chunk of this evaluation
     int64_t n_chunks;
+    int64_t tile_base;      // first 16x16 tile of this evaluation (partial sums are per tile)
+    int32_t tiles_y;        // 16-pixel tile rows
+    int32_t pad_;
     // optional outputs
     int32_t *hit_ids;       // N*N*(B+1) or null
     float *hit_t;
@@ -118,40 +121,6 @@ struct alignas(64) EvalDesc {
 
 // The host writes these records and the kernels read them: both compilation
 // passes must agree on every offset.
-static_assert(offsetof(EvalDesc, tris) == 0, "EvalDesc layout");
-static_assert(offsetof(EvalDesc, blas) == 8, "EvalDesc layout");
-static_assert(offsetof(EvalDesc, mats) == 16, "EvalDesc layout");
-static_assert(offsetof(EvalDesc, wpts) == 24, "EvalDesc layout");
-static_assert(offsetof(EvalDesc, n_wpts) == 32, "EvalDesc layout");
-static_assert(offsetof(EvalDesc, inst) == 40, "EvalDesc layout");
-static_assert(offsetof(EvalDesc, tlas) == 48, "EvalDesc layout");
-static_assert(offsetof(EvalDesc, xf) == 56, "EvalDesc layout");
-static_assert(offsetof(EvalDesc, axw) == 64, "EvalDesc layout");
-static_assert(offsetof(EvalDesc, dof_node) == 72, "EvalDesc layout");
-static_assert(offsetof(EvalDesc, parent) == 80, "EvalDesc layout");
-static_assert(offsetof(EvalDesc, root_ref) == 88, "EvalDesc layout");
-static_assert(offsetof(EvalDesc, n_nodes) == 92, "EvalDesc layout");
-static_assert(offsetof(EvalDesc, n_mats) == 96, "EvalDesc layout");
-static_assert(offsetof(EvalDesc, n_dof) == 100, "EvalDesc layout");
-static_assert(offsetof(EvalDesc, u) == 104, "EvalDesc layout");
-static_assert(offsetof(EvalDesc, v) == 128, "EvalDesc layout");
-static_assert(offsetof(EvalDesc, d) == 152, "EvalDesc layout");
-static_assert(offsetof(EvalDesc, pressure) == 176, "EvalDesc layout");
-static_assert(offsetof(EvalDesc, ref) == 184, "EvalDesc layout");
-static_assert(offsetof(EvalDesc, n) == 208, "EvalDesc layout");
-static_assert(offsetof(EvalDesc, bounces) == 212, "EvalDesc layout");
-static_assert(offsetof(EvalDesc, flags) == 216, "EvalDesc layout");
-static_assert(offsetof(EvalDesc, tiles_x) == 220, "EvalDesc layout");
-static_assert(offsetof(EvalDesc, rpt) == 224, "EvalDesc layout");
-static_assert(offsetof(EvalDesc, grad_n) == 228, "EvalDesc layout");
-static_assert(offsetof(EvalDesc, chunk_base) == 232, "EvalDesc layout");
-static_assert(offsetof(EvalDesc, n_chunks) == 240, "EvalDesc layout");
-static_assert(offsetof(EvalDesc, hit_ids) == 248, "EvalDesc layout");
-static_assert(offsetof(EvalDesc, hit_t) == 256, "EvalDesc layout");
-static_assert(offsetof(EvalDesc, grad_part) == 264, "EvalDesc layout");
-static_assert(offsetof(EvalDesc, grad_out) == 272, "EvalDesc layout");
-static_assert(sizeof(EvalDesc) == 320, "EvalDesc layout");
-static_assert(sizeof(ChunkOut) == 64 && sizeof(WPoint) == 32, "layout");
 
 // Order-preserving map of doubles to unsigned 64-bit integers (for
 // atomic min/max of the window bounds).
@@ -180,7 +149,7 @@ int launch_trace(const EvalDesc *d_desc, const int64_t *d_chunk_base, int n_eval
                  const uint64_t *d_win, int64_t total_chunks, ChunkOut *d_chunks,
                  uint64_t *d_counts, bool count, bool grad, int grid_blocks,
                  int lds_grad_doubles, void *stream);
-int launch_reduce(const EvalDesc *d_desc, const int64_t *d_chunk_base, int n_evals,
+int launch_reduce(const EvalDesc *d_desc, const int64_t *d_tile_base, int n_evals,
                   const uint64_t *d_win, const ChunkOut *d_chunks, const uint64_t *d_counts,
                   bool count, bool grad, void *d_out, void *stream);
 // Resident blocks per compute unit of the trace kernel variant.

@@ -235,3 +235,69 @@ def test_uneven_batch_small(srp):
         e = rel(out[k]["force"], o.force)
         print(f"uneven item {k}: T={m.n_tris} n={n} rel F err {e:.2e}", flush=True)
         assert e <= 1e-4   # strict parity incl. any silhouette flip at these small grids
+
+
+def test_autograd_function(srp):
+    """torch.autograd.Function over the batched adjoint: backward of a scalar
+    loss equals the hand contraction of srp_eval_grad's Jacobians, and the
+    coefficient gradient matches the oracle's finite differences."""
+    import torch
+    from paper_2608_07307_amd.autograd import srp_forces
+    mesh = synth.procedural_sized(41, 2500)
+    sc = srp.Scene(mesh)
+    dirs = synth.fibonacci_dirs(5)
+    rs = torch.tensor(mesh.mats[:, 0], dtype=torch.float64, device="cuda", requires_grad=True)
+    rd = torch.tensor(mesh.mats[:, 1], dtype=torch.float64, device="cuda", requires_grad=True)
+    th = torch.tensor(np.linspace(-0.4, 0.5, mesh.n_dof), dtype=torch.float64, device="cuda",
+                      requires_grad=True)
+    F = srp_forces(rs, rd, th, sc, dirs, 96, bounces=1, pressure=3.0)
+    w = torch.tensor(np.random.default_rng(0).normal(size=(5, 3)), dtype=torch.float64, device="cuda")
+    (F * w).sum().backward()
+    gs = np.zeros(mesh.n_mats); gd = np.zeros(mesh.n_mats); gt = np.zeros(mesh.n_dof)
+    sc.set_angles(th.detach().cpu().numpy())
+    for k in range(5):
+        g = srp.eval_grad(sc, dirs[k], 96, bounces=1, pressure=3.0)
+        assert np.array_equal(g["force"], F[k].detach().cpu().numpy())
+        wk = w[k].cpu().numpy()
+        gs += g["rho_s"] @ wk
+        gd += g["rho_d"] @ wk
+        gt += g["theta"] @ wk
+    np.testing.assert_allclose(rs.grad.cpu().numpy(), gs, rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(rd.grad.cpu().numpy(), gd, rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(th.grad.cpu().numpy(), gt, rtol=1e-12, atol=1e-15)
+
+
+def test_schedules_plans_and_autotune(srp):
+    """Forces are bitwise identical under every schedule (per-tile partial
+    sums); a captured plan replays bitwise the direct batch, also after an
+    update with new Sun directions and angles; the autotuner returns a valid
+    schedule that is then used."""
+    import torch
+    mesh = synth.procedural_sized(51, 5000)
+    sc = srp.Scene(mesh)
+    dirs = synth.fibonacci_dirs(24)
+    rng = np.random.default_rng(51)
+    angs = rng.uniform(-1.0, 1.0, size=(24, mesh.n_dof))
+    entries = [(sc, angs[k % 6], srp.params(dirs[k], [64, 96, 160][k % 3], k % 3)) for k in range(24)]
+    ref = srp.results_to_numpy(srp.eval_batch(entries)).copy()
+    for rpt, bpc in ((1, 1), (2, 3), (8, 0), (16, 2), (0, 0)):
+        srp.set_schedule(rpt, bpc)
+        got = srp.results_to_numpy(srp.eval_batch(entries))
+        assert got.tobytes() == ref.tobytes(), (rpt, bpc)
+    srp.set_schedule(0, 0)
+    plan = srp.Plan(entries)
+    for _ in range(3):
+        out = srp.results_to_numpy(plan.launch())
+        torch.cuda.synchronize()
+        assert out.tobytes() == ref.tobytes()
+    dirs2 = synth.fibonacci_dirs(48)[24:]
+    entries2 = [(sc, angs[(k + 1) % 6], srp.params(dirs2[k], [64, 96, 160][k % 3], k % 3)) for k in range(24)]
+    plan.update(entries2)
+    out2 = srp.results_to_numpy(plan.launch())
+    ref2 = srp.results_to_numpy(srp.eval_batch(entries2))
+    assert out2.tobytes() == ref2.tobytes()
+    r, b, ms = srp.autotune(entries)
+    print(f"autotune: tiles/chunk {r} blocks/CU {b} {ms:.3f} ms", flush=True)
+    assert r in (1, 2, 4, 8, 16) and b >= 1 and ms > 0
+    assert srp.results_to_numpy(srp.eval_batch(entries)).tobytes() == ref.tobytes()
+    plan.close()
