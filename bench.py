@@ -83,6 +83,12 @@ def main():
     log(f"counts per batch: box {n_box:.3e} tri {n_tri:.3e} rays {rays_total:.3e} "
         f"(tests/ray {(n_box + n_tri) / rays_total:.1f})")
 
+    # schedule: the autotuner picks tiles per chunk and blocks per CU (untimed)
+    tune = srp.autotune(entries, grad=True)
+    log(f"autotune (forward+adjoint): tiles/chunk {tune[0]}, blocks/CU {tune[1]}, {tune[2]:.3f} ms")
+    tune_fwd = srp.autotune(entries, grad=False)
+    log(f"autotune (forward): tiles/chunk {tune_fwd[0]}, blocks/CU {tune_fwd[1]}, {tune_fwd[2]:.3f} ms")
+
     # headline: batched forward + adjoint
     for _ in range(args.warmup):
         srp.eval_grad_batch(entries, out, grad, stream)
@@ -175,6 +181,7 @@ def main():
                         f"6 materials), {N}x{N} rays, {B} bounces, batch of {E} attitudes, "
                         f"forward + fixed-visibility adjoint per step",
             "batch": E, "n": N, "bounces": B, "triangles": mesh.n_tris,
+            "schedule": {"tiles_per_chunk": tune[0], "blocks_per_cu": tune[1]},
         },
         "grays_per_s": round(rays_total * args.steps / (dt * args.steps) / 1e9, 4),
         "grays_per_s_primary": round(rays_primary / dt / 1e9, 4),

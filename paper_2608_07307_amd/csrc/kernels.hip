@@ -70,7 +70,7 @@ __device__ __forceinline__ void m3_zero(float *M) {
 }
 
 template <bool COUNT, bool GRAD>
-__global__ __launch_bounds__(BLOCK) void k_trace(const EvalDesc *__restrict__ descs,
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(GRAD ? 3 : 4))) void k_trace(const EvalDesc *__restrict__ descs,
                                                  const int64_t *__restrict__ chunk_base, int n_evals,
                                                  const uint64_t *__restrict__ win, int grid_blocks,
                                                  int64_t total_chunks, ChunkOut *__restrict__ chunks,
@@ -123,6 +123,7 @@ __global__ __launch_bounds__(BLOCK) void k_trace(const EvalDesc *__restrict__ de
         const int px = cx * TILE + (wv & 1) * 8 + (lane & 7);
         const int py0 = cy * TILE * D.rpt + (wv >> 1) * 8 + (lane >> 3);
         const int B = D.bounces;
+        const TraceCtx TC = trace_ctx(D);
 
         double *gw = nullptr;
         int gK = D.n_nodes, gM = D.n_mats;
@@ -160,7 +161,7 @@ __global__ __launch_bounds__(BLOCK) void k_trace(const EvalDesc *__restrict__ de
                 const int64_t pix = (int64_t)py * N + px;
                 for (int gen = 0; gen <= B; ++gen) {
                     Hit h;
-                    if (!trace_closest<COUNT>(D, o, d, tmin, excl, stack, BLOCK, h, nbox, ntri)) {
+                    if (!trace_closest<COUNT>(TC, o, d, tmin, excl, stack, BLOCK, h, nbox, ntri)) {
                         status |= SRP_STATUS_STACK;
                         break;
                     }
@@ -170,8 +171,8 @@ __global__ __launch_bounds__(BLOCK) void k_trace(const EvalDesc *__restrict__ de
                     }
                     if (h.tri < 0) break;
                     if (gen == 0) n_hit++; else n_sec_hit++;
-                    const TriRec &T = D.tris[h.tri];
-                    const Inst &I = D.inst[h.inst];
+                    const TriRec SRP_GLOBAL &T = TC.tris[h.tri];
+                    const Inst SRP_GLOBAL &I = TC.inst[h.inst];
                     float e1[3] = {T.v1[0] - T.v0[0], T.v1[1] - T.v0[1], T.v1[2] - T.v0[2]};
                     float e2[3] = {T.v2[0] - T.v0[0], T.v2[1] - T.v0[1], T.v2[2] - T.v0[2]};
                     float nl[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],

@@ -113,57 +113,146 @@ struct Hit {
 // looping.
 constexpr uint32_t MAX_VISITS = 1u << 22;
 
+// Device loads through these pointers are global-memory loads (the pointers
+// come from a descriptor in memory, which would otherwise make them generic).
+#if defined(__HIP_DEVICE_COMPILE__)
+#define SRP_GLOBAL __attribute__((address_space(1)))
+#else
+#define SRP_GLOBAL
+#endif
+
+// What one traversal needs from an evaluation's descriptor, held in registers.
+struct TraceCtx {
+    const BNode SRP_GLOBAL *blas;
+    const BNode SRP_GLOBAL *tlas;
+    const TriRec SRP_GLOBAL *tris;
+    const Inst SRP_GLOBAL *inst;
+    uint32_t root;
+};
+
+SRP_HD inline TraceCtx trace_ctx(const EvalDesc &D) {
+    TraceCtx c;
+    c.blas = (const BNode SRP_GLOBAL *)D.blas;
+    c.tlas = (const BNode SRP_GLOBAL *)D.tlas;
+    c.tris = (const TriRec SRP_GLOBAL *)D.tris;
+    c.inst = (const Inst SRP_GLOBAL *)D.inst;
+    c.root = D.root_ref;
+    return c;
+}
+
+struct NodeData {
+    float4 a, b, c;
+    uint4 r;
+};
+
+SRP_HD inline NodeData load_node(const BNode SRP_GLOBAL *n) {
+    const float4 SRP_GLOBAL *q = (const float4 SRP_GLOBAL *)n;
+    NodeData v;
+    v.a = q[0];
+    v.b = q[1];
+    v.c = q[2];
+    v.r = ((const uint4 SRP_GLOBAL *)n)[3];
+    return v;
+}
+
+// Closest hit along o + t d, t > tmin, skipping triangle `exclude_id`.
+// The top level is traversed in the world frame; at a top-level leaf the
+// instance's bottom level is traversed in its own (rest-pose) frame until the
+// stack returns to the depth it had on entry, then the top level resumes.
+// Bottom-level traversal descends internal nodes before testing a leaf, so the
+// lanes of a wave test leaves together.  Returns false only when the stack or
+// the visit bound is exceeded (corrupted data).
 template <bool COUNT>
-SRP_HD inline bool trace_closest(const EvalDesc &D, const float o[3], const float d[3], float tmin,
+SRP_HD inline bool trace_closest(const TraceCtx &C, const float o[3], const float d[3], float tmin,
                                  int32_t exclude_id, uint32_t *stack, int stride, Hit &h, uint32_t &nbox,
                                  uint32_t &ntri, uint32_t *steps = nullptr) {
     h.t = T_INF;
     h.tri = -1;
     h.inst = -1;
     h.id = 0x7FFFFFFF;
-    uint32_t ref = D.root_ref;
-    if (ref == REF_NONE) return true;
-    // world frame (top level)
+    if (C.root == REF_NONE) return true;
     const float wix = safe_inv(d[0]), wiy = safe_inv(d[1]), wiz = safe_inv(d[2]);
     const float woix = o[0] * wix, woiy = o[1] * wiy, woiz = o[2] * wiz;
-    float ix = wix, iy = wiy, iz = wiz, oix = woix, oiy = woiy, oiz = woiz;
-    Frame F;
-    int inst = -1;
+    uint32_t visits = 0;
     int sp = 0;
-    for (uint32_t visit = 0;; ++visit) {
-        if (visit >= MAX_VISITS) return false;
-        if (steps) ++*steps;
-        uint32_t ty = ref_type(ref);
-        if (ty == REF_BLAS_NODE || ty == REF_TLAS_NODE) {
-            const BNode *nb = (ty == REF_TLAS_NODE ? D.tlas : D.blas) + ref_index(ref);
-            const float4 *q = reinterpret_cast<const float4 *>(nb);
-            float4 A = q[0], B = q[1], C = q[2];
-            uint4 R = reinterpret_cast<const uint4 *>(nb)[3];
-            float t0 = box_enter(A.x, A.y, A.z, A.w, B.x, B.y, ix, iy, iz, oix, oiy, oiz, tmin, h.t);
-            float t1 = box_enter(B.z, B.w, C.x, C.y, C.z, C.w, ix, iy, iz, oix, oiy, oiz, tmin, h.t);
+    uint32_t ref = C.root;
+    for (;;) {
+        // ---- top level (world frame): walk to the next instance to enter
+        while (ref_type(ref) == REF_TLAS_NODE) {
+            if (++visits > MAX_VISITS) return false;
+            if (steps) ++*steps;
+            const NodeData N = load_node(C.tlas + ref_index(ref));
+            float t0 = box_enter(N.a.x, N.a.y, N.a.z, N.a.w, N.b.x, N.b.y, wix, wiy, wiz, woix, woiy, woiz, tmin, h.t);
+            float t1 = box_enter(N.b.z, N.b.w, N.c.x, N.c.y, N.c.z, N.c.w, wix, wiy, wiz, woix, woiy, woiz, tmin, h.t);
             if (COUNT) nbox += 2;
             bool h0 = t0 != T_INF, h1 = t1 != T_INF;
             if (h0 && h1) {
-                uint32_t nr = t0 <= t1 ? R.x : R.y, fr = t0 <= t1 ? R.y : R.x;
                 if (sp >= STACK_DEPTH) return false;
-                stack[sp * stride] = fr;
+                stack[sp * stride] = t0 <= t1 ? N.r.y : N.r.x;
                 ++sp;
-                ref = nr;
-                continue;
+                ref = t0 <= t1 ? N.r.x : N.r.y;
+            } else if (h0) {
+                ref = N.r.x;
+            } else if (h1) {
+                ref = N.r.y;
+            } else {
+                if (sp == 0) return true;
+                ref = stack[--sp * stride];
             }
-            if (h0) { ref = R.x; continue; }
-            if (h1) { ref = R.y; continue; }
-        } else if (ty == REF_BLAS_LEAF) {
-            uint32_t p = ref_index(ref);
-            uint32_t first = p >> 3, cnt = (p & 7u) + 1u;
+        }
+        // ---- bottom level of one instance (rest-pose frame; t is preserved)
+        const int inst = (int)ref_index(ref);
+        const Inst SRP_GLOBAL &I = C.inst[inst];
+        float lo[3], ld[3];
+        {
+            float r0 = o[0] - I.t[0], r1 = o[1] - I.t[1], r2 = o[2] - I.t[2];
+            lo[0] = I.R[0] * r0 + I.R[3] * r1 + I.R[6] * r2;
+            lo[1] = I.R[1] * r0 + I.R[4] * r1 + I.R[7] * r2;
+            lo[2] = I.R[2] * r0 + I.R[5] * r1 + I.R[8] * r2;
+            ld[0] = I.R[0] * d[0] + I.R[3] * d[1] + I.R[6] * d[2];
+            ld[1] = I.R[1] * d[0] + I.R[4] * d[1] + I.R[7] * d[2];
+            ld[2] = I.R[2] * d[0] + I.R[5] * d[1] + I.R[8] * d[2];
+        }
+        Frame F;
+        frame_setup(lo, ld, F);
+        const int base = sp;
+        ref = I.root;
+        for (;;) {
+            while (ref_type(ref) == REF_BLAS_NODE) {
+                if (++visits > MAX_VISITS) return false;
+                if (steps) ++*steps;
+                const NodeData N = load_node(C.blas + ref_index(ref));
+                float t0 = box_enter(N.a.x, N.a.y, N.a.z, N.a.w, N.b.x, N.b.y, F.ix, F.iy, F.iz, F.oix, F.oiy, F.oiz, tmin, h.t);
+                float t1 = box_enter(N.b.z, N.b.w, N.c.x, N.c.y, N.c.z, N.c.w, F.ix, F.iy, F.iz, F.oix, F.oiy, F.oiz, tmin, h.t);
+                if (COUNT) nbox += 2;
+                bool h0 = t0 != T_INF, h1 = t1 != T_INF;
+                if (h0 && h1) {
+                    if (sp >= STACK_DEPTH) return false;
+                    stack[sp * stride] = t0 <= t1 ? N.r.y : N.r.x;
+                    ++sp;
+                    ref = t0 <= t1 ? N.r.x : N.r.y;
+                } else if (h0) {
+                    ref = N.r.x;
+                } else if (h1) {
+                    ref = N.r.y;
+                } else {
+                    ref = sp > base ? stack[--sp * stride] : REF_NONE;
+                }
+            }
+            if (ref == REF_NONE) break;
+            // leaf: test its triangles
+            if (++visits > MAX_VISITS) return false;
+            if (steps) ++*steps;
+            const uint32_t p = ref_index(ref);
+            const uint32_t first = p >> 3, cnt = (p & 7u) + 1u;
             for (uint32_t k = 0; k < cnt; ++k) {
-                const float4 *q = reinterpret_cast<const float4 *>(D.tris + first + k);
-                float4 A = q[0], B = q[1], C = q[2];
-                int32_t id = f2i(A.w);
+                const float4 SRP_GLOBAL *q = (const float4 SRP_GLOBAL *)(C.tris + first + k);
+                const float4 A = q[0], B = q[1], Cc = q[2];
+                const int32_t id = f2i(A.w);
                 if (COUNT) ntri++;
                 if (id == exclude_id) continue;
-                float va[3] = {A.x, A.y, A.z}, vb[3] = {B.x, B.y, B.z}, vc[3] = {C.x, C.y, C.z};
-                float t = tri_hit(F, va, vb, vc);
+                const float va[3] = {A.x, A.y, A.z}, vb[3] = {B.x, B.y, B.z}, vc[3] = {Cc.x, Cc.y, Cc.z};
+                const float t = tri_hit(F, va, vb, vc);
                 if (t > tmin && (t < h.t || (t == h.t && id < h.id))) {
                     h.t = t;
                     h.tri = (int32_t)(first + k);
@@ -171,38 +260,12 @@ SRP_HD inline bool trace_closest(const EvalDesc &D, const float o[3], const floa
                     h.id = id;
                 }
             }
-        } else {
-            // top-level leaf: enter the instance (rigid transform; t is preserved)
-            inst = (int)ref_index(ref);
-            const Inst &I = D.inst[inst];
-            float r0 = o[0] - I.t[0], r1 = o[1] - I.t[1], r2 = o[2] - I.t[2];
-            float lo[3], ld[3];
-            lo[0] = I.R[0] * r0 + I.R[3] * r1 + I.R[6] * r2;
-            lo[1] = I.R[1] * r0 + I.R[4] * r1 + I.R[7] * r2;
-            lo[2] = I.R[2] * r0 + I.R[5] * r1 + I.R[8] * r2;
-            ld[0] = I.R[0] * d[0] + I.R[3] * d[1] + I.R[6] * d[2];
-            ld[1] = I.R[1] * d[0] + I.R[4] * d[1] + I.R[7] * d[2];
-            ld[2] = I.R[2] * d[0] + I.R[5] * d[1] + I.R[8] * d[2];
-            frame_setup(lo, ld, F);
-            ix = F.ix; iy = F.iy; iz = F.iz;
-            oix = F.oix; oiy = F.oiy; oiz = F.oiz;
-            if (sp >= STACK_DEPTH) return false;
-            stack[sp * stride] = REF_EXIT;
-            ++sp;
-            ref = I.root;
-            continue;
+            if (sp == base) break;
+            ref = stack[--sp * stride];
         }
-        // pop
-        for (;;) {
-            if (sp == 0) return true;
-            --sp;
-            ref = stack[sp * stride];
-            if (ref != REF_EXIT) break;
-            ix = wix; iy = wiy; iz = wiz;
-            oix = woix; oiy = woiy; oiz = woiz;
-            inst = -1;
-        }
+        // ---- back to the top level
+        if (sp == 0) return true;
+        ref = stack[--sp * stride];
     }
 }
-
 }  // namespace srp
