@@ -942,8 +942,12 @@ int srp_autotune(const srp_batch_item *items, int64_t n_items, int32_t flags, in
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     bool cnt = false;
-    for (int64_t k = 0; k < n_items; ++k) cnt |= (items[k].p.flags & SRP_F_COUNT) != 0;
-    int occ = trace_blocks_per_cu(cnt, grad, MAX_GRAD_SLOTS);
+    int mg = 0;
+    for (int64_t k = 0; k < n_items; ++k) {
+        cnt |= (items[k].p.flags & SRP_F_COUNT) != 0;
+        if (grad && items[k].scene) mg = std::max(mg, 9 * items[k].scene->h.n_nodes + 6 * items[k].scene->h.n_mats);
+    }
+    int occ = trace_blocks_per_cu(cnt, grad, mg);
     Schedule best;
     double best_t = INFINITY;
     const int rpts[] = {1, 2, 4, 8, 16};
