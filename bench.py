@@ -43,6 +43,9 @@ def main():
     ap.add_argument("--bounces", type=int, default=2)
     ap.add_argument("--plain", type=int, default=16, help="evaluations timed on the plain path")
     ap.add_argument("--cpu-samples", type=int, default=2, help="batch items the oracle times (0: skip)")
+    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (profiling runs)")
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="also run a device copy of this many MiB (calibrates memory counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this SRP path has no multi-GPU mode "
@@ -83,11 +86,21 @@ def main():
     log(f"counts per batch: box {n_box:.3e} tri {n_tri:.3e} rays {rays_total:.3e} "
         f"(tests/ray {(n_box + n_tri) / rays_total:.1f})")
 
+    if args.copy_mb:
+        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE readings calibrate the counters
+        src = torch.ones(args.copy_mb * (1 << 20) // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy probe: {args.copy_mb} MiB read + {args.copy_mb} MiB written")
+
     # schedule: the autotuner picks tiles per chunk and blocks per CU (untimed)
-    tune = srp.autotune(entries, grad=True)
-    log(f"autotune (forward+adjoint): tiles/chunk {tune[0]}, blocks/CU {tune[1]}, {tune[2]:.3f} ms")
-    tune_fwd = srp.autotune(entries, grad=False)
-    log(f"autotune (forward): tiles/chunk {tune_fwd[0]}, blocks/CU {tune_fwd[1]}, {tune_fwd[2]:.3f} ms")
+    tune = (0, 0, 0.0)
+    if not args.no_tune:
+        tune = srp.autotune(entries, grad=True)
+        log(f"autotune (forward+adjoint): tiles/chunk {tune[0]}, blocks/CU {tune[1]}, {tune[2]:.3f} ms")
+        tune_fwd = srp.autotune(entries, grad=False)
+        log(f"autotune (forward): tiles/chunk {tune_fwd[0]}, blocks/CU {tune_fwd[1]}, {tune_fwd[2]:.3f} ms")
 
     # headline: batched forward + adjoint
     for _ in range(args.warmup):
