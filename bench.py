@@ -90,7 +90,7 @@ def main():
         # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE readings calibrate the counters
         src = torch.ones(args.copy_mb * (1 << 20) // 4, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
-        dst.copy_(src)
+        torch.mul(src, 2.0, out=dst)          # one elementwise kernel: reads and writes copy_mb MiB
         torch.cuda.synchronize()
         log(f"copy probe: {args.copy_mb} MiB read + {args.copy_mb} MiB written")
 
@@ -98,9 +98,9 @@ def main():
     tune = (0, 0, 0.0)
     if not args.no_tune:
         tune = srp.autotune(entries, grad=True)
-        log(f"autotune (forward+adjoint): tiles/chunk {tune[0]}, blocks/CU {tune[1]}, {tune[2]:.3f} ms")
+        log(f"autotune (forward+adjoint): patches/chunk {tune[0]}, blocks/CU {tune[1]}, {tune[2]:.3f} ms")
         tune_fwd = srp.autotune(entries, grad=False)
-        log(f"autotune (forward): tiles/chunk {tune_fwd[0]}, blocks/CU {tune_fwd[1]}, {tune_fwd[2]:.3f} ms")
+        log(f"autotune (forward): patches/chunk {tune_fwd[0]}, blocks/CU {tune_fwd[1]}, {tune_fwd[2]:.3f} ms")
 
     # headline: batched forward + adjoint
     for _ in range(args.warmup):
@@ -194,7 +194,7 @@ def main():
                         f"6 materials), {N}x{N} rays, {B} bounces, batch of {E} attitudes, "
                         f"forward + fixed-visibility adjoint per step",
             "batch": E, "n": N, "bounces": B, "triangles": mesh.n_tris,
-            "schedule": {"tiles_per_chunk": tune[0], "blocks_per_cu": tune[1]},
+            "schedule": {"patches_per_chunk": tune[0], "blocks_per_cu": tune[1]},
         },
         "grays_per_s": round(rays_total * args.steps / (dt * args.steps) / 1e9, 4),
         "grays_per_s_primary": round(rays_primary / dt / 1e9, 4),

@@ -207,19 +207,21 @@ int srp_plan_update(srp_plan *plan, const srp_batch_item *items, int64_t n_items
 int srp_plan_launch(srp_plan *plan, void *hip_stream);   /* stream-ordered; returns once queued */
 int srp_plan_destroy(srp_plan *plan);
 
-/* Launch schedule of batched evaluations: 16x16-pixel tiles per work chunk
- * (rays per thread) and resident blocks per compute unit of the persistent
- * grid; 0 = automatic (autotuned value for the batch's size class if any,
- * else a heuristic).  Forces and torques do not depend on the schedule (every
- * tile keeps its own partial sum); gradients are deterministic per schedule. */
-int srp_set_schedule(int32_t tiles_per_chunk, int32_t blocks_per_cu);
+/* Launch schedule of batched evaluations: 8x8-pixel patches per work chunk
+ * (1..64; a chunk is one wave's work item) and resident blocks per compute
+ * unit of the persistent grid (1..64, capped at the kernel's occupancy);
+ * 0 = automatic (autotuned value for the batch's size class if any, else a
+ * heuristic).  Forces and torques do not depend on the schedule (every patch
+ * keeps its own partial sum); gradients are deterministic per schedule.
+ * Errors: SRP_ERR_ARG (out of range). */
+int srp_set_schedule(int32_t patches_per_chunk, int32_t blocks_per_cu);
 
-/* Times the batch under candidate schedules (tiles per chunk 1..16, full and
- * half occupancy) and keeps the fastest for batches of the same size class
- * (total primary rays to a power of two, bounce count, gradient flag).
- * Outputs the choice and its time (ms); any output pointer may be NULL.
- * Blocks.  Errors as srp_eval_batch. */
-int srp_autotune(const srp_batch_item *items, int64_t n_items, int32_t flags, int32_t *tiles_per_chunk,
+/* Times the batch under candidate schedules (patches per chunk 1..64 in powers
+ * of two, full and half occupancy) and keeps the fastest for batches of the
+ * same size class (total primary rays to a power of two, bounce count,
+ * gradient flag).  Outputs the choice and its time (ms); any output pointer
+ * may be NULL.  Blocks.  Errors as srp_eval_batch. */
+int srp_autotune(const srp_batch_item *items, int64_t n_items, int32_t flags, int32_t *patches_per_chunk,
                  int32_t *blocks_per_cu, double *best_ms);
 
 /* ---- orbit propagation (Sec. 3) and panel sun tracking (Sec. 4.4.2) ---- */

@@ -246,13 +246,13 @@ def propagate(scene: Scene, y0, t0, h, n_steps, mu, mass, p_ref, r_ref, n, bounc
     return traj, dict(n_evals=st.n_evals, srp_seconds=st.srp_seconds)
 
 
-def set_schedule(tiles_per_chunk=0, blocks_per_cu=0):
+def set_schedule(patches_per_chunk=0, blocks_per_cu=0):
     """srp_set_schedule (0 = automatic)."""
-    L.check(_load().srp_set_schedule(int(tiles_per_chunk), int(blocks_per_cu)))
+    L.check(_load().srp_set_schedule(int(patches_per_chunk), int(blocks_per_cu)))
 
 
 def autotune(entries, grad=False):
-    """srp_autotune over a batch; returns (tiles_per_chunk, blocks_per_cu, ms)."""
+    """srp_autotune over a batch; returns (patches_per_chunk, blocks_per_cu, ms)."""
     arr, keep = _items(entries)
     r, b, ms = C.c_int32(), C.c_int32(), C.c_double()
     L.check(_load().srp_autotune(arr, len(entries), L.SRP_PLAN_GRAD if grad else 0, C.byref(r),

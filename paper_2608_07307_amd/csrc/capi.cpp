@@ -192,10 +192,11 @@ struct BatchOut {
     srp_result *h_copy = nullptr;    // optional pinned host copy of the results (graph plans)
 };
 
-// Schedule of a batch launch: 16x16 tiles per chunk (= rays per thread) and
-// resident blocks per compute unit of the persistent grid.  0 = automatic.
+// Schedule of a batch launch: 8x8-pixel patches per chunk (a chunk is one
+// wave's work item) and resident blocks per compute unit of the persistent
+// grid.  0 = automatic.
 struct Schedule {
-    int rpt = 0;
+    int ppc = 0;
     int bpc = 0;
 };
 Schedule g_override;                    // srp_set_schedule
@@ -231,14 +232,14 @@ struct Layout {
     int64_t n = 0;
     bool grad = false, count = false;
     Schedule sch;
-    std::vector<int64_t> chunk_base, tile_base;
+    std::vector<int64_t> chunk_base, patch_base;
     std::vector<int> tiles_x, tiles_y;
     std::vector<int> item_slot;
     std::vector<SlotRec> slots;
     int max_grad_n = 0;
-    int64_t total_chunks = 0, total_tiles = 0, max_wpts = 0;
-    size_t o_desc = 0, o_cbase = 0, o_tbase = 0, o_win = 0, o_slots = 0, stage_bytes = 0;
-    size_t o_tiles = 0, o_counts = 0, o_gpart = 0, dev_bytes = 0;
+    int64_t total_chunks = 0, total_patches = 0, max_wpts = 0;
+    size_t o_desc = 0, o_cbase = 0, o_pbase = 0, o_win = 0, o_slots = 0, stage_bytes = 0;
+    size_t o_patches = 0, o_counts = 0, o_gpart = 0, o_queue = 0, o_spill = 0, dev_bytes = 0;
     std::vector<size_t> gpart_off;
     int grid = 1, wb = 1;
 };
@@ -264,21 +265,22 @@ int check_items(const srp_batch_item *items, int64_t n, bool grad, const BatchOu
     return SRP_OK;
 }
 
-Schedule pick_schedule(const srp_batch_item *items, int64_t n, bool grad, int64_t total_tiles, int occ) {
+Schedule pick_schedule(const srp_batch_item *items, int64_t n, bool grad, int64_t total_patches, int occ) {
     Schedule s = g_override;
-    if (!s.rpt || !s.bpc) {
+    if (!s.ppc || !s.bpc) {
         auto f = g_tuned.find(tune_key(items, n, grad));
         if (f != g_tuned.end()) {
-            if (!s.rpt) s.rpt = f->second.rpt;
+            if (!s.ppc) s.ppc = f->second.ppc;
             if (!s.bpc) s.bpc = f->second.bpc;
         }
     }
     if (!s.bpc) s.bpc = occ;
-    if (!s.rpt) {
-        // largest tiles-per-chunk that still leaves >= 4 chunks per resident block
-        int64_t resident = (int64_t)g_ws.n_cu * s.bpc;
-        s.rpt = 1;
-        while (s.rpt < 8 && total_tiles / (2 * s.rpt) >= 4 * resident) s.rpt *= 2;
+    if (!s.ppc) {
+        // largest patches-per-chunk (up to 4) that still leaves >= 16 chunks per
+        // resident wave: small chunks spread expensive image regions best
+        int64_t resident = (int64_t)g_ws.n_cu * s.bpc * (BLOCK / 64);
+        s.ppc = 1;
+        while (s.ppc < 4 && total_patches / (2 * s.ppc) >= 16 * resident) s.ppc *= 2;
     }
     s.bpc = std::max(1, std::min(s.bpc, occ));
     return s;
@@ -290,7 +292,7 @@ int layout_build(const srp_batch_item *items, int64_t n, bool grad, Schedule for
     L.n = n;
     L.grad = grad;
     L.chunk_base.assign(n + 1, 0);
-    L.tile_base.assign(n + 1, 0);
+    L.patch_base.assign(n + 1, 0);
     L.tiles_x.assign(n, 0);
     L.tiles_y.assign(n, 0);
     for (int64_t k = 0; k < n; ++k) {
@@ -298,21 +300,24 @@ int layout_build(const srp_batch_item *items, int64_t n, bool grad, Schedule for
         L.count |= (it.p.flags & SRP_F_COUNT) != 0;
         L.tiles_x[k] = (it.p.n + TILE - 1) / TILE;
         L.tiles_y[k] = (it.p.n + TILE - 1) / TILE;
-        L.tile_base[k] = L.total_tiles;
-        L.total_tiles += (int64_t)L.tiles_x[k] * L.tiles_y[k];
+        L.patch_base[k] = L.total_patches;
+        L.total_patches += 4 * (int64_t)L.tiles_x[k] * L.tiles_y[k];
         if (grad) L.max_grad_n = std::max(L.max_grad_n, 9 * it.scene->h.n_nodes + 6 * it.scene->h.n_mats);
         L.max_wpts = std::max<int64_t>(L.max_wpts, (int64_t)it.scene->h.wpts.size());
     }
-    L.tile_base[n] = L.total_tiles;
+    L.patch_base[n] = L.total_patches;
     int occ = trace_blocks_per_cu(L.count, grad, L.max_grad_n);
-    L.sch = (force.rpt && force.bpc) ? force : pick_schedule(items, n, grad, L.total_tiles, occ);
-    if (force.rpt) L.sch.rpt = force.rpt;
+    L.sch = (force.ppc && force.bpc) ? force : pick_schedule(items, n, grad, L.total_patches, occ);
+    if (force.ppc) L.sch.ppc = force.ppc;
     if (force.bpc) L.sch.bpc = std::min(force.bpc, occ);
     for (int64_t k = 0; k < n; ++k) {
         L.chunk_base[k] = L.total_chunks;
-        L.total_chunks += (int64_t)L.tiles_x[k] * ((L.tiles_y[k] + L.sch.rpt - 1) / L.sch.rpt);
+        L.total_chunks += (L.patch_base[k + 1] - L.patch_base[k] + L.sch.ppc - 1) / L.sch.ppc;
     }
     L.chunk_base[n] = L.total_chunks;
+    // the work counters are 32-bit and overshoot their range by at most one per wave
+    if (L.total_chunks > ((int64_t)1 << 31))
+        return fail(SRP_ERR_ARG, "batch too large: more than 2^31 chunks (split it or raise patches per chunk)");
 
     // articulation slots: the scene's current slot, or one per distinct angle vector
     std::map<std::pair<const srp_scene *, std::vector<double>>, int> slot_of;
@@ -334,19 +339,19 @@ int layout_build(const srp_batch_item *items, int64_t n, bool grad, Schedule for
         slot_of.emplace(key, L.item_slot[k]);
     }
 
-    // staging (uploaded every launch): descs | chunk_base | tile_base | win | slots
+    // staging (uploaded every launch): descs | chunk_base | patch_base | win | slots
     L.o_desc = 0;
     L.o_cbase = align_up(sizeof(EvalDesc) * n);
-    L.o_tbase = align_up(L.o_cbase + sizeof(int64_t) * (n + 1));
-    L.o_win = align_up(L.o_tbase + sizeof(int64_t) * (n + 1));
+    L.o_pbase = align_up(L.o_cbase + sizeof(int64_t) * (n + 1));
+    L.o_win = align_up(L.o_pbase + sizeof(int64_t) * (n + 1));
     L.o_slots = align_up(L.o_win + sizeof(uint64_t) * WIN_STRIDE * n);
     size_t off = L.o_slots;
     for (auto &s : L.slots) { s.off = off; off = align_up(off + s.L.bytes); }
     L.stage_bytes = off;
-    // device-only: tile partials | counts | gradient partials (per chunk)
-    L.o_tiles = align_up(L.stage_bytes);
-    L.o_counts = align_up(L.o_tiles + sizeof(ChunkOut) * L.total_tiles);
-    L.o_gpart = align_up(L.o_counts + (L.count ? sizeof(uint64_t) * 2 * L.total_tiles : 0));
+    // device-only: patch partials | counts | gradient partials (per chunk)
+    L.o_patches = align_up(L.stage_bytes);
+    L.o_counts = align_up(L.o_patches + sizeof(PatchOut) * L.total_patches);
+    L.o_gpart = align_up(L.o_counts + (L.count ? sizeof(uint64_t) * 2 * L.total_patches : 0));
     L.gpart_off.assign(n, 0);
     size_t goff = L.o_gpart;
     if (grad)
@@ -355,9 +360,15 @@ int layout_build(const srp_batch_item *items, int64_t n, bool grad, Schedule for
             int gn = 9 * items[k].scene->h.n_nodes + 6 * items[k].scene->h.n_mats;
             goff = align_up(goff + sizeof(double) * gn * (L.chunk_base[k + 1] - L.chunk_base[k]));
         }
-    L.dev_bytes = align_up(goff);
+    // persistent grid: one chunk per wave at a time, at most bpc resident blocks per CU
+    const int64_t waves = BLOCK / 64;
+    L.grid = (int)std::max<int64_t>(1, std::min<int64_t>((L.total_chunks + waves - 1) / waves,
+                                                         (int64_t)g_ws.n_cu * L.sch.bpc));
+    // the work counters, then the traversal stacks' spill area (per thread of the grid)
+    L.o_queue = align_up(goff);
+    L.o_spill = align_up(L.o_queue + sizeof(uint32_t) * N_QUEUES * QUEUE_STRIDE);
+    L.dev_bytes = align_up(L.o_spill + sizeof(uint32_t) * STACK_SPILL * (size_t)BLOCK * L.grid);
     L.wb = (int)std::min<int64_t>(64, std::max<int64_t>(1, (L.max_wpts + 2047) / 2048));
-    L.grid = (int)std::max<int64_t>(1, std::min<int64_t>(L.total_chunks, (int64_t)g_ws.n_cu * L.sch.bpc));
     return SRP_OK;
 }
 
@@ -366,7 +377,7 @@ void staging_fill(const Layout &L, const srp_batch_item *items, const BatchOut &
     const int64_t n = L.n;
     EvalDesc *desc = reinterpret_cast<EvalDesc *>(H + L.o_desc);
     std::memcpy(H + L.o_cbase, L.chunk_base.data(), sizeof(int64_t) * (n + 1));
-    std::memcpy(H + L.o_tbase, L.tile_base.data(), sizeof(int64_t) * (n + 1));
+    std::memcpy(H + L.o_pbase, L.patch_base.data(), sizeof(int64_t) * (n + 1));
     uint64_t *win = reinterpret_cast<uint64_t *>(H + L.o_win);
     for (int64_t k = 0; k < WIN_STRIDE * n; ++k) win[k] = enc_f64(INFINITY);
     for (auto &s : L.slots) slot_pack(s.s, s.L, H + s.off);
@@ -411,10 +422,11 @@ void staging_fill(const Layout &L, const srp_batch_item *items, const BatchOut &
         D.flags = it.p.flags;
         D.tiles_x = L.tiles_x[k];
         D.tiles_y = L.tiles_y[k];
-        D.rpt = L.sch.rpt;
+        D.ppc = L.sch.ppc;
         D.chunk_base = L.chunk_base[k];
         D.n_chunks = L.chunk_base[k + 1] - L.chunk_base[k];
-        D.tile_base = L.tile_base[k];
+        D.patch_base = L.patch_base[k];
+        D.n_patches = L.patch_base[k + 1] - L.patch_base[k];
         D.grad_n = L.grad ? 9 * sc->h.n_nodes + 6 * sc->h.n_mats : 0;
         D.grad_part = L.grad ? reinterpret_cast<double *>(Dv + L.gpart_off[k]) : nullptr;
         D.grad_out = (L.grad && bo.d_grad) ? bo.d_grad + k * bo.grad_stride : nullptr;
@@ -429,11 +441,13 @@ int enqueue(const Layout &L, char *Dv, const char *H, size_t copy_bytes, const B
     HIPCHK(hipMemcpyAsync(Dv, H, copy_bytes, hipMemcpyHostToDevice, stream));
     const EvalDesc *d_desc = reinterpret_cast<const EvalDesc *>(Dv + L.o_desc);
     const int64_t *d_cbase = reinterpret_cast<const int64_t *>(Dv + L.o_cbase);
-    const int64_t *d_tbase = reinterpret_cast<const int64_t *>(Dv + L.o_tbase);
+    const int64_t *d_pbase = reinterpret_cast<const int64_t *>(Dv + L.o_pbase);
     uint64_t *d_win = reinterpret_cast<uint64_t *>(Dv + L.o_win);
-    ChunkOut *d_tiles = reinterpret_cast<ChunkOut *>(Dv + L.o_tiles);
+    PatchOut *d_patches = reinterpret_cast<PatchOut *>(Dv + L.o_patches);
     uint64_t *d_counts = L.count ? reinterpret_cast<uint64_t *>(Dv + L.o_counts) : nullptr;
-    int e = launch_window(d_desc, (int)L.n, L.wb, d_win, stream);
+    uint32_t *d_queue = reinterpret_cast<uint32_t *>(Dv + L.o_queue);
+    uint32_t *d_spill = reinterpret_cast<uint32_t *>(Dv + L.o_spill);
+    int e = launch_window(d_desc, (int)L.n, L.wb, d_win, d_queue, stream);
     if (e) return fail(SRP_ERR_DEVICE, std::string("window kernel: ") + hipGetErrorString((hipError_t)e));
     std::pair<hipEvent_t, hipEvent_t> ev{};
     if (profile) {
@@ -441,14 +455,14 @@ int enqueue(const Layout &L, char *Dv, const char *H, size_t copy_bytes, const B
         if (rc) return rc;
         HIPCHK(hipEventRecord(ev.first, stream));
     }
-    e = launch_trace(d_desc, d_cbase, (int)L.n, d_win, L.total_chunks, d_tiles, d_counts, L.count, L.grad, L.grid,
-                     L.max_grad_n, stream);
+    e = launch_trace(d_desc, d_cbase, (int)L.n, d_win, L.total_chunks, d_queue, d_spill, d_patches, d_counts, L.count,
+                     L.grad, L.grid, L.max_grad_n, stream);
     if (e) return fail(SRP_ERR_DEVICE, std::string("trace kernel: ") + hipGetErrorString((hipError_t)e));
     if (profile) {
         HIPCHK(hipEventRecord(ev.second, stream));
         g_prof.pairs.push_back(ev);
     }
-    e = launch_reduce(d_desc, d_tbase, (int)L.n, d_win, d_tiles, d_counts, L.count, L.grad, bo.d_out, stream);
+    e = launch_reduce(d_desc, d_pbase, (int)L.n, d_win, d_patches, d_counts, L.count, L.grad, bo.d_out, stream);
     if (e) return fail(SRP_ERR_DEVICE, std::string("reduce kernel: ") + hipGetErrorString((hipError_t)e));
     if (bo.h_copy) HIPCHK(hipMemcpyAsync(bo.h_copy, bo.d_out, sizeof(srp_result) * L.n, hipMemcpyDeviceToHost, stream));
     return SRP_OK;
@@ -556,7 +570,8 @@ int plan_refill(PlanImpl *P, const srp_batch_item *items, int64_t n, bool *compa
     const Layout &L = P->L;
     if (L2.n != L.n || L2.stage_bytes != L.stage_bytes || L2.dev_bytes > L.dev_bytes || L2.grid != L.grid ||
         L2.wb != L.wb || L2.count != L.count || L2.max_grad_n != L.max_grad_n || L2.chunk_base != L.chunk_base ||
-        L2.tile_base != L.tile_base || L2.o_tiles != L.o_tiles || L2.o_counts != L.o_counts)
+        L2.patch_base != L.patch_base || L2.o_patches != L.o_patches || L2.o_counts != L.o_counts ||
+        L2.o_queue != L.o_queue || L2.o_spill != L.o_spill)
         return SRP_OK;
     if (P->pending) HIPCHK(hipEventSynchronize(P->done));
     P->pending = false;
@@ -905,17 +920,17 @@ int srp_plan_destroy(srp_plan *plan) {
     return SRP_OK;
 }
 
-int srp_set_schedule(int32_t tiles_per_chunk, int32_t blocks_per_cu) {
+int srp_set_schedule(int32_t patches_per_chunk, int32_t blocks_per_cu) {
     g_err.clear();
-    if (tiles_per_chunk < 0 || tiles_per_chunk > 64 || blocks_per_cu < 0 || blocks_per_cu > 64)
+    if (patches_per_chunk < 0 || patches_per_chunk > MAX_PPC || blocks_per_cu < 0 || blocks_per_cu > 64)
         return fail(SRP_ERR_ARG, "schedule out of range");
     std::lock_guard<std::mutex> lk(g_ws.mu);
-    g_override.rpt = tiles_per_chunk;
+    g_override.ppc = patches_per_chunk;
     g_override.bpc = blocks_per_cu;
     return SRP_OK;
 }
 
-int srp_autotune(const srp_batch_item *items, int64_t n_items, int32_t flags, int32_t *tiles_per_chunk,
+int srp_autotune(const srp_batch_item *items, int64_t n_items, int32_t flags, int32_t *patches_per_chunk,
                  int32_t *blocks_per_cu, double *best_ms) {
     g_err.clear();
     if (!items || n_items <= 0) return fail(SRP_ERR_ARG, "null or empty batch");
@@ -950,32 +965,46 @@ int srp_autotune(const srp_batch_item *items, int64_t n_items, int32_t flags, in
     int occ = trace_blocks_per_cu(cnt, grad, mg);
     Schedule best;
     double best_t = INFINITY;
-    const int rpts[] = {1, 2, 4, 8, 16};
-    for (int r : rpts) {
-        for (int b : {occ, std::max(1, occ / 2)}) {
+    int64_t total_patches = 0;
+    for (int64_t k = 0; k < n_items; ++k) {
+        const int64_t t = (items[k].p.n + TILE - 1) / TILE;
+        total_patches += 4 * t * t;
+    }
+    // candidates: patches per chunk 1..64 (powers of two) that give every
+    // resident wave at least one chunk and at most 64 (the gradient partials
+    // are per chunk), at full and half occupancy
+    std::vector<Schedule> cands;
+    for (int b : {occ, std::max(1, occ / 2)}) {
+        const int64_t resident = (int64_t)g_ws.n_cu * b * (BLOCK / 64);
+        for (int ppc = 1; ppc <= MAX_PPC; ppc *= 2) {
+            const int64_t chunks = (total_patches + ppc - 1) / ppc;
+            if ((chunks < resident && ppc > 1) || chunks > 64 * resident) continue;
             Schedule sc;
-            sc.rpt = r;
+            sc.ppc = ppc;
             sc.bpc = b;
-            double tmin = INFINITY;
-            for (int rep = 0; rep < 3 && rc == 0; ++rep) {
-                if ((rc = run_batch(items, n_items, grad, bo, g_ws.stream, sc))) break;
-                HIPCHK(hipStreamSynchronize(g_ws.stream));
-                g_ws.pending = false;
-                if (rep == 0) continue;   // warm-up
-                HIPCHK(hipEventRecord(e0, g_ws.stream));
-                if ((rc = run_batch(items, n_items, grad, bo, g_ws.stream, sc))) break;
-                HIPCHK(hipEventRecord(e1, g_ws.stream));
-                HIPCHK(hipEventSynchronize(e1));
-                g_ws.pending = false;
-                float ms = 0;
-                HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-                tmin = std::min(tmin, (double)ms);
-            }
-            if (rc) break;
-            if (tmin < best_t) { best_t = tmin; best = sc; }
-            if (b == 1) break;
+            cands.push_back(sc);
+        }
+        if (b == 1) break;
+    }
+    if (cands.empty()) cands.push_back(pick_schedule(items, n_items, grad, total_patches, occ));
+    for (const Schedule &sc : cands) {
+        double tmin = INFINITY;
+        for (int rep = 0; rep < 3 && rc == 0; ++rep) {
+            if ((rc = run_batch(items, n_items, grad, bo, g_ws.stream, sc))) break;
+            HIPCHK(hipStreamSynchronize(g_ws.stream));
+            g_ws.pending = false;
+            if (rep == 0) continue;   // warm-up
+            HIPCHK(hipEventRecord(e0, g_ws.stream));
+            if ((rc = run_batch(items, n_items, grad, bo, g_ws.stream, sc))) break;
+            HIPCHK(hipEventRecord(e1, g_ws.stream));
+            HIPCHK(hipEventSynchronize(e1));
+            g_ws.pending = false;
+            float ms = 0;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            tmin = std::min(tmin, (double)ms);
         }
         if (rc) break;
+        if (tmin < best_t) { best_t = tmin; best = sc; }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -983,7 +1012,7 @@ int srp_autotune(const srp_batch_item *items, int64_t n_items, int32_t flags, in
     if (d_grad) (void)hipFree(d_grad);
     if (rc) return rc;
     g_tuned[tune_key(items, n_items, grad)] = best;
-    if (tiles_per_chunk) *tiles_per_chunk = best.rpt;
+    if (patches_per_chunk) *patches_per_chunk = best.ppc;
     if (blocks_per_cu) *blocks_per_cu = best.bpc;
     if (best_ms) *best_ms = best_t;
     return SRP_OK;

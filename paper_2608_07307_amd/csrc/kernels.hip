@@ -4,17 +4,17 @@
 //             mesh (FP64 bounds of every (vertex, node) point on the image
 //             axes u, v and the photon direction d), merged across blocks with
 //             order-preserving 64-bit atomic min.
-//   k_trace   persistent: blocks walk the chunks (16 x 16*rpt pixels of one
-//             evaluation) with a uniform grid stride; one ray per lane, an 8x8
-//             pixel patch per wave; two-level traversal (top level over the
-//             kinematic-tree nodes, rigid instance transform, bottom level in
-//             rest-pose coordinates) with a per-lane stack in LDS; watertight
-//             FP32 triangle test; momentum law at each hit; specular secondary
-//             rays iteratively; FP64 per-lane sums, wave butterfly, fixed
-//             block order, one partial per chunk (no floating-point atomics,
-//             so results do not depend on scheduling).  The GRAD variant also
+//   k_trace   persistent: every wave takes chunks (runs of 8x8-pixel patches
+//             of one evaluation) from per-XCD work queues until none is left,
+//             with no block barrier; one ray per lane; two-level traversal (top level over
+//             the kinematic-tree nodes, rigid instance transform, bottom level
+//             in rest-pose coordinates) with a per-lane stack (LDS ring, global
+//             spill); watertight FP32 triangle test; momentum law at each hit;
+//             specular secondary rays iteratively; FP64 per-lane sums, wave
+//             butterfly, one partial per patch (no floating-point atomics, so
+//             results do not depend on scheduling).  The GRAD variant also
 //             differentiates each ray's hit chain at fixed visibility.
-//   k_reduce  per evaluation, sums its chunk partials in chunk order, scales by
+//   k_reduce  per evaluation, sums its patch partials in a fixed order, scales by
 //             P * A_pix and writes the srp_result (and the gradients).
 //
 // The per-pixel structure, the iterative secondary rays and the GPU-side
@@ -30,6 +30,16 @@ namespace srp {
 namespace {
 
 constexpr int WAVE = 64;
+constexpr int HWREG_XCC_ID = 20;   // hardware register holding the wave's XCD (accelerator complex die)
+
+// Occupancy targets of the trace kernels (waves per SIMD): the register
+// budget the compiler keeps to.
+#ifndef SRP_WPE_FWD
+#define SRP_WPE_FWD 4
+#endif
+#ifndef SRP_WPE_GRAD
+#define SRP_WPE_GRAD 4
+#endif
 constexpr int MAX_CHAIN = SRP_MAX_BOUNCES + 1;
 
 __device__ __forceinline__ double wave_sum(double x) {
@@ -69,253 +79,304 @@ __device__ __forceinline__ void m3_zero(float *M) {
     for (int i = 0; i < 9; ++i) M[i] = 0.0f;
 }
 
+// lane-private LDS accumulator: *p += v as one LDS add (the order of one
+// lane's adds is its program order)
+__device__ __forceinline__ void lds_add(double *p, double v) {
+    (void)__hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// A wave-uniform float held in a scalar register.
+__device__ __forceinline__ float uniform_f32(float x) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
+
+// Orders this wave's earlier LDS accesses before its later ones across lanes
+// (one wave's LDS operations execute in issue order; this keeps the compiler
+// from reordering them).
+__device__ __forceinline__ void wave_lds_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
 template <bool COUNT, bool GRAD>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(GRAD ? 3 : 4))) void k_trace(const EvalDesc *__restrict__ descs,
-                                                 const int64_t *__restrict__ chunk_base, int n_evals,
-                                                 const uint64_t *__restrict__ win, int grid_blocks,
-                                                 int64_t total_chunks, ChunkOut *__restrict__ chunks,
-                                                 uint64_t *__restrict__ counts) {
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(GRAD ? SRP_WPE_GRAD : SRP_WPE_FWD))) void k_trace(
+    const EvalDesc *__restrict__ descs, const int64_t *__restrict__ chunk_base, int n_evals,
+    const uint64_t *__restrict__ win, int grid_blocks, int64_t total_chunks, uint32_t *queue, uint32_t *spill,
+    PatchOut *__restrict__ patches, uint64_t *__restrict__ counts, int lds_grad_doubles) {
     extern __shared__ char smem[];
-    uint32_t *stack = reinterpret_cast<uint32_t *>(smem) + threadIdx.x;   // entry s at [s * BLOCK]
-    double *gacc = reinterpret_cast<double *>(smem + sizeof(uint32_t) * STACK_DEPTH * BLOCK);
-    __shared__ double s_red[BLOCK / WAVE][8];
-    __shared__ uint32_t s_cnt[BLOCK / WAVE][6];
-
     const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid >> 6;
+    LaneStack stack;
+    stack.ring = reinterpret_cast<uint32_t *>(smem) + tid;   // slot k at [k * BLOCK]
+    stack.stride = BLOCK;
+    stack.spill = (uint32_t SRP_GLOBAL *)spill + (size_t)blockIdx.x * BLOCK + tid;
+    stack.sstride = grid_blocks * BLOCK;
+    // per-lane FP64 force/torque sums of the current patch (component k at [k * BLOCK]):
+    // kept in LDS and updated with LDS adds, out of the traversal's registers
+    double *lacc = reinterpret_cast<double *>(smem + sizeof(uint32_t) * STACK_LDS * BLOCK) + tid;
+    double *gw = reinterpret_cast<double *>(smem + sizeof(uint32_t) * STACK_LDS * BLOCK) + 6 * BLOCK +
+                 (size_t)wv * lds_grad_doubles;
 
-    // Persistent blocks walk the chunks with a uniform grid stride: the loop
-    // control is identical for every thread, so the block barriers below never
-    // sit under divergent control flow (a per-block atomic work counter read
-    // back through LDS did, and its loop was restructured so that the lane
-    // doing the atomic left the loop the other lanes kept re-entering).
-    for (int64_t c = blockIdx.x; c < total_chunks; c += grid_blocks) {
-
-        // evaluation owning chunk c (chunk_base is increasing; chunk_base[n_evals] = total)
-        int lo = 0, hi = n_evals - 1;
-        while (lo < hi) {
-            int mid = (lo + hi + 1) >> 1;
-            if (chunk_base[mid] <= c) lo = mid; else hi = mid - 1;
+    // Every wave is persistent on its own and takes chunks from work queues:
+    // queue r (one per XCD, each counter on its own 256-byte line) hands out
+    // chunks r, r + N_QUEUES, r + 2 N_QUEUES, ... in order.  A wave drains the
+    // queue of the XCD it runs on and then helps with the others; a relaxed
+    // load skips drained queues without an atomic.  Every queue walks the whole
+    // batch in order, so expensive image regions spread over the grid and over
+    // time, and each counter sees an eighth of the traffic.  Lane 0 talks to
+    // the counters and broadcasts the chunk, so the loop control is
+    // wave-uniform, and there is no block barrier anywhere.
+    uint32_t r = __builtin_amdgcn_s_getreg((HWREG_XCC_ID << 0) | (0 << 6) | (3 << 11)) & (N_QUEUES - 1);
+    int tried = 1;
+    int64_t n_r = (total_chunks - r + N_QUEUES - 1) / N_QUEUES;   // chunks of queue r
+    int cur = -1;                          // evaluation of the previous chunk
+    int64_t cur_begin = 0, cur_end = -1;   // its chunk range
+    float o0[3], su[3], sv[3], dd[3];      // its ray grid (FP32 constants)
+    float tmin2 = 0.0f;
+    bool empty = true;
+    #pragma unroll 1
+    for (;;) {
+        int64_t c;
+        #pragma unroll 1
+        for (;;) {
+            uint32_t v = 0;
+            if (lane == 0) {
+                uint32_t *qr = queue + r * QUEUE_STRIDE;
+                v = __hip_atomic_load(qr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (v < (uint32_t)n_r) v = atomicAdd(qr, 1u);
+            }
+            c = (int64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+            if (c < n_r || tried == N_QUEUES) break;
+            r = (r + 1) & (N_QUEUES - 1);
+            ++tried;
+            n_r = (total_chunks - r + N_QUEUES - 1) / N_QUEUES;
         }
-        const EvalDesc &D = descs[lo];
+        if (c >= n_r) break;   // every queue drained
+        c = r + c * N_QUEUES;
+
+        if (c < cur_begin || c >= cur_end) {
+            // evaluation owning chunk c (chunk_base is increasing; chunk_base[n_evals] = total)
+            int lo = (cur >= 0 && c >= cur_end) ? cur : 0, hi = n_evals - 1;
+            while (lo < hi) {
+                int mid = (lo + hi + 1) >> 1;
+                if (chunk_base[mid] <= c) lo = mid; else hi = mid - 1;
+            }
+            cur = lo;
+            cur_begin = chunk_base[lo];
+            cur_end = chunk_base[lo + 1];
+            const EvalDesc &D = descs[lo];
+            // window -> ray grid (FP64 -> FP32 constants)
+            const uint64_t *W = win + (size_t)lo * WIN_STRIDE;
+            const double umin = dec_f64(W[0]), umax = -dec_f64(W[1]);
+            const double vmin = dec_f64(W[2]), vmax = -dec_f64(W[3]), hmin = dec_f64(W[4]);
+            const double wu = umax - umin, wv_ = vmax - vmin;
+            empty = !(wu * wv_ > 0.0) || !(wu < INFINITY) || !(wv_ < INFINITY) || D.root_ref == REF_NONE;
+            const double L = fmax(wu, wv_);
+            const double h0 = hmin - 1e-3 * L - 1e-3;
+            const double du = wu / D.n, dv = wv_ / D.n;
+            // (wave-uniform values computed on the vector unit: moved to scalar registers)
+            for (int k = 0; k < 3; ++k) {
+                o0[k] = uniform_f32((float)((umin + 0.5 * du) * D.u[k] + (vmin + 0.5 * dv) * D.v[k] + h0 * D.d[k]));
+                su[k] = uniform_f32((float)(du * D.u[k]));
+                sv[k] = uniform_f32((float)(dv * D.v[k]));
+                dd[k] = uniform_f32((float)D.d[k]);
+            }
+            tmin2 = uniform_f32((float)(1e-6 * L));
+            empty = __builtin_amdgcn_readfirstlane((int)empty) != 0;
+        }
+        const EvalDesc &D = descs[cur];
         const int64_t kc = c - D.chunk_base;
         const int N = D.n;
 
-        // window -> ray grid (FP64 -> FP32 constants)
-        const uint64_t *W = win + (size_t)lo * WIN_STRIDE;
-        const double umin = dec_f64(W[0]), umax = -dec_f64(W[1]);
-        const double vmin = dec_f64(W[2]), vmax = -dec_f64(W[3]), hmin = dec_f64(W[4]);
-        const double wu = umax - umin, wv_ = vmax - vmin;
-        const bool empty = !(wu * wv_ > 0.0) || !(wu < INFINITY) || !(wv_ < INFINITY) ||
-                           D.root_ref == REF_NONE;
-        const double L = fmax(wu, wv_);
-        const double h0 = hmin - 1e-3 * L - 1e-3;
-        const double du = wu / N, dv = wv_ / N;
-        float o0[3], su[3], sv[3], dd[3];
-        for (int k = 0; k < 3; ++k) {
-            o0[k] = (float)((umin + 0.5 * du) * D.u[k] + (vmin + 0.5 * dv) * D.v[k] + h0 * D.d[k]);
-            su[k] = (float)(du * D.u[k]);
-            sv[k] = (float)(dv * D.v[k]);
-            dd[k] = (float)D.d[k];
-        }
-        const float tmin2 = (float)(1e-6 * L);
-
-        const int cy = (int)(kc / D.tiles_x), cx = (int)(kc % D.tiles_x);
-        const int px = cx * TILE + (wv & 1) * 8 + (lane & 7);
-        const int py0 = cy * TILE * D.rpt + (wv >> 1) * 8 + (lane >> 3);
+        const int64_t p0 = kc * D.ppc, p1 = min(p0 + D.ppc, D.n_patches);
         const int B = D.bounces;
         const TraceCtx TC = trace_ctx(D);
 
-        double *gw = nullptr;
-        int gK = D.n_nodes, gM = D.n_mats;
+        const int gK = D.n_nodes;
         if (GRAD) {
-            gw = gacc + (size_t)wv * D.grad_n;
             for (int i = lane; i < D.grad_n; i += WAVE) gw[i] = 0.0;
+            wave_lds_fence();
         }
 
-        for (int r = 0; r < D.rpt; ++r) {
-            // one 16x16 tile per iteration; its sums go to the tile's own slot, so
-            // the forward result does not depend on how many tiles a chunk holds
-            double acc[6] = {0, 0, 0, 0, 0, 0};
-            uint32_t n_hit = 0, n_sec = 0, n_sec_hit = 0, nbox = 0, ntri = 0, status = 0;
-            const int tile_row = cy * D.rpt + r;
-            const int py = py0 + r * TILE;
-            const bool inside = px < N && py < N;
-            const bool valid = !empty && inside;
-            ChainHit chain[GRAD ? MAX_CHAIN : 1];
-            int K = 0;
-            if (inside && D.hit_ids) {   // generations a chain does not reach stay "no hit"
-                const int64_t pix = (int64_t)py * N + px;
-                for (int gen = 0; gen <= B; ++gen) {
-                    D.hit_ids[pix * (B + 1) + gen] = -1;
-                    D.hit_t[pix * (B + 1) + gen] = 0.0f;
-                }
-            }
-            if (valid) {
-                float o[3], d[3];
-                for (int k = 0; k < 3; ++k) {
-                    o[k] = fmaf((float)py, sv[k], fmaf((float)px, su[k], o0[k]));
-                    d[k] = dd[k];
-                }
-                float w = 1.0f, tmin = 0.0f;
-                int32_t excl = -1;
-                const int64_t pix = (int64_t)py * N + px;
-                for (int gen = 0; gen <= B; ++gen) {
-                    Hit h;
-                    if (!trace_closest<COUNT>(TC, o, d, tmin, excl, stack, BLOCK, h, nbox, ntri)) {
-                        status |= SRP_STATUS_STACK;
-                        break;
+        #pragma unroll 1
+        for (int64_t pt = p0; pt < p1; ++pt) {
+            // one 8x8 patch per iteration, one ray per lane; its sums go to the
+            // patch's own slot, so the forward result does not depend on the
+            // chunking or on which wave runs it
+            const int tile = (int)(pt >> 2), q = (int)(pt & 3);
+            const int px = (tile % D.tiles_x) * TILE + (q & 1) * PATCH + (lane & 7);
+            const int py = (tile / D.tiles_x) * TILE + (q >> 1) * PATCH + (lane >> 3);
+            for (int k = 0; k < 6; ++k) lacc[k * BLOCK] = 0.0;
+            // hit counts packed in 10-bit fields (primary hits, secondary rays, secondary hits;
+            // a patch sums at most 64 * SRP_MAX_BOUNCES of each), the status separately
+            uint32_t hcnt = 0, nbox = 0, ntri = 0, status = 0;
+            {
+                const bool inside = px < N && py < N;
+                const bool valid = !empty && inside;
+                ChainHit chain[GRAD ? MAX_CHAIN : 1];
+                int K = 0;
+                if (inside && D.hit_ids) {   // generations a chain does not reach stay "no hit"
+                    const int64_t pix = (int64_t)py * N + px;
+                    for (int gen = 0; gen <= B; ++gen) {
+                        D.hit_ids[pix * (B + 1) + gen] = -1;
+                        D.hit_t[pix * (B + 1) + gen] = 0.0f;
                     }
-                    if (D.hit_ids) {
-                        D.hit_ids[pix * (B + 1) + gen] = h.tri >= 0 ? h.id : -1;
-                        D.hit_t[pix * (B + 1) + gen] = h.tri >= 0 ? h.t : 0.0f;
-                    }
-                    if (h.tri < 0) break;
-                    if (gen == 0) n_hit++; else n_sec_hit++;
-                    const TriRec SRP_GLOBAL &T = TC.tris[h.tri];
-                    const Inst SRP_GLOBAL &I = TC.inst[h.inst];
-                    float e1[3] = {T.v1[0] - T.v0[0], T.v1[1] - T.v0[1], T.v1[2] - T.v0[2]};
-                    float e2[3] = {T.v2[0] - T.v0[0], T.v2[1] - T.v0[1], T.v2[2] - T.v0[2]};
-                    float nl[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
-                                   e1[0] * e2[1] - e1[1] * e2[0]};
-                    float n[3];
-                    for (int k = 0; k < 3; ++k) n[k] = I.R[3 * k] * nl[0] + I.R[3 * k + 1] * nl[1] + I.R[3 * k + 2] * nl[2];
-                    float inv = rsqrtf(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
-                    float nd = (n[0] * d[0] + n[1] * d[1] + n[2] * d[2]) * inv;
-                    if (nd > 0.0f) inv = -inv;
-                    for (int k = 0; k < 3; ++k) n[k] *= inv;
-                    const float cth = -(n[0] * d[0] + n[1] * d[1] + n[2] * d[2]);
-                    const float rs = D.mats[2 * T.mat], rd = D.mats[2 * T.mat + 1];
-                    const float a = w * (1.0f - rs), b = -2.0f * w * (rs * cth + rd * (1.0f / 3.0f));
-                    float f[3], x[3], rr[3];
+                }
+                if (valid) {
+                    float o[3], d[3];
                     for (int k = 0; k < 3; ++k) {
-                        f[k] = a * d[k] + b * n[k];
-                        x[k] = fmaf(h.t, d[k], o[k]);
-                        rr[k] = x[k] - (float)D.ref[k];
+                        o[k] = fmaf((float)py, sv[k], fmaf((float)px, su[k], o0[k]));
+                        d[k] = dd[k];
                     }
-                    acc[0] += (double)f[0];
-                    acc[1] += (double)f[1];
-                    acc[2] += (double)f[2];
-                    acc[3] += (double)(rr[1] * f[2] - rr[2] * f[1]);
-                    acc[4] += (double)(rr[2] * f[0] - rr[0] * f[2]);
-                    acc[5] += (double)(rr[0] * f[1] - rr[1] * f[0]);
-                    if (GRAD) {
-                        ChainHit &ch = chain[K];
-                        for (int k = 0; k < 3; ++k) { ch.n[k] = n[k]; ch.d[k] = d[k]; }
-                        ch.c = cth; ch.w = w; ch.rs = rs; ch.rd = rd;
-                        ch.mat = T.mat; ch.node = T.node;
-                    }
-                    ++K;
-                    if (gen == B || !(rs > 0.0f)) break;
-                    for (int k = 0; k < 3; ++k) {
-                        o[k] = x[k];
-                        d[k] = fmaf(2.0f * cth, n[k], d[k]);
-                    }
-                    w *= rs;
-                    tmin = tmin2;
-                    excl = T.id;
-                    n_sec++;
-                }
-            }
-            if (GRAD) {
-                // Reverse sweep over the chain at fixed visibility.
-                //   A  = d(sum of later contributions)/d(incoming direction)   (3x3)
-                //   Tn = later contributions divided by the weight after this hit
-                int Kmax = K;
-                for (int m = 32; m >= 1; m >>= 1) Kmax = max(Kmax, __shfl_xor(Kmax, m, WAVE));
-                float A[9], Tn[3] = {0, 0, 0};
-                m3_zero(A);
-                for (int k = Kmax - 1; k >= 0; --k) {
-                    const bool act = k < K;
-                    float Hm[9], gmat[6];
-                    int node = 0, mat = 0;
-                    if (act) {
-                        const ChainHit ch = chain[k];
-                        const float *n = ch.n, *d = ch.d;
-                        const float w = ch.w, rs = ch.rs, rd = ch.rd, cc = ch.c;
-                        const float sc = rs * cc + rd * (1.0f / 3.0f);
-                        // material terms
-                        for (int i = 0; i < 3; ++i) {
-                            gmat[i] = w * (-d[i] - 2.0f * cc * n[i] + Tn[i]);
-                            gmat[3 + i] = w * (-2.0f / 3.0f) * n[i];
+                    float w = 1.0f, tmin = 0.0f;
+                    int32_t excl = -1;
+                    const int64_t pix = (int64_t)py * N + px;
+                    #pragma unroll 1
+                    for (int gen = 0; gen <= B; ++gen) {
+                        Hit h;
+                        if (!trace_closest<COUNT>(TC, o, d, tmin, excl, stack, h, nbox, ntri)) {
+                            status |= SRP_STATUS_STACK;
+                            break;
                         }
-                        // G = dF/dn (explicit) + A (2c I - 2 n d^T)
-                        float G[9];
-                        for (int i = 0; i < 3; ++i)
-                            for (int j = 0; j < 3; ++j) {
-                                float e = w * (2.0f * rs * n[i] * d[j] - (i == j ? 2.0f * sc : 0.0f));
-                                float an = A[3 * i] * n[0] + A[3 * i + 1] * n[1] + A[3 * i + 2] * n[2];
-                                e += 2.0f * cc * A[3 * i + j] - 2.0f * an * d[j];
-                                G[3 * i + j] = e;
+                        if (D.hit_ids) {
+                            D.hit_ids[pix * (B + 1) + gen] = h.tri >= 0 ? h.id : -1;
+                            D.hit_t[pix * (B + 1) + gen] = h.tri >= 0 ? h.t : 0.0f;
+                        }
+                        if (h.tri < 0) break;
+                        hcnt += gen == 0 ? 1u : (1u << 20);
+                        const TriRec SRP_GLOBAL &T = TC.tris[h.tri];
+                        const Inst SRP_GLOBAL &I = TC.inst[h.inst];
+                        float e1[3] = {T.v1[0] - T.v0[0], T.v1[1] - T.v0[1], T.v1[2] - T.v0[2]};
+                        float e2[3] = {T.v2[0] - T.v0[0], T.v2[1] - T.v0[1], T.v2[2] - T.v0[2]};
+                        float nl[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+                                       e1[0] * e2[1] - e1[1] * e2[0]};
+                        float n[3];
+                        for (int k = 0; k < 3; ++k) n[k] = I.R[3 * k] * nl[0] + I.R[3 * k + 1] * nl[1] + I.R[3 * k + 2] * nl[2];
+                        float inv = rsqrtf(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+                        float nd = (n[0] * d[0] + n[1] * d[1] + n[2] * d[2]) * inv;
+                        if (nd > 0.0f) inv = -inv;
+                        for (int k = 0; k < 3; ++k) n[k] *= inv;
+                        const float cth = -(n[0] * d[0] + n[1] * d[1] + n[2] * d[2]);
+                        const float rs = D.mats[2 * T.mat], rd = D.mats[2 * T.mat + 1];
+                        const float a = w * (1.0f - rs), b = -2.0f * w * (rs * cth + rd * (1.0f / 3.0f));
+                        float f[3], x[3], rr[3];
+                        for (int k = 0; k < 3; ++k) {
+                            f[k] = a * d[k] + b * n[k];
+                            x[k] = fmaf(h.t, d[k], o[k]);
+                            rr[k] = x[k] - (float)D.ref[k];
+                        }
+                        lds_add(lacc, (double)f[0]);
+                        lds_add(lacc + BLOCK, (double)f[1]);
+                        lds_add(lacc + 2 * BLOCK, (double)f[2]);
+                        lds_add(lacc + 3 * BLOCK, (double)(rr[1] * f[2] - rr[2] * f[1]));
+                        lds_add(lacc + 4 * BLOCK, (double)(rr[2] * f[0] - rr[0] * f[2]));
+                        lds_add(lacc + 5 * BLOCK, (double)(rr[0] * f[1] - rr[1] * f[0]));
+                        if (GRAD) {
+                            ChainHit &ch = chain[K];
+                            for (int k = 0; k < 3; ++k) { ch.n[k] = n[k]; ch.d[k] = d[k]; }
+                            ch.c = cth; ch.w = w; ch.rs = rs; ch.rd = rd;
+                            ch.mat = T.mat; ch.node = T.node;
+                        }
+                        ++K;
+                        if (gen == B || !(rs > 0.0f)) break;
+                        for (int k = 0; k < 3; ++k) {
+                            o[k] = x[k];
+                            d[k] = fmaf(2.0f * cth, n[k], d[k]);
+                        }
+                        w *= rs;
+                        tmin = tmin2;
+                        excl = T.id;
+                        hcnt += 1u << 10;
+                    }
+                }
+                if (GRAD) {
+                    // Reverse sweep over the chain at fixed visibility.
+                    //   A  = d(sum of later contributions)/d(incoming direction)   (3x3)
+                    //   Tn = later contributions divided by the weight after this hit
+                    int Kmax = K;
+                    for (int m = 32; m >= 1; m >>= 1) Kmax = max(Kmax, __shfl_xor(Kmax, m, WAVE));
+                    float A[9], Tn[3] = {0, 0, 0};
+                    m3_zero(A);
+                    for (int k = Kmax - 1; k >= 0; --k) {
+                        const bool act = k < K;
+                        float Hm[9], gmat[6];
+                        int node = 0, mat = 0;
+                        if (act) {
+                            const ChainHit ch = chain[k];
+                            const float *n = ch.n, *d = ch.d;
+                            const float w = ch.w, rs = ch.rs, rd = ch.rd, cc = ch.c;
+                            const float sc = rs * cc + rd * (1.0f / 3.0f);
+                            // material terms
+                            for (int i = 0; i < 3; ++i) {
+                                gmat[i] = w * (-d[i] - 2.0f * cc * n[i] + Tn[i]);
+                                gmat[3 + i] = w * (-2.0f / 3.0f) * n[i];
                             }
-                        // H = -G [n]x
-                        for (int i = 0; i < 3; ++i) {
-                            const float g0 = G[3 * i], g1 = G[3 * i + 1], g2 = G[3 * i + 2];
-                            Hm[3 * i + 0] = -(g1 * n[2] - g2 * n[1]);
-                            Hm[3 * i + 1] = -(g2 * n[0] - g0 * n[2]);
-                            Hm[3 * i + 2] = -(g0 * n[1] - g1 * n[0]);
+                            // G = dF/dn (explicit) + A (2c I - 2 n d^T)
+                            float G[9];
+                            for (int i = 0; i < 3; ++i)
+                                for (int j = 0; j < 3; ++j) {
+                                    float e = w * (2.0f * rs * n[i] * d[j] - (i == j ? 2.0f * sc : 0.0f));
+                                    float an = A[3 * i] * n[0] + A[3 * i + 1] * n[1] + A[3 * i + 2] * n[2];
+                                    e += 2.0f * cc * A[3 * i + j] - 2.0f * an * d[j];
+                                    G[3 * i + j] = e;
+                                }
+                            // H = -G [n]x
+                            for (int i = 0; i < 3; ++i) {
+                                const float g0 = G[3 * i], g1 = G[3 * i + 1], g2 = G[3 * i + 2];
+                                Hm[3 * i + 0] = -(g1 * n[2] - g2 * n[1]);
+                                Hm[3 * i + 1] = -(g2 * n[0] - g0 * n[2]);
+                                Hm[3 * i + 2] = -(g0 * n[1] - g1 * n[0]);
+                            }
+                            // A <- dF_k/dd + A (I - 2 n n^T);  Tn <- f_k + rs Tn
+                            float An[3];
+                            for (int i = 0; i < 3; ++i) An[i] = A[3 * i] * n[0] + A[3 * i + 1] * n[1] + A[3 * i + 2] * n[2];
+                            for (int i = 0; i < 3; ++i)
+                                for (int j = 0; j < 3; ++j)
+                                    A[3 * i + j] = A[3 * i + j] - 2.0f * An[i] * n[j] +
+                                                   w * ((i == j ? 1.0f - rs : 0.0f) + 2.0f * rs * n[i] * n[j]);
+                            for (int i = 0; i < 3; ++i) Tn[i] = (1.0f - rs) * d[i] - 2.0f * sc * n[i] + rs * Tn[i];
+                            node = ch.node;
+                            mat = ch.mat;
                         }
-                        // A <- dF_k/dd + A (I - 2 n n^T);  Tn <- f_k + rs Tn
-                        float An[3];
-                        for (int i = 0; i < 3; ++i) An[i] = A[3 * i] * n[0] + A[3 * i + 1] * n[1] + A[3 * i + 2] * n[2];
-                        for (int i = 0; i < 3; ++i)
-                            for (int j = 0; j < 3; ++j)
-                                A[3 * i + j] = A[3 * i + j] - 2.0f * An[i] * n[j] +
-                                               w * ((i == j ? 1.0f - rs : 0.0f) + 2.0f * rs * n[i] * n[j]);
-                        for (int i = 0; i < 3; ++i) Tn[i] = (1.0f - rs) * d[i] - 2.0f * sc * n[i] + rs * Tn[i];
-                        node = ch.node;
-                        mat = ch.mat;
+                        wave_scatter_add(gw, node, act, Hm, 9, 9);
+                        wave_scatter_add(gw + 9 * gK, mat, act, gmat, 6, 6);
                     }
-                    wave_scatter_add(gw, node, act, Hm, 9, 9);
-                    wave_scatter_add(gw + 9 * gK, mat, act, gmat, 6, 6);
                 }
             }
 
-            // block reduction of the tile's sums (fixed order)
-            for (int k = 0; k < 6; ++k) {
-                double s = wave_sum(acc[k]);
-                if (lane == 0) s_red[wv][k] = s;
-            }
-            uint32_t cnts[6] = {n_hit, n_sec, n_sec_hit, nbox, ntri, status};
-            for (int k = 0; k < 6; ++k) {
-                uint32_t s = cnts[k];
-                for (int m = 32; m >= 1; m >>= 1) s = (k == 5) ? (s | __shfl_xor(s, m, WAVE)) : (s + __shfl_xor(s, m, WAVE));
-                if (lane == 0) s_cnt[wv][k] = s;
-            }
-            __syncthreads();
-            if (tid == 0 && tile_row < D.tiles_y) {
-                ChunkOut co;
-                for (int k = 0; k < 6; ++k) {
-                    double s = s_red[0][k];
-                    for (int w2 = 1; w2 < BLOCK / WAVE; ++w2) s += s_red[w2][k];
-                    co.f[k] = s;
-                }
-                uint32_t cs[6] = {0, 0, 0, 0, 0, 0};
-                for (int w2 = 0; w2 < BLOCK / WAVE; ++w2)
-                    for (int k = 0; k < 6; ++k) cs[k] = (k == 5) ? (cs[k] | s_cnt[w2][k]) : (cs[k] + s_cnt[w2][k]);
-                co.hits = cs[0];
-                co.sec = cs[1];
-                co.sec_hits = cs[2];
-                co.flags = cs[5];
-                const int64_t t = D.tile_base + (int64_t)tile_row * D.tiles_x + cx;
-                chunks[t] = co;
+            // the patch's sums: wave butterfly (every lane ends with the total), lane 0
+            // stores; a patch without a hit has zero sums (secondary hits need a primary)
+            double tot[6] = {0, 0, 0, 0, 0, 0};
+            if (__ballot((hcnt & 1023u) != 0))
+                for (int k = 0; k < 6; ++k) tot[k] = wave_sum(lacc[k * BLOCK]);
+            for (int m = 32; m >= 1; m >>= 1) {
+                hcnt += __shfl_xor(hcnt, m, WAVE);
+                status |= __shfl_xor(status, m, WAVE);
                 if (COUNT) {
-                    counts[2 * t] = cs[3];
-                    counts[2 * t + 1] = cs[4];
+                    nbox += __shfl_xor(nbox, m, WAVE);
+                    ntri += __shfl_xor(ntri, m, WAVE);
                 }
             }
-            __syncthreads();   // s_red and s_cnt are reused by the next tile
+            const uint32_t cnts[6] = {hcnt & 1023u, (hcnt >> 10) & 1023u, hcnt >> 20, nbox, ntri, status};
+            if (lane == 0) {
+                PatchOut co;
+                for (int k = 0; k < 6; ++k) co.f[k] = tot[k];
+                co.hits = cnts[0];
+                co.sec = cnts[1];
+                co.sec_hits = cnts[2];
+                co.flags = cnts[5];
+                const int64_t t = D.patch_base + pt;
+                patches[t] = co;
+                if (COUNT) {
+                    counts[2 * t] = cnts[3];
+                    counts[2 * t + 1] = cnts[4];
+                }
+            }
         }
         if (GRAD) {
-            __syncthreads();
+            wave_lds_fence();
             double *dst = D.grad_part + (size_t)kc * D.grad_n;
-            for (int i = tid; i < D.grad_n; i += BLOCK) {
-                double s = gacc[i];
-                for (int w2 = 1; w2 < BLOCK / WAVE; ++w2) s += gacc[(size_t)w2 * D.grad_n + i];
-                dst[i] = s;
-            }
-            (void)gM;
+            for (int i = lane; i < D.grad_n; i += WAVE) dst[i] = gw[i];
         }
-        __syncthreads();   // s_red, s_cnt and gacc are reused by the next chunk
     }
 }
 
@@ -323,8 +384,11 @@ constexpr int WBLOCK = 256;   // threads per block of the window and reduce kern
 
 // Loop strides use compile-time block sizes and an explicit grid-width
 // argument, so termination never depends on runtime-filled dispatch values.
-__global__ __launch_bounds__(WBLOCK) void k_window(const EvalDesc *__restrict__ descs, uint64_t *win, int blocks_x) {
+__global__ __launch_bounds__(WBLOCK) void k_window(const EvalDesc *__restrict__ descs, uint64_t *win, int blocks_x,
+                                                  uint32_t *queue) {
     const EvalDesc &D = descs[blockIdx.y];
+    // the trace kernel's work counters start at zero
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < N_QUEUES) queue[threadIdx.x * QUEUE_STRIDE] = 0u;
     double mn[5] = {INFINITY, INFINITY, INFINITY, INFINITY, INFINITY};
     const int64_t stride = (int64_t)blocks_x * WBLOCK;
     for (int64_t i = (int64_t)blockIdx.x * WBLOCK + threadIdx.x; i < D.n_wpts; i += stride) {
@@ -360,18 +424,18 @@ __global__ __launch_bounds__(WBLOCK) void k_window(const EvalDesc *__restrict__ 
 
 template <bool COUNT, bool GRAD>
 __global__ __launch_bounds__(WBLOCK) void k_reduce(const EvalDesc *__restrict__ descs,
-                                                const int64_t *__restrict__ tile_base,
+                                                const int64_t *__restrict__ patch_base,
                                                 const uint64_t *__restrict__ win,
-                                                const ChunkOut *__restrict__ chunks,
+                                                const PatchOut *__restrict__ patches,
                                                 const uint64_t *__restrict__ counts, srp_result *out) {
     const int e = blockIdx.x, tid = threadIdx.x;
     const EvalDesc &D = descs[e];
-    const int64_t c0 = tile_base[e], c1 = tile_base[e + 1];
+    const int64_t c0 = patch_base[e], c1 = patch_base[e + 1];
     double f[6] = {0, 0, 0, 0, 0, 0};
     uint64_t cn[5] = {0, 0, 0, 0, 0};
     uint32_t st = 0;
     for (int64_t c = c0 + tid; c < c1; c += WBLOCK) {
-        const ChunkOut &co = chunks[c];
+        const PatchOut &co = patches[c];
         for (int k = 0; k < 6; ++k) f[k] += co.f[k];
         cn[0] += co.hits;
         cn[1] += co.sec;
@@ -417,13 +481,40 @@ __global__ __launch_bounds__(WBLOCK) void k_reduce(const EvalDesc *__restrict__ 
         out[e] = r;
     }
     if (GRAD) {
-        // sum chunk partials per component (fixed chunk order), then assemble
+        // sum the chunk partials per component, then assemble.  The chunks are
+        // split into P contiguous slices (P threads per component when the
+        // components fit the block several times); each slice is summed with
+        // four interleaved accumulators and the slices are added in order, so
+        // the result depends only on the batch layout.
         const int G = D.grad_n, K = D.n_nodes, M = D.n_mats, J = D.n_dof;
         __shared__ double sg[MAX_GRAD_SLOTS];
-        for (int i = tid; i < G; i += WBLOCK) {
-            double s = 0.0;
-            for (int64_t c = 0; c < D.n_chunks; ++c) s += D.grad_part[(size_t)c * G + i];
-            sg[i] = s;
+        __shared__ double sl[WBLOCK];
+        const double *gp = D.grad_part;
+        const int64_t NC = D.n_chunks;
+        const int P = (G > 0 && G <= WBLOCK) ? WBLOCK / G : 1;
+        auto slice_sum = [&](int i, int64_t c0, int64_t c1) {
+            double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+            int64_t c = c0;
+            for (; c + 4 <= c1; c += 4) {
+                a0 += gp[(size_t)c * G + i];
+                a1 += gp[(size_t)(c + 1) * G + i];
+                a2 += gp[(size_t)(c + 2) * G + i];
+                a3 += gp[(size_t)(c + 3) * G + i];
+            }
+            for (; c < c1; ++c) a0 += gp[(size_t)c * G + i];
+            return (a0 + a1) + (a2 + a3);
+        };
+        if (P > 1) {
+            const int i = tid % G, p = tid / G;
+            if (p < P) sl[p * G + i] = slice_sum(i, NC * p / P, NC * (p + 1) / P);
+            __syncthreads();
+            for (int j = tid; j < G; j += WBLOCK) {
+                double t = 0.0;
+                for (int q = 0; q < P; ++q) t += sl[q * G + j];
+                sg[j] = t;
+            }
+        } else {
+            for (int j = tid; j < G; j += WBLOCK) sg[j] = slice_sum(j, 0, NC);
         }
         __syncthreads();
         double *g = D.grad_out;
@@ -457,35 +548,39 @@ int check(hipError_t e) { return e == hipSuccess ? 0 : (int)e; }
 
 }  // namespace
 
-int launch_window(const EvalDesc *d_desc, int n_evals, int blocks_x, uint64_t *d_win, void *stream) {
+int launch_window(const EvalDesc *d_desc, int n_evals, int blocks_x, uint64_t *d_win, uint32_t *d_queue,
+                  void *stream) {
     if (n_evals <= 0) return 0;
-    hipLaunchKernelGGL(k_window, dim3(blocks_x, n_evals), dim3(WBLOCK), 0, (hipStream_t)stream, d_desc, d_win, blocks_x);
+    hipLaunchKernelGGL(k_window, dim3(blocks_x, n_evals), dim3(WBLOCK), 0, (hipStream_t)stream, d_desc, d_win, blocks_x,
+                       d_queue);
     return check(hipGetLastError());
 }
 
+size_t trace_lds_bytes(bool grad, int lds_grad_doubles) {
+    return sizeof(uint32_t) * STACK_LDS * BLOCK + sizeof(double) * 6 * BLOCK +
+           (grad ? sizeof(double) * (BLOCK / 64) * lds_grad_doubles : 0);
+}
+
 int launch_trace(const EvalDesc *d_desc, const int64_t *d_chunk_base, int n_evals, const uint64_t *d_win,
-                 int64_t total_chunks, ChunkOut *d_chunks, uint64_t *d_counts, bool count, bool grad,
-                 int grid_blocks, int lds_grad_doubles, void *stream) {
+                 int64_t total_chunks, uint32_t *d_queue, uint32_t *d_spill, PatchOut *d_chunks,
+                 uint64_t *d_counts, bool count, bool grad, int grid_blocks, int lds_grad_doubles, void *stream) {
     if (total_chunks <= 0) return 0;
-    size_t lds = sizeof(uint32_t) * STACK_DEPTH * BLOCK + (grad ? sizeof(double) * (BLOCK / 64) * lds_grad_doubles : 0);
+    const size_t lds = trace_lds_bytes(grad, lds_grad_doubles);
+    const int lgd = grad ? lds_grad_doubles : 0;
     hipStream_t s = (hipStream_t)stream;
-    if (count && grad)
-        hipLaunchKernelGGL((k_trace<true, true>), dim3(grid_blocks), dim3(BLOCK), lds, s, d_desc, d_chunk_base,
-                           n_evals, d_win, grid_blocks, total_chunks, d_chunks, d_counts);
-    else if (count)
-        hipLaunchKernelGGL((k_trace<true, false>), dim3(grid_blocks), dim3(BLOCK), lds, s, d_desc, d_chunk_base,
-                           n_evals, d_win, grid_blocks, total_chunks, d_chunks, d_counts);
-    else if (grad)
-        hipLaunchKernelGGL((k_trace<false, true>), dim3(grid_blocks), dim3(BLOCK), lds, s, d_desc, d_chunk_base,
-                           n_evals, d_win, grid_blocks, total_chunks, d_chunks, d_counts);
-    else
-        hipLaunchKernelGGL((k_trace<false, false>), dim3(grid_blocks), dim3(BLOCK), lds, s, d_desc, d_chunk_base,
-                           n_evals, d_win, grid_blocks, total_chunks, d_chunks, d_counts);
+#define SRP_LAUNCH_TRACE(C, G)                                                                                \
+    hipLaunchKernelGGL((k_trace<C, G>), dim3(grid_blocks), dim3(BLOCK), lds, s, d_desc, d_chunk_base, n_evals, \
+                       d_win, grid_blocks, total_chunks, d_queue, d_spill, d_chunks, d_counts, lgd)
+    if (count && grad) SRP_LAUNCH_TRACE(true, true);
+    else if (count) SRP_LAUNCH_TRACE(true, false);
+    else if (grad) SRP_LAUNCH_TRACE(false, true);
+    else SRP_LAUNCH_TRACE(false, false);
+#undef SRP_LAUNCH_TRACE
     return check(hipGetLastError());
 }
 
 int launch_reduce(const EvalDesc *d_desc, const int64_t *d_tile_base, int n_evals, const uint64_t *d_win,
-                  const ChunkOut *d_chunks, const uint64_t *d_counts, bool count, bool grad, void *d_out,
+                  const PatchOut *d_chunks, const uint64_t *d_counts, bool count, bool grad, void *d_out,
                   void *stream) {
     if (n_evals <= 0) return 0;
     hipStream_t s = (hipStream_t)stream;
@@ -502,7 +597,7 @@ int launch_reduce(const EvalDesc *d_desc, const int64_t *d_tile_base, int n_eval
 }
 
 int trace_blocks_per_cu(bool count, bool grad, int lds_grad_doubles) {
-    size_t lds = sizeof(uint32_t) * STACK_DEPTH * BLOCK + (grad ? sizeof(double) * (BLOCK / 64) * lds_grad_doubles : 0);
+    const size_t lds = trace_lds_bytes(grad, lds_grad_doubles);
     int nb = 0;
     hipError_t e;
     if (count && grad) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_trace<true, true>, BLOCK, lds);

@@ -29,11 +29,19 @@ constexpr uint32_t REF_TLAS_LEAF = 3u;
 constexpr uint32_t REF_EXIT = 0xFFFFFFFEu;  // stack marker: leave the current instance
 constexpr uint32_t REF_NONE = 0xFFFFFFFFu;
 constexpr int LEAF_MAX = 8;
-constexpr int STACK_DEPTH = 32;             // per-lane traversal stack entries (LDS)
+constexpr int STACK_DEPTH = 32;             // per-lane traversal stack entries
+#ifndef SRP_STACK_LDS
+#define SRP_STACK_LDS 16                    // (a host build may shrink it to exercise the spill path)
+#endif
+constexpr int STACK_LDS = SRP_STACK_LDS;    // of which the newest live in LDS (a ring)
+constexpr int STACK_SPILL = STACK_DEPTH - STACK_LDS;   // older ones: per-lane global spill area
+static_assert((STACK_LDS & (STACK_LDS - 1)) == 0, "the LDS ring size is a power of two");
 constexpr int BLAS_MAX_DEPTH = 24;          // internal nodes on any root-to-leaf path
 constexpr int TLAS_MAX_DEPTH = 7;           // <= 128 instances, median split
-constexpr int BLOCK = 256;                  // threads per block of the trace kernel
-constexpr int TILE = 16;                    // a chunk is TILE columns x (TILE * rpt) rows
+constexpr int BLOCK = 256;                  // threads per block of the trace kernel (4 waves)
+constexpr int PATCH = 8;                    // a patch is PATCH x PATCH pixels: one ray per lane of a wave
+constexpr int TILE = 16;                    // patches are numbered by 16x16 tile (row-major), 4 per tile
+constexpr int MAX_PPC = 64;                 // patches per chunk (one wave's work item) at most
 constexpr int MAX_GRAD_SLOTS = 960;         // doubles per wave for gradient partials (LDS <= 64 KB)
 
 #define SRP_HD __host__ __device__
@@ -75,8 +83,8 @@ struct alignas(32) WPoint {
     int32_t pad;
 };
 
-// Per-chunk partial sums (unscaled: multiply by P * A_pix).
-struct alignas(64) ChunkOut {
+// Per-patch partial sums (unscaled: multiply by P * A_pix).
+struct alignas(64) PatchOut {
     double f[6];        // force (3), torque (3)
     uint32_t hits, sec, sec_hits, flags;
 };
@@ -104,12 +112,13 @@ struct alignas(64) EvalDesc {
     double ref[3];
     int32_t n, bounces;
     uint32_t flags;
-    int32_t tiles_x;
-    int32_t rpt;            // rows of tiles per chunk (rays per thread)
+    int32_t tiles_x;        // 16-pixel tile columns
+    int32_t ppc;            // patches per chunk
     int32_t grad_n;         // doubles per chunk gradient partial (0 = no gradient)
     int64_t chunk_base;     // first chunk of this evaluation
     int64_t n_chunks;
-    int64_t tile_base;      // first 16x16 tile of this evaluation (partial sums are per tile)
+    int64_t patch_base;     // first patch of this evaluation (partial sums are per patch)
+    int64_t n_patches;      // 4 * tiles_x * tiles_y
     int32_t tiles_y;        // 16-pixel tile rows
     int32_t pad_;
     // optional outputs
@@ -138,19 +147,20 @@ SRP_HD inline double dec_f64(uint64_t e) {
 // window slots per evaluation: enc(umin), enc(-umax), enc(vmin), enc(-vmax), enc(hmin)
 constexpr int WIN_STRIDE = 8;
 
-struct LaunchCfg {
-    int rpt;              // rays per thread (tile rows per chunk)
-    int blocks_per_cu;    // persistent grid factor
-};
-
 // Kernel launchers (kernels.hip)
-int launch_window(const EvalDesc *d_desc, int n_evals, int blocks_x, uint64_t *d_win, void *stream);
+// Work queues of the trace kernel: N_QUEUES counters QUEUE_STRIDE words apart
+// (launch_window zeroes them).
+constexpr int N_QUEUES = 8;
+constexpr int QUEUE_STRIDE = 64;
+int launch_window(const EvalDesc *d_desc, int n_evals, int blocks_x, uint64_t *d_win, uint32_t *d_queue,
+                  void *stream);
+// d_spill: grid_blocks * BLOCK * STACK_SPILL words; chunk counts below 2^31.
 int launch_trace(const EvalDesc *d_desc, const int64_t *d_chunk_base, int n_evals,
-                 const uint64_t *d_win, int64_t total_chunks, ChunkOut *d_chunks,
-                 uint64_t *d_counts, bool count, bool grad, int grid_blocks,
+                 const uint64_t *d_win, int64_t total_chunks, uint32_t *d_queue, uint32_t *d_spill,
+                 PatchOut *d_patches, uint64_t *d_counts, bool count, bool grad, int grid_blocks,
                  int lds_grad_doubles, void *stream);
-int launch_reduce(const EvalDesc *d_desc, const int64_t *d_tile_base, int n_evals,
-                  const uint64_t *d_win, const ChunkOut *d_chunks, const uint64_t *d_counts,
+int launch_reduce(const EvalDesc *d_desc, const int64_t *d_patch_base, int n_evals,
+                  const uint64_t *d_win, const PatchOut *d_patches, const uint64_t *d_counts,
                   bool count, bool grad, void *d_out, void *stream);
 // Resident blocks per compute unit of the trace kernel variant.
 int trace_blocks_per_cu(bool count, bool grad, int lds_grad_doubles);

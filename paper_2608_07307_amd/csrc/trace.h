@@ -4,8 +4,7 @@
 // trace_closest: closest hit of one ray in a two-level hierarchy (top level
 // over the kinematic-tree nodes in world coordinates; per node a bottom level
 // in rest-pose coordinates entered through the node's rigid transform, which
-// preserves the ray parameter t), with a per-lane stack whose entries are
-// STACK_DEPTH apart by `stride` words.
+// preserves the ray parameter t), with a per-lane traversal stack (LaneStack).
 #pragma once
 #include <math.h>
 #include <stdint.h>
@@ -155,16 +154,52 @@ SRP_HD inline NodeData load_node(const BNode SRP_GLOBAL *n) {
     return v;
 }
 
+// Per-lane traversal stack of up to STACK_DEPTH entries.  The newest entry
+// is held in a register (`top`); below it the next STACK_LDS entries sit in a
+// ring (entry s in slot s mod STACK_LDS, slots `stride` words apart, in LDS on
+// the GPU), and pushing past that evicts the oldest ring entry to the lane's
+// spill array (entry e at spill[e * sstride], global memory on the GPU) while
+// popping brings it back.  A pop therefore never waits for memory: the ring
+// read that refills `top` is needed only by the next pop.  Rays rarely hold
+// more than a handful of entries, so the spill path is almost never taken,
+// but any hierarchy the builder accepts still traverses exactly.
+struct LaneStack {
+    uint32_t *ring;
+    int stride;
+    uint32_t SRP_GLOBAL *spill;
+    int sstride;
+};
+
+// Entry e (0-based from the bottom) of the ring/spill part.
+SRP_HD inline void st_store(const LaneStack &S, int e, uint32_t v) {
+    const int slot = (e & (STACK_LDS - 1)) * S.stride;
+    if (e >= STACK_LDS) S.spill[(e - STACK_LDS) * S.sstride] = S.ring[slot];
+    S.ring[slot] = v;
+}
+SRP_HD inline uint32_t st_load(const LaneStack &S, int e) {
+    // entry e is the newest of the ring part: read it, then refill its slot
+    // with the entry STACK_LDS below it if that one was spilled
+    const int slot = (e & (STACK_LDS - 1)) * S.stride;
+    const uint32_t v = S.ring[slot];
+    if (e >= STACK_LDS) S.ring[slot] = S.spill[(e - STACK_LDS) * S.sstride];
+    return v;
+}
+
 // Closest hit along o + t d, t > tmin, skipping triangle `exclude_id`.
-// The top level is traversed in the world frame; at a top-level leaf the
-// instance's bottom level is traversed in its own (rest-pose) frame until the
-// stack returns to the depth it had on entry, then the top level resumes.
-// Bottom-level traversal descends internal nodes before testing a leaf, so the
-// lanes of a wave test leaves together.  Returns false only when the stack or
-// the visit bound is exceeded (corrupted data).
+// Top-level nodes are tested in the world frame; a top-level leaf enters its
+// instance (the ray in the node's rest-pose frame; t is preserved) and the
+// instance's bottom-level nodes are tested in that frame.  One stack holds
+// both kinds of reference, so a popped reference's type says which frame it
+// belongs to and leaving an instance needs no bookkeeping.  The loop is
+// "descend, then test leaves": every lane steps through inner nodes and
+// instance entries until it holds a leaf (or is done), then the lanes test
+// their leaves together; lanes in different instances advance in the same
+// steps.  The descent loop has a single exit (stack overflow and the visit
+// bound are reported after it).  Returns false only when the stack or the
+// visit bound is exceeded (corrupted data).
 template <bool COUNT>
 SRP_HD inline bool trace_closest(const TraceCtx &C, const float o[3], const float d[3], float tmin,
-                                 int32_t exclude_id, uint32_t *stack, int stride, Hit &h, uint32_t &nbox,
+                                 int32_t exclude_id, const LaneStack &stack, Hit &h, uint32_t &nbox,
                                  uint32_t &ntri, uint32_t *steps = nullptr) {
     h.t = T_INF;
     h.tri = -1;
@@ -173,99 +208,93 @@ SRP_HD inline bool trace_closest(const TraceCtx &C, const float o[3], const floa
     if (C.root == REF_NONE) return true;
     const float wix = safe_inv(d[0]), wiy = safe_inv(d[1]), wiz = safe_inv(d[2]);
     const float woix = o[0] * wix, woiy = o[1] * wiy, woiz = o[2] * wiz;
+    Frame F;   // the current instance's frame
+    F.ix = F.iy = F.iz = F.oix = F.oiy = F.oiz = 0.0f;
+    int inst = -1;
     uint32_t visits = 0;
-    int sp = 0;
+    bool overflow = false;
+    int sp = 0;              // entries on the stack; the newest is `top`
+    uint32_t top = REF_NONE;
     uint32_t ref = C.root;
     for (;;) {
-        // ---- top level (world frame): walk to the next instance to enter
-        while (ref_type(ref) == REF_TLAS_NODE) {
-            if (++visits > MAX_VISITS) return false;
+        // ---- descend: inner nodes of either level and instance entries
+        while (ref_type(ref) != REF_BLAS_LEAF && ref != REF_NONE && visits < MAX_VISITS) {
+            ++visits;
             if (steps) ++*steps;
-            const NodeData N = load_node(C.tlas + ref_index(ref));
-            float t0 = box_enter(N.a.x, N.a.y, N.a.z, N.a.w, N.b.x, N.b.y, wix, wiy, wiz, woix, woiy, woiz, tmin, h.t);
-            float t1 = box_enter(N.b.z, N.b.w, N.c.x, N.c.y, N.c.z, N.c.w, wix, wiy, wiz, woix, woiy, woiz, tmin, h.t);
-            if (COUNT) nbox += 2;
-            bool h0 = t0 != T_INF, h1 = t1 != T_INF;
-            if (h0 && h1) {
-                if (sp >= STACK_DEPTH) return false;
-                stack[sp * stride] = t0 <= t1 ? N.r.y : N.r.x;
-                ++sp;
-                ref = t0 <= t1 ? N.r.x : N.r.y;
-            } else if (h0) {
-                ref = N.r.x;
-            } else if (h1) {
-                ref = N.r.y;
+            if (ref_type(ref) == REF_TLAS_LEAF) {
+                // enter the instance: the ray in the node's rest-pose frame
+                inst = (int)ref_index(ref);
+                const Inst SRP_GLOBAL &I = C.inst[inst];
+                float lo[3], ld[3];
+                const float r0 = o[0] - I.t[0], r1 = o[1] - I.t[1], r2 = o[2] - I.t[2];
+                lo[0] = I.R[0] * r0 + I.R[3] * r1 + I.R[6] * r2;
+                lo[1] = I.R[1] * r0 + I.R[4] * r1 + I.R[7] * r2;
+                lo[2] = I.R[2] * r0 + I.R[5] * r1 + I.R[8] * r2;
+                ld[0] = I.R[0] * d[0] + I.R[3] * d[1] + I.R[6] * d[2];
+                ld[1] = I.R[1] * d[0] + I.R[4] * d[1] + I.R[7] * d[2];
+                ld[2] = I.R[2] * d[0] + I.R[5] * d[1] + I.R[8] * d[2];
+                frame_setup(lo, ld, F);
+                ref = I.root;
             } else {
-                if (sp == 0) return true;
-                ref = stack[--sp * stride];
-            }
-        }
-        // ---- bottom level of one instance (rest-pose frame; t is preserved)
-        const int inst = (int)ref_index(ref);
-        const Inst SRP_GLOBAL &I = C.inst[inst];
-        float lo[3], ld[3];
-        {
-            float r0 = o[0] - I.t[0], r1 = o[1] - I.t[1], r2 = o[2] - I.t[2];
-            lo[0] = I.R[0] * r0 + I.R[3] * r1 + I.R[6] * r2;
-            lo[1] = I.R[1] * r0 + I.R[4] * r1 + I.R[7] * r2;
-            lo[2] = I.R[2] * r0 + I.R[5] * r1 + I.R[8] * r2;
-            ld[0] = I.R[0] * d[0] + I.R[3] * d[1] + I.R[6] * d[2];
-            ld[1] = I.R[1] * d[0] + I.R[4] * d[1] + I.R[7] * d[2];
-            ld[2] = I.R[2] * d[0] + I.R[5] * d[1] + I.R[8] * d[2];
-        }
-        Frame F;
-        frame_setup(lo, ld, F);
-        const int base = sp;
-        ref = I.root;
-        for (;;) {
-            while (ref_type(ref) == REF_BLAS_NODE) {
-                if (++visits > MAX_VISITS) return false;
-                if (steps) ++*steps;
-                const NodeData N = load_node(C.blas + ref_index(ref));
-                float t0 = box_enter(N.a.x, N.a.y, N.a.z, N.a.w, N.b.x, N.b.y, F.ix, F.iy, F.iz, F.oix, F.oiy, F.oiz, tmin, h.t);
-                float t1 = box_enter(N.b.z, N.b.w, N.c.x, N.c.y, N.c.z, N.c.w, F.ix, F.iy, F.iz, F.oix, F.oiy, F.oiz, tmin, h.t);
+                const bool tl = ref_type(ref) == REF_TLAS_NODE;
+                const NodeData N = load_node((tl ? C.tlas : C.blas) + ref_index(ref));
+                const float ix = tl ? wix : F.ix, iy = tl ? wiy : F.iy, iz = tl ? wiz : F.iz;
+                const float oix = tl ? woix : F.oix, oiy = tl ? woiy : F.oiy, oiz = tl ? woiz : F.oiz;
+                const float t0 = box_enter(N.a.x, N.a.y, N.a.z, N.a.w, N.b.x, N.b.y, ix, iy, iz, oix, oiy, oiz, tmin, h.t);
+                const float t1 = box_enter(N.b.z, N.b.w, N.c.x, N.c.y, N.c.z, N.c.w, ix, iy, iz, oix, oiy, oiz, tmin, h.t);
                 if (COUNT) nbox += 2;
-                bool h0 = t0 != T_INF, h1 = t1 != T_INF;
+                const bool h0 = t0 != T_INF, h1 = t1 != T_INF;
                 if (h0 && h1) {
-                    if (sp >= STACK_DEPTH) return false;
-                    stack[sp * stride] = t0 <= t1 ? N.r.y : N.r.x;
-                    ++sp;
-                    ref = t0 <= t1 ? N.r.x : N.r.y;
-                } else if (h0) {
-                    ref = N.r.x;
-                } else if (h1) {
-                    ref = N.r.y;
+                    // descend into the nearer child, push the other
+                    const bool first0 = t0 <= t1;
+                    if (sp < STACK_DEPTH) {
+                        if (sp > 0) st_store(stack, sp - 1, top);
+                        top = first0 ? N.r.y : N.r.x;
+                        ++sp;
+                    } else {
+                        overflow = true;
+                    }
+                    ref = first0 ? N.r.x : N.r.y;
+                } else if (h0 || h1) {
+                    ref = h0 ? N.r.x : N.r.y;
+                } else if (sp > 0) {
+                    ref = top;
+                    --sp;
+                    if (sp > 0) top = st_load(stack, sp - 1);
                 } else {
-                    ref = sp > base ? stack[--sp * stride] : REF_NONE;
+                    ref = REF_NONE;
                 }
             }
-            if (ref == REF_NONE) break;
-            // leaf: test its triangles
-            if (++visits > MAX_VISITS) return false;
-            if (steps) ++*steps;
-            const uint32_t p = ref_index(ref);
-            const uint32_t first = p >> 3, cnt = (p & 7u) + 1u;
-            for (uint32_t k = 0; k < cnt; ++k) {
-                const float4 SRP_GLOBAL *q = (const float4 SRP_GLOBAL *)(C.tris + first + k);
-                const float4 A = q[0], B = q[1], Cc = q[2];
-                const int32_t id = f2i(A.w);
-                if (COUNT) ntri++;
-                if (id == exclude_id) continue;
-                const float va[3] = {A.x, A.y, A.z}, vb[3] = {B.x, B.y, B.z}, vc[3] = {Cc.x, Cc.y, Cc.z};
-                const float t = tri_hit(F, va, vb, vc);
-                if (t > tmin && (t < h.t || (t == h.t && id < h.id))) {
-                    h.t = t;
-                    h.tri = (int32_t)(first + k);
-                    h.inst = inst;
-                    h.id = id;
-                }
-            }
-            if (sp == base) break;
-            ref = stack[--sp * stride];
         }
-        // ---- back to the top level
-        if (sp == 0) return true;
-        ref = stack[--sp * stride];
+        if (overflow || visits >= MAX_VISITS) return false;
+        if (ref == REF_NONE) return true;
+        // ---- leaf: test its triangles (in the current instance's frame)
+        ++visits;
+        if (steps) ++*steps;
+        const uint32_t p = ref_index(ref);
+        const uint32_t first = p >> 3, cnt = (p & 7u) + 1u;
+        for (uint32_t k = 0; k < cnt; ++k) {
+            const float4 SRP_GLOBAL *q = (const float4 SRP_GLOBAL *)(C.tris + first + k);
+            const float4 A = q[0], B = q[1], Cc = q[2];
+            const int32_t id = f2i(A.w);
+            if (COUNT) ntri++;
+            if (id == exclude_id) continue;
+            const float va[3] = {A.x, A.y, A.z}, vb[3] = {B.x, B.y, B.z}, vc[3] = {Cc.x, Cc.y, Cc.z};
+            const float t = tri_hit(F, va, vb, vc);
+            if (t > tmin && (t < h.t || (t == h.t && id < h.id))) {
+                h.t = t;
+                h.tri = (int32_t)(first + k);
+                h.inst = inst;
+                h.id = id;
+            }
+        }
+        if (sp > 0) {
+            ref = top;
+            --sp;
+            if (sp > 0) top = st_load(stack, sp - 1);
+        } else {
+            ref = REF_NONE;
+        }
     }
 }
 }  // namespace srp

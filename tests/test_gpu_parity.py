@@ -268,7 +268,7 @@ def test_autograd_function(srp):
 
 
 def test_schedules_plans_and_autotune(srp):
-    """Forces are bitwise identical under every schedule (per-tile partial
+    """Forces are bitwise identical under every schedule (per-patch partial
     sums); a captured plan replays bitwise the direct batch, also after an
     update with new Sun directions and angles; the autotuner returns a valid
     schedule that is then used."""
@@ -280,10 +280,10 @@ def test_schedules_plans_and_autotune(srp):
     angs = rng.uniform(-1.0, 1.0, size=(24, mesh.n_dof))
     entries = [(sc, angs[k % 6], srp.params(dirs[k], [64, 96, 160][k % 3], k % 3)) for k in range(24)]
     ref = srp.results_to_numpy(srp.eval_batch(entries)).copy()
-    for rpt, bpc in ((1, 1), (2, 3), (8, 0), (16, 2), (0, 0)):
-        srp.set_schedule(rpt, bpc)
+    for ppc, bpc in ((1, 1), (2, 3), (3, 2), (8, 0), (16, 2), (64, 4), (0, 0)):
+        srp.set_schedule(ppc, bpc)
         got = srp.results_to_numpy(srp.eval_batch(entries))
-        assert got.tobytes() == ref.tobytes(), (rpt, bpc)
+        assert got.tobytes() == ref.tobytes(), (ppc, bpc)
     srp.set_schedule(0, 0)
     plan = srp.Plan(entries)
     for _ in range(3):
@@ -297,7 +297,7 @@ def test_schedules_plans_and_autotune(srp):
     ref2 = srp.results_to_numpy(srp.eval_batch(entries2))
     assert out2.tobytes() == ref2.tobytes()
     r, b, ms = srp.autotune(entries)
-    print(f"autotune: tiles/chunk {r} blocks/CU {b} {ms:.3f} ms", flush=True)
-    assert r in (1, 2, 4, 8, 16) and b >= 1 and ms > 0
+    print(f"autotune: patches/chunk {r} blocks/CU {b} {ms:.3f} ms", flush=True)
+    assert r in (1, 2, 4, 8, 16, 32, 64) and b >= 1 and ms > 0
     assert srp.results_to_numpy(srp.eval_batch(entries)).tobytes() == ref.tobytes()
     plan.close()
