@@ -61,14 +61,9 @@ def main():
     torch.cuda.set_device(dev)
     log = lambda *a: print(*a, file=sys.stderr, flush=True)  # noqa: E731
 
-    mesh = synth.procedural_spacecraft(seed=2)
+    mesh, dirs, angles, _, _ = synth.c2_batch(args.batch)
     scene = srp.Scene(mesh)
     B, N, E = args.bounces, args.n, args.batch
-    dirs = synth.fibonacci_dirs(E)
-    rng = np.random.default_rng(1002)
-    angles = np.zeros((E, mesh.n_dof))
-    roots = [0, mesh.n_dof // 2]                      # the two wing root hinges
-    angles[:, roots] = rng.uniform(-np.pi / 2, np.pi / 2, size=(E, 2))
     entries = [(scene, angles[k], srp.params(dirs[k], N, B)) for k in range(E)]
     stride = 3 * (2 * mesh.n_mats + mesh.n_dof)
     out = torch.empty(E * srp.RESULT_DTYPE.itemsize, dtype=torch.uint8, device=dev)

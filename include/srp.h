@@ -165,7 +165,10 @@ int srp_eval(srp_scene *scene, const srp_eval_params *params, srp_result *out,
  * fixed-order reduction).  out_dev: device array of n_items srp_result,
  * written in stream order on hip_stream (a hipStream_t; NULL = null stream).
  * The call returns once the work is queued; host inputs may be reused then.
- * Results are bitwise independent of scheduling.  Errors as srp_eval, checked
+ * A batch whose device workspace (about 64 bytes per 8x8-pixel patch, plus
+ * gradient partials) would exceed 2 GiB runs as consecutive sub-batches; the
+ * call may then block while earlier sub-batches run.  Results are bitwise
+ * independent of scheduling and of that split.  Errors as srp_eval, checked
  * for every item before anything is queued. */
 int srp_eval_batch(const srp_batch_item *items, int64_t n_items, srp_result *out_dev,
                    void *hip_stream);

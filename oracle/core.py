@@ -204,10 +204,10 @@ def shade_frozen(scene, sun_dir, n, bounces, grid: dict, ids, pressure=1.0, ref=
 
 
 def fd_gradients(scene, sun_dir, n, bounces, grid, ids, pressure=1.0, angles=None, h=1e-4,
-                 which=("rho_s", "rho_d", "theta")):
+                 which=("rho_s", "rho_d", "theta"), theta_idx=None):
     """Central finite differences (FP64) of the fixed-visibility force with
-    respect to each material's rho_s and rho_d and each hinge angle.
-    Returns dict name -> array (count, 3)."""
+    respect to each material's rho_s and rho_d and each hinge angle (or the
+    hinges listed in theta_idx).  Returns dict name -> array (count, 3)."""
     ang = np.zeros(scene.n_dof) if angles is None else np.asarray(angles, float).copy()
     out = {}
 
@@ -225,12 +225,13 @@ def fd_gradients(scene, sun_dir, n, bounces, grid, ids, pressure=1.0, angles=Non
             g[m] = (F(_unchecked(scene, mp), ang) - F(_unchecked(scene, mm), ang)) / (2 * h)
         out[name] = g
     if "theta" in which:
-        g = np.zeros((scene.n_dof, 3))
-        for j in range(scene.n_dof):
+        idx = range(scene.n_dof) if theta_idx is None else list(theta_idx)
+        g = np.zeros((len(idx), 3))
+        for r, j in enumerate(idx):
             ap, am = ang.copy(), ang.copy()
             ap[j] += h
             am[j] -= h
-            g[j] = (F(scene, ap) - F(scene, am)) / (2 * h)
+            g[r] = (F(scene, ap) - F(scene, am)) / (2 * h)
         out["theta"] = g
     return out
 

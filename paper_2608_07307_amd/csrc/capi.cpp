@@ -265,7 +265,22 @@ int check_items(const srp_batch_item *items, int64_t n, bool grad, const BatchOu
     return SRP_OK;
 }
 
-Schedule pick_schedule(const srp_batch_item *items, int64_t n, bool grad, int64_t total_patches, int occ) {
+// Gradient partials are per chunk: a launch keeps them under this many bytes
+// by raising the patches per chunk; a batch whose whole device workspace
+// would exceed WORKSPACE_CAP runs as consecutive sub-batches.
+constexpr size_t GRAD_PART_CAP = (size_t)256 << 20;
+constexpr size_t WORKSPACE_CAP = (size_t)2 << 30;
+
+// Smallest power-of-two patches per chunk (<= MAX_PPC) whose gradient partials fit GRAD_PART_CAP.
+int min_ppc_for_grad(int64_t total_patches, int max_grad_n) {
+    int ppc = 1;
+    while (ppc < MAX_PPC && (size_t)((total_patches + ppc - 1) / ppc) * max_grad_n * sizeof(double) > GRAD_PART_CAP)
+        ppc *= 2;
+    return ppc;
+}
+
+Schedule pick_schedule(const srp_batch_item *items, int64_t n, bool grad, int64_t total_patches, int occ,
+                       int max_grad_n) {
     Schedule s = g_override;
     if (!s.ppc || !s.bpc) {
         auto f = g_tuned.find(tune_key(items, n, grad));
@@ -282,6 +297,7 @@ Schedule pick_schedule(const srp_batch_item *items, int64_t n, bool grad, int64_
         s.ppc = 1;
         while (s.ppc < 4 && total_patches / (2 * s.ppc) >= 16 * resident) s.ppc *= 2;
     }
+    if (grad) s.ppc = std::max(s.ppc, min_ppc_for_grad(total_patches, max_grad_n));
     s.bpc = std::max(1, std::min(s.bpc, occ));
     return s;
 }
@@ -307,9 +323,10 @@ int layout_build(const srp_batch_item *items, int64_t n, bool grad, Schedule for
     }
     L.patch_base[n] = L.total_patches;
     int occ = trace_blocks_per_cu(L.count, grad, L.max_grad_n);
-    L.sch = (force.ppc && force.bpc) ? force : pick_schedule(items, n, grad, L.total_patches, occ);
+    L.sch = (force.ppc && force.bpc) ? force : pick_schedule(items, n, grad, L.total_patches, occ, L.max_grad_n);
     if (force.ppc) L.sch.ppc = force.ppc;
     if (force.bpc) L.sch.bpc = std::min(force.bpc, occ);
+    if (grad) L.sch.ppc = std::max(L.sch.ppc, min_ppc_for_grad(L.total_patches, L.max_grad_n));
     for (int64_t k = 0; k < n; ++k) {
         L.chunk_base[k] = L.total_chunks;
         L.total_chunks += (L.patch_base[k + 1] - L.patch_base[k] + L.sch.ppc - 1) / L.sch.ppc;
@@ -469,6 +486,8 @@ int enqueue(const Layout &L, char *Dv, const char *H, size_t copy_bytes, const B
 }
 
 // Queues one batch on `stream` through the shared workspace.  Caller holds g_ws.mu.
+// A batch whose device workspace would exceed WORKSPACE_CAP is split into
+// halves, run one after the other (results land at their items' offsets).
 int run_batch(const srp_batch_item *items, int64_t n, bool grad, const BatchOut &bo, hipStream_t stream,
               Schedule force = Schedule()) {
     if (n <= 0) return SRP_OK;
@@ -476,6 +495,15 @@ int run_batch(const srp_batch_item *items, int64_t n, bool grad, const BatchOut 
     if (rc) return rc;
     Layout L;
     if ((rc = layout_build(items, n, grad, force, &L))) return rc;
+    if (L.dev_bytes > WORKSPACE_CAP && n > 1) {
+        const int64_t h = n / 2;
+        BatchOut b2 = bo;
+        b2.d_out = bo.d_out + h;
+        if (bo.d_grad) b2.d_grad = bo.d_grad + h * bo.grad_stride;
+        if (bo.h_copy) b2.h_copy = bo.h_copy + h;
+        if ((rc = run_batch(items, h, grad, bo, stream, force))) return rc;
+        return run_batch(items + h, n - h, grad, b2, stream, force);
+    }
     if ((rc = ws_wait())) return rc;   // staging and workspace reuse
     if ((rc = ws_reserve(L.dev_bytes, L.stage_bytes))) return rc;
     staging_fill(L, items, bo, g_ws.h_stage, g_ws.d_buf);
@@ -979,6 +1007,7 @@ int srp_autotune(const srp_batch_item *items, int64_t n_items, int32_t flags, in
         for (int ppc = 1; ppc <= MAX_PPC; ppc *= 2) {
             const int64_t chunks = (total_patches + ppc - 1) / ppc;
             if ((chunks < resident && ppc > 1) || chunks > 64 * resident) continue;
+            if (grad && ppc < min_ppc_for_grad(total_patches, mg)) continue;
             Schedule sc;
             sc.ppc = ppc;
             sc.bpc = b;
@@ -986,7 +1015,7 @@ int srp_autotune(const srp_batch_item *items, int64_t n_items, int32_t flags, in
         }
         if (b == 1) break;
     }
-    if (cands.empty()) cands.push_back(pick_schedule(items, n_items, grad, total_patches, occ));
+    if (cands.empty()) cands.push_back(pick_schedule(items, n_items, grad, total_patches, occ, mg));
     for (const Schedule &sc : cands) {
         double tmin = INFINITY;
         for (int rep = 0; rep < 3 && rc == 0; ++rep) {

@@ -129,7 +129,55 @@ struct alignas(64) EvalDesc {
 };
 
 // The host writes these records and the kernels read them: both compilation
-// passes must agree on every offset.
+// passes (host and gfx950) must agree on every offset.
+static_assert(sizeof(EvalDesc) == 320, "EvalDesc layout");
+static_assert(offsetof(EvalDesc, tris) == 0, "EvalDesc layout");
+static_assert(offsetof(EvalDesc, blas) == 8, "EvalDesc layout");
+static_assert(offsetof(EvalDesc, mats) == 16, "EvalDesc layout");
+static_assert(offsetof(EvalDesc, wpts) == 24, "EvalDesc layout");
+static_assert(offsetof(EvalDesc, n_wpts) == 32, "EvalDesc layout");
+static_assert(offsetof(EvalDesc, inst) == 40, "EvalDesc layout");
+static_assert(offsetof(EvalDesc, tlas) == 48, "EvalDesc layout");
+static_assert(offsetof(EvalDesc, xf) == 56, "EvalDesc layout");
+static_assert(offsetof(EvalDesc, axw) == 64, "EvalDesc layout");
+static_assert(offsetof(EvalDesc, dof_node) == 72, "EvalDesc layout");
+static_assert(offsetof(EvalDesc, parent) == 80, "EvalDesc layout");
+static_assert(offsetof(EvalDesc, root_ref) == 88, "EvalDesc layout");
+static_assert(offsetof(EvalDesc, n_nodes) == 92, "EvalDesc layout");
+static_assert(offsetof(EvalDesc, n_mats) == 96, "EvalDesc layout");
+static_assert(offsetof(EvalDesc, n_dof) == 100, "EvalDesc layout");
+static_assert(offsetof(EvalDesc, u) == 104, "EvalDesc layout");
+static_assert(offsetof(EvalDesc, v) == 128, "EvalDesc layout");
+static_assert(offsetof(EvalDesc, d) == 152, "EvalDesc layout");
+static_assert(offsetof(EvalDesc, pressure) == 176, "EvalDesc layout");
+static_assert(offsetof(EvalDesc, ref) == 184, "EvalDesc layout");
+static_assert(offsetof(EvalDesc, n) == 208, "EvalDesc layout");
+static_assert(offsetof(EvalDesc, bounces) == 212, "EvalDesc layout");
+static_assert(offsetof(EvalDesc, flags) == 216, "EvalDesc layout");
+static_assert(offsetof(EvalDesc, tiles_x) == 220, "EvalDesc layout");
+static_assert(offsetof(EvalDesc, ppc) == 224, "EvalDesc layout");
+static_assert(offsetof(EvalDesc, grad_n) == 228, "EvalDesc layout");
+static_assert(offsetof(EvalDesc, chunk_base) == 232, "EvalDesc layout");
+static_assert(offsetof(EvalDesc, n_chunks) == 240, "EvalDesc layout");
+static_assert(offsetof(EvalDesc, patch_base) == 248, "EvalDesc layout");
+static_assert(offsetof(EvalDesc, n_patches) == 256, "EvalDesc layout");
+static_assert(offsetof(EvalDesc, tiles_y) == 264, "EvalDesc layout");
+static_assert(offsetof(EvalDesc, hit_ids) == 272, "EvalDesc layout");
+static_assert(offsetof(EvalDesc, hit_t) == 280, "EvalDesc layout");
+static_assert(offsetof(EvalDesc, grad_part) == 288, "EvalDesc layout");
+static_assert(offsetof(EvalDesc, grad_out) == 296, "EvalDesc layout");
+static_assert(sizeof(PatchOut) == 64, "PatchOut layout");
+static_assert(offsetof(PatchOut, f) == 0, "PatchOut layout");
+static_assert(offsetof(PatchOut, hits) == 48, "PatchOut layout");
+static_assert(offsetof(PatchOut, flags) == 60, "PatchOut layout");
+static_assert(sizeof(WPoint) == 32, "WPoint layout");
+static_assert(offsetof(WPoint, node) == 24, "WPoint layout");
+static_assert(offsetof(Inst, t) == 36, "Inst layout");
+static_assert(offsetof(Inst, root) == 48, "Inst layout");
+static_assert(offsetof(BNode, ref0) == 48, "BNode layout");
+static_assert(offsetof(TriRec, id) == 12, "TriRec layout");
+static_assert(offsetof(TriRec, mat) == 28, "TriRec layout");
+static_assert(offsetof(TriRec, node) == 44, "TriRec layout");
 
 // Order-preserving map of doubles to unsigned 64-bit integers (for
 // atomic min/max of the window bounds).

@@ -187,6 +187,26 @@ def plate(origin, eu, ev, rho=(0.3, 0.2), nu=1, nv=1) -> Scene:
     return b.build([rho], name="plate")
 
 
+def stacked_plates(n_plates=1 << 19, spacing=1e-5, size=1.0, rho=(0.4, 0.2), power=1.0) -> Scene:
+    """n_plates identical size x size squares (2 triangles each) at heights
+    z_i = spacing * i**power: a ray along -z passes through every plate, so
+    both children of every hierarchy node on the way to the top plate are hit
+    (a traversal stack as deep as the tree; power > 1 crowds the plates
+    towards z = 0, which makes the tree deeper than a balanced one)."""
+    n = int(n_plates)
+    z = np.arange(n, dtype=np.float64) ** power * spacing
+    sq = np.array([[0, 0], [size, 0], [size, size], [0, size]], np.float64)
+    verts = np.empty((n, 4, 3))
+    verts[:, :, :2] = sq[None]
+    verts[:, :, 2] = z[:, None]
+    base = 4 * np.arange(n, dtype=np.int64)[:, None]
+    tris = np.concatenate([base + np.array([0, 1, 2]), base + np.array([0, 2, 3])], axis=1).reshape(-1, 3)
+    one = np.zeros(1, np.int32)
+    return Scene(verts.reshape(-1, 3), tris.astype(np.int32), np.zeros(2 * n, np.int32), np.zeros(2 * n, np.int32),
+                 np.array([rho], np.float64), np.array([-1], np.int32), one, np.zeros((1, 3)), one,
+                 np.zeros((1, 3, 3)), np.zeros((1, 3)), np.zeros((1, 3)), name="stacked_plates")
+
+
 def hinged_plate(width=2.0, length=3.0, rho=(0.3, 0.2), axis=(0, 1, 0),
                  pivot=(0, 0, 0), lim=HALF_PI) -> Scene:
     """Root with no triangles + one panel node: plate x in [-w/2,w/2],

@@ -108,3 +108,18 @@ def compare_eval(mesh, angles, sun, n, bounces, gpu, orc, pressure=1.0):
     rep["t_err_vis_matched"] = torque_err(gpu["torque"], vm.torque, vm.force, grid["L"])
     rep["hits_gpu"], rep["hits_orc"] = int(gpu["n_hits"]), int(orc.n_hits)
     return rep
+
+
+def check_report(rep, strict=True):
+    """Primary ids equal outside the edge band; the visibility-matched force
+    and torque (oracle physics on the GPU's hits) within F_TOL; the plain
+    force within F_TOL when no ray flipped, else within what the flipped rays
+    can carry (each moves F by about 1/N_hit; bound 4/N_hit per flipped ray)."""
+    assert rep["primary_outside_band"] == 0, rep
+    assert rep["f_err_vis_matched"] <= F_TOL, rep
+    assert rep["t_err_vis_matched"] <= F_TOL, rep
+    if strict:
+        flips = rep["primary_mismatch"] + rep.get("secondary_mismatch", 0)
+        allow = F_TOL + 4.0 * flips / max(rep["hits_orc"], 1)
+        assert rep["f_err"] <= allow, rep
+        assert rep["t_err"] <= allow, rep
