@@ -31,6 +31,24 @@ sys.path.insert(0, ROOT)
 
 PEAK_LANE_OPS = 256 * 64 * 2.4e9     # CUs x lanes x clock: one VALU lane-op per lane per cycle
 BOX_OPS, TRI_OPS = 10, 30             # algorithmic lane-ops per ray-box / ray-triangle test
+TRAFFIC = os.path.join(ROOT, "profiles", "k_trace_grad_traffic.json")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the adjoint trace kernel from the committed
+    FETCH_SIZE / WRITE_SIZE counter runs, or None when the kernel sources have
+    changed since those counters were taken."""
+    import hashlib
+    try:
+        with open(TRAFFIC) as f:
+            rec = json.load(f)
+        h = hashlib.sha256()
+        for src in rec["sources"]:
+            with open(os.path.join(ROOT, src), "rb") as f:
+                h.update(f.read())
+        return rec["traffic_bytes_per_launch"] if h.hexdigest() == rec["sources_sha256"] else None
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def main():
@@ -44,6 +62,8 @@ def main():
     ap.add_argument("--plain", type=int, default=16, help="evaluations timed on the plain path")
     ap.add_argument("--cpu-samples", type=int, default=2, help="batch items the oracle times (0: skip)")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (profiling runs)")
+    ap.add_argument("--schedule", default="", help="PPC,BPC: fixed patches per chunk and blocks per CU "
+                    "for both launches (implies --no-tune; profiling runs)")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="also run a device copy of this many MiB (calibrates memory counters)")
     args = ap.parse_args()
@@ -91,7 +111,12 @@ def main():
 
     # schedule: the autotuner picks tiles per chunk and blocks per CU (untimed)
     tune = (0, 0, 0.0)
-    if not args.no_tune:
+    if args.schedule:
+        ppc, bpc = (int(x) for x in args.schedule.split(","))
+        srp.set_schedule(ppc, bpc)
+        tune = (ppc, bpc, 0.0)
+        log(f"schedule fixed: patches/chunk {ppc}, blocks/CU {bpc}")
+    elif not args.no_tune:
         tune = srp.autotune(entries, grad=True)
         log(f"autotune (forward+adjoint): patches/chunk {tune[0]}, blocks/CU {tune[1]}, {tune[2]:.3f} ms")
         tune_fwd = srp.autotune(entries, grad=False)
@@ -203,7 +228,8 @@ def main():
             "peak": round(peak, 4),
             "unit": "Tlane-op/s",
             "frac": round(achieved / peak, 4),
-            "traffic": None,
+            "traffic": measured_traffic(),
+            "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "kernel": "k_trace<GRAD> (forward + adjoint)",
             "work_per_launch": {"box_tests": n_box, "tri_tests": n_tri,
                                 "lane_ops": work, "ops_per_box": BOX_OPS, "ops_per_tri": TRI_OPS},
