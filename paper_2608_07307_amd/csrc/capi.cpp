@@ -21,7 +21,7 @@ struct srp_scene {
     int device = 0;
     SceneHost h;
     TriRec *d_tris = nullptr;
-    BNode *d_blas = nullptr;
+    BNode4 *d_blas = nullptr;
     float *d_mats = nullptr;
     WPoint *d_wpts = nullptr;
     int32_t *d_parent = nullptr;
@@ -422,7 +422,7 @@ void staging_fill(const Layout &L, const srp_batch_item *items, const BatchOut &
             root = sc->cur.root_ref;
         }
         D.inst = reinterpret_cast<const Inst *>(slot_base + SL.inst);
-        D.tlas = reinterpret_cast<const BNode *>(slot_base + SL.tlas);
+        D.tlas = reinterpret_cast<const BNode4 *>(slot_base + SL.tlas);
         D.xf = reinterpret_cast<const double *>(slot_base + SL.xf);
         D.axw = reinterpret_cast<const double *>(slot_base + SL.axw);
         D.dof_node = reinterpret_cast<const int32_t *>(slot_base + SL.dof_node);
@@ -694,7 +694,7 @@ int srp_build_scene(const double *verts, int64_t n_verts, const int32_t *tris, i
     if ((rc = upload_slot(sc))) { free_scene(sc); return rc; }
     // the host copies of the large arrays are no longer needed
     std::vector<TriRec>().swap(sc->h.tris);
-    std::vector<BNode>().swap(sc->h.blas);
+    std::vector<BNode4>().swap(sc->h.blas);
     sc->h.wpts.shrink_to_fit();
     *out = sc;
     return SRP_OK;

@@ -18,7 +18,8 @@ struct NodeInfo {
     double lo[3] = {0}, hi[3] = {0};
     int32_t dof_offset = 0;
     uint32_t blas_root = REF_NONE;   // REF_NONE when the node has no triangles
-    int32_t blas_depth = 0;
+    int32_t blas_depth = 0;          // 4-wide levels
+    int32_t blas_worst = 0;          // most traversal-stack entries a ray can hold in this hierarchy
     double blo[3] = {0}, bhi[3] = {0};  // padded rest-pose bounds of the node's triangles
     double n0[3] = {0, 0, 0};           // area-weighted rest-pose normal (unit, or 0 if none)
 };
@@ -26,9 +27,10 @@ struct NodeInfo {
 // Host image of one articulation slot (see srp_internal.h for the layout).
 struct SlotHost {
     std::vector<Inst> inst;
-    std::vector<BNode> tlas;
+    std::vector<BNode4> tlas;
     uint32_t root_ref = REF_NONE;
     int tlas_depth = 0;
+    int stack_worst = 0;           // most traversal-stack entries a ray can hold
     std::vector<double> xf;        // K x 12: R (row-major) then t
     std::vector<double> axw;       // J x 3
     std::vector<int32_t> dof_node; // J
@@ -47,7 +49,7 @@ struct SceneHost {
     std::vector<NodeInfo> nodes;
     std::vector<float> mats;        // 2 per material
     std::vector<TriRec> tris;       // leaf order
-    std::vector<BNode> blas;
+    std::vector<BNode4> blas;
     std::vector<WPoint> wpts;
     std::vector<int32_t> parent;
     double pad = 0;                 // box padding (metres)

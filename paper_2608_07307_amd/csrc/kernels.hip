@@ -380,7 +380,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(GRAD ? SR
     }
 }
 
-constexpr int WBLOCK = 256;   // threads per block of the window and reduce kernels
+constexpr int WBLOCK = 256;   // threads per block of the window kernel
 
 // Loop strides use compile-time block sizes and an explicit grid-width
 // argument, so termination never depends on runtime-filled dispatch values.
@@ -422,19 +422,22 @@ __global__ __launch_bounds__(WBLOCK) void k_window(const EvalDesc *__restrict__ 
     }
 }
 
+constexpr int RBLOCK = 1024;   // threads per block of the reduce kernel (one block per evaluation)
+
 template <bool COUNT, bool GRAD>
-__global__ __launch_bounds__(WBLOCK) void k_reduce(const EvalDesc *__restrict__ descs,
+__global__ __launch_bounds__(RBLOCK) void k_reduce(const EvalDesc *__restrict__ descs,
                                                 const int64_t *__restrict__ patch_base,
                                                 const uint64_t *__restrict__ win,
                                                 const PatchOut *__restrict__ patches,
                                                 const uint64_t *__restrict__ counts, srp_result *out) {
-    const int e = blockIdx.x, tid = threadIdx.x;
+    const int e = blockIdx.x, tid = threadIdx.x, lane = tid & (WAVE - 1), wid = tid >> 6;
     const EvalDesc &D = descs[e];
+    // patch partials: per-thread strided sums, wave butterflies, waves in order
     const int64_t c0 = patch_base[e], c1 = patch_base[e + 1];
     double f[6] = {0, 0, 0, 0, 0, 0};
-    uint64_t cn[5] = {0, 0, 0, 0, 0};
+    unsigned long long cn[5] = {0, 0, 0, 0, 0};
     uint32_t st = 0;
-    for (int64_t c = c0 + tid; c < c1; c += WBLOCK) {
+    for (int64_t c = c0 + tid; c < c1; c += RBLOCK) {
         const PatchOut &co = patches[c];
         for (int k = 0; k < 6; ++k) f[k] += co.f[k];
         cn[0] += co.hits;
@@ -443,21 +446,20 @@ __global__ __launch_bounds__(WBLOCK) void k_reduce(const EvalDesc *__restrict__ 
         st |= co.flags;
         if (COUNT) { cn[3] += counts[2 * c]; cn[4] += counts[2 * c + 1]; }
     }
-    __shared__ double sf[256][6];
-    __shared__ unsigned long long sc[256][5];
-    __shared__ uint32_t ss[256];
-    for (int k = 0; k < 6; ++k) sf[tid][k] = f[k];
-    for (int k = 0; k < 5; ++k) sc[tid][k] = cn[k];
-    ss[tid] = st;
-    __syncthreads();
-    for (int s = 128; s >= 1; s >>= 1) {
-        if (tid < s) {
-            for (int k = 0; k < 6; ++k) sf[tid][k] += sf[tid + s][k];
-            for (int k = 0; k < 5; ++k) sc[tid][k] += sc[tid + s][k];
-            ss[tid] |= ss[tid + s];
-        }
-        __syncthreads();
+    for (int k = 0; k < 6; ++k) f[k] = wave_sum(f[k]);
+    for (int m = 32; m >= 1; m >>= 1) {
+        for (int k = 0; k < 5; ++k) cn[k] += __shfl_xor(cn[k], m, WAVE);
+        st |= __shfl_xor(st, m, WAVE);
     }
+    __shared__ double sf[RBLOCK / WAVE][6];
+    __shared__ unsigned long long sc[RBLOCK / WAVE][5];
+    __shared__ uint32_t ss[RBLOCK / WAVE];
+    if (lane == 0) {
+        for (int k = 0; k < 6; ++k) sf[wid][k] = f[k];
+        for (int k = 0; k < 5; ++k) sc[wid][k] = cn[k];
+        ss[wid] = st;
+    }
+    __syncthreads();
     const uint64_t *W = win + (size_t)e * WIN_STRIDE;
     const double umin = dec_f64(W[0]), umax = -dec_f64(W[1]);
     const double vmin = dec_f64(W[2]), vmax = -dec_f64(W[3]);
@@ -465,18 +467,26 @@ __global__ __launch_bounds__(WBLOCK) void k_reduce(const EvalDesc *__restrict__ 
     const bool empty = !(wu * wv > 0.0) || !(wu < INFINITY) || !(wv < INFINITY) || D.root_ref == REF_NONE;
     const double scale = empty ? 0.0 : D.pressure * (wu * wv / ((double)D.n * (double)D.n));
     if (tid == 0) {
+        double F[6] = {0, 0, 0, 0, 0, 0};
+        unsigned long long N[5] = {0, 0, 0, 0, 0};
+        uint32_t S = 0;
+        for (int w = 0; w < RBLOCK / WAVE; ++w) {
+            for (int k = 0; k < 6; ++k) F[k] += sf[w][k];
+            for (int k = 0; k < 5; ++k) N[k] += sc[w][k];
+            S |= ss[w];
+        }
         srp_result r;
         for (int k = 0; k < 3; ++k) {
-            r.force[k] = scale * sf[0][k];
-            r.torque[k] = scale * sf[0][3 + k];
+            r.force[k] = scale * F[k];
+            r.torque[k] = scale * F[3 + k];
         }
         r.n_rays = (int64_t)D.n * D.n;
-        r.n_hits = (int64_t)sc[0][0];
-        r.n_secondary = (int64_t)sc[0][1];
-        r.n_secondary_hits = (int64_t)sc[0][2];
-        r.n_box_tests = COUNT ? (int64_t)sc[0][3] : 0;
-        r.n_tri_tests = COUNT ? (int64_t)sc[0][4] : 0;
-        r.status = ss[0];
+        r.n_hits = (int64_t)N[0];
+        r.n_secondary = (int64_t)N[1];
+        r.n_secondary_hits = (int64_t)N[2];
+        r.n_box_tests = COUNT ? (int64_t)N[3] : 0;
+        r.n_tri_tests = COUNT ? (int64_t)N[4] : 0;
+        r.status = S;
         r.reserved = 0;
         out[e] = r;
     }
@@ -488,46 +498,42 @@ __global__ __launch_bounds__(WBLOCK) void k_reduce(const EvalDesc *__restrict__ 
         // the result depends only on the batch layout.
         const int G = D.grad_n, K = D.n_nodes, M = D.n_mats, J = D.n_dof;
         __shared__ double sg[MAX_GRAD_SLOTS];
-        __shared__ double sl[WBLOCK];
+        __shared__ double sl[RBLOCK];
         const double *gp = D.grad_part;
         const int64_t NC = D.n_chunks;
-        const int P = (G > 0 && G <= WBLOCK) ? WBLOCK / G : 1;
+        const int P = (G > 0 && G <= RBLOCK) ? RBLOCK / G : 1;
         auto slice_sum = [&](int i, int64_t c0, int64_t c1) {
-            double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+            double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
             int64_t c = c0;
-            for (; c + 4 <= c1; c += 4) {
-                a0 += gp[(size_t)c * G + i];
-                a1 += gp[(size_t)(c + 1) * G + i];
-                a2 += gp[(size_t)(c + 2) * G + i];
-                a3 += gp[(size_t)(c + 3) * G + i];
-            }
-            for (; c < c1; ++c) a0 += gp[(size_t)c * G + i];
-            return (a0 + a1) + (a2 + a3);
+            for (; c + 8 <= c1; c += 8)
+                for (int u = 0; u < 8; ++u) a[u] += gp[(size_t)(c + u) * G + i];
+            for (; c < c1; ++c) a[0] += gp[(size_t)c * G + i];
+            return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
         };
         if (P > 1) {
             const int i = tid % G, p = tid / G;
             if (p < P) sl[p * G + i] = slice_sum(i, NC * p / P, NC * (p + 1) / P);
             __syncthreads();
-            for (int j = tid; j < G; j += WBLOCK) {
+            for (int j = tid; j < G; j += RBLOCK) {
                 double t = 0.0;
                 for (int q = 0; q < P; ++q) t += sl[q * G + j];
                 sg[j] = t;
             }
         } else {
-            for (int j = tid; j < G; j += WBLOCK) sg[j] = slice_sum(j, 0, NC);
+            for (int j = tid; j < G; j += RBLOCK) sg[j] = slice_sum(j, 0, NC);
         }
         __syncthreads();
         double *g = D.grad_out;
         if (g) {
             // rho_s (M x 3), rho_d (M x 3)
-            for (int i = tid; i < 6 * M; i += WBLOCK) {
+            for (int i = tid; i < 6 * M; i += RBLOCK) {
                 int m = i / 6, k = i % 6;
                 double v = scale * sg[9 * K + i];
                 if (k < 3) g[3 * m + k] = v;
                 else g[3 * M + 3 * m + (k - 3)] = v;
             }
             // theta: (sum of S_q over the subtree of the joint's node) * world axis
-            for (int j = tid; j < J; j += WBLOCK) {
+            for (int j = tid; j < J; j += RBLOCK) {
                 const int p = D.dof_node[j];
                 double S[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
                 for (int q = 0; q < K; ++q) {
@@ -586,13 +592,13 @@ int launch_reduce(const EvalDesc *d_desc, const int64_t *d_tile_base, int n_eval
     hipStream_t s = (hipStream_t)stream;
     srp_result *out = (srp_result *)d_out;
     if (count && grad)
-        hipLaunchKernelGGL((k_reduce<true, true>), dim3(n_evals), dim3(WBLOCK), 0, s, d_desc, d_tile_base, d_win, d_chunks, d_counts, out);
+        hipLaunchKernelGGL((k_reduce<true, true>), dim3(n_evals), dim3(RBLOCK), 0, s, d_desc, d_tile_base, d_win, d_chunks, d_counts, out);
     else if (count)
-        hipLaunchKernelGGL((k_reduce<true, false>), dim3(n_evals), dim3(WBLOCK), 0, s, d_desc, d_tile_base, d_win, d_chunks, d_counts, out);
+        hipLaunchKernelGGL((k_reduce<true, false>), dim3(n_evals), dim3(RBLOCK), 0, s, d_desc, d_tile_base, d_win, d_chunks, d_counts, out);
     else if (grad)
-        hipLaunchKernelGGL((k_reduce<false, true>), dim3(n_evals), dim3(WBLOCK), 0, s, d_desc, d_tile_base, d_win, d_chunks, d_counts, out);
+        hipLaunchKernelGGL((k_reduce<false, true>), dim3(n_evals), dim3(RBLOCK), 0, s, d_desc, d_tile_base, d_win, d_chunks, d_counts, out);
     else
-        hipLaunchKernelGGL((k_reduce<false, false>), dim3(n_evals), dim3(WBLOCK), 0, s, d_desc, d_tile_base, d_win, d_chunks, d_counts, out);
+        hipLaunchKernelGGL((k_reduce<false, false>), dim3(n_evals), dim3(RBLOCK), 0, s, d_desc, d_tile_base, d_win, d_chunks, d_counts, out);
     return check(hipGetLastError());
 }
 

@@ -28,6 +28,12 @@ struct Prim {
     int32_t tri;
 };
 
+// Binary node of the build (host only); the device gets the 4-wide collapse.
+struct BNode2 {
+    float lo[2][3], hi[2][3];
+    uint32_t ref[2];
+};
+
 struct Box {
     float lo[3], hi[3];
     Box() {
@@ -55,7 +61,7 @@ int ceil_log2(int64_t x) {
 struct BlasBuilder {
     std::vector<Prim> &P;
     const std::vector<TriRec> &rec;   // by original triangle index
-    std::vector<BNode> &nodes;
+    std::vector<BNode2> &nodes;
     std::vector<TriRec> &out;
     float pad;
     int max_depth = 0;
@@ -146,19 +152,112 @@ struct BlasBuilder {
         if (mid <= b || mid >= e) mid = b + n / 2;
 
         uint32_t me = (uint32_t)nodes.size();
-        nodes.push_back(BNode{});
+        nodes.push_back(BNode2{});
         max_depth = std::max(max_depth, depth + 1);
         Box lb, rb;
         uint32_t l = build(b, mid, depth + 1, lb);
         uint32_t r = build(mid, e, depth + 1, rb);
-        BNode &nd = nodes[me];
+        BNode2 &nd = nodes[me];
         for (int a = 0; a < 3; ++a) {
-            nd.lo0[a] = lb.lo[a] - pad; nd.hi0[a] = lb.hi[a] + pad;
-            nd.lo1[a] = rb.lo[a] - pad; nd.hi1[a] = rb.hi[a] + pad;
+            nd.lo[0][a] = lb.lo[a] - pad; nd.hi[0][a] = lb.hi[a] + pad;
+            nd.lo[1][a] = rb.lo[a] - pad; nd.hi[1][a] = rb.hi[a] + pad;
         }
-        nd.ref0 = l;
-        nd.ref1 = r;
+        nd.ref[0] = l;
+        nd.ref[1] = r;
         return make_ref(REF_BLAS_NODE, me);
+    }
+};
+
+// Collapses a binary hierarchy into 4-wide nodes: a node takes the children
+// of its binary node and keeps replacing its largest-area inner child by that
+// child's two children until it has four (or only leaves).  References of
+// `inner` type are rewritten; leaves pass through.
+struct Collapser {
+    const std::vector<BNode2> &bin;
+    std::vector<BNode4> &out;
+    uint32_t inner;      // REF_BLAS_NODE or REF_TLAS_NODE
+    const std::vector<NodeInfo> *leaf_info = nullptr;   // top level: an instance leaf's node (for its worst case)
+    int max_depth = 0;   // 4-wide levels
+    int worst = 0;       // most stack entries any ray can hold below the root: on every path, a
+                         // node with n children pushes at most n - 1 (plus, at the top level,
+                         // what the entered instance's hierarchy can push)
+    std::vector<int> node_worst;   // per node this collapse emitted: out[base + i]
+    size_t base = 0;
+
+    int worst_of(uint32_t ref) const {
+        if (ref == REF_NONE) return 0;
+        if (ref_type(ref) == inner) return node_worst[ref_index(ref) - base];
+        if (leaf_info && ref_type(ref) == REF_TLAS_LEAF) return (*leaf_info)[ref_index(ref)].blas_worst;
+        return 0;
+    }
+    uint32_t root(uint32_t ref) {
+        base = out.size();
+        node_worst.clear();
+        const uint32_t r = run(ref, 0);
+        worst = worst_of(r);
+        return r;
+    }
+
+    struct Child {
+        uint32_t ref;
+        float lo[3], hi[3];
+        double area() const {
+            double dx = (double)hi[0] - lo[0], dy = (double)hi[1] - lo[1], dz = (double)hi[2] - lo[2];
+            return dx * dy + dy * dz + dz * dx;
+        }
+    };
+
+    uint32_t run(uint32_t ref, int depth) {
+        if (ref == REF_NONE || ref_type(ref) != inner) return ref;
+        Child ch[4];
+        int n = 0;
+        auto take = [&](const BNode2 &b, int k) {
+            Child c;
+            c.ref = b.ref[k];
+            for (int a = 0; a < 3; ++a) { c.lo[a] = b.lo[k][a]; c.hi[a] = b.hi[k][a]; }
+            return c;
+        };
+        const BNode2 &b = bin[ref_index(ref)];
+        ch[n++] = take(b, 0);
+        ch[n++] = take(b, 1);
+        while (n < 4) {
+            int best = -1;
+            double ba = -1;
+            for (int k = 0; k < n; ++k)
+                if (ch[k].ref != REF_NONE && ref_type(ch[k].ref) == inner && ch[k].area() > ba) {
+                    ba = ch[k].area();
+                    best = k;
+                }
+            if (best < 0) break;
+            const BNode2 &c = bin[ref_index(ch[best].ref)];
+            ch[best] = take(c, 0);
+            ch[n++] = take(c, 1);
+        }
+        const uint32_t me = (uint32_t)out.size();
+        BNode4 e;
+        for (int k = 0; k < 4; ++k) {
+            e.lox[k] = e.loy[k] = e.loz[k] = INFINITY;
+            e.hix[k] = e.hiy[k] = e.hiz[k] = INFINITY;
+            e.ref[k] = REF_NONE;
+            e.pad[k] = 0;
+        }
+        out.push_back(e);
+        node_worst.push_back(0);   // index me - base
+        max_depth = std::max(max_depth, depth + 1);
+        uint32_t refs[4];
+        int below = 0;
+        for (int k = 0; k < n; ++k) {
+            refs[k] = run(ch[k].ref, depth + 1);
+            below = std::max(below, worst_of(refs[k]));
+        }
+        node_worst[me - base] = n - 1 + below;
+        BNode4 &nd = out[me];
+        for (int k = 0; k < n; ++k) {
+            nd.lox[k] = ch[k].lo[0]; nd.loy[k] = ch[k].lo[1]; nd.loz[k] = ch[k].lo[2];
+            nd.hix[k] = ch[k].hi[0]; nd.hiy[k] = ch[k].hi[1]; nd.hiz[k] = ch[k].hi[2];
+            nd.ref[k] = refs[k];
+        }
+        return make_ref(inner, me);
     }
 };
 
@@ -319,15 +418,23 @@ int scene_build(const double *verts, int64_t n_verts, const int32_t *tris, int64
             }
             p.tri = lst[i];
         }
-        BlasBuilder B{P, rec, S->blas, S->tris, (float)S->pad};
+        std::vector<BNode2> bin;
+        BlasBuilder B{P, rec, bin, S->tris, (float)S->pad};
         Box root;
-        o.blas_root = B.build(0, (int)P.size(), 0, root);
+        const uint32_t broot = B.build(0, (int)P.size(), 0, root);
         if (B.depth_error) {
             *err = "node " + std::to_string(k) + ": hierarchy exceeds the traversal stack";
             return SRP_ERR_DEPTH;
         }
-        o.blas_depth = B.max_depth;
-        S->max_blas_depth = std::max(S->max_blas_depth, B.max_depth);
+        Collapser Cl{bin, S->blas, REF_BLAS_NODE};
+        o.blas_root = Cl.root(broot);
+        o.blas_depth = Cl.max_depth;
+        o.blas_worst = Cl.worst;
+        S->max_blas_depth = std::max(S->max_blas_depth, Cl.max_depth);
+        if (Cl.worst > STACK_DEPTH) {
+            *err = "node " + std::to_string(k) + ": hierarchy exceeds the traversal stack";
+            return SRP_ERR_DEPTH;
+        }
         for (int a = 0; a < 3; ++a) { o.blo[a] = (double)root.lo[a] - S->pad; o.bhi[a] = (double)root.hi[a] + S->pad; }
     }
     if ((int64_t)S->blas.size() >= (int64_t(1) << 30)) { *err = "srp_build_scene: hierarchy too large"; return SRP_ERR_ARG; }
@@ -352,7 +459,7 @@ SlotLayout slot_layout(int n_nodes, int n_tlas, int n_dof) {
     SlotLayout L;
     L.inst = 0;
     L.tlas = al(L.inst + sizeof(Inst) * (size_t)n_nodes);
-    L.xf = al(L.tlas + sizeof(BNode) * (size_t)std::max(n_tlas, 1));
+    L.xf = al(L.tlas + sizeof(BNode4) * (size_t)std::max(n_tlas, 1));
     L.axw = al(L.xf + sizeof(double) * 12 * (size_t)n_nodes);
     L.dof_node = al(L.axw + sizeof(double) * 3 * (size_t)std::max(n_dof, 1));
     L.bytes = al(L.dof_node + sizeof(int32_t) * (size_t)std::max(n_dof, 1));
@@ -361,7 +468,7 @@ SlotLayout slot_layout(int n_nodes, int n_tlas, int n_dof) {
 
 void slot_pack(const SlotHost &s, const SlotLayout &L, char *dst) {
     std::memcpy(dst + L.inst, s.inst.data(), sizeof(Inst) * s.inst.size());
-    if (!s.tlas.empty()) std::memcpy(dst + L.tlas, s.tlas.data(), sizeof(BNode) * s.tlas.size());
+    if (!s.tlas.empty()) std::memcpy(dst + L.tlas, s.tlas.data(), sizeof(BNode4) * s.tlas.size());
     std::memcpy(dst + L.xf, s.xf.data(), sizeof(double) * s.xf.size());
     if (!s.axw.empty()) std::memcpy(dst + L.axw, s.axw.data(), sizeof(double) * s.axw.size());
     if (!s.dof_node.empty()) std::memcpy(dst + L.dof_node, s.dof_node.data(), sizeof(int32_t) * s.dof_node.size());
@@ -374,7 +481,7 @@ struct TItem {
     int32_t inst;
 };
 
-uint32_t tlas_build(std::vector<TItem> &it, int b, int e, std::vector<BNode> &nodes, int depth, int &maxd,
+uint32_t tlas_build(std::vector<TItem> &it, int b, int e, std::vector<BNode2> &nodes, int depth, int &maxd,
                     float lo[3], float hi[3]) {
     for (int a = 0; a < 3; ++a) { lo[a] = INFINITY; hi[a] = -INFINITY; }
     for (int k = b; k < e; ++k)
@@ -391,15 +498,15 @@ uint32_t tlas_build(std::vector<TItem> &it, int b, int e, std::vector<BNode> &no
         return x.c[ax] < y.c[ax] || (x.c[ax] == y.c[ax] && x.inst < y.inst);
     });
     uint32_t me = (uint32_t)nodes.size();
-    nodes.push_back(BNode{});
+    nodes.push_back(BNode2{});
     maxd = std::max(maxd, depth + 1);
     float llo[3], lhi[3], rlo[3], rhi[3];
     uint32_t l = tlas_build(it, b, mid, nodes, depth + 1, maxd, llo, lhi);
     uint32_t r = tlas_build(it, mid, e, nodes, depth + 1, maxd, rlo, rhi);
-    BNode &n = nodes[me];
-    for (int a = 0; a < 3; ++a) { n.lo0[a] = llo[a]; n.hi0[a] = lhi[a]; n.lo1[a] = rlo[a]; n.hi1[a] = rhi[a]; }
-    n.ref0 = l;
-    n.ref1 = r;
+    BNode2 &n = nodes[me];
+    for (int a = 0; a < 3; ++a) { n.lo[0][a] = llo[a]; n.hi[0][a] = lhi[a]; n.lo[1][a] = rlo[a]; n.hi[1][a] = rhi[a]; }
+    n.ref[0] = l;
+    n.ref[1] = r;
     return make_ref(REF_TLAS_NODE, me);
 }
 }  // namespace
@@ -477,13 +584,21 @@ int slot_build(const SceneHost &S, const double *angles, SlotHost *out, std::str
         items.push_back(ti);
     }
     out->tlas_depth = 0;
+    out->stack_worst = 0;
     if (items.empty()) {
         out->root_ref = REF_NONE;
     } else {
         float lo[3], hi[3];
-        out->root_ref = tlas_build(items, 0, (int)items.size(), out->tlas, 0, out->tlas_depth, lo, hi);
+        std::vector<BNode2> bin;
+        int bdepth = 0;
+        const uint32_t broot = tlas_build(items, 0, (int)items.size(), bin, 0, bdepth, lo, hi);
+        Collapser Cl{bin, out->tlas, REF_TLAS_NODE};
+        Cl.leaf_info = &S.nodes;
+        out->root_ref = Cl.root(broot);
+        out->tlas_depth = Cl.max_depth;
+        out->stack_worst = Cl.worst;
     }
-    if (out->tlas_depth + 1 + S.max_blas_depth > STACK_DEPTH) {
+    if (out->stack_worst > STACK_DEPTH) {
         *err = "hierarchy depth exceeds the traversal stack";
         return SRP_ERR_DEPTH;
     }

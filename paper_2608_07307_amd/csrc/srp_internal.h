@@ -3,13 +3,13 @@
 // Device memory of a scene (built once, Sec. 4.4.1: one rigid node = one
 // bottom-level hierarchy in rest-pose coordinates):
 //   TriRec  tris[T]   triangles in leaf order, 48 B each (3 corners + ids)
-//   BNode   blas[..]  binary hierarchy nodes of all tree nodes, 64 B each
+//   BNode4  blas[..]  4-wide hierarchy nodes of all tree nodes, 128 B each
 //   float2  mats[M]   (rho_s, rho_d)
 //   WPoint  wpts[..]  distinct (vertex, tree node) pairs, for the window pass
 // Device memory of an articulation slot (one per distinct hinge-angle vector,
 // Sec. 4.4.2 steps 1, 4, 5 as rigid instance transforms):
 //   Inst    inst[K]   local->world transform + bottom-level root, 64 B each
-//   BNode   tlas[..]  top-level hierarchy over the instances' world boxes
+//   BNode4  tlas[..]  top-level hierarchy over the instances' world boxes
 //   double  xf[K][12] FP64 transforms (window pass)
 //   double  axw[J][3] world-frame hinge axes (gradient)
 //   int32   dof_node[J]
@@ -29,15 +29,15 @@ constexpr uint32_t REF_TLAS_LEAF = 3u;
 constexpr uint32_t REF_EXIT = 0xFFFFFFFEu;  // stack marker: leave the current instance
 constexpr uint32_t REF_NONE = 0xFFFFFFFFu;
 constexpr int LEAF_MAX = 8;
-constexpr int STACK_DEPTH = 32;             // per-lane traversal stack entries
+constexpr int STACK_DEPTH = 64;             // per-lane traversal stack entries (the build checks each hierarchy's worst case)
 #ifndef SRP_STACK_LDS
 #define SRP_STACK_LDS 16                    // (a host build may shrink it to exercise the spill path)
 #endif
 constexpr int STACK_LDS = SRP_STACK_LDS;    // of which the newest live in LDS (a ring)
 constexpr int STACK_SPILL = STACK_DEPTH - STACK_LDS;   // older ones: per-lane global spill area
 static_assert((STACK_LDS & (STACK_LDS - 1)) == 0, "the LDS ring size is a power of two");
-constexpr int BLAS_MAX_DEPTH = 24;          // internal nodes on any root-to-leaf path
-constexpr int TLAS_MAX_DEPTH = 7;           // <= 128 instances, median split
+constexpr int BLAS_MAX_DEPTH = 24;          // binary internal nodes on any root-to-leaf path (build)
+constexpr int TLAS_MAX_DEPTH = 7;           // <= 128 instances, median split (build)
 constexpr int BLOCK = 256;                  // threads per block of the trace kernel (4 waves)
 constexpr int PATCH = 8;                    // a patch is PATCH x PATCH pixels: one ray per lane of a wave
 constexpr int TILE = 16;                    // patches are numbered by 16x16 tile (row-major), 4 per tile
@@ -50,13 +50,17 @@ SRP_HD inline uint32_t make_ref(uint32_t type, uint32_t idx) { return (type << 3
 SRP_HD inline uint32_t ref_type(uint32_t r) { return r >> 30; }
 SRP_HD inline uint32_t ref_index(uint32_t r) { return r & 0x3FFFFFFFu; }
 
-struct alignas(64) BNode {
-    float lo0[3], hi0[3];
-    float lo1[3], hi1[3];
-    uint32_t ref0, ref1;
-    uint32_t pad0, pad1;
+// 4-wide hierarchy node: the boxes of up to four children as structure of
+// arrays inside the node (one 16-byte load gives one bound of all four), their
+// references, 128 B.  An empty slot has reference REF_NONE and a box with
+// every coordinate +inf, which no ray enters.
+struct alignas(128) BNode4 {
+    float lox[4], loy[4], loz[4];
+    float hix[4], hiy[4], hiz[4];
+    uint32_t ref[4];
+    uint32_t pad[4];
 };
-static_assert(sizeof(BNode) == 64, "BNode is one 64-byte line");
+static_assert(sizeof(BNode4) == 128, "BNode4 is 128 bytes");
 
 struct alignas(16) TriRec {
     float v0[3];
@@ -93,13 +97,13 @@ struct alignas(64) PatchOut {
 struct alignas(64) EvalDesc {
     // scene
     const TriRec *tris;
-    const BNode *blas;
+    const BNode4 *blas;
     const float *mats;       // 2 floats per material
     const WPoint *wpts;
     int64_t n_wpts;
     // articulation slot
     const Inst *inst;
-    const BNode *tlas;
+    const BNode4 *tlas;
     const double *xf;        // K x 12
     const double *axw;       // J x 3
     const int32_t *dof_node; // J
@@ -174,7 +178,7 @@ static_assert(sizeof(WPoint) == 32, "WPoint layout");
 static_assert(offsetof(WPoint, node) == 24, "WPoint layout");
 static_assert(offsetof(Inst, t) == 36, "Inst layout");
 static_assert(offsetof(Inst, root) == 48, "Inst layout");
-static_assert(offsetof(BNode, ref0) == 48, "BNode layout");
+static_assert(offsetof(BNode4, ref) == 96, "BNode4 layout");
 static_assert(offsetof(TriRec, id) == 12, "TriRec layout");
 static_assert(offsetof(TriRec, mat) == 28, "TriRec layout");
 static_assert(offsetof(TriRec, node) == 44, "TriRec layout");

@@ -122,8 +122,8 @@ constexpr uint32_t MAX_VISITS = 1u << 22;
 
 // What one traversal needs from an evaluation's descriptor, held in registers.
 struct TraceCtx {
-    const BNode SRP_GLOBAL *blas;
-    const BNode SRP_GLOBAL *tlas;
+    const BNode4 SRP_GLOBAL *blas;
+    const BNode4 SRP_GLOBAL *tlas;
     const TriRec SRP_GLOBAL *tris;
     const Inst SRP_GLOBAL *inst;
     uint32_t root;
@@ -131,27 +131,41 @@ struct TraceCtx {
 
 SRP_HD inline TraceCtx trace_ctx(const EvalDesc &D) {
     TraceCtx c;
-    c.blas = (const BNode SRP_GLOBAL *)D.blas;
-    c.tlas = (const BNode SRP_GLOBAL *)D.tlas;
+    c.blas = (const BNode4 SRP_GLOBAL *)D.blas;
+    c.tlas = (const BNode4 SRP_GLOBAL *)D.tlas;
     c.tris = (const TriRec SRP_GLOBAL *)D.tris;
     c.inst = (const Inst SRP_GLOBAL *)D.inst;
     c.root = D.root_ref;
     return c;
 }
 
-struct NodeData {
-    float4 a, b, c;
+struct NodeData4 {
+    float4 lx, ly, lz, hx, hy, hz;
     uint4 r;
 };
 
-SRP_HD inline NodeData load_node(const BNode SRP_GLOBAL *n) {
+SRP_HD inline NodeData4 load_node4(const BNode4 SRP_GLOBAL *n) {
     const float4 SRP_GLOBAL *q = (const float4 SRP_GLOBAL *)n;
-    NodeData v;
-    v.a = q[0];
-    v.b = q[1];
-    v.c = q[2];
-    v.r = ((const uint4 SRP_GLOBAL *)n)[3];
+    NodeData4 v;
+    v.lx = q[0];
+    v.ly = q[1];
+    v.lz = q[2];
+    v.hx = q[3];
+    v.hy = q[4];
+    v.hz = q[5];
+    v.r = ((const uint4 SRP_GLOBAL *)n)[6];
     return v;
+}
+
+// Orders (t[i], r[i]) so that t[i] <= t[j] for i < j (five compare-exchanges).
+SRP_HD inline void sort4(float t[4], uint32_t r[4]) {
+    auto cx = [&](int i, int j) {
+        const bool sw = t[j] < t[i];
+        const float ti = sw ? t[j] : t[i], tj = sw ? t[i] : t[j];
+        const uint32_t ri = sw ? r[j] : r[i], rj = sw ? r[i] : r[j];
+        t[i] = ti; t[j] = tj; r[i] = ri; r[j] = rj;
+    };
+    cx(0, 1); cx(2, 3); cx(0, 2); cx(1, 3); cx(1, 2);
 }
 
 // Per-lane traversal stack of up to STACK_DEPTH entries.  The newest entry
@@ -186,6 +200,8 @@ SRP_HD inline uint32_t st_load(const LaneStack &S, int e) {
 }
 
 // Closest hit along o + t d, t > tmin, skipping triangle `exclude_id`.
+// Both levels are 4-wide: a node visit tests the four child boxes, descends
+// into the nearest hit child and pushes the other hit children far to near.
 // Top-level nodes are tested in the world frame; a top-level leaf enters its
 // instance (the ray in the node's rest-pose frame; t is preserved) and the
 // instance's bottom-level nodes are tested in that frame.  One stack holds
@@ -237,26 +253,32 @@ SRP_HD inline bool trace_closest(const TraceCtx &C, const float o[3], const floa
                 ref = I.root;
             } else {
                 const bool tl = ref_type(ref) == REF_TLAS_NODE;
-                const NodeData N = load_node((tl ? C.tlas : C.blas) + ref_index(ref));
+                const NodeData4 N = load_node4((tl ? C.tlas : C.blas) + ref_index(ref));
                 const float ix = tl ? wix : F.ix, iy = tl ? wiy : F.iy, iz = tl ? wiz : F.iz;
                 const float oix = tl ? woix : F.oix, oiy = tl ? woiy : F.oiy, oiz = tl ? woiz : F.oiz;
-                const float t0 = box_enter(N.a.x, N.a.y, N.a.z, N.a.w, N.b.x, N.b.y, ix, iy, iz, oix, oiy, oiz, tmin, h.t);
-                const float t1 = box_enter(N.b.z, N.b.w, N.c.x, N.c.y, N.c.z, N.c.w, ix, iy, iz, oix, oiy, oiz, tmin, h.t);
-                if (COUNT) nbox += 2;
-                const bool h0 = t0 != T_INF, h1 = t1 != T_INF;
-                if (h0 && h1) {
-                    // descend into the nearer child, push the other
-                    const bool first0 = t0 <= t1;
-                    if (sp < STACK_DEPTH) {
-                        if (sp > 0) st_store(stack, sp - 1, top);
-                        top = first0 ? N.r.y : N.r.x;
-                        ++sp;
+                float t[4] = {
+                    box_enter(N.lx.x, N.ly.x, N.lz.x, N.hx.x, N.hy.x, N.hz.x, ix, iy, iz, oix, oiy, oiz, tmin, h.t),
+                    box_enter(N.lx.y, N.ly.y, N.lz.y, N.hx.y, N.hy.y, N.hz.y, ix, iy, iz, oix, oiy, oiz, tmin, h.t),
+                    box_enter(N.lx.z, N.ly.z, N.lz.z, N.hx.z, N.hy.z, N.hz.z, ix, iy, iz, oix, oiy, oiz, tmin, h.t),
+                    box_enter(N.lx.w, N.ly.w, N.lz.w, N.hx.w, N.hy.w, N.hz.w, ix, iy, iz, oix, oiy, oiz, tmin, h.t)};
+                uint32_t r[4] = {N.r.x, N.r.y, N.r.z, N.r.w};
+                if (COUNT) nbox += (r[0] != REF_NONE) + (r[1] != REF_NONE) + (r[2] != REF_NONE) + (r[3] != REF_NONE);
+                sort4(t, r);
+                const int hits = (t[0] != T_INF) + (t[1] != T_INF) + (t[2] != T_INF) + (t[3] != T_INF);
+                if (hits > 0) {
+                    // push the other hit children far to near, descend into the nearest
+                    if (sp + hits - 1 <= STACK_DEPTH) {
+                        for (int k = 3; k >= 1; --k) {
+                            if (k < hits) {
+                                if (sp > 0) st_store(stack, sp - 1, top);
+                                top = r[k];
+                                ++sp;
+                            }
+                        }
                     } else {
                         overflow = true;
                     }
-                    ref = first0 ? N.r.x : N.r.y;
-                } else if (h0 || h1) {
-                    ref = h0 ? N.r.x : N.r.y;
+                    ref = r[0];
                 } else if (sp > 0) {
                     ref = top;
                     --sp;

@@ -151,11 +151,12 @@ def test_c5_adjoint_batch(srp):
 
 
 def test_deep_hierarchy_spills_the_stack(srp):
-    """2^20 stacked plates (2M triangles) seen face-on: the way to the top
-    plate pushes 18 entries, one more than the register and the LDS ring
-    hold, so the global spill path runs.  The force equals the face-on plate
-    closed form P*A*(1 + rho_s + 2 rho_d / 3) along the photon direction; ids
-    equal the oracle's."""
+    """2^20 stacked plates (2M triangles) seen face-on: every child box on the
+    way to the top plate is hit, so the descent pushes three entries per 4-wide
+    level (~27), more than the register and the LDS ring hold, and the global
+    spill path runs.  The force equals the face-on plate closed form
+    P*A*(1 + rho_s + 2 rho_d / 3) along the photon direction; every ray hits
+    the top plate, as in the oracle."""
     mesh = synth.stacked_plates(1 << 20)
     sc = srp.Scene(mesh)
     rs, rd = mesh.mats[0]
