@@ -184,7 +184,10 @@ struct LaneStack {
     int sstride;
 };
 
-// Entry e (0-based from the bottom) of the ring/spill part.
+// Entry e (0-based from the bottom) of the ring/spill part.  e = -1 is the
+// slot below the bottom: storing or loading it touches ring slot
+// STACK_LDS - 1, which holds no live entry while the stack is that short, so
+// callers need not test for an empty stack.
 SRP_HD inline void st_store(const LaneStack &S, int e, uint32_t v) {
     const int slot = (e & (STACK_LDS - 1)) * S.stride;
     if (e >= STACK_LDS) S.spill[(e - STACK_LDS) * S.sstride] = S.ring[slot];
@@ -265,24 +268,35 @@ SRP_HD inline bool trace_closest(const TraceCtx &C, const float o[3], const floa
                 if (COUNT) nbox += (r[0] != REF_NONE) + (r[1] != REF_NONE) + (r[2] != REF_NONE) + (r[3] != REF_NONE);
                 sort4(t, r);
                 const int hits = (t[0] != T_INF) + (t[1] != T_INF) + (t[2] != T_INF) + (t[3] != T_INF);
-                if (hits > 0) {
-                    // push the other hit children far to near, descend into the nearest
-                    if (sp + hits - 1 <= STACK_DEPTH) {
-                        for (int k = 3; k >= 1; --k) {
-                            if (k < hits) {
-                                if (sp > 0) st_store(stack, sp - 1, top);
-                                top = r[k];
-                                ++sp;
-                            }
-                        }
-                    } else {
+                if (hits > 1) {
+                    // push the other hit children far to near: afterwards the ring holds
+                    // ..., old top (entry sp - 1), r[np], ..., r[2] and r[1] is the top
+                    const int np = hits - 1;
+                    if (sp + np > STACK_DEPTH) {
                         overflow = true;
+                    } else if (sp + 2 < STACK_LDS) {
+                        // nothing reaches the spill part: three fixed-slot stores (the ones
+                        // past the new top write free slots)
+                        const int m = STACK_LDS - 1;
+                        stack.ring[((sp - 1) & m) * stack.stride] = top;
+                        stack.ring[(sp & m) * stack.stride] = np == 3 ? r[3] : r[2];
+                        stack.ring[((sp + 1) & m) * stack.stride] = r[2];
+                        top = r[1];
+                        sp += np;
+                    } else {
+                        for (int k = np; k >= 1; --k) {
+                            st_store(stack, sp - 1, top);
+                            top = r[k];
+                            ++sp;
+                        }
                     }
-                    ref = r[0];
+                }
+                if (hits > 0) {
+                    ref = r[0];   // descend into the nearest
                 } else if (sp > 0) {
                     ref = top;
                     --sp;
-                    if (sp > 0) top = st_load(stack, sp - 1);
+                    top = st_load(stack, sp - 1);
                 } else {
                     ref = REF_NONE;
                 }
@@ -313,7 +327,7 @@ SRP_HD inline bool trace_closest(const TraceCtx &C, const float o[3], const floa
         if (sp > 0) {
             ref = top;
             --sp;
-            if (sp > 0) top = st_load(stack, sp - 1);
+            top = st_load(stack, sp - 1);
         } else {
             ref = REF_NONE;
         }
