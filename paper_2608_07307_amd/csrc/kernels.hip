@@ -48,12 +48,12 @@ __device__ __forceinline__ double wave_sum(double x) {
     return x;
 }
 
-// Per-hit record kept for the fixed-visibility adjoint of one ray chain.
-struct ChainHit {
-    float n[3], d[3];
-    float c, w, rs, rd;
-    int32_t mat, node;
-};
+// The adjoint keeps one word per hit of a lane's chain in LDS: the triangle's
+// leaf-order index, with the top bit set when the geometric normal was flipped
+// to face the incoming ray.  The reverse sweep recomputes the normal from it
+// bit for bit and recovers each incoming direction and weight backwards from
+// the last ones (a mirror reflection is its own inverse).
+constexpr uint32_t CHAIN_FLIP = 0x80000000u;
 
 // Adds per-lane vectors into per-wave LDS accumulators acc[key * stride + 0..n),
 // one wave-wide FP64 sum per distinct key (keys processed lowest lane first).
@@ -113,7 +113,11 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(GRAD ? SR
     // per-lane FP64 force/torque sums of the current patch (component k at [k * BLOCK]):
     // kept in LDS and updated with LDS adds, out of the traversal's registers
     double *lacc = reinterpret_cast<double *>(smem + sizeof(uint32_t) * STACK_LDS * BLOCK) + tid;
-    double *gw = reinterpret_cast<double *>(smem + sizeof(uint32_t) * STACK_LDS * BLOCK) + 6 * BLOCK +
+    // adjoint only: the hit chains (hit k at [k * BLOCK]), then per-wave gradient sums
+    uint32_t *lchain = reinterpret_cast<uint32_t *>(smem + sizeof(uint32_t) * STACK_LDS * BLOCK +
+                                                    sizeof(double) * 6 * BLOCK) + tid;
+    double *gw = reinterpret_cast<double *>(smem + sizeof(uint32_t) * STACK_LDS * BLOCK + sizeof(double) * 6 * BLOCK +
+                                            sizeof(uint32_t) * MAX_CHAIN * BLOCK) +
                  (size_t)wv * lds_grad_doubles;
 
     // Every wave is persistent on its own and takes chunks from work queues:
@@ -212,8 +216,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(GRAD ? SR
             {
                 const bool inside = px < N && py < N;
                 const bool valid = !empty && inside;
-                ChainHit chain[GRAD ? MAX_CHAIN : 1];
                 int K = 0;
+                float d[3] = {dd[0], dd[1], dd[2]}, w = 1.0f;   // the current ray's direction and weight
+                bool cont = false;                              // the last hit spawned a ray
                 if (inside && D.hit_ids) {   // generations a chain does not reach stay "no hit"
                     const int64_t pix = (int64_t)py * N + px;
                     for (int gen = 0; gen <= B; ++gen) {
@@ -222,12 +227,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(GRAD ? SR
                     }
                 }
                 if (valid) {
-                    float o[3], d[3];
-                    for (int k = 0; k < 3; ++k) {
-                        o[k] = fmaf((float)py, sv[k], fmaf((float)px, su[k], o0[k]));
-                        d[k] = dd[k];
-                    }
-                    float w = 1.0f, tmin = 0.0f;
+                    float o[3];
+                    for (int k = 0; k < 3; ++k) o[k] = fmaf((float)py, sv[k], fmaf((float)px, su[k], o0[k]));
+                    float tmin = 0.0f;
                     int32_t excl = -1;
                     const int64_t pix = (int64_t)py * N + px;
                     #pragma unroll 1
@@ -253,7 +255,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(GRAD ? SR
                         for (int k = 0; k < 3; ++k) n[k] = I.R[3 * k] * nl[0] + I.R[3 * k + 1] * nl[1] + I.R[3 * k + 2] * nl[2];
                         float inv = rsqrtf(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
                         float nd = (n[0] * d[0] + n[1] * d[1] + n[2] * d[2]) * inv;
-                        if (nd > 0.0f) inv = -inv;
+                        const bool flip = nd > 0.0f;
+                        if (flip) inv = -inv;
                         for (int k = 0; k < 3; ++k) n[k] *= inv;
                         const float cth = -(n[0] * d[0] + n[1] * d[1] + n[2] * d[2]);
                         const float rs = D.mats[2 * T.mat], rd = D.mats[2 * T.mat + 1];
@@ -270,13 +273,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(GRAD ? SR
                         lds_add(lacc + 3 * BLOCK, (double)(rr[1] * f[2] - rr[2] * f[1]));
                         lds_add(lacc + 4 * BLOCK, (double)(rr[2] * f[0] - rr[0] * f[2]));
                         lds_add(lacc + 5 * BLOCK, (double)(rr[0] * f[1] - rr[1] * f[0]));
-                        if (GRAD) {
-                            ChainHit &ch = chain[K];
-                            for (int k = 0; k < 3; ++k) { ch.n[k] = n[k]; ch.d[k] = d[k]; }
-                            ch.c = cth; ch.w = w; ch.rs = rs; ch.rd = rd;
-                            ch.mat = T.mat; ch.node = T.node;
-                        }
+                        if (GRAD) lchain[K * BLOCK] = (uint32_t)h.tri | (flip ? CHAIN_FLIP : 0u);
                         ++K;
+                        cont = false;
                         if (gen == B || !(rs > 0.0f)) break;
                         for (int k = 0; k < 3; ++k) {
                             o[k] = x[k];
@@ -285,6 +284,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(GRAD ? SR
                         w *= rs;
                         tmin = tmin2;
                         excl = T.id;
+                        cont = true;
                         hcnt += 1u << 10;
                     }
                 }
@@ -301,9 +301,29 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(GRAD ? SR
                         float Hm[9], gmat[6];
                         int node = 0, mat = 0;
                         if (act) {
-                            const ChainHit ch = chain[k];
-                            const float *n = ch.n, *d = ch.d;
-                            const float w = ch.w, rs = ch.rs, rd = ch.rd, cc = ch.c;
+                            // hit k's normal exactly as the forward pass computed it
+                            const uint32_t ew = lchain[k * BLOCK];
+                            const TriRec SRP_GLOBAL &T = TC.tris[ew & ~CHAIN_FLIP];
+                            const Inst SRP_GLOBAL &I = TC.inst[T.node];
+                            float e1[3] = {T.v1[0] - T.v0[0], T.v1[1] - T.v0[1], T.v1[2] - T.v0[2]};
+                            float e2[3] = {T.v2[0] - T.v0[0], T.v2[1] - T.v0[1], T.v2[2] - T.v0[2]};
+                            float nl[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+                                           e1[0] * e2[1] - e1[1] * e2[0]};
+                            float n[3];
+                            for (int i = 0; i < 3; ++i)
+                                n[i] = I.R[3 * i] * nl[0] + I.R[3 * i + 1] * nl[1] + I.R[3 * i + 2] * nl[2];
+                            float inv = rsqrtf(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+                            if (ew & CHAIN_FLIP) inv = -inv;
+                            for (int i = 0; i < 3; ++i) n[i] *= inv;
+                            const float rs = D.mats[2 * T.mat], rd = D.mats[2 * T.mat + 1];
+                            // (d, w) hold the ray after hit k when hit k spawned one: undo the
+                            // reflection and the weight factor to get hit k's incoming ray
+                            if (k < K - 1 || cont) {
+                                const float dn = n[0] * d[0] + n[1] * d[1] + n[2] * d[2];
+                                for (int i = 0; i < 3; ++i) d[i] = fmaf(-2.0f * dn, n[i], d[i]);
+                                w = w / rs;
+                            }
+                            const float cc = -(n[0] * d[0] + n[1] * d[1] + n[2] * d[2]);
                             const float sc = rs * cc + rd * (1.0f / 3.0f);
                             // material terms
                             for (int i = 0; i < 3; ++i) {
@@ -334,8 +354,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(GRAD ? SR
                                     A[3 * i + j] = A[3 * i + j] - 2.0f * An[i] * n[j] +
                                                    w * ((i == j ? 1.0f - rs : 0.0f) + 2.0f * rs * n[i] * n[j]);
                             for (int i = 0; i < 3; ++i) Tn[i] = (1.0f - rs) * d[i] - 2.0f * sc * n[i] + rs * Tn[i];
-                            node = ch.node;
-                            mat = ch.mat;
+                            node = T.node;
+                            mat = T.mat;
                         }
                         wave_scatter_add(gw, node, act, Hm, 9, 9);
                         wave_scatter_add(gw + 9 * gK, mat, act, gmat, 6, 6);
@@ -564,7 +584,7 @@ int launch_window(const EvalDesc *d_desc, int n_evals, int blocks_x, uint64_t *d
 
 size_t trace_lds_bytes(bool grad, int lds_grad_doubles) {
     return sizeof(uint32_t) * STACK_LDS * BLOCK + sizeof(double) * 6 * BLOCK +
-           (grad ? sizeof(double) * (BLOCK / 64) * lds_grad_doubles : 0);
+           (grad ? sizeof(uint32_t) * MAX_CHAIN * BLOCK + sizeof(double) * (BLOCK / 64) * lds_grad_doubles : 0);
 }
 
 int launch_trace(const EvalDesc *d_desc, const int64_t *d_chunk_base, int n_evals, const uint64_t *d_win,
