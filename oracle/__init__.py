@@ -18,4 +18,6 @@ from .core import (  # noqa: F401
     fd_gradients,
     OracleResult,
     threads,
+    diffuse_set,
+    record_slots,
 )

@@ -34,7 +34,8 @@ class _Scene(C.Structure):
 
 class _Params(C.Structure):
     _fields_ = [("sun_dir", C.c_double * 3), ("pressure", C.c_double), ("n", C.c_int32),
-                ("bounces", C.c_int32), ("ref", C.c_double * 3)]
+                ("bounces", C.c_int32), ("ref", C.c_double * 3), ("n_diffuse", C.c_int32),
+                ("pad_", C.c_int32)]
 
 
 class _Grid(C.Structure):
@@ -47,7 +48,8 @@ class _Grid(C.Structure):
 class _Result(C.Structure):
     _fields_ = [("force", C.c_double * 3), ("torque", C.c_double * 3), ("n_rays", C.c_int64),
                 ("n_hits", C.c_int64), ("n_secondary", C.c_int64),
-                ("n_secondary_hits", C.c_int64), ("grid", _Grid)]
+                ("n_secondary_hits", C.c_int64), ("n_diffuse", C.c_int64),
+                ("n_diffuse_hits", C.c_int64), ("grid", _Grid)]
 
 
 def _load():
@@ -63,8 +65,9 @@ def _load():
         _lib.orc_articulate.argtypes = [P, P, P]
         _lib.orc_node_transforms.argtypes = [P, P, P]
         _lib.orc_threads.restype = C.c_int32
+        _lib.orc_diffuse_set.argtypes = [C.c_int32, P]
         for f in ("orc_eval", "orc_shade_frozen", "orc_grid_of", "orc_articulate",
-                  "orc_node_transforms"):
+                  "orc_node_transforms", "orc_diffuse_set"):
             getattr(_lib, f).restype = C.c_int
     return _lib
 
@@ -88,9 +91,15 @@ class _SceneRef:
                         _ptr(k[6]), _ptr(k[7]), _ptr(k[8]), _ptr(k[9]), _ptr(k[10]))
 
 
-def _params(sun_dir, pressure, n, bounces, ref):
+def _params(sun_dir, pressure, n, bounces, ref, diffuse=0):
     return _Params((C.c_double * 3)(*np.asarray(sun_dir, float)), float(pressure), int(n),
-                   int(bounces), (C.c_double * 3)(*np.asarray(ref, float)))
+                   int(bounces), (C.c_double * 3)(*np.asarray(ref, float)), int(diffuse), 0)
+
+
+def record_slots(bounces, diffuse=0):
+    """Recorded hits per pixel: B + 1 chain generations, then the B diffuse
+    fans of K rays (the fan of generation g at B + 1 + g K)."""
+    return bounces + 1 + bounces * max(int(diffuse), 0)
 
 
 @dataclass
@@ -104,6 +113,8 @@ class OracleResult:
     grid: dict
     ids: np.ndarray | None = None
     ts: np.ndarray | None = None
+    n_diffuse: int = 0
+    n_diffuse_hits: int = 0
 
 
 def _grid_dict(g: _Grid) -> dict:
@@ -128,19 +139,20 @@ def _angles(scene, angles):
 
 
 def eval_srp(scene, sun_dir, n, bounces=0, pressure=1.0, ref=(0, 0, 0), angles=None,
-             use_bvh=None, pixels=None, record=False) -> OracleResult:
+             use_bvh=None, pixels=None, record=False, diffuse=0) -> OracleResult:
     """Force and torque of one evaluation (sum over all N*N pixels, or over
-    the listed pixel indices p = j*N + i).  With record=True also returns the
-    per-pixel hit ids and t of every generation, shape (n_pix, B+1)."""
+    the listed pixel indices p = j*N + i), with `diffuse` diffuse rays per
+    emitting hit.  With record=True also returns the per-pixel hit ids and t
+    of every ray, shape (n_pix, record_slots(bounces, diffuse))."""
     lib = _load()
     sr = _SceneRef(scene)
     ang = _angles(scene, angles)
-    P = _params(sun_dir, pressure, n, bounces, ref)
+    P = _params(sun_dir, pressure, n, bounces, ref, diffuse)
     if use_bvh is None:
         use_bvh = scene.n_tris > 64
     pix = None if pixels is None else np.ascontiguousarray(pixels, dtype=np.int64)
     npx = n * n if pix is None else pix.shape[0]
-    G = bounces + 1
+    G = record_slots(bounces, diffuse)
     ids = np.empty((npx, G), np.int32) if record else None
     ts = np.empty((npx, G), np.float64) if record else None
     out = _Result()
@@ -149,7 +161,17 @@ def eval_srp(scene, sun_dir, n, bounces=0, pressure=1.0, ref=(0, 0, 0), angles=N
     if rc != 0:
         raise ValueError(f"oracle eval failed ({rc})")
     return OracleResult(np.array(out.force[:]), np.array(out.torque[:]), out.n_rays, out.n_hits,
-                        out.n_secondary, out.n_secondary_hits, _grid_dict(out.grid), ids, ts)
+                        out.n_secondary, out.n_secondary_hits, _grid_dict(out.grid), ids, ts,
+                        out.n_diffuse, out.n_diffuse_hits)
+
+
+def diffuse_set(K) -> np.ndarray:
+    """The K local diffuse directions (K, 3) in the hit's (t, b, n) frame."""
+    lib = _load()
+    out = np.empty((int(K), 3))
+    if lib.orc_diffuse_set(int(K), _ptr(out)) != 0:
+        raise ValueError("K must be >= 1")
+    return out
 
 
 def threads() -> int:
@@ -187,24 +209,26 @@ def node_transforms(scene, angles=None) -> np.ndarray:
 
 
 def shade_frozen(scene, sun_dir, n, bounces, grid: dict, ids, pressure=1.0, ref=(0, 0, 0),
-                 angles=None) -> OracleResult:
-    """Fixed-visibility re-shade of recorded chains (ids shape (N*N, B+1))."""
+                 angles=None, diffuse=0) -> OracleResult:
+    """Fixed-visibility re-shade of recorded rays (ids shape
+    (N*N, record_slots(bounces, diffuse)))."""
     lib = _load()
     sr = _SceneRef(scene)
-    ids = np.ascontiguousarray(ids, dtype=np.int32).reshape(n * n, bounces + 1)
+    ids = np.ascontiguousarray(ids, dtype=np.int32).reshape(n * n, record_slots(bounces, diffuse))
     g = _grid_struct(grid)
     out = _Result()
     rc = lib.orc_shade_frozen(C.byref(sr.c), _ptr(_angles(scene, angles)),
-                              C.byref(_params(sun_dir, pressure, n, bounces, ref)), C.byref(g),
+                              C.byref(_params(sun_dir, pressure, n, bounces, ref, diffuse)), C.byref(g),
                               _ptr(ids), C.byref(out))
     if rc != 0:
         raise ValueError(f"oracle shade failed ({rc})")
     return OracleResult(np.array(out.force[:]), np.array(out.torque[:]), out.n_rays, out.n_hits,
-                        out.n_secondary, out.n_secondary_hits, grid)
+                        out.n_secondary, out.n_secondary_hits, grid, None, None, out.n_diffuse,
+                        out.n_diffuse_hits)
 
 
 def fd_gradients(scene, sun_dir, n, bounces, grid, ids, pressure=1.0, angles=None, h=1e-4,
-                 which=("rho_s", "rho_d", "theta"), theta_idx=None):
+                 which=("rho_s", "rho_d", "theta"), theta_idx=None, diffuse=0):
     """Central finite differences (FP64) of the fixed-visibility force with
     respect to each material's rho_s and rho_d and each hinge angle (or the
     hinges listed in theta_idx).  Returns dict name -> array (count, 3)."""
@@ -212,7 +236,7 @@ def fd_gradients(scene, sun_dir, n, bounces, grid, ids, pressure=1.0, angles=Non
     out = {}
 
     def F(sc, a):
-        return shade_frozen(sc, sun_dir, n, bounces, grid, ids, pressure, (0, 0, 0), a).force
+        return shade_frozen(sc, sun_dir, n, bounces, grid, ids, pressure, (0, 0, 0), a, diffuse).force
 
     for col, name in ((0, "rho_s"), (1, "rho_d")):
         if name not in which:

@@ -39,15 +39,34 @@
  *      edges; a triangle whose projection along the ray has zero area (zero-
  *      area triangles, exactly edge-on triangles) is never hit.
  *   R6 closest hit: smallest t; on an exact tie the smallest triangle index.
- *   R7 secondary rays are specular only: at a hit with rho_s > 0 the ray
- *      continues along d' = d + 2 c n with weight w rho_s, from the hit point,
- *      excluding the source triangle and requiring t > 1e-6 L; a miss ends
- *      the chain.  Diffuse re-emission is not traced (its Lambertian recoil is
- *      the rho_d/3 term of the law).
+ *   R7 the specular chain: at a hit with rho_s > 0 the ray continues along
+ *      d' = d + 2 c n with weight w rho_s, from the hit point, excluding the
+ *      source triangle and requiring t > 1e-6 L; a miss ends the chain.
+ *      Without diffuse rays (R10) diffuse re-emission is not traced: its
+ *      Lambertian recoil is the rho_d/3 term of the law.
  *   R8 per hit: dF = w P A_pix [(1-rho_s) d - 2 (rho_s c + rho_d/3) n],
  *      c = -n.d, dtau = (x - ref) x dF.
  *   R9 summation order: pixels in row-major order (j outer, i inner), within
- *      a pixel its chain in generation order.
+ *      a pixel its chain in generation order, each emitting hit followed by
+ *      its diffuse rays in set order.
+ *   R10 diffuse secondary rays (Sec. 4.3: the number of secondary rays made
+ *      at each interaction sets the level of scattering; Sec. 6.1 uses 16
+ *      diffuse rays with two secondary levels).  With K > 0, a chain hit of
+ *      generation g < B on a material with rho_d > 0 also emits K diffuse
+ *      rays of weight w rho_d / K each, from the hit point (same exclusion
+ *      and t > 1e-6 L as R7).  Their directions are a fixed cosine-weighted
+ *      set: ray k has u = (k + 1/2)/K, phi = 2 pi frac(k (sqrt(5) - 1)/2) and
+ *      local direction (sqrt(u) cos phi, sqrt(u) sin phi, sqrt(1 - u)) (a
+ *      Fibonacci point set on the unit disk lifted to the hemisphere, which
+ *      makes the lifted directions cosine distributed), placed in the hit's
+ *      frame (t, b, n): t = normalize(h x n) with h = (1, 2, 3) (e_x if
+ *      h x n = 0), b = n x t.  The emitting hit's diffuse recoil is the
+ *      exact mean m of the K emitted world directions instead of 2/3 n:
+ *      dF = w P A_pix [(1 - rho_s) d - 2 rho_s c n - rho_d m], so the fan's
+ *      momentum is accounted for exactly.  A diffuse ray that hits deposits
+ *      at its first hit by the R8 law with its own weight and direction and
+ *      spawns nothing; one that misses leaves.  Diffuse rays count as
+ *      secondary rays.
  *
  * Units: metres, N/m^2 for the pressure, newtons and newton-metres out.
  */
@@ -440,31 +459,103 @@ static void tri_normal(const double *tv, double *n)
     n[0] /= l; n[1] /= l; n[2] /= l;
 }
 
-/* Contribution of one hit (R8): ray weight w, incoming direction d, geometric
- * normal nf, material (rs, rd), hit point x, scale = P A_pix.  Writes dF and
- * dtau, the normal n oriented against d, and returns c = -n.d. */
-static double shade(double scale, double w, const double *d, const double *nf, double rs, double rd,
-                    const double *x, const double *ref, double *dF, double *dT, double *n)
+/* Normal nf oriented against the incoming direction d (R4); returns c = -n.d. */
+static double orient(const double *nf, const double *d, double *n)
 {
     double sgn = v_dot(nf, d) > 0 ? -1.0 : 1.0;
     for (int c = 0; c < 3; ++c) n[c] = sgn * nf[c];
-    double cth = -v_dot(n, d);
+    return -v_dot(n, d);
+}
+
+/* Contribution of one hit (R8): ray weight w, incoming direction d, oriented
+ * normal n with c = -n.d, material (rs, rd), hit point x, scale = P A_pix.
+ * mdiff = NULL: the law's Lambertian recoil 2/3 rho_d n; else the emitted
+ * diffuse rays' mean direction m replaces 2/3 n (R10).  Writes dF and dtau. */
+static void shade(double scale, double w, const double *d, const double *n, double cth, double rs,
+                  double rd, const double *mdiff, const double *x, const double *ref, double *dF, double *dT)
+{
     double a = w * scale * (1.0 - rs);
-    double b = -2.0 * w * scale * (rs * cth + rd / 3.0);
-    for (int c = 0; c < 3; ++c) dF[c] = a * d[c] + b * n[c];
+    if (!mdiff) {
+        double b = -2.0 * w * scale * (rs * cth + rd / 3.0);
+        for (int c = 0; c < 3; ++c) dF[c] = a * d[c] + b * n[c];
+    } else {
+        double b = -2.0 * w * scale * rs * cth, e = -w * scale * rd;
+        for (int c = 0; c < 3; ++c) dF[c] = a * d[c] + b * n[c] + e * mdiff[c];
+    }
     double r[3];
     v_sub(x, ref, r);
     v_cross(r, dF, dT);
-    return cth;
+}
+
+/* ------------------------------------------------------------ diffuse set (R10) */
+static const double ORC_PI = 3.14159265358979323846;
+
+/* Local direction of diffuse ray k of K. */
+static void diffuse_local(int32_t K, int32_t k, double *l)
+{
+    double g = (sqrt(5.0) - 1.0) / 2.0;
+    double u = ((double)k + 0.5) / (double)K;
+    double f = (double)k * g;
+    f -= floor(f);
+    double phi = 2.0 * ORC_PI * f;
+    double r = sqrt(u);
+    l[0] = r * cos(phi);
+    l[1] = r * sin(phi);
+    l[2] = sqrt(1.0 - u);
+}
+
+int orc_diffuse_set(int32_t K, double *l)
+{
+    if (K < 1 || !l) return ORC_ERR_ARG;
+    for (int32_t k = 0; k < K; ++k) diffuse_local(K, k, l + 3 * k);
+    return ORC_OK;
+}
+
+/* Tangent frame of unit normal n: t = normalize(h x n), b = n x t. */
+static void tangent_frame(const double *n, double *t, double *b)
+{
+    const double h[3] = {1.0, 2.0, 3.0}, ex[3] = {1.0, 0.0, 0.0};
+    v_cross(h, n, t);
+    double l = v_norm(t);
+    if (!(l > 0)) {
+        v_cross(ex, n, t);
+        l = v_norm(t);
+    }
+    t[0] /= l; t[1] /= l; t[2] /= l;
+    v_cross(n, t, b);
+}
+
+/* World directions of the K diffuse rays at a hit with oriented normal n
+ * (dirs: K x 3) and their mean m. */
+static void diffuse_fan(int32_t K, const double *n, double *dirs, double *m)
+{
+    double t[3], b[3];
+    tangent_frame(n, t, b);
+    m[0] = m[1] = m[2] = 0.0;
+    for (int32_t k = 0; k < K; ++k) {
+        double l[3];
+        diffuse_local(K, k, l);
+        for (int c = 0; c < 3; ++c) {
+            dirs[3 * k + c] = l[0] * t[c] + l[1] * b[c] + l[2] * n[c];
+            m[c] += dirs[3 * k + c];
+        }
+    }
+    for (int c = 0; c < 3; ++c) m[c] /= (double)K;
+}
+
+int32_t orc_record_slots(const orc_params *P)
+{
+    return P->bounces + 1 + P->bounces * (P->n_diffuse > 0 ? P->n_diffuse : 0);
 }
 
 /* ------------------------------------------------------------ evaluation */
-typedef struct { double f[6]; int64_t hits, sec, sec_hits; } pix_out;
+typedef struct { double f[6]; int64_t hits, sec, sec_hits, dif, dif_hits; } pix_out;
 
 static void trace_pixel(const orc_scene *S, const double *wtri, const bvh *B, const orc_params *P,
-                        const orc_grid *g, int64_t pix, pix_out *po, int32_t *ids, double *ts)
+                        const orc_grid *g, int64_t pix, pix_out *po, int32_t *ids, double *ts,
+                        double *fan /* K x 3 scratch */)
 {
-    int32_t n = P->n;
+    int32_t n = P->n, K = P->n_diffuse > 0 ? P->n_diffuse : 0;
     int64_t i = pix % n, j = pix / n;
     double o[3], d[3] = {g->d[0], g->d[1], g->d[2]};
     pixel_origin(g, n, i, j, o);
@@ -475,10 +566,6 @@ static void trace_pixel(const orc_scene *S, const double *wtri, const bvh *B, co
     int64_t exclude = -1;
     double scale = P->pressure * g->a_pix;
     for (int32_t gen = 0; gen <= P->bounces; ++gen) {
-        if (ids) ids[gen] = -1;
-        if (ts) ts[gen] = 0.0;
-    }
-    for (int32_t gen = 0; gen <= P->bounces; ++gen) {
         double bt;
         int64_t bi;
         closest_hit(B, wtri, S->nt, o, d, tmin, exclude, &bt, &bi);
@@ -488,12 +575,39 @@ static void trace_pixel(const orc_scene *S, const double *wtri, const bvh *B, co
         if (gen == 0) po->hits++;
         else po->sec_hits++;
         double x[3] = {o[0] + bt * d[0], o[1] + bt * d[1], o[2] + bt * d[2]};
-        double nf[3], nn[3], dF[3], dT[3];
+        double nf[3], nn[3], dF[3], dT[3], m[3];
         tri_normal(wtri + 9 * bi, nf);
-        int32_t m = S->tri_mat[bi];
-        double rs = S->mats[2 * m], rd = S->mats[2 * m + 1];
-        double cth = shade(scale, w, d, nf, rs, rd, x, P->ref, dF, dT, nn);
+        double cth = orient(nf, d, nn);
+        int32_t mt = S->tri_mat[bi];
+        double rs = S->mats[2 * mt], rd = S->mats[2 * mt + 1];
+        int emit = gen < P->bounces && K > 0 && rd > 0.0;   /* R10 */
+        if (emit) diffuse_fan(K, nn, fan, m);
+        shade(scale, w, d, nn, cth, rs, rd, emit ? m : NULL, x, P->ref, dF, dT);
         for (int c = 0; c < 3; ++c) { ks_add(&acc[c], dF[c]); ks_add(&acc[3 + c], dT[c]); }
+        if (emit) {
+            double wd = w * rd / (double)K;
+            for (int32_t k = 0; k < K; ++k) {
+                const double *e = fan + 3 * k;
+                double et;
+                int64_t ei;
+                po->sec++;
+                po->dif++;
+                closest_hit(B, wtri, S->nt, x, e, 1e-6 * g->L, bi, &et, &ei);
+                int32_t slot = P->bounces + 1 + gen * K + k;
+                if (ei < 0) continue;
+                if (ids) ids[slot] = (int32_t)ei;
+                if (ts) ts[slot] = et;
+                po->sec_hits++;
+                po->dif_hits++;
+                double y[3] = {x[0] + et * e[0], x[1] + et * e[1], x[2] + et * e[2]};
+                double mf[3], mn[3], eF[3], eT[3];
+                tri_normal(wtri + 9 * ei, mf);
+                double ce = orient(mf, e, mn);
+                int32_t me = S->tri_mat[ei];
+                shade(scale, wd, e, mn, ce, S->mats[2 * me], S->mats[2 * me + 1], NULL, y, P->ref, eF, eT);
+                for (int c = 0; c < 3; ++c) { ks_add(&acc[c], eF[c]); ks_add(&acc[3 + c], eT[c]); }
+            }
+        }
         if (gen == P->bounces || !(rs > 0.0)) break;
         /* R7: specular continuation */
         for (int c = 0; c < 3; ++c) { o[c] = x[c]; d[c] = d[c] + 2.0 * cth * nn[c]; }
@@ -516,6 +630,8 @@ static void finish(const orc_scene *S, const orc_params *P, const orc_grid *g, c
         out->n_hits += po[k].hits;
         out->n_secondary += po[k].sec;
         out->n_secondary_hits += po[k].sec_hits;
+        out->n_diffuse += po[k].dif;
+        out->n_diffuse_hits += po[k].dif_hits;
     }
     for (int c = 0; c < 3; ++c) { out->force[c] = ks_val(&acc[c]); out->torque[c] = ks_val(&acc[3 + c]); }
     out->n_rays = np;
@@ -528,7 +644,7 @@ int orc_eval(const orc_scene *S, const double *angles, const orc_params *P, int3
 {
     int rc = orc_validate(S);
     if (rc) return rc;
-    if (!P || P->n < 1 || P->bounces < 0 || P->bounces > 8 || !out) return ORC_ERR_ARG;
+    if (!P || P->n < 1 || P->bounces < 0 || P->bounces > 8 || P->n_diffuse < 0 || !out) return ORC_ERR_ARG;
     double *wtri = (double *)malloc(sizeof(double) * 9 * (size_t)(S->nt + 1));
     if (!wtri) return ORC_ERR_OOM;
     orc_articulate(S, angles, wtri);
@@ -536,7 +652,7 @@ int orc_eval(const orc_scene *S, const double *angles, const orc_params *P, int3
     rc = grid_setup(S, wtri, P, &g);
     if (rc) { free(wtri); return rc; }
     int64_t np = pixels ? n_pixels : (int64_t)P->n * P->n;
-    int32_t G = P->bounces + 1;
+    int32_t G = orc_record_slots(P);
     if (ids) for (int64_t k = 0; k < np * G; ++k) ids[k] = -1;
     if (ts) for (int64_t k = 0; k < np * G; ++k) ts[k] = 0.0;
     if (!(g.wu * g.wv > 0)) {               /* R3: empty window */
@@ -555,12 +671,24 @@ int orc_eval(const orc_scene *S, const double *angles, const orc_params *P, int3
     }
     pix_out *po = (pix_out *)malloc(sizeof(pix_out) * (size_t)(np + 1));
     if (!po) { if (have_bvh) bvh_free(&B); free(wtri); return ORC_ERR_OOM; }
-#pragma omp parallel for schedule(dynamic, 64)
-    for (int64_t k = 0; k < np; ++k) {
-        int64_t pix = pixels ? pixels[k] : k;
-        trace_pixel(S, wtri, have_bvh ? &B : NULL, P, &g, pix, &po[k],
-                    ids ? ids + k * G : NULL, ts ? ts + k * G : NULL);
+    int oom = 0;
+#pragma omp parallel
+    {
+        double *fan = (double *)malloc(sizeof(double) * 3 * (size_t)(P->n_diffuse + 1));
+        if (!fan) {
+#pragma omp atomic write
+            oom = 1;
+        }
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t k = 0; k < np; ++k) {
+            if (!fan) continue;
+            int64_t pix = pixels ? pixels[k] : k;
+            trace_pixel(S, wtri, have_bvh ? &B : NULL, P, &g, pix, &po[k],
+                        ids ? ids + k * G : NULL, ts ? ts + k * G : NULL, fan);
+        }
+        free(fan);
     }
+    if (oom) { free(po); if (have_bvh) bvh_free(&B); free(wtri); return ORC_ERR_OOM; }
     finish(S, P, &g, po, np, out);
     free(po);
     if (have_bvh) bvh_free(&B);
@@ -581,7 +709,8 @@ int orc_grid_of(const orc_scene *S, const double *angles, const orc_params *P, o
 }
 
 /* ------------------------------------------------------------ frozen visibility
- * Re-shades every ray chain for given hit ids (all generations) on a frozen
+ * Re-shades every ray chain for given hit ids (all generations and, with
+ * diffuse rays, every fan's rays, in the orc_eval record layout) on a frozen
  * grid (window, pixel area, origins), after articulating with `angles` and
  * using the materials in S.  Hit points are the intersections of each chain's
  * rays with the planes of its frozen triangles.  At the angles the ids were
@@ -593,45 +722,81 @@ int orc_shade_frozen(const orc_scene *S, const double *angles, const orc_params 
 {
     int rc = orc_validate(S);
     if (rc) return rc;
+    if (!P || P->n < 1 || P->bounces < 0 || P->n_diffuse < 0 || !ids || !out) return ORC_ERR_ARG;
     double *wtri = (double *)malloc(sizeof(double) * 9 * (size_t)(S->nt + 1));
     if (!wtri) return ORC_ERR_OOM;
     orc_articulate(S, angles, wtri);
     int64_t np = (int64_t)P->n * P->n;
-    int32_t G = P->bounces + 1;
+    int32_t G = orc_record_slots(P), K = P->n_diffuse;
     pix_out *po = (pix_out *)malloc(sizeof(pix_out) * (size_t)(np + 1));
     if (!po) { free(wtri); return ORC_ERR_OOM; }
     double scale = P->pressure * g->a_pix;
-#pragma omp parallel for schedule(static)
-    for (int64_t k = 0; k < np; ++k) {
-        int64_t i = k % P->n, j = k / P->n;
-        double o[3], d[3] = {g->d[0], g->d[1], g->d[2]};
-        pixel_origin(g, P->n, i, j, o);
-        ksum acc[6];
-        memset(acc, 0, sizeof acc);
-        memset(&po[k], 0, sizeof po[k]);
-        double w = 1.0;
-        for (int32_t gen = 0; gen < G; ++gen) {
-            int32_t tri = ids[k * G + gen];
-            if (tri < 0) break;
-            const double *tv = wtri + 9 * (int64_t)tri;
-            double nf[3], nn[3], dF[3], dT[3], r0[3];
-            tri_normal(tv, nf);
-            v_sub(tv, o, r0);
-            double t = v_dot(r0, nf) / v_dot(d, nf);
-            double x[3] = {o[0] + t * d[0], o[1] + t * d[1], o[2] + t * d[2]};
-            int32_t m = S->tri_mat[tri];
-            double rs = S->mats[2 * m], rd = S->mats[2 * m + 1];
-            double cth = shade(scale, w, d, nf, rs, rd, x, P->ref, dF, dT, nn);
-            for (int c = 0; c < 3; ++c) { ks_add(&acc[c], dF[c]); ks_add(&acc[3 + c], dT[c]); }
-            if (gen == 0) po[k].hits++;
-            else po[k].sec_hits++;
-            for (int c = 0; c < 3; ++c) { o[c] = x[c]; d[c] = d[c] + 2.0 * cth * nn[c]; }
-            w *= rs;
+    int oom = 0;
+#pragma omp parallel
+    {
+        double *fan = (double *)malloc(sizeof(double) * 3 * (size_t)(K + 1));
+        if (!fan) {
+#pragma omp atomic write
+            oom = 1;
         }
-        for (int c = 0; c < 6; ++c) po[k].f[c] = ks_val(&acc[c]);
+#pragma omp for schedule(static)
+        for (int64_t k = 0; k < np; ++k) {
+            if (!fan) continue;
+            int64_t i = k % P->n, j = k / P->n;
+            double o[3], d[3] = {g->d[0], g->d[1], g->d[2]};
+            pixel_origin(g, P->n, i, j, o);
+            ksum acc[6];
+            memset(acc, 0, sizeof acc);
+            memset(&po[k], 0, sizeof po[k]);
+            double w = 1.0;
+            for (int32_t gen = 0; gen <= P->bounces; ++gen) {
+                int32_t tri = ids[k * G + gen];
+                if (tri < 0) break;
+                const double *tv = wtri + 9 * (int64_t)tri;
+                double nf[3], nn[3], dF[3], dT[3], r0[3], m[3];
+                tri_normal(tv, nf);
+                v_sub(tv, o, r0);
+                double t = v_dot(r0, nf) / v_dot(d, nf);
+                double x[3] = {o[0] + t * d[0], o[1] + t * d[1], o[2] + t * d[2]};
+                double cth = orient(nf, d, nn);
+                int32_t mt = S->tri_mat[tri];
+                double rs = S->mats[2 * mt], rd = S->mats[2 * mt + 1];
+                int emit = gen < P->bounces && K > 0 && rd > 0.0;
+                if (emit) diffuse_fan(K, nn, fan, m);
+                shade(scale, w, d, nn, cth, rs, rd, emit ? m : NULL, x, P->ref, dF, dT);
+                for (int c = 0; c < 3; ++c) { ks_add(&acc[c], dF[c]); ks_add(&acc[3 + c], dT[c]); }
+                if (gen == 0) po[k].hits++;
+                else po[k].sec_hits++;
+                if (emit) {
+                    for (int32_t q = 0; q < K; ++q) {
+                        int32_t et = ids[k * G + P->bounces + 1 + gen * K + q];
+                        po[k].sec++;
+                        po[k].dif++;
+                        if (et < 0) continue;
+                        const double *e = fan + 3 * q, *ev = wtri + 9 * (int64_t)et;
+                        double mf[3], mn[3], eF[3], eT[3], r1[3];
+                        tri_normal(ev, mf);
+                        v_sub(ev, x, r1);
+                        double te = v_dot(r1, mf) / v_dot(e, mf);
+                        double y[3] = {x[0] + te * e[0], x[1] + te * e[1], x[2] + te * e[2]};
+                        double ce = orient(mf, e, mn);
+                        int32_t me = S->tri_mat[et];
+                        shade(scale, w * rd / (double)K, e, mn, ce, S->mats[2 * me], S->mats[2 * me + 1], NULL,
+                              y, P->ref, eF, eT);
+                        for (int c = 0; c < 3; ++c) { ks_add(&acc[c], eF[c]); ks_add(&acc[3 + c], eT[c]); }
+                        po[k].sec_hits++;
+                        po[k].dif_hits++;
+                    }
+                }
+                for (int c = 0; c < 3; ++c) { o[c] = x[c]; d[c] = d[c] + 2.0 * cth * nn[c]; }
+                w *= rs;
+            }
+            for (int c = 0; c < 6; ++c) po[k].f[c] = ks_val(&acc[c]);
+        }
+        free(fan);
     }
-    finish(S, P, g, po, np, out);
+    if (!oom) finish(S, P, g, po, np, out);
     free(po);
     free(wtri);
-    return ORC_OK;
+    return oom ? ORC_ERR_OOM : ORC_OK;
 }

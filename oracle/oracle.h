@@ -34,6 +34,8 @@ typedef struct {
     int32_t n;                /* N x N rays */
     int32_t bounces;          /* secondary generations */
     double ref[3];            /* torque reference point */
+    int32_t n_diffuse;        /* diffuse rays per emitting hit (R10), 0 = none */
+    int32_t pad_;
 } orc_params;
 
 typedef struct {
@@ -45,6 +47,7 @@ typedef struct {
 typedef struct {
     double force[3], torque[3];
     int64_t n_rays, n_hits, n_secondary, n_secondary_hits;
+    int64_t n_diffuse, n_diffuse_hits;   /* the diffuse part of the secondary counts */
     orc_grid grid;
 } orc_result;
 
@@ -56,7 +59,12 @@ int orc_articulate(const orc_scene *S, const double *angles, double *wtri /* nt 
 int orc_grid_of(const orc_scene *S, const double *angles, const orc_params *P, orc_grid *g);
 int orc_eval(const orc_scene *S, const double *angles, const orc_params *P, int32_t use_bvh,
              const int64_t *pixels, int64_t n_pixels, orc_result *out,
-             int32_t *ids /* n_pix x (B+1) or NULL */, double *ts /* same or NULL */);
+             int32_t *ids /* n_pix x R or NULL */, double *ts /* same or NULL */);
 int orc_shade_frozen(const orc_scene *S, const double *angles, const orc_params *P,
-                     const orc_grid *g, const int32_t *ids /* N*N x (B+1) */, orc_result *out);
+                     const orc_grid *g, const int32_t *ids /* N*N x R */, orc_result *out);
+/* R = record slots per pixel: B + 1 chain generations, then B fans of K
+ * diffuse rays (fan of generation g at slot B + 1 + g K). */
+int32_t orc_record_slots(const orc_params *P);
+/* Diffuse set (R10): the K local directions, K x 3. */
+int orc_diffuse_set(int32_t K, double *l);
 #endif
