@@ -49,6 +49,7 @@ extern "C" {
 
 #define SRP_MAX_N 8192     /* largest ray grid side */
 #define SRP_MAX_BOUNCES 4  /* largest number of secondary generations */
+#define SRP_MAX_DIFFUSE 64 /* largest number of diffuse rays per emitting hit */
 #define SRP_MAX_NODES 128  /* largest number of tree nodes */
 #define SRP_MAX_MATS 64    /* largest number of materials */
 
@@ -85,7 +86,17 @@ typedef struct {
     int32_t bounces;       /* specular secondary generations B, 0..SRP_MAX_BOUNCES */
     double ref[3];         /* torque reference point, body frame */
     uint32_t flags;        /* SRP_F_* */
-    uint32_t reserved;
+    /* Diffuse rays K per emitting hit, 0..SRP_MAX_DIFFUSE (Sec. 4.3: the
+     * secondary rays made at each interaction set the level of scattering;
+     * Sec. 6.1 uses 16).  0: diffuse re-emission is the law's Lambertian
+     * recoil only.  K > 0: a chain hit of generation g < B on a material
+     * with rho_d > 0 also emits K rays of weight w rho_d / K along a fixed
+     * cosine-weighted set (u = (k + 1/2)/K, phi = 2 pi frac(k (sqrt5 - 1)/2),
+     * local (sqrt(u) cos phi, sqrt(u) sin phi, sqrt(1 - u)) in the frame
+     * t = normalize((1,2,3) x n), b = n x t); its recoil is the set's mean
+     * direction; each diffuse ray deposits at its first hit (flat-plate
+     * law) and spawns nothing.  Diffuse rays count as secondary rays. */
+    int32_t n_diffuse;
 } srp_eval_params;
 
 /* Result of one evaluation.  n_box_tests / n_tri_tests are filled only with
@@ -153,11 +164,15 @@ int srp_set_panel_angles(srp_scene *scene, const double *angles, int32_t n_dof);
 
 /* One evaluation at the scene's current angles; blocks until the result is
  * on the host.  Optional per-ray records (host buffers, may be NULL):
- *   hit_ids: N*N*(B+1) int32, pixel p = j*N + i (row j, column i) major,
- *            generation minor; the original triangle index or -1;
+ *   hit_ids: N*N*R int32 with R = (B+1) + B*K rays per pixel, pixel
+ *            p = j*N + i (row j, column i) major; within a pixel the chain's
+ *            generations 0..B, then generation g's fan of K diffuse rays at
+ *            B+1+g*K..; the original triangle index, or -1 for a miss or a
+ *            ray not traced;
  *   hit_t:   same layout, ray parameter of the hit (0 where none).
- * Errors: SRP_ERR_ARG (null scene/params/out, N or B out of range,
- * non-finite or zero sun_dir, non-finite pressure/ref), SRP_ERR_DEVICE. */
+ * Errors: SRP_ERR_ARG (null scene/params/out, N, B or K out of range,
+ * non-finite or zero sun_dir, non-finite pressure/ref), SRP_ERR_OOM (record
+ * buffer), SRP_ERR_DEVICE. */
 int srp_eval(srp_scene *scene, const srp_eval_params *params, srp_result *out,
              int32_t *hit_ids, float *hit_t);
 
@@ -177,7 +192,8 @@ int srp_eval_batch(const srp_batch_item *items, int64_t n_items, srp_result *out
  * triangles of every generation, window, pixel area and ray origins frozen):
  *   dF_drho_s: n_mats x 3, dF_drho_d: n_mats x 3, dF_dtheta: n_dof x 3 (host).
  * dF_dtheta is with respect to the clamped angles.  Any gradient pointer may
- * be NULL.  Blocks until the results are on the host.  Errors as srp_eval. */
+ * be NULL.  Blocks until the results are on the host.  Errors as srp_eval;
+ * SRP_ERR_ARG for n_diffuse > 0 (the adjoint covers the specular chain only). */
 int srp_eval_grad(srp_scene *scene, const srp_eval_params *params, srp_result *out,
                   double *dF_drho_s, double *dF_drho_d, double *dF_dtheta);
 
@@ -257,7 +273,7 @@ typedef struct {
     int32_t n;          /* SRP ray grid N */
     int32_t bounces;    /* SRP secondary generations */
     int32_t track_sun;  /* 1: wing roots track the Sun (srp_sun_tracking_angles) every stage */
-    int32_t reserved;
+    int32_t n_diffuse;  /* SRP diffuse rays per emitting hit (srp_eval_params.n_diffuse) */
     double ref[3];      /* torque reference point */
 } srp_orbit_params;
 

@@ -22,7 +22,7 @@ def _load():
     return L.load()
 
 
-def params(sun_dir, n, bounces=0, pressure=1.0, ref=(0.0, 0.0, 0.0), count=False):
+def params(sun_dir, n, bounces=0, pressure=1.0, ref=(0.0, 0.0, 0.0), count=False, diffuse=0):
     p = L.srp_eval_params()
     p.sun_dir[:] = [float(x) for x in sun_dir]
     p.pressure = float(pressure)
@@ -30,7 +30,14 @@ def params(sun_dir, n, bounces=0, pressure=1.0, ref=(0.0, 0.0, 0.0), count=False
     p.bounces = int(bounces)
     p.ref[:] = [float(x) for x in ref]
     p.flags = L.SRP_F_COUNT if count else 0
+    p.n_diffuse = int(diffuse)
     return p
+
+
+def record_slots(bounces, diffuse=0):
+    """Recorded rays per pixel: B + 1 chain generations, then B fans of K
+    diffuse rays (generation g's fan at B + 1 + g K)."""
+    return int(bounces) + 1 + int(bounces) * int(diffuse)
 
 
 class Scene:
@@ -97,16 +104,18 @@ def _result_dict(r) -> dict:
 
 
 def eval(scene: Scene, sun_dir, n, bounces=0, pressure=1.0, ref=(0, 0, 0), count=False,
-         record=False) -> dict:
-    """srp_eval at the scene's current angles.  With record=True the result
-    also holds ids (N*N, B+1) int32 and ts (N*N, B+1) float32."""
+         record=False, diffuse=0) -> dict:
+    """srp_eval at the scene's current angles with `diffuse` diffuse rays per
+    emitting hit.  With record=True the result also holds ids (N*N, R) int32
+    and ts (N*N, R) float32, R = record_slots(bounces, diffuse)."""
     lib = _load()
-    p = params(sun_dir, n, bounces, pressure, ref, count)
+    p = params(sun_dir, n, bounces, pressure, ref, count, diffuse)
     r = L.srp_result()
     ids = ts = None
     if record:
-        ids = np.empty((n * n, bounces + 1), np.int32)
-        ts = np.empty((n * n, bounces + 1), np.float32)
+        R = record_slots(bounces, diffuse)
+        ids = np.empty((n * n, R), np.int32)
+        ts = np.empty((n * n, R), np.float32)
     L.check(lib.srp_eval(scene.handle, C.byref(p), C.byref(r), L.ptr(ids), L.ptr(ts)))
     out = _result_dict(r)
     if record:
@@ -232,11 +241,11 @@ def rk4(y0, t0, h, n_steps, accel) -> np.ndarray:
 
 
 def propagate(scene: Scene, y0, t0, h, n_steps, mu, mass, p_ref, r_ref, n, bounces=0,
-              track_sun=False, angles0=None, ref=(0.0, 0.0, 0.0)):
+              track_sun=False, angles0=None, ref=(0.0, 0.0, 0.0), diffuse=0):
     """srp_propagate: heliocentric two-body + ray-traced SRP, RK4, one GPU
     evaluation per stage.  Returns (traj (n_steps+1, 7), stats dict)."""
     op = L.srp_orbit_params(float(mu), float(mass), float(p_ref), float(r_ref), int(n), int(bounces),
-                            1 if track_sun else 0, 0, (C.c_double * 3)(*ref))
+                            1 if track_sun else 0, int(diffuse), (C.c_double * 3)(*ref))
     y = np.ascontiguousarray(y0, dtype=np.float64)
     a0 = None if angles0 is None else np.ascontiguousarray(angles0, dtype=np.float64)
     traj = np.zeros((n_steps + 1, 7))

@@ -11,7 +11,7 @@ LIB_PATH = os.path.join(HERE, "libsrp_mi355x.so")
 
 SRP_OK, SRP_ERR_ARG, SRP_ERR_OOM, SRP_ERR_DEVICE, SRP_ERR_DEPTH = 0, -1, -2, -3, -4
 SRP_F_COUNT = 1
-SRP_MAX_N, SRP_MAX_BOUNCES, SRP_MAX_NODES, SRP_MAX_MATS = 8192, 4, 128, 64
+SRP_MAX_N, SRP_MAX_BOUNCES, SRP_MAX_NODES, SRP_MAX_MATS, SRP_MAX_DIFFUSE = 8192, 4, 128, 64, 64
 
 EXPORTS = [
     "srp_build_scene", "srp_destroy_scene", "srp_scene_n_dof", "srp_set_materials",
@@ -37,7 +37,7 @@ class srp_node(C.Structure):
 class srp_eval_params(C.Structure):
     _fields_ = [("sun_dir", C.c_double * 3), ("pressure", C.c_double), ("n", C.c_int32),
                 ("bounces", C.c_int32), ("ref", C.c_double * 3), ("flags", C.c_uint32),
-                ("reserved", C.c_uint32)]
+                ("n_diffuse", C.c_int32)]
 
 
 class srp_result(C.Structure):
@@ -54,7 +54,7 @@ class srp_batch_item(C.Structure):
 class srp_orbit_params(C.Structure):
     _fields_ = [("mu", C.c_double), ("mass", C.c_double), ("p_ref", C.c_double),
                 ("r_ref", C.c_double), ("n", C.c_int32), ("bounces", C.c_int32),
-                ("track_sun", C.c_int32), ("reserved", C.c_int32), ("ref", C.c_double * 3)]
+                ("track_sun", C.c_int32), ("n_diffuse", C.c_int32), ("ref", C.c_double * 3)]
 
 
 class srp_prop_stats(C.Structure):

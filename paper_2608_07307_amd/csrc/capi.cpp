@@ -29,7 +29,7 @@ struct srp_scene {
     SlotLayout slot_L{};
     SlotHost cur;
     std::vector<double> angles;    // current (clamped) angles
-    // captured single-evaluation launches keyed by (n, bounces, flags)
+    // captured single-evaluation launches keyed by (n, diffuse rays, bounces, flags)
     std::map<uint64_t, PlanImpl *> eval_plans;
     srp_result *d_res = nullptr;   // device result of those launches
     srp_result *h_res = nullptr;   // pinned host copy
@@ -68,8 +68,39 @@ struct Workspace {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
     bool pending = false;
+    float *d_dset = nullptr;       // diffuse direction sets, K = 1..SRP_MAX_DIFFUSE
 };
 Workspace g_ws;
+
+// Diffuse direction sets: for K = 1..SRP_MAX_DIFFUSE, K entries (x, y, z, 0)
+// then their mean; set K starts at entry (K - 1)(K + 2)/2.  Ray k of K has
+// u = (k + 1/2)/K, phi = 2 pi frac(k (sqrt5 - 1)/2) and local direction
+// (sqrt(u) cos phi, sqrt(u) sin phi, sqrt(1 - u)): Fibonacci points on the
+// unit disk lifted to the hemisphere, so the directions are cosine
+// distributed about the normal.  Computed in FP64, stored as FP32.
+size_t dset_entry(int K) { return (size_t)(K - 1) * (size_t)(K + 2) / 2; }
+
+std::vector<float> diffuse_sets() {
+    std::vector<float> t(4 * dset_entry(SRP_MAX_DIFFUSE + 1), 0.0f);
+    const double g = (std::sqrt(5.0) - 1.0) / 2.0, two_pi = 6.283185307179586476925;
+    for (int K = 1; K <= SRP_MAX_DIFFUSE; ++K) {
+        float *e = &t[4 * dset_entry(K)];
+        double m[3] = {0, 0, 0};
+        for (int k = 0; k < K; ++k) {
+            const double u = (k + 0.5) / K;
+            double f = k * g;
+            f -= std::floor(f);
+            const double r = std::sqrt(u), ph = two_pi * f;
+            const double l[3] = {r * std::cos(ph), r * std::sin(ph), std::sqrt(1.0 - u)};
+            for (int c = 0; c < 3; ++c) {
+                e[4 * k + c] = (float)l[c];
+                m[c] += l[c];
+            }
+        }
+        for (int c = 0; c < 3; ++c) e[4 * K + c] = (float)(m[c] / K);
+    }
+    return t;
+}
 
 // Optional timing of the trace-kernel launches (HIP events on the launch stream).
 struct Profile {
@@ -111,6 +142,15 @@ int ws_init() {
     HIPCHK(hipDeviceGetAttribute(&g_ws.n_cu, hipDeviceAttributeMultiprocessorCount, g_ws.device));
     HIPCHK(hipStreamCreateWithFlags(&g_ws.stream, hipStreamNonBlocking));
     HIPCHK(hipEventCreateWithFlags(&g_ws.done, hipEventDisableTiming));
+    {
+        const std::vector<float> t = diffuse_sets();
+        if (hipMalloc(&g_ws.d_dset, t.size() * sizeof(float)) != hipSuccess) {
+            (void)hipGetLastError();
+            g_ws.d_dset = nullptr;
+            return fail(SRP_ERR_OOM, "diffuse set allocation failed");
+        }
+        HIPCHK(hipMemcpy(g_ws.d_dset, t.data(), t.size() * sizeof(float), hipMemcpyHostToDevice));
+    }
     g_ws.init = true;
     return SRP_OK;
 }
@@ -163,6 +203,8 @@ int check_params(const srp_eval_params *p) {
     if (!(s > 0) || !std::isfinite(s)) return fail(SRP_ERR_ARG, "zero sun_dir");
     if (!std::isfinite(p->pressure) || !finite3(p->ref)) return fail(SRP_ERR_ARG, "non-finite pressure or ref");
     if (p->flags & ~(uint32_t)SRP_F_COUNT) return fail(SRP_ERR_ARG, "unknown flags");
+    if (p->n_diffuse < 0 || p->n_diffuse > SRP_MAX_DIFFUSE)
+        return fail(SRP_ERR_ARG, "n_diffuse must be in 0.." + std::to_string(SRP_MAX_DIFFUSE));
     return SRP_OK;
 }
 
@@ -208,15 +250,18 @@ int ilog2(int64_t x) {
     return k;
 }
 
-// Autotuner key: total primary rays (power-of-two bucket), bounces, gradient.
+// Autotuner key: total primary rays (power-of-two bucket), bounces, diffuse
+// rays, gradient.
 uint64_t tune_key(const srp_batch_item *items, int64_t n, bool grad) {
     int64_t rays = 0;
-    int b = 0;
+    int b = 0, kd = 0;
     for (int64_t k = 0; k < n; ++k) {
         rays += (int64_t)items[k].p.n * items[k].p.n;
         b = std::max(b, (int)items[k].p.bounces);
+        kd = std::max(kd, (int)items[k].p.n_diffuse);
     }
-    return ((uint64_t)ilog2(std::max<int64_t>(rays, 1)) << 8) | ((uint64_t)b << 1) | (grad ? 1u : 0u);
+    return ((uint64_t)ilog2(std::max<int64_t>(rays, 1)) << 16) | ((uint64_t)kd << 8) | ((uint64_t)b << 1) |
+           (grad ? 1u : 0u);
 }
 
 struct SlotRec {
@@ -255,6 +300,8 @@ int check_items(const srp_batch_item *items, int64_t n, bool grad, const BatchOu
         if (it.angles)
             for (int j = 0; j < it.scene->h.n_dof; ++j)
                 if (!std::isfinite(it.angles[j])) return fail(SRP_ERR_ARG, "item " + std::to_string(k) + ": non-finite angle");
+        if (grad && it.p.n_diffuse > 0)
+            return fail(SRP_ERR_ARG, "item " + std::to_string(k) + ": the adjoint does not cover diffuse rays (n_diffuse must be 0)");
         if (grad) {
             int gn = 9 * it.scene->h.n_nodes + 6 * it.scene->h.n_mats;
             if (gn > MAX_GRAD_SLOTS) return fail(SRP_ERR_ARG, "gradient needs 9*nodes + 6*materials <= 960");
@@ -437,6 +484,8 @@ void staging_fill(const Layout &L, const srp_batch_item *items, const BatchOut &
         D.n = it.p.n;
         D.bounces = it.p.bounces;
         D.flags = it.p.flags;
+        D.n_diffuse = it.p.n_diffuse;
+        D.dset = it.p.n_diffuse > 0 ? g_ws.d_dset + 4 * dset_entry(it.p.n_diffuse) : nullptr;
         D.tiles_x = L.tiles_x[k];
         D.tiles_y = L.tiles_y[k];
         D.ppc = L.sch.ppc;
@@ -758,7 +807,8 @@ int srp_eval(srp_scene *scene, const srp_eval_params *params, srp_result *out, i
         if (hipMalloc(&scene->d_res, sizeof(srp_result)) != hipSuccess) { (void)hipGetLastError(); return fail(SRP_ERR_OOM, "result allocation failed"); }
         if (hipHostMalloc(&scene->h_res, sizeof(srp_result), hipHostMallocDefault) != hipSuccess) { (void)hipGetLastError(); return fail(SRP_ERR_OOM, "pinned result allocation failed"); }
     }
-    size_t nrec = (hit_ids || hit_t) ? (size_t)params->n * params->n * (params->bounces + 1) : 0;
+    const size_t R = (size_t)params->bounces + 1 + (size_t)params->bounces * params->n_diffuse;
+    size_t nrec = (hit_ids || hit_t) ? (size_t)params->n * params->n * R : 0;
     if (nrec) {
         // recorded evaluations (tests, fixed-visibility checks) take the direct path
         static char *d_rec = nullptr;
@@ -787,7 +837,8 @@ int srp_eval(srp_scene *scene, const srp_eval_params *params, srp_result *out, i
         if (hit_t) HIPCHK(hipMemcpy(hit_t, d_rec + nrec * 4, nrec * 4, hipMemcpyDeviceToHost));
     } else {
         // replay of a captured single-evaluation launch (one graph launch + one sync)
-        uint64_t key = ((uint64_t)params->n << 16) | ((uint64_t)params->bounces << 8) | params->flags;
+        uint64_t key = ((uint64_t)params->n << 24) | ((uint64_t)params->n_diffuse << 16) |
+                       ((uint64_t)params->bounces << 8) | params->flags;
         PlanImpl *P = nullptr;
         auto f = scene->eval_plans.find(key);
         if (f != scene->eval_plans.end()) {

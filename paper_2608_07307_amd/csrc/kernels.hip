@@ -55,6 +55,9 @@ __device__ __forceinline__ double wave_sum(double x) {
 // the last ones (a mirror reflection is its own inverse).
 constexpr uint32_t CHAIN_FLIP = 0x80000000u;
 
+// LDS words per lane of a pending diffuse fan (forward kernels).
+constexpr int FAN_WORDS = 7;
+
 // Adds per-lane vectors into per-wave LDS accumulators acc[key * stride + 0..n),
 // one wave-wide FP64 sum per distinct key (keys processed lowest lane first).
 __device__ void wave_scatter_add(double *acc, int key, bool active, const float *vals, int n, int stride) {
@@ -98,6 +101,69 @@ __device__ __forceinline__ void wave_lds_fence() {
     __builtin_amdgcn_wave_barrier();
 }
 
+// Hit record -> unit normal n facing the incoming direction d, c = -n.d, the
+// material's (rho_s, rho_d) and the original triangle index; returns whether
+// the geometric normal was flipped.
+__device__ __forceinline__ bool hit_normal(const TraceCtx &TC, const EvalDesc &D, const Hit &h, const float d[3],
+                                           float n[3], float &c, float &rs, float &rd, int32_t &id) {
+    const TriRec SRP_GLOBAL &T = TC.tris[h.tri];
+    const Inst SRP_GLOBAL &I = TC.inst[h.inst];
+    float e1[3] = {T.v1[0] - T.v0[0], T.v1[1] - T.v0[1], T.v1[2] - T.v0[2]};
+    float e2[3] = {T.v2[0] - T.v0[0], T.v2[1] - T.v0[1], T.v2[2] - T.v0[2]};
+    float nl[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+    for (int k = 0; k < 3; ++k) n[k] = I.R[3 * k] * nl[0] + I.R[3 * k + 1] * nl[1] + I.R[3 * k + 2] * nl[2];
+    float inv = rsqrtf(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+    const float nd = (n[0] * d[0] + n[1] * d[1] + n[2] * d[2]) * inv;
+    const bool flip = nd > 0.0f;
+    if (flip) inv = -inv;
+    for (int k = 0; k < 3; ++k) n[k] *= inv;
+    c = -(n[0] * d[0] + n[1] * d[1] + n[2] * d[2]);
+    rs = D.mats[2 * T.mat];
+    rd = D.mats[2 * T.mat + 1];
+    id = T.id;
+    return flip;
+}
+
+// Adds force f at point x (and its torque about ref) to the lane's FP64 sums.
+__device__ __forceinline__ void deposit(double *lacc, const float f[3], const float x[3], const double ref[3]) {
+    float rr[3];
+    for (int k = 0; k < 3; ++k) rr[k] = x[k] - (float)ref[k];
+    lds_add(lacc, (double)f[0]);
+    lds_add(lacc + BLOCK, (double)f[1]);
+    lds_add(lacc + 2 * BLOCK, (double)f[2]);
+    lds_add(lacc + 3 * BLOCK, (double)(rr[1] * f[2] - rr[2] * f[1]));
+    lds_add(lacc + 4 * BLOCK, (double)(rr[2] * f[0] - rr[0] * f[2]));
+    lds_add(lacc + 5 * BLOCK, (double)(rr[0] * f[1] - rr[1] * f[0]));
+}
+
+// Tangent frame of a diffuse fan about unit normal n: t = normalize(h x n)
+// with the fixed helper h = (1, 2, 3) (e_x when h x n vanishes), b = n x t.
+// A generic helper keeps the frame smooth for every normal but +-h.
+__device__ __forceinline__ void fan_frame(const float n[3], float t[3], float b[3]) {
+    float c0 = 2.0f * n[2] - 3.0f * n[1], c1 = 3.0f * n[0] - n[2], c2 = n[1] - 2.0f * n[0];
+    float l2 = c0 * c0 + c1 * c1 + c2 * c2;
+    if (!(l2 > 0.0f)) {
+        c0 = 0.0f;
+        c1 = -n[2];
+        c2 = n[1];
+        l2 = c1 * c1 + c2 * c2;
+    }
+    const float il = rsqrtf(l2);
+    t[0] = c0 * il;
+    t[1] = c1 * il;
+    t[2] = c2 * il;
+    b[0] = n[1] * t[2] - n[2] * t[1];
+    b[1] = n[2] * t[0] - n[0] * t[2];
+    b[2] = n[0] * t[1] - n[1] * t[0];
+}
+
+// World direction of the fan ray with local direction l about normal n.
+__device__ __forceinline__ void fan_dir(const float n[3], const float4 l, float d[3]) {
+    float t[3], b[3];
+    fan_frame(n, t, b);
+    for (int k = 0; k < 3; ++k) d[k] = l.x * t[k] + l.y * b[k] + l.z * n[k];
+}
+
 template <bool COUNT, bool GRAD>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(GRAD ? SRP_WPE_GRAD : SRP_WPE_FWD))) void k_trace(
     const EvalDesc *__restrict__ descs, const int64_t *__restrict__ chunk_base, int n_evals,
@@ -113,9 +179,12 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(GRAD ? SR
     // per-lane FP64 force/torque sums of the current patch (component k at [k * BLOCK]):
     // kept in LDS and updated with LDS adds, out of the traversal's registers
     double *lacc = reinterpret_cast<double *>(smem + sizeof(uint32_t) * STACK_LDS * BLOCK) + tid;
-    // adjoint only: the hit chains (hit k at [k * BLOCK]), then per-wave gradient sums
+    // adjoint only: the hit chains (hit k at [k * BLOCK]), then per-wave gradient sums;
+    // forward only: the pending diffuse fan (emitter normal, then the specular ray's
+    // direction and weight waiting for the fan to finish), word k at [k * BLOCK]
     uint32_t *lchain = reinterpret_cast<uint32_t *>(smem + sizeof(uint32_t) * STACK_LDS * BLOCK +
                                                     sizeof(double) * 6 * BLOCK) + tid;
+    float *lfan = reinterpret_cast<float *>(lchain);
     double *gw = reinterpret_cast<double *>(smem + sizeof(uint32_t) * STACK_LDS * BLOCK + sizeof(double) * 6 * BLOCK +
                                             sizeof(uint32_t) * MAX_CHAIN * BLOCK) +
                  (size_t)wv * lds_grad_doubles;
@@ -193,6 +262,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(GRAD ? SR
 
         const int64_t p0 = kc * D.ppc, p1 = min(p0 + D.ppc, D.n_patches);
         const int B = D.bounces;
+        const int KD = GRAD ? 0 : D.n_diffuse;          // diffuse rays per emitting hit
+        const int R = B + 1 + B * KD;                   // recorded rays per pixel
+        const float4 *dset = reinterpret_cast<const float4 *>(D.dset);   // KD directions, then their mean
         const TraceCtx TC = trace_ctx(D);
 
         const int gK = D.n_nodes;
@@ -210,20 +282,22 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(GRAD ? SR
             const int px = (tile % D.tiles_x) * TILE + (q & 1) * PATCH + (lane & 7);
             const int py = (tile / D.tiles_x) * TILE + (q >> 1) * PATCH + (lane >> 3);
             for (int k = 0; k < 6; ++k) lacc[k * BLOCK] = 0.0;
-            // hit counts packed in 10-bit fields (primary hits, secondary rays, secondary hits;
-            // a patch sums at most 64 * SRP_MAX_BOUNCES of each), the status separately
-            uint32_t hcnt = 0, nbox = 0, ntri = 0, status = 0;
+            // hit counts packed in 10-bit fields (primary hits, specular secondary rays and
+            // their hits; a patch sums at most 64 * SRP_MAX_BOUNCES of each), diffuse rays and
+            // their hits in 16-bit fields (at most 64 * SRP_MAX_BOUNCES * SRP_MAX_DIFFUSE), the
+            // status separately
+            uint32_t hcnt = 0, dcnt = 0, nbox = 0, ntri = 0, status = 0;
             {
                 const bool inside = px < N && py < N;
                 const bool valid = !empty && inside;
+                const int64_t pix = (int64_t)py * N + px;
                 int K = 0;
                 float d[3] = {dd[0], dd[1], dd[2]}, w = 1.0f;   // the current ray's direction and weight
-                bool cont = false;                              // the last hit spawned a ray
-                if (inside && D.hit_ids) {   // generations a chain does not reach stay "no hit"
-                    const int64_t pix = (int64_t)py * N + px;
-                    for (int gen = 0; gen <= B; ++gen) {
-                        D.hit_ids[pix * (B + 1) + gen] = -1;
-                        D.hit_t[pix * (B + 1) + gen] = 0.0f;
+                bool cont = false;                              // the last chain hit spawned a specular ray
+                if (inside && D.hit_ids) {   // rays that are not traced or miss stay "no hit"
+                    for (int s = 0; s < R; ++s) {
+                        D.hit_ids[pix * R + s] = -1;
+                        D.hit_t[pix * R + s] = 0.0f;
                     }
                 }
                 if (valid) {
@@ -231,59 +305,104 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(GRAD ? SR
                     for (int k = 0; k < 3; ++k) o[k] = fmaf((float)py, sv[k], fmaf((float)px, su[k], o0[k]));
                     float tmin = 0.0f;
                     int32_t excl = -1;
-                    const int64_t pix = (int64_t)py * N + px;
+                    // One loop traces the lane's specular chain and, after an emitting hit, its
+                    // fan of diffuse rays, then resumes the chain: lanes without a fan keep
+                    // following their chains while others trace fan rays.
+                    int gen = 0;   // chain generation (of the emitting hit while its fan is traced)
+                    int fk = -1;   // fan ray being traced; -1 while the chain is
                     #pragma unroll 1
-                    for (int gen = 0; gen <= B; ++gen) {
+                    for (;;) {
                         Hit h;
                         if (!trace_closest<COUNT>(TC, o, d, tmin, excl, stack, h, nbox, ntri)) {
                             status |= SRP_STATUS_STACK;
                             break;
                         }
+                        if (!GRAD && fk >= 0) {
+                            // diffuse ray: deposits at its first hit and spawns nothing
+                            if (D.hit_ids) {
+                                const int64_t slot = pix * R + (B + 1 + gen * KD + fk);
+                                D.hit_ids[slot] = h.tri >= 0 ? h.id : -1;
+                                D.hit_t[slot] = h.tri >= 0 ? h.t : 0.0f;
+                            }
+                            dcnt += 1u;
+                            if (h.tri >= 0) {
+                                dcnt += 1u << 16;
+                                float n[3], c, rs, rd;
+                                int32_t id;
+                                hit_normal(TC, D, h, d, n, c, rs, rd, id);
+                                const float a = w * (1.0f - rs), b = -2.0f * w * (rs * c + rd * (1.0f / 3.0f));
+                                float f[3], x[3];
+                                for (int k = 0; k < 3; ++k) {
+                                    f[k] = a * d[k] + b * n[k];
+                                    x[k] = fmaf(h.t, d[k], o[k]);
+                                }
+                                deposit(lacc, f, x, D.ref);
+                            }
+                            if (++fk < KD) {
+                                const float fn[3] = {lfan[0], lfan[BLOCK], lfan[2 * BLOCK]};
+                                fan_dir(fn, dset[fk], d);
+                                continue;
+                            }
+                            // fan done: the emitting hit's specular ray, if it spawned one
+                            fk = -1;
+                            const float cw = lfan[6 * BLOCK];
+                            if (!(cw > 0.0f)) break;
+                            for (int k = 0; k < 3; ++k) d[k] = lfan[(3 + k) * BLOCK];
+                            w = cw;
+                            ++gen;
+                            hcnt += 1u << 10;
+                            continue;
+                        }
                         if (D.hit_ids) {
-                            D.hit_ids[pix * (B + 1) + gen] = h.tri >= 0 ? h.id : -1;
-                            D.hit_t[pix * (B + 1) + gen] = h.tri >= 0 ? h.t : 0.0f;
+                            D.hit_ids[pix * R + gen] = h.tri >= 0 ? h.id : -1;
+                            D.hit_t[pix * R + gen] = h.tri >= 0 ? h.t : 0.0f;
                         }
                         if (h.tri < 0) break;
                         hcnt += gen == 0 ? 1u : (1u << 20);
-                        const TriRec SRP_GLOBAL &T = TC.tris[h.tri];
-                        const Inst SRP_GLOBAL &I = TC.inst[h.inst];
-                        float e1[3] = {T.v1[0] - T.v0[0], T.v1[1] - T.v0[1], T.v1[2] - T.v0[2]};
-                        float e2[3] = {T.v2[0] - T.v0[0], T.v2[1] - T.v0[1], T.v2[2] - T.v0[2]};
-                        float nl[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
-                                       e1[0] * e2[1] - e1[1] * e2[0]};
-                        float n[3];
-                        for (int k = 0; k < 3; ++k) n[k] = I.R[3 * k] * nl[0] + I.R[3 * k + 1] * nl[1] + I.R[3 * k + 2] * nl[2];
-                        float inv = rsqrtf(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
-                        float nd = (n[0] * d[0] + n[1] * d[1] + n[2] * d[2]) * inv;
-                        const bool flip = nd > 0.0f;
-                        if (flip) inv = -inv;
-                        for (int k = 0; k < 3; ++k) n[k] *= inv;
-                        const float cth = -(n[0] * d[0] + n[1] * d[1] + n[2] * d[2]);
-                        const float rs = D.mats[2 * T.mat], rd = D.mats[2 * T.mat + 1];
-                        const float a = w * (1.0f - rs), b = -2.0f * w * (rs * cth + rd * (1.0f / 3.0f));
-                        float f[3], x[3], rr[3];
-                        for (int k = 0; k < 3; ++k) {
-                            f[k] = a * d[k] + b * n[k];
-                            x[k] = fmaf(h.t, d[k], o[k]);
-                            rr[k] = x[k] - (float)D.ref[k];
+                        float n[3], cth, rs, rd;
+                        int32_t id;
+                        const bool flip = hit_normal(TC, D, h, d, n, cth, rs, rd, id);
+                        const bool emit = !GRAD && KD > 0 && gen < B && rd > 0.0f;
+                        const bool spec = gen < B && rs > 0.0f;
+                        const float a = w * (1.0f - rs);
+                        float f[3], x[3], ft[3] = {0, 0, 0}, fb[3] = {0, 0, 0};
+                        if (emit) {
+                            // the fan's exact mean direction replaces the Lambertian 2/3 n recoil
+                            fan_frame(n, ft, fb);
+                            const float4 m = dset[KD];
+                            const float b = -2.0f * w * rs * cth - w * rd * m.z, e = -w * rd;
+                            for (int k = 0; k < 3; ++k) f[k] = a * d[k] + b * n[k] + e * (m.x * ft[k] + m.y * fb[k]);
+                        } else {
+                            const float b = -2.0f * w * (rs * cth + rd * (1.0f / 3.0f));
+                            for (int k = 0; k < 3; ++k) f[k] = a * d[k] + b * n[k];
                         }
-                        lds_add(lacc, (double)f[0]);
-                        lds_add(lacc + BLOCK, (double)f[1]);
-                        lds_add(lacc + 2 * BLOCK, (double)f[2]);
-                        lds_add(lacc + 3 * BLOCK, (double)(rr[1] * f[2] - rr[2] * f[1]));
-                        lds_add(lacc + 4 * BLOCK, (double)(rr[2] * f[0] - rr[0] * f[2]));
-                        lds_add(lacc + 5 * BLOCK, (double)(rr[0] * f[1] - rr[1] * f[0]));
+                        for (int k = 0; k < 3; ++k) x[k] = fmaf(h.t, d[k], o[k]);
+                        deposit(lacc, f, x, D.ref);
                         if (GRAD) lchain[K * BLOCK] = (uint32_t)h.tri | (flip ? CHAIN_FLIP : 0u);
                         ++K;
                         cont = false;
-                        if (gen == B || !(rs > 0.0f)) break;
+                        if (!emit && !spec) break;
                         for (int k = 0; k < 3; ++k) {
                             o[k] = x[k];
-                            d[k] = fmaf(2.0f * cth, n[k], d[k]);
+                            d[k] = fmaf(2.0f * cth, n[k], d[k]);   // the specular direction
+                        }
+                        tmin = tmin2;
+                        excl = id;
+                        if (emit) {
+                            // keep the emitter normal and the pending specular ray, trace fan ray 0
+                            for (int k = 0; k < 3; ++k) {
+                                lfan[k * BLOCK] = n[k];
+                                lfan[(3 + k) * BLOCK] = d[k];
+                            }
+                            lfan[6 * BLOCK] = spec ? w * rs : 0.0f;
+                            w = w * rd / (float)KD;
+                            fk = 0;
+                            const float4 l = dset[0];
+                            for (int k = 0; k < 3; ++k) d[k] = l.x * ft[k] + l.y * fb[k] + l.z * n[k];
+                            continue;
                         }
                         w *= rs;
-                        tmin = tmin2;
-                        excl = T.id;
+                        ++gen;
                         cont = true;
                         hcnt += 1u << 10;
                     }
@@ -370,13 +489,15 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(GRAD ? SR
                 for (int k = 0; k < 6; ++k) tot[k] = wave_sum(lacc[k * BLOCK]);
             for (int m = 32; m >= 1; m >>= 1) {
                 hcnt += __shfl_xor(hcnt, m, WAVE);
+                if (!GRAD) dcnt += __shfl_xor(dcnt, m, WAVE);
                 status |= __shfl_xor(status, m, WAVE);
                 if (COUNT) {
                     nbox += __shfl_xor(nbox, m, WAVE);
                     ntri += __shfl_xor(ntri, m, WAVE);
                 }
             }
-            const uint32_t cnts[6] = {hcnt & 1023u, (hcnt >> 10) & 1023u, hcnt >> 20, nbox, ntri, status};
+            const uint32_t cnts[6] = {hcnt & 1023u, ((hcnt >> 10) & 1023u) + (dcnt & 0xffffu),
+                                      (hcnt >> 20) + (dcnt >> 16), nbox, ntri, status};
             if (lane == 0) {
                 PatchOut co;
                 for (int k = 0; k < 6; ++k) co.f[k] = tot[k];
@@ -584,7 +705,8 @@ int launch_window(const EvalDesc *d_desc, int n_evals, int blocks_x, uint64_t *d
 
 size_t trace_lds_bytes(bool grad, int lds_grad_doubles) {
     return sizeof(uint32_t) * STACK_LDS * BLOCK + sizeof(double) * 6 * BLOCK +
-           (grad ? sizeof(uint32_t) * MAX_CHAIN * BLOCK + sizeof(double) * (BLOCK / 64) * lds_grad_doubles : 0);
+           (grad ? sizeof(uint32_t) * MAX_CHAIN * BLOCK + sizeof(double) * (BLOCK / 64) * lds_grad_doubles
+                 : sizeof(float) * FAN_WORDS * BLOCK);
 }
 
 int launch_trace(const EvalDesc *d_desc, const int64_t *d_chunk_base, int n_evals, const uint64_t *d_win,

@@ -196,6 +196,7 @@ int prop_accel(double, const double *r, const double *, double *a, void *user) {
     p.pressure = O.p_ref * (O.r_ref / rn) * (O.r_ref / rn);
     p.n = O.n;
     p.bounces = O.bounces;
+    p.n_diffuse = O.n_diffuse;
     std::memcpy(p.ref, O.ref, sizeof p.ref);
     srp_result res;
     if ((rc = srp_eval(C.sc, &p, &res, nullptr, nullptr))) return rc;

@@ -124,12 +124,13 @@ struct alignas(64) EvalDesc {
     int64_t patch_base;     // first patch of this evaluation (partial sums are per patch)
     int64_t n_patches;      // 4 * tiles_x * tiles_y
     int32_t tiles_y;        // 16-pixel tile rows
-    int32_t pad_;
+    int32_t n_diffuse;      // diffuse rays per emitting hit (0 = none)
     // optional outputs
-    int32_t *hit_ids;       // N*N*(B+1) or null
+    int32_t *hit_ids;       // N*N*R (R = B+1 + B*n_diffuse) or null
     float *hit_t;
     double *grad_part;      // n_chunks x grad_n (gradient partials)
     double *grad_out;       // 3*(2M+J) final gradient or null
+    const float *dset;      // n_diffuse > 0: the diffuse set, 4 floats per ray (x, y, z, 0), then its mean
 };
 
 // The host writes these records and the kernels read them: both compilation
@@ -166,10 +167,12 @@ static_assert(offsetof(EvalDesc, n_chunks) == 240, "EvalDesc layout");
 static_assert(offsetof(EvalDesc, patch_base) == 248, "EvalDesc layout");
 static_assert(offsetof(EvalDesc, n_patches) == 256, "EvalDesc layout");
 static_assert(offsetof(EvalDesc, tiles_y) == 264, "EvalDesc layout");
+static_assert(offsetof(EvalDesc, n_diffuse) == 268, "EvalDesc layout");
 static_assert(offsetof(EvalDesc, hit_ids) == 272, "EvalDesc layout");
 static_assert(offsetof(EvalDesc, hit_t) == 280, "EvalDesc layout");
 static_assert(offsetof(EvalDesc, grad_part) == 288, "EvalDesc layout");
 static_assert(offsetof(EvalDesc, grad_out) == 296, "EvalDesc layout");
+static_assert(offsetof(EvalDesc, dset) == 304, "EvalDesc layout");
 static_assert(sizeof(PatchOut) == 64, "PatchOut layout");
 static_assert(offsetof(PatchOut, f) == 0, "PatchOut layout");
 static_assert(offsetof(PatchOut, hits) == 48, "PatchOut layout");

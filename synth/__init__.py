@@ -22,4 +22,4 @@ from .scenes import (  # noqa: F401
     merge_static,
 )
 from .dirs import random_dirs, fibonacci_dirs  # noqa: F401
-from .workloads import c2_batch, c3_spad, c4_uneven, c5_batch  # noqa: F401
+from .workloads import c2_batch, c3_spad, c4_uneven, c5_batch, diffuse_batch  # noqa: F401

@@ -10,6 +10,8 @@ angles); shared by the benchmark and the full-size tests.  No SRP arithmetic.
              hinges U(-90, 90) deg, random Sun directions (seed 4), B = 1.
   c5_batch   ~1M-triangle greebled spacecraft (seed 5), 256 Fibonacci
              directions, all 64 hinges U(-0.3, 0.3) rad (seed 1005), 2048^2, B = 1.
+  diffuse_batch  the c2 mesh and attitudes at the paper's ray-traced setting
+             (256^2 window, two secondary levels, 16 diffuse rays per hit).
 """
 from __future__ import annotations
 
@@ -58,3 +60,9 @@ def c5_batch(E: int = 256):
     rng = np.random.default_rng(1005)
     angles = rng.uniform(-0.3, 0.3, size=(E, mesh.n_dof))
     return mesh, dirs, angles, 2048, 1
+
+
+def diffuse_batch(E: int = 64):
+    """Returns mesh, dirs, angles, N, B and K (diffuse rays per emitting hit)."""
+    mesh, dirs, angles, _, _ = c2_batch(E)
+    return mesh, dirs, angles, 256, 2, 16

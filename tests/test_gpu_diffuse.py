@@ -1,0 +1,158 @@
+"""GPU parity of diffuse secondary rays: the library's fans (K rays per
+emitting hit from the fixed cosine-weighted set, exact-mean recoil, first-hit
+deposit) against the FP64 oracle's, per ray and in the force, on seeded
+scenes; invariants; batches mixing K and B; the paper's ray-traced setting
+(256^2 window, two secondary levels, 16 diffuse rays) at full batch size."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from parity import check_report, compare_eval
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def srp():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2608_07307_amd as m
+    return m
+
+
+def _show(tag, rep):
+    print(tag, {k: (round(v, 9) if isinstance(v, float) else v) for k, v in rep.items()}, flush=True)
+
+
+def _compare(srp, tag, sc, mesh, ang, sun, n, B, K, pressure=1.0):
+    """Recorded GPU evaluation against the oracle's: chain ids outside the edge
+    band equal, fans equal on all but a few rays (FP32 vs FP64 directions can
+    take a different triangle at an edge), the oracle's FP64 physics on the
+    GPU's rays within 1e-5, the plain force within what flipped rays carry."""
+    sc.set_angles(ang)
+    g = srp.eval(sc, sun, n, bounces=B, pressure=pressure, record=True, diffuse=K)
+    o = oracle.eval_srp(mesh, sun, n, bounces=B, pressure=pressure, angles=ang, record=True, diffuse=K)
+    rep = compare_eval(mesh, ang, sun, n, B, g, o, pressure=pressure, diffuse=K)
+    _show(tag, rep)
+    check_report(rep)
+    if B and K:
+        assert rep["diffuse_match_fraction"] >= 0.999, rep
+    flips = rep["primary_mismatch"] + rep.get("secondary_mismatch", 0)
+    assert abs(g["n_secondary"] - o.n_secondary) <= flips * (1 + B * K), (g["n_secondary"], o.n_secondary)
+    assert abs(g["n_secondary_hits"] - o.n_secondary_hits) <= flips * (1 + B * K) + rep.get("diffuse_mismatch", 0)
+    return g, o
+
+
+@pytest.mark.parametrize("B,K", [(1, 1), (2, 16), (1, 64)])
+def test_box_wing_fans(srp, B, K):
+    mesh = synth.box_wing()
+    sc = srp.Scene(mesh)
+    for seed in (2001, 2002):
+        _compare(srp, f"box_wing B={B} K={K} seed={seed}", sc, mesh, (0.9, -0.4),
+                 synth.random_dirs(seed)[0], 96, B, K)
+
+
+@pytest.mark.parametrize("B,K", [(2, 16), (4, 5), (1, 64)])
+def test_procedural_fans(srp, B, K):
+    """~4k-triangle procedural spacecraft (concave: fans land on the bus, the
+    dish and the panels), 128^2 rays."""
+    mesh = synth.procedural_sized(21, 4000)
+    sc = srp.Scene(mesh)
+    rng = np.random.default_rng(2100 + B)
+    for seed in (2101, 2102):
+        ang = rng.uniform(-1.2, 1.2, mesh.n_dof)
+        _compare(srp, f"procedural B={B} K={K} seed={seed}", sc, mesh, ang, synth.random_dirs(seed)[0],
+                 128, B, K, pressure=3.5)
+
+
+def test_ragged_grid_and_record_layout(srp):
+    """N = 37 (partial patches and tiles): every fan slot of a hit on a
+    material without rho_d, and of a chain generation not reached, is -1."""
+    mesh = synth.procedural_sized(23, 2500)
+    sc = srp.Scene(mesh)
+    B, K, n = 2, 9, 37
+    g, o = _compare(srp, "ragged N=37", sc, mesh, np.zeros(mesh.n_dof), synth.random_dirs(2301)[0], n, B, K)
+    ids = g["ids"]
+    assert ids.shape == (n * n, B + 1 + B * K)
+    for gen in range(B):
+        chain = ids[:, gen]
+        rd = np.where(chain >= 0, mesh.mats[mesh.tri_mat[np.maximum(chain, 0)], 1], 0.0)
+        fan = ids[:, B + 1 + gen * K:B + 1 + (gen + 1) * K]
+        assert (fan[rd == 0] == -1).all()
+
+
+def test_exact_mean_recoil_on_gpu(srp):
+    """Face-on plate, rho_s = 0, rho_d = 0.8, K = 64, every fan ray escapes:
+    F_z = -P A (1 + rd <l_z>) with <l_z> the mean of the set's normal
+    components, and the tangential force is P A rd |<l_xy>|."""
+    rd = 0.8
+    mesh = synth.plate((0, 0, 0), (1, 0, 0), (0, 1, 0), rho=(0.0, rd))
+    sc = srp.Scene(mesh)
+    g = srp.eval(sc, (0, 0, 1), 64, bounces=1, pressure=2.0, diffuse=64)
+    PA = 2.0 * 1.0
+    m = oracle.diffuse_set(64).mean(0)
+    assert g["n_hits"] == 64 * 64 and g["n_secondary"] == 64 * 64 * 64 and g["n_secondary_hits"] == 0
+    np.testing.assert_allclose(g["force"][2], -PA * (1 + rd * m[2]), rtol=1e-6)
+    np.testing.assert_allclose(np.hypot(*g["force"][:2]), PA * rd * np.hypot(m[0], m[1]), rtol=1e-4)
+
+
+def test_fans_change_nothing_without_rho_d_or_levels(srp):
+    """K has no effect (bitwise) without a material with rho_d > 0, or with
+    B = 0."""
+    mesh = synth.procedural_sized(24, 3000)
+    nod = mesh.with_mats(np.column_stack([mesh.mats[:, 0], np.zeros(mesh.n_mats)]))
+    sun = synth.random_dirs(2401)[0]
+    for m, B in ((nod, 2), (mesh, 0)):
+        sc = srp.Scene(m)
+        a = srp.eval(sc, sun, 80, bounces=B)
+        b = srp.eval(sc, sun, 80, bounces=B, diffuse=16)
+        assert a["force"].tobytes() == b["force"].tobytes() and a["n_secondary"] == b["n_secondary"]
+
+
+def test_batch_mixing_fans_and_levels(srp):
+    """One launch with K in {0, 1, 7, 16, 64} and B in {0, 1, 2, 4} over two
+    scenes: every item equals its own single evaluation bitwise; the K = 64,
+    B = 4 item agrees with the oracle."""
+    m1, m2 = synth.box_wing(), synth.procedural_sized(25, 3000)
+    s1, s2 = srp.Scene(m1), srp.Scene(m2)
+    dirs = synth.random_dirs(2501, 10)
+    specs = [(s1, m1, (0.3, 0.2), 64, 2, 16), (s2, m2, None, 96, 1, 7), (s1, m1, (-0.5, 1.0), 40, 4, 64),
+             (s2, m2, None, 72, 0, 16), (s1, m1, (1.2, -1.2), 64, 2, 0), (s2, m2, None, 50, 2, 1),
+             (s2, m2, None, 128, 4, 64), (s1, m1, (0.0, 0.4), 33, 1, 16)]
+    entries = []
+    for k, (sc, m, ang, n, B, K) in enumerate(specs):
+        a = np.zeros(m.n_dof) if ang is None else np.asarray(ang, float)
+        entries.append((sc, a, srp.params(dirs[k], n, B, diffuse=K)))
+    r = srp.results_to_numpy(srp.eval_batch(entries)).copy()
+    assert (r["status"] == 0).all()
+    for k, (sc, m, ang, n, B, K) in enumerate(specs):
+        sc.set_angles(entries[k][1])
+        single = srp.eval(sc, dirs[k], n, bounces=B, diffuse=K)
+        assert single["force"].tobytes() == r[k]["force"].tobytes(), k
+        assert single["n_secondary_hits"] == r[k]["n_secondary_hits"], k
+    _compare(srp, "batch item K=64 B=4", s2, m2, np.zeros(m2.n_dof), dirs[6], 128, 4, 64)
+
+
+def test_adjoint_rejects_fans(srp):
+    mesh = synth.box_wing()
+    sc = srp.Scene(mesh)
+    with pytest.raises(srp.SrpError):
+        srp.eval_grad_batch([(sc, None, srp.params((0, 0, 1), 32, 1, diffuse=4))])
+    with pytest.raises(srp.SrpError):
+        srp.eval(sc, (0, 0, 1), 32, bounces=1, diffuse=65)
+
+
+def test_paper_setting_batch(srp):
+    """The ~50k-triangle spacecraft at the paper's ray-traced setting (256^2,
+    two secondary levels, 16 diffuse rays), 64 attitudes in one launch: every
+    item succeeds; three sampled items (their single recorded evaluations are
+    bitwise the batch's) against the oracle."""
+    mesh, dirs, angles, n, B, K = synth.diffuse_batch(64)
+    sc = srp.Scene(mesh)
+    entries = [(sc, angles[k], srp.params(dirs[k], n, B, diffuse=K)) for k in range(len(dirs))]
+    r = srp.results_to_numpy(srp.eval_batch(entries)).copy()
+    assert (r["status"] == 0).all() and (r["n_hits"] > 0).all()
+    for k in (0, 29, 63):
+        g, _ = _compare(srp, f"paper setting item {k}", sc, mesh, angles[k], dirs[k], n, B, K)
+        assert g["force"].tobytes() == r[k]["force"].tobytes()
