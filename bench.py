@@ -64,6 +64,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (profiling runs)")
     ap.add_argument("--schedule", default="", help="PPC,BPC: fixed patches per chunk and blocks per CU "
                     "for both launches (implies --no-tune; profiling runs)")
+    ap.add_argument("--spad", type=int, default=1, help="SPAD vs direct propagation measurement (0: skip)")
+    ap.add_argument("--spad-steps", type=int, default=400, help="RK4 steps of the SPAD comparison orbit")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="also run a device copy of this many MiB (calibrates memory counters)")
     args = ap.parse_args()
@@ -211,6 +213,66 @@ def main():
     }
     log(f"paper setting (N={dN}, B={dB}, K={dK}): {E / d_dt:.1f} evals/s, {d_rays / d_dt / 1e9:.2f} Grays/s")
 
+    # SPAD (precomputed table + interpolation) against direct ray tracing during
+    # propagation: the paper's 20 x 10 grids (plain and shifted by 5 deg) built at
+    # the ray-traced setting, one revolution of the circular orbit C (0.388 AU)
+    # with the attitude inertially fixed (hinges at the first attitude's angles)
+    spad = None
+    if args.spad:
+        AU, MU_SUN, P1AU, MASS = 1.495978707e11, 1.32712440018e20, 4.56e-6, 1000.0
+        deg = np.pi / 180
+        grids = {"20x10": srp.spad_grid(20, 10, -180 * deg, -90 * deg, 18 * deg, 18 * deg),
+                 "20x10S": srp.spad_grid(20, 10, -175 * deg, -85 * deg, 18 * deg, 18 * deg)}
+        srp.spad_build(scene, grids["20x10"], dN, bounces=dB, angles=angles[0], diffuse=dK)   # warm-up
+        torch.cuda.synchronize()
+        tabs, build_ms = {}, {}
+        for name, G in grids.items():
+            t0 = time.perf_counter()
+            tabs[name] = srp.spad_build(scene, G, dN, bounces=dB, pressure=P1AU, angles=angles[0], diffuse=dK)
+            build_ms[name] = (time.perf_counter() - t0) * 1e3
+        a = 0.388 * AU
+        y0 = np.array([a, 0, 0, 0, np.sqrt(MU_SUN / a), 0])
+        steps = args.spad_steps
+        h = 2 * np.pi * np.sqrt(a ** 3 / MU_SUN) / steps
+        t0 = time.perf_counter()
+        direct, st = srp.propagate(scene, y0, 0.0, h, steps, MU_SUN, MASS, P1AU, AU, dN, bounces=dB,
+                                   angles0=angles[0], diffuse=dK)
+        direct_s = time.perf_counter() - t0
+        sep, spad_s = {}, {}
+        for name, G in grids.items():
+            t0 = time.perf_counter()
+            tr = srp.propagate_spad(G, tabs[name], P1AU, y0, 0.0, h, steps, MU_SUN, MASS, P1AU, AU)
+            spad_s[name] = time.perf_counter() - t0
+            sep[name] = float(np.linalg.norm(tr[-1, 1:4] - direct[-1, 1:4]) / 1e3)
+        kep = srp.propagate_spad(grids["20x10"], 0.0 * tabs["20x10"], P1AU, y0, 0.0, h, steps, MU_SUN, MASS,
+                                 P1AU, AU)
+        # interpolation error per evaluation along the orbit plane (elevation 0, 1 deg steps)
+        az = np.arange(360) * deg
+        S = np.stack([np.cos(az), np.sin(az), np.zeros_like(az)], 1)
+        ref_f = srp.results_to_numpy(srp.eval_batch(
+            [(scene, angles[0], srp.params(S[k], dN, dB, P1AU, diffuse=dK)) for k in range(360)]))["force"].copy()
+        scale = float(np.linalg.norm(ref_f, axis=1).mean())
+        interp_err = {name: round(float(np.sqrt(np.mean([np.sum((srp.spad_interp(G, tabs[name], S[k])[:3] - ref_f[k]) ** 2)
+                                                          for k in range(360)])) / scale), 5)
+                      for name, G in grids.items()}
+        spad = {
+            "workload": f"{mesh.n_tris}-triangle spacecraft, {dN}x{dN} rays, {dB} secondary levels, {dK} diffuse "
+                        f"rays; orbit C (a = 0.388 AU, e = 0), one revolution, {steps} RK4 steps, "
+                        f"mass {MASS:.0f} kg, fixed attitude",
+            "table_nodes": 200,
+            "table_build_ms": {k: round(v, 3) for k, v in build_ms.items()},
+            "direct_ms_per_step": round(direct_s / steps * 1e3, 4),
+            "direct_evals": st["n_evals"],
+            "spad_us_per_step": {k: round(v / steps * 1e6, 3) for k, v in spad_s.items()},
+            "interp_rms_rel_err_el0": interp_err,
+            "final_separation_km": {k: round(v, 4) for k, v in sep.items()},
+            "srp_displacement_km": round(float(np.linalg.norm(kep[-1, 1:4] - direct[-1, 1:4]) / 1e3), 3),
+        }
+        log(f"SPAD: table {build_ms['20x10']:.1f} ms, direct {direct_s / steps * 1e3:.2f} ms/step, "
+            f"SPAD {spad_s['20x10'] / steps * 1e6:.1f} us/step, separation 20x10 {sep['20x10']:.3f} km, "
+            f"20x10S {sep['20x10S']:.3f} km (SRP displacement {spad['srp_displacement_km']} km); "
+            f"interpolation rms error {interp_err}")
+
     # oracle on a bounded sample (CPU baseline and parity of the sampled items)
     cpu = None
     parity = None
@@ -259,6 +321,7 @@ def main():
         "batched_forward_grays_per_s": round(rays_total / fwd_dt / 1e9, 4),
         "plain_evals_per_s": round(plain_eps, 3),
         "paper_setting": paper_setting,
+        "spad": spad,
         "parity": parity,
         "roofline": {
             "bound": "alu",

@@ -292,6 +292,47 @@ typedef struct {
 int srp_propagate(srp_scene *scene, const srp_orbit_params *op, const double *angles0, const double *y0,
                   double t0, double h, int64_t n_steps, double *traj, srp_prop_stats *stats);
 
+/* ---- SPAD tables (Sec. 2 and Sec. 4.2: SRP precomputed over attitudes and
+ * interpolated during propagation; Sec. 6.1: 20 azimuth x 10 elevation grids
+ * from -180 / -90 deg, and a copy shifted by 5 deg) ---- */
+
+/* Grid of Sun directions in the body frame: az_j = az0 + j*daz (j < n_az),
+ * el_i = el0 + i*del (i < n_el), radians; node (i, j) is the direction
+ * s = (cos el cos az, cos el sin az, sin el).  Azimuth wraps around when
+ * n_az*daz is a full turn (within 1e-9 rad). */
+typedef struct {
+    int32_t n_az, n_el;   /* 1..2^24 nodes in total */
+    double az0, el0;      /* first azimuth and elevation, finite */
+    double daz, del;      /* spacings, > 0 */
+} srp_spad_grid;
+
+/* Builds a table: force and torque at every node direction with the scene at
+ * `angles` (host, n_dof values; NULL = the scene's current angles) and the
+ * params' n, bounces, n_diffuse, pressure, ref and flags (its sun_dir is
+ * ignored), in one batched launch.  table: host, n_el x n_az x 6 doubles
+ * (force, torque), elevation-major; caller-owned.  Blocks.  Errors: as
+ * srp_eval_batch, SRP_ERR_ARG for an invalid grid, SRP_ERR_OOM,
+ * SRP_ERR_DEPTH. */
+int srp_spad_build(srp_scene *scene, const srp_eval_params *params, const double *angles,
+                   const srp_spad_grid *grid, double *table);
+
+/* Bilinear interpolation of a table at Sun direction sun_dir (body frame, any
+ * nonzero length): azimuth atan2(s_y, s_x), elevation atan2(s_z, hypot(s_x,
+ * s_y)); between the four surrounding nodes; azimuth held at the first / last
+ * column unless the grid wraps; elevations beyond the first / last row take
+ * that row.  out: 6 doubles (force, torque).  Host only.  Errors:
+ * SRP_ERR_ARG (null, invalid grid, zero or non-finite sun_dir). */
+int srp_spad_interp(const srp_spad_grid *grid, const double *table, const double *sun_dir, double *out);
+
+/* Propagation as srp_propagate with the SRP force interpolated from a table
+ * built at pressure p_table, scaled to the stage's pressure
+ * p_ref (r_ref/|r|)^2: F = interp(-r/|r|) p / p_table.  Uses mu, mass, p_ref and
+ * r_ref of op (track_sun must be 0: the table has fixed hinge angles).  traj as
+ * srp_rk4.  Host only.  Errors: SRP_ERR_ARG. */
+int srp_propagate_spad(const srp_spad_grid *grid, const double *table, double p_table,
+                       const srp_orbit_params *op, const double *y0, double t0, double h,
+                       int64_t n_steps, double *traj);
+
 /* Measurement hook (not part of an evaluation): srp_profile(1) starts timing
  * every trace-kernel launch with a pair of HIP events recorded on the launch
  * stream, srp_profile(0) stops; both reset the totals.  srp_profile_read waits

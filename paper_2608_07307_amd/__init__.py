@@ -255,6 +255,43 @@ def propagate(scene: Scene, y0, t0, h, n_steps, mu, mass, p_ref, r_ref, n, bounc
     return traj, dict(n_evals=st.n_evals, srp_seconds=st.srp_seconds)
 
 
+def spad_grid(n_az, n_el, az0, el0, daz, de):
+    """srp_spad_grid (angles in radians)."""
+    return L.srp_spad_grid(int(n_az), int(n_el), float(az0), float(el0), float(daz), float(de))
+
+
+def spad_build(scene: Scene, grid, n, bounces=0, pressure=1.0, ref=(0.0, 0.0, 0.0), angles=None, diffuse=0):
+    """srp_spad_build: (n_el, n_az, 6) force and torque at every grid direction."""
+    tab = np.zeros((grid.n_el, grid.n_az, 6))
+    p = params((1.0, 0.0, 0.0), n, bounces, pressure, ref, False, diffuse)
+    a = None if angles is None else np.ascontiguousarray(angles, dtype=np.float64)
+    L.check(_load().srp_spad_build(scene.handle, C.byref(p), L.ptr(a) if a is not None and a.size else None,
+                                   C.byref(grid), L.ptr(tab)))
+    return tab
+
+
+def spad_interp(grid, table, sun_dir) -> np.ndarray:
+    """srp_spad_interp: interpolated (force, torque) at a Sun direction."""
+    t = np.ascontiguousarray(table, dtype=np.float64)
+    s = np.ascontiguousarray(sun_dir, dtype=np.float64)
+    out = np.zeros(6)
+    L.check(_load().srp_spad_interp(C.byref(grid), L.ptr(t), L.ptr(s), L.ptr(out)))
+    return out
+
+
+def propagate_spad(grid, table, p_table, y0, t0, h, n_steps, mu, mass, p_ref, r_ref):
+    """srp_propagate_spad: RK4 two-body + SRP interpolated from a SPAD table
+    (built at pressure p_table).  Returns traj (n_steps+1, 7)."""
+    op = L.srp_orbit_params(float(mu), float(mass), float(p_ref), float(r_ref), 0, 0, 0, 0,
+                            (C.c_double * 3)(0.0, 0.0, 0.0))
+    t = np.ascontiguousarray(table, dtype=np.float64)
+    y = np.ascontiguousarray(y0, dtype=np.float64)
+    traj = np.zeros((n_steps + 1, 7))
+    L.check(_load().srp_propagate_spad(C.byref(grid), L.ptr(t), float(p_table), C.byref(op), L.ptr(y), float(t0),
+                                       float(h), int(n_steps), L.ptr(traj)))
+    return traj
+
+
 def set_schedule(patches_per_chunk=0, blocks_per_cu=0):
     """srp_set_schedule (0 = automatic)."""
     L.check(_load().srp_set_schedule(int(patches_per_chunk), int(blocks_per_cu)))

@@ -19,7 +19,7 @@ EXPORTS = [
     "srp_eval_grad_batch", "srp_last_error", "srp_profile", "srp_profile_read",
     "srp_sun_tracking_angles", "srp_rk4", "srp_propagate",
     "srp_plan_create", "srp_plan_update", "srp_plan_launch", "srp_plan_destroy",
-    "srp_set_schedule", "srp_autotune",
+    "srp_set_schedule", "srp_autotune", "srp_spad_build", "srp_spad_interp", "srp_propagate_spad",
 ]
 SRP_PLAN_GRAD = 1
 
@@ -55,6 +55,11 @@ class srp_orbit_params(C.Structure):
     _fields_ = [("mu", C.c_double), ("mass", C.c_double), ("p_ref", C.c_double),
                 ("r_ref", C.c_double), ("n", C.c_int32), ("bounces", C.c_int32),
                 ("track_sun", C.c_int32), ("n_diffuse", C.c_int32), ("ref", C.c_double * 3)]
+
+
+class srp_spad_grid(C.Structure):
+    _fields_ = [("n_az", C.c_int32), ("n_el", C.c_int32), ("az0", C.c_double), ("el0", C.c_double),
+                ("daz", C.c_double), ("del_", C.c_double)]
 
 
 class srp_prop_stats(C.Structure):
@@ -109,12 +114,16 @@ def load(path: str | None = None):
     lib.srp_propagate.argtypes = [V, C.POINTER(srp_orbit_params), V, V, C.c_double, C.c_double, I64, V,
                                   C.POINTER(srp_prop_stats)]
     lib.srp_profile_read.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+    lib.srp_spad_build.argtypes = [V, C.POINTER(srp_eval_params), V, C.POINTER(srp_spad_grid), V]
+    lib.srp_spad_interp.argtypes = [C.POINTER(srp_spad_grid), V, V, V]
+    lib.srp_propagate_spad.argtypes = [C.POINTER(srp_spad_grid), V, C.c_double, C.POINTER(srp_orbit_params), V,
+                                       C.c_double, C.c_double, I64, V]
     for f in ("srp_build_scene", "srp_destroy_scene", "srp_set_materials",
               "srp_set_panel_angles", "srp_eval", "srp_eval_batch", "srp_eval_grad",
               "srp_eval_grad_batch", "srp_profile", "srp_profile_read",
               "srp_sun_tracking_angles", "srp_rk4", "srp_propagate", "srp_plan_create",
               "srp_plan_update", "srp_plan_launch", "srp_plan_destroy", "srp_set_schedule",
-              "srp_autotune"):
+              "srp_autotune", "srp_spad_build", "srp_spad_interp", "srp_propagate_spad"):
         getattr(lib, f).restype = C.c_int
     _lib = lib
     return lib
