@@ -66,6 +66,10 @@ def main():
                     "for both launches (implies --no-tune; profiling runs)")
     ap.add_argument("--spad", type=int, default=1, help="SPAD vs direct propagation measurement (0: skip)")
     ap.add_argument("--spad-steps", type=int, default=400, help="RK4 steps of the SPAD comparison orbit")
+    ap.add_argument("--p2", type=int, default=1,
+                    help="20-revolution propagation timing (0: skip, 1: fixed panels, 2: also tracking panels)")
+    ap.add_argument("--p2-revs", type=int, default=20)
+    ap.add_argument("--p2-rtol", type=float, default=1e-9)
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="also run a device copy of this many MiB (calibrates memory counters)")
     args = ap.parse_args()
@@ -273,6 +277,46 @@ def main():
             f"20x10S {sep['20x10S']:.3f} km (SRP displacement {spad['srp_displacement_km']} km); "
             f"interpolation rms error {interp_err}")
 
+    # 20 revolutions of the paper's reference orbit (a = 0.557 AU, e = 0.682,
+    # perihelion start) with adaptive RK7(8) and one ray-traced evaluation per
+    # stage at the paper's ray-traced setting; the same span with the SPAD
+    # tables; with --p2 2 also with sun-tracking panels
+    p2 = None
+    if args.p2 and spad is not None:
+        a2, e2 = 0.557 * AU, 0.682
+        rp = a2 * (1 - e2)
+        y2 = np.array([rp, 0, 0, 0, np.sqrt(MU_SUN * (1 + e2) / rp), 0])
+        T2 = 2 * np.pi * np.sqrt(a2 ** 3 / MU_SUN)
+        opts = srp.rk78_opts(T2 / 100, True, args.p2_rtol, [args.p2_rtol * AU] * 3 + [args.p2_rtol * 1e5] * 3)
+        p2 = {"workload": f"reference orbit a = 0.557 AU, e = 0.682, {args.p2_revs} revolutions from perihelion, "
+                          f"adaptive RK7(8) (rtol {args.p2_rtol:g}), {dN}x{dN} rays, {dB} secondary levels, "
+                          f"{dK} diffuse rays, mass {MASS:.0f} kg"}
+        runs = [("fixed_panels", False)] + ([("tracking_panels", True)] if args.p2 > 1 else [])
+        finals = {}
+        for name, track in runs:
+            t0 = time.perf_counter()
+            tr2, st2 = srp.propagate_rk78(scene, y2, 0.0, args.p2_revs * T2, opts, MU_SUN, MASS, P1AU, AU, dN,
+                                          bounces=dB, track_sun=track, angles0=angles[0], diffuse=dK)
+            dt2 = time.perf_counter() - t0
+            finals[name] = tr2[-1, 1:4]
+            p2[name] = {"total_s": round(dt2, 3), "steps": len(tr2) - 1, "srp_evals": st2["n_evals"],
+                        "ms_per_eval": round(dt2 / st2["n_evals"] * 1e3, 4),
+                        "srp_share": round(st2["srp_seconds"] / dt2, 4)}
+            log(f"P2 {name}: {args.p2_revs} revolutions in {dt2:.2f} s, {len(tr2) - 1} steps, "
+                f"{st2['n_evals']} evaluations")
+        sep2 = {}
+        for name, G in grids.items():
+            t0 = time.perf_counter()
+            tr2 = srp.propagate_spad_rk78(G, tabs[name], P1AU, y2, 0.0, args.p2_revs * T2, opts, MU_SUN, MASS,
+                                          P1AU, AU)
+            p2[f"spad_{name}_s"] = round(time.perf_counter() - t0, 4)
+            sep2[name] = float(np.linalg.norm(tr2[-1, 1:4] - finals["fixed_panels"]) / 1e3)
+        p2["final_separation_km"] = {f"spad_{k}": round(v, 3) for k, v in sep2.items()}
+        if "tracking_panels" in finals:
+            p2["final_separation_km"]["tracking_vs_fixed_panels"] = round(
+                float(np.linalg.norm(finals["tracking_panels"] - finals["fixed_panels"]) / 1e3), 3)
+        log(f"P2 separations (km): {p2['final_separation_km']}")
+
     # oracle on a bounded sample (CPU baseline and parity of the sampled items)
     cpu = None
     parity = None
@@ -322,6 +366,7 @@ def main():
         "plain_evals_per_s": round(plain_eps, 3),
         "paper_setting": paper_setting,
         "spad": spad,
+        "p2": p2,
         "parity": parity,
         "roofline": {
             "bound": "alu",

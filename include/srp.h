@@ -265,6 +265,32 @@ typedef int (*srp_accel_fn)(double t, const double *r, const double *v, double *
 int srp_rk4(const double *y0, double t0, double h, int64_t n_steps, srp_accel_fn accel, void *user,
             double *traj);
 
+/* Step control of srp_rk78. */
+typedef struct {
+    double h0;          /* fixed step, or the first trial step (s), > 0 */
+    int32_t adaptive;   /* 0: fixed steps t0 + k*h0, the last one ending at t1; 1: adaptive */
+    int32_t reserved;
+    double rtol;        /* adaptive: relative tolerance, >= 0 */
+    double atol[6];     /* adaptive: absolute tolerances of x, y, z (m), vx, vy, vz (m/s), >= 0 */
+    double h_min;       /* adaptive: error when a rejected step would shrink below this (s), >= 0 */
+    double h_max;       /* adaptive: largest step (s); 0 = no limit */
+} srp_rk78_opts;
+
+/* Explicit Runge-Kutta 7(8) (the paper's RK78, Sec. 3; Fehlberg's 13-stage
+ * embedded pair) for y = [r; v], y' = [v; a(t, r, v)] from t0 to t1 > t0,
+ * advancing the 8th-order solution.  Adaptive steps are accepted when
+ * max_i |err_i| / (atol_i + rtol max(|y_i|, |y_new_i|)) <= 1 (err = the
+ * embedded 7th-order error estimate; a component with zero error counts 0)
+ * and every trial step is the previous one
+ * times 0.9 err^(-1/8) within [0.2, 5] (capped at h_max), shortened to end at
+ * t1.  traj: caller-owned, max_rows x 7 doubles (t, r, v), row 0 = t0; the
+ * accepted steps follow.  *n_rows = rows written; *n_evals (may be NULL) =
+ * derivative evaluations (13 per trial step).  Host only.  Errors:
+ * SRP_ERR_ARG (invalid argument, more than max_rows rows, a step below h_min,
+ * a non-finite state), or the callback's code. */
+int srp_rk78(const double *y0, double t0, double t1, const srp_rk78_opts *opts, srp_accel_fn accel,
+             void *user, double *traj, int64_t max_rows, int64_t *n_rows, int64_t *n_evals);
+
 typedef struct {
     double mu;          /* gravitational parameter of the central body (Sun), m^3/s^2 */
     double mass;        /* spacecraft mass, kg */
@@ -332,6 +358,18 @@ int srp_spad_interp(const srp_spad_grid *grid, const double *table, const double
 int srp_propagate_spad(const srp_spad_grid *grid, const double *table, double p_table,
                        const srp_orbit_params *op, const double *y0, double t0, double h,
                        int64_t n_steps, double *traj);
+
+/* srp_propagate with srp_rk78 from t0 to t1 (13 SRP evaluations per trial
+ * step; sun tracking per stage when op->track_sun).  traj, max_rows and
+ * n_rows as srp_rk78.  Errors as srp_propagate and srp_rk78. */
+int srp_propagate_rk78(srp_scene *scene, const srp_orbit_params *op, const double *angles0, const double *y0,
+                       double t0, double t1, const srp_rk78_opts *opts, double *traj, int64_t max_rows,
+                       int64_t *n_rows, srp_prop_stats *stats);
+
+/* srp_propagate_spad with srp_rk78.  Errors as srp_propagate_spad and srp_rk78. */
+int srp_propagate_spad_rk78(const srp_spad_grid *grid, const double *table, double p_table,
+                            const srp_orbit_params *op, const double *y0, double t0, double t1,
+                            const srp_rk78_opts *opts, double *traj, int64_t max_rows, int64_t *n_rows);
 
 /* Measurement hook (not part of an evaluation): srp_profile(1) starts timing
  * every trace-kernel launch with a pair of HIP events recorded on the launch

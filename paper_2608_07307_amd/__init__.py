@@ -255,6 +255,72 @@ def propagate(scene: Scene, y0, t0, h, n_steps, mu, mass, p_ref, r_ref, n, bounc
     return traj, dict(n_evals=st.n_evals, srp_seconds=st.srp_seconds)
 
 
+def rk78_opts(h0, adaptive=False, rtol=0.0, atol=(0.0,) * 6, h_min=0.0, h_max=0.0):
+    """srp_rk78_opts: fixed steps h0, or adaptive with tolerances rtol and
+    atol (6 values or one for all)."""
+    a = np.broadcast_to(np.asarray(atol, dtype=np.float64), (6,))
+    return L.srp_rk78_opts(float(h0), 1 if adaptive else 0, 0, float(rtol), (C.c_double * 6)(*a), float(h_min),
+                           float(h_max))
+
+
+def rk78(y0, t0, t1, accel, opts, max_rows=1 << 16):
+    """srp_rk78 with a Python acceleration accel(t, r, v) -> a (host only).
+    Returns (rows (t, y) of the accepted steps, derivative evaluations)."""
+    err = []
+
+    def cb(t, r, v, a, _):
+        try:
+            out = accel(t, np.ctypeslib.as_array(r, (3,)).copy(), np.ctypeslib.as_array(v, (3,)).copy())
+            for i in range(3):
+                a[i] = float(out[i])
+            return 0
+        except Exception as e:  # reported after the call
+            err.append(e)
+            return -1
+
+    f = L.ACCEL_FN(cb)
+    y = np.ascontiguousarray(y0, dtype=np.float64)
+    traj = np.zeros((max_rows, 7))
+    rows, evals = C.c_int64(0), C.c_int64(0)
+    rc = _load().srp_rk78(L.ptr(y), float(t0), float(t1), C.byref(opts), f, None, L.ptr(traj), int(max_rows),
+                          C.byref(rows), C.byref(evals))
+    if err:
+        raise err[0]
+    L.check(rc)
+    return traj[:rows.value].copy(), evals.value
+
+
+def propagate_rk78(scene: Scene, y0, t0, t1, opts, mu, mass, p_ref, r_ref, n, bounces=0, track_sun=False,
+                   angles0=None, ref=(0.0, 0.0, 0.0), diffuse=0, max_rows=1 << 16):
+    """srp_propagate_rk78: two-body + ray-traced SRP with RK7(8), one GPU
+    evaluation per stage.  Returns (rows (t, r, v), stats dict)."""
+    op = L.srp_orbit_params(float(mu), float(mass), float(p_ref), float(r_ref), int(n), int(bounces),
+                            1 if track_sun else 0, int(diffuse), (C.c_double * 3)(*ref))
+    y = np.ascontiguousarray(y0, dtype=np.float64)
+    a0 = None if angles0 is None else np.ascontiguousarray(angles0, dtype=np.float64)
+    traj = np.zeros((max_rows, 7))
+    rows = C.c_int64(0)
+    st = L.srp_prop_stats()
+    L.check(_load().srp_propagate_rk78(scene.handle, C.byref(op), L.ptr(a0) if a0 is not None and a0.size else None,
+                                       L.ptr(y), float(t0), float(t1), C.byref(opts), L.ptr(traj), int(max_rows),
+                                       C.byref(rows), C.byref(st)))
+    return traj[:rows.value].copy(), dict(n_evals=st.n_evals, srp_seconds=st.srp_seconds)
+
+
+def propagate_spad_rk78(grid, table, p_table, y0, t0, t1, opts, mu, mass, p_ref, r_ref, max_rows=1 << 16):
+    """srp_propagate_spad_rk78.  Returns rows (t, r, v) of the accepted steps."""
+    op = L.srp_orbit_params(float(mu), float(mass), float(p_ref), float(r_ref), 0, 0, 0, 0,
+                            (C.c_double * 3)(0.0, 0.0, 0.0))
+    t = np.ascontiguousarray(table, dtype=np.float64)
+    y = np.ascontiguousarray(y0, dtype=np.float64)
+    traj = np.zeros((max_rows, 7))
+    rows = C.c_int64(0)
+    L.check(_load().srp_propagate_spad_rk78(C.byref(grid), L.ptr(t), float(p_table), C.byref(op), L.ptr(y),
+                                            float(t0), float(t1), C.byref(opts), L.ptr(traj), int(max_rows),
+                                            C.byref(rows)))
+    return traj[:rows.value].copy()
+
+
 def spad_grid(n_az, n_el, az0, el0, daz, de):
     """srp_spad_grid (angles in radians)."""
     return L.srp_spad_grid(int(n_az), int(n_el), float(az0), float(el0), float(daz), float(de))

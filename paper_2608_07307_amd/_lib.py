@@ -20,6 +20,7 @@ EXPORTS = [
     "srp_sun_tracking_angles", "srp_rk4", "srp_propagate",
     "srp_plan_create", "srp_plan_update", "srp_plan_launch", "srp_plan_destroy",
     "srp_set_schedule", "srp_autotune", "srp_spad_build", "srp_spad_interp", "srp_propagate_spad",
+    "srp_rk78", "srp_propagate_rk78", "srp_propagate_spad_rk78",
 ]
 SRP_PLAN_GRAD = 1
 
@@ -60,6 +61,11 @@ class srp_orbit_params(C.Structure):
 class srp_spad_grid(C.Structure):
     _fields_ = [("n_az", C.c_int32), ("n_el", C.c_int32), ("az0", C.c_double), ("el0", C.c_double),
                 ("daz", C.c_double), ("del_", C.c_double)]
+
+
+class srp_rk78_opts(C.Structure):
+    _fields_ = [("h0", C.c_double), ("adaptive", C.c_int32), ("reserved", C.c_int32), ("rtol", C.c_double),
+                ("atol", C.c_double * 6), ("h_min", C.c_double), ("h_max", C.c_double)]
 
 
 class srp_prop_stats(C.Structure):
@@ -115,6 +121,14 @@ def load(path: str | None = None):
                                   C.POINTER(srp_prop_stats)]
     lib.srp_profile_read.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     lib.srp_spad_build.argtypes = [V, C.POINTER(srp_eval_params), V, C.POINTER(srp_spad_grid), V]
+    lib.srp_rk78.argtypes = [V, C.c_double, C.c_double, C.POINTER(srp_rk78_opts), ACCEL_FN, V, V, I64,
+                             C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+    lib.srp_propagate_rk78.argtypes = [V, C.POINTER(srp_orbit_params), V, V, C.c_double, C.c_double,
+                                       C.POINTER(srp_rk78_opts), V, I64, C.POINTER(C.c_int64),
+                                       C.POINTER(srp_prop_stats)]
+    lib.srp_propagate_spad_rk78.argtypes = [C.POINTER(srp_spad_grid), V, C.c_double, C.POINTER(srp_orbit_params),
+                                            V, C.c_double, C.c_double, C.POINTER(srp_rk78_opts), V, I64,
+                                            C.POINTER(C.c_int64)]
     lib.srp_spad_interp.argtypes = [C.POINTER(srp_spad_grid), V, V, V]
     lib.srp_propagate_spad.argtypes = [C.POINTER(srp_spad_grid), V, C.c_double, C.POINTER(srp_orbit_params), V,
                                        C.c_double, C.c_double, I64, V]
@@ -123,7 +137,8 @@ def load(path: str | None = None):
               "srp_eval_grad_batch", "srp_profile", "srp_profile_read",
               "srp_sun_tracking_angles", "srp_rk4", "srp_propagate", "srp_plan_create",
               "srp_plan_update", "srp_plan_launch", "srp_plan_destroy", "srp_set_schedule",
-              "srp_autotune", "srp_spad_build", "srp_spad_interp", "srp_propagate_spad"):
+              "srp_autotune", "srp_spad_build", "srp_spad_interp", "srp_propagate_spad", "srp_rk78",
+              "srp_propagate_rk78", "srp_propagate_spad_rk78"):
         getattr(lib, f).restype = C.c_int
     _lib = lib
     return lib

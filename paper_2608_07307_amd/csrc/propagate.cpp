@@ -2,10 +2,11 @@
 // y = [x; v], y' = [v; a_g + a_SRP]) and sun tracking of the solar panels
 // (Sec. 4.4.2 steps 2-4: panel normal, rotate towards the Sun, clamp).
 //
-// The integrator is the classical fixed-step fourth-order Runge-Kutta scheme;
-// every stage requests one SRP acceleration (Sec. 3), which srp_propagate
-// obtains from the GPU evaluation with the Sun direction and pressure of the
-// stage's position.  The spacecraft attitude is inertially fixed (Sec. 5.1),
+// The integrators are the classical fixed-step fourth-order Runge-Kutta scheme
+// and the paper's RK78 (Fehlberg's 7(8) pair, fixed or adaptive steps); every
+// stage requests one SRP acceleration (Sec. 3), which srp_propagate obtains
+// from the GPU evaluation with the Sun direction and pressure of the stage's
+// position.  The spacecraft attitude is inertially fixed (Sec. 5.1),
 // so the body frame is the heliocentric inertial frame and the Sun is at the
 // origin.
 #include <cmath>
@@ -166,6 +167,132 @@ int srp_rk4(const double *y0, double t0, double h, int64_t n_steps, srp_accel_fn
     return SRP_OK;
 }
 
+// Fehlberg's embedded Runge-Kutta 7(8) pair (13 stages; NASA TR R-287, 1968),
+// the paper's RK78 (Sec. 3): nodes, coefficients (row i uses stages 0..i-1),
+// 8th-order weights and the weight of the local error estimate
+// (k0 + k10 - k11 - k12) h of the embedded 7th-order solution.
+namespace {
+constexpr double RK_C[13] = {0.0, 2.0 / 27, 1.0 / 9, 1.0 / 6, 5.0 / 12, 1.0 / 2, 5.0 / 6, 1.0 / 6, 2.0 / 3, 1.0 / 3, 1.0, 0.0, 1.0};
+constexpr double RK_A[13][12] = {
+    {},
+    {2.0 / 27},
+    {1.0 / 36, 1.0 / 12},
+    {1.0 / 24, 0, 1.0 / 8},
+    {5.0 / 12, 0, -25.0 / 16, 25.0 / 16},
+    {1.0 / 20, 0, 0, 1.0 / 4, 1.0 / 5},
+    {-25.0 / 108, 0, 0, 125.0 / 108, -65.0 / 27, 125.0 / 54},
+    {31.0 / 300, 0, 0, 0, 61.0 / 225, -2.0 / 9, 13.0 / 900},
+    {2.0, 0, 0, -53.0 / 6, 704.0 / 45, -107.0 / 9, 67.0 / 90, 3.0},
+    {-91.0 / 108, 0, 0, 23.0 / 108, -976.0 / 135, 311.0 / 54, -19.0 / 60, 17.0 / 6, -1.0 / 12},
+    {2383.0 / 4100, 0, 0, -341.0 / 164, 4496.0 / 1025, -301.0 / 82, 2133.0 / 4100, 45.0 / 82, 45.0 / 164, 18.0 / 41},
+    {3.0 / 205, 0, 0, 0, 0, -6.0 / 41, -3.0 / 205, -3.0 / 41, 3.0 / 41, 6.0 / 41, 0},
+    {-1777.0 / 4100, 0, 0, -341.0 / 164, 4496.0 / 1025, -289.0 / 82, 2193.0 / 4100, 51.0 / 82, 33.0 / 164, 12.0 / 41, 0, 1.0},
+};
+constexpr double RK_B8[13] = {0, 0, 0, 0, 0, 34.0 / 105, 9.0 / 35, 9.0 / 35, 9.0 / 280, 9.0 / 280, 0, 41.0 / 840, 41.0 / 840};
+constexpr double RK_ERR = 41.0 / 840;
+
+// One 8th-order step: y8 and the error estimate err.
+int rk78_step(srp_accel_fn accel, void *user, double t, const double *y, double h, double *y8, double *err) {
+    double k[13][6];
+    for (int i = 0; i < 13; ++i) {
+        double yi[6];
+        for (int c = 0; c < 6; ++c) {
+            double acc = y[c];
+            for (int j = 0; j < i; ++j)
+                if (RK_A[i][j] != 0.0) acc += h * RK_A[i][j] * k[j][c];
+            yi[c] = acc;
+        }
+        std::memcpy(k[i], yi + 3, 3 * sizeof(double));
+        int rc = accel(t + RK_C[i] * h, yi, yi + 3, k[i] + 3, user);
+        if (rc) return rc;
+    }
+    for (int c = 0; c < 6; ++c) {
+        double acc = y[c];
+        for (int i = 0; i < 13; ++i)
+            if (RK_B8[i] != 0.0) acc += h * RK_B8[i] * k[i][c];
+        y8[c] = acc;
+        err[c] = RK_ERR * h * (k[0][c] + k[10][c] - k[11][c] - k[12][c]);
+    }
+    return SRP_OK;
+}
+}  // namespace
+
+// RK7(8) from t0 to t1 (srp.h): fixed steps t0 + k h0 (the last ending at t1),
+// or adaptive steps accepted when max_i |err_i| / (atol_i + rtol max(|y_i|,
+// |y8_i|)) <= 1 (a zero error counts 0) and resized by 0.9 err^(-1/8) within
+// [0.2, 5].
+int srp_rk78(const double *y0, double t0, double t1, const srp_rk78_opts *o, srp_accel_fn accel, void *user,
+             double *traj, int64_t max_rows, int64_t *n_rows, int64_t *n_evals) {
+    if (!y0 || !o || !accel || !traj || !n_rows || max_rows < 1 || !std::isfinite(t0) || !std::isfinite(t1) ||
+        !(t1 > t0) || !(o->h0 > 0) || !std::isfinite(o->h0)) {
+        set_error("srp_rk78: invalid argument");
+        return SRP_ERR_ARG;
+    }
+    double tol_sum = o->rtol;
+    for (int c = 0; c < 6; ++c) {
+        if (!(o->atol[c] >= 0) || !std::isfinite(o->atol[c])) { set_error("srp_rk78: invalid atol"); return SRP_ERR_ARG; }
+        tol_sum += o->atol[c];
+    }
+    if (o->adaptive && (!(o->rtol >= 0) || !(tol_sum > 0) || !(o->h_min >= 0))) {
+        set_error("srp_rk78: adaptive steps need rtol >= 0, some tolerance > 0 and h_min >= 0");
+        return SRP_ERR_ARG;
+    }
+    double y[6], y8[6], err[6];
+    std::memcpy(y, y0, sizeof y);
+    int64_t rows = 1, evals = 0;
+    traj[0] = t0;
+    std::memcpy(traj + 1, y, sizeof y);
+    auto emit = [&](double t) -> int {
+        if (rows >= max_rows) { set_error("srp_rk78: more steps than max_rows"); return SRP_ERR_ARG; }
+        traj[7 * rows] = t;
+        std::memcpy(traj + 7 * rows + 1, y, sizeof y);
+        ++rows;
+        return SRP_OK;
+    };
+    int rc = SRP_OK;
+    if (!o->adaptive) {
+        const double q = std::ceil((t1 - t0) / o->h0 * (1 - 1e-12));
+        if (!(q >= 1) || q > 1e12) { set_error("srp_rk78: step count out of range"); return SRP_ERR_ARG; }
+        const int64_t n = (int64_t)q;
+        for (int64_t k = 0; k < n && !rc; ++k) {
+            const double tk = t0 + (double)k * o->h0, hs = k == n - 1 ? t1 - tk : o->h0;
+            if ((rc = rk78_step(accel, user, tk, y, hs, y8, err))) break;
+            evals += 13;
+            std::memcpy(y, y8, sizeof y);
+            rc = emit(k == n - 1 ? t1 : t0 + (double)(k + 1) * o->h0);
+        }
+    } else {
+        double t = t0, h = o->h0;
+        while (t < t1 && !rc) {
+            const bool last = h >= t1 - t;
+            const double hs = last ? t1 - t : h;
+            if ((rc = rk78_step(accel, user, t, y, hs, y8, err))) break;
+            evals += 13;
+            double e = 0;
+            for (int c = 0; c < 6; ++c) {
+                const double sc = o->atol[c] + o->rtol * std::fmax(std::fabs(y[c]), std::fabs(y8[c]));
+                if (!std::isfinite(y8[c]) || std::isnan(err[c])) { e = NAN; break; }
+                if (err[c] != 0.0) e = std::fmax(e, std::fabs(err[c]) / sc);   // zero error counts 0, also where sc = 0
+            }
+            if (std::isnan(e)) { set_error("srp_rk78: non-finite state or error estimate"); rc = SRP_ERR_ARG; break; }
+            const double fac = e == 0 ? 5.0 : std::fmin(5.0, std::fmax(0.2, 0.9 * std::pow(e, -1.0 / 8.0)));
+            if (e > 1.0) {
+                h = hs * fac;
+                if (h < o->h_min) { set_error("srp_rk78: step below h_min"); rc = SRP_ERR_ARG; }
+                continue;
+            }
+            t = last ? t1 : t + hs;
+            std::memcpy(y, y8, sizeof y);
+            h = hs * fac;
+            if (o->h_max > 0) h = std::fmin(h, o->h_max);
+            rc = emit(t);
+        }
+    }
+    *n_rows = rows;
+    if (n_evals) *n_evals = evals;
+    return rc;
+}
+
 }  // extern "C"
 
 namespace {
@@ -208,6 +335,24 @@ int prop_accel(double, const double *r, const double *, double *a, void *user) {
     return SRP_OK;
 }
 }  // namespace
+
+extern "C" int srp_propagate_rk78(srp_scene *scene, const srp_orbit_params *op, const double *angles0,
+                                  const double *y0, double t0, double t1, const srp_rk78_opts *opts, double *traj,
+                                  int64_t max_rows, int64_t *n_rows, srp_prop_stats *stats) {
+    if (!scene || !op || !y0 || !traj || !opts || !n_rows) { set_error("null argument"); return SRP_ERR_ARG; }
+    if (!(op->mass > 0) || !std::isfinite(op->mu) || !std::isfinite(op->p_ref) || !(op->r_ref > 0)) {
+        set_error("invalid orbit parameters");
+        return SRP_ERR_ARG;
+    }
+    const SceneHost &S = scene_host(scene);
+    PropCtx C{scene, op, std::vector<double>(S.n_dof, 0.0)};
+    if (angles0 && S.n_dof) std::memcpy(C.angles.data(), angles0, sizeof(double) * S.n_dof);
+    int rc = srp_set_panel_angles(scene, C.angles.data(), S.n_dof);
+    if (rc < 0) return rc;
+    rc = srp_rk78(y0, t0, t1, opts, prop_accel, &C, traj, max_rows, n_rows, nullptr);
+    if (stats) { stats->n_evals = C.evals; stats->srp_seconds = C.secs; }
+    return rc;
+}
 
 extern "C" int srp_propagate(srp_scene *scene, const srp_orbit_params *op, const double *angles0, const double *y0,
                              double t0, double h, int64_t n_steps, double *traj, srp_prop_stats *stats) {

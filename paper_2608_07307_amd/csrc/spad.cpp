@@ -169,4 +169,20 @@ int srp_propagate_spad(const srp_spad_grid *grid, const double *table, double p_
     return srp_rk4(y0, t0, h, n_steps, spad_accel, &C, traj);
 }
 
+int srp_propagate_spad_rk78(const srp_spad_grid *grid, const double *table, double p_table,
+                            const srp_orbit_params *op, const double *y0, double t0, double t1,
+                            const srp_rk78_opts *opts, double *traj, int64_t max_rows, int64_t *n_rows) {
+    if (!table || !op || !y0 || !traj || !opts || !n_rows) { set_error("null argument"); return SRP_ERR_ARG; }
+    int rc = check_grid(grid);
+    if (rc) return rc;
+    if (!(p_table > 0) || !std::isfinite(p_table) || !(op->mass > 0) || !std::isfinite(op->mu) ||
+        !std::isfinite(op->p_ref) || !(op->r_ref > 0)) {
+        set_error("invalid table pressure or orbit parameters");
+        return SRP_ERR_ARG;
+    }
+    if (op->track_sun) { set_error("a SPAD table is built at fixed hinge angles: track_sun must be 0"); return SRP_ERR_ARG; }
+    SpadCtx C{grid, table, p_table, op};
+    return srp_rk78(y0, t0, t1, opts, spad_accel, &C, traj, max_rows, n_rows, nullptr);
+}
+
 }  // extern "C"
