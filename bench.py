@@ -91,7 +91,7 @@ def main():
     scene = srp.Scene(mesh)
     B, N, E = args.bounces, args.n, args.batch
     entries = [(scene, angles[k], srp.params(dirs[k], N, B)) for k in range(E)]
-    stride = 3 * (2 * mesh.n_mats + mesh.n_dof)
+    stride = srp.grad_size(scene)
     out = torch.empty(E * srp.RESULT_DTYPE.itemsize, dtype=torch.uint8, device=dev)
     grad = torch.zeros((E, stride), dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()

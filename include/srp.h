@@ -46,6 +46,8 @@ extern "C" {
 
 /* srp_eval_params.flags */
 #define SRP_F_COUNT 1u     /* also count box and triangle tests (slower kernel variant) */
+#define SRP_F_GRAD_DIR 2u  /* gradient calls: also dF/dd (photon direction); without it those
+                              9 outputs are 0.  srp_eval_grad sets it when dF_ddir is non-NULL */
 
 #define SRP_MAX_N 8192     /* largest ray grid side */
 #define SRP_MAX_BOUNCES 4  /* largest number of secondary generations */
@@ -190,17 +192,28 @@ int srp_eval_batch(const srp_batch_item *items, int64_t n_items, srp_result *out
 
 /* One evaluation plus the gradient of the force at fixed visibility (hit
  * triangles of every generation, window, pixel area and ray origins frozen):
- *   dF_drho_s: n_mats x 3, dF_drho_d: n_mats x 3, dF_dtheta: n_dof x 3 (host).
- * dF_dtheta is with respect to the clamped angles.  Any gradient pointer may
- * be NULL.  Blocks until the results are on the host.  Errors as srp_eval;
- * SRP_ERR_ARG for n_diffuse > 0 (the adjoint covers the specular chain only). */
+ *   dF_drho_s: n_mats x 3, dF_drho_d: n_mats x 3, dF_dtheta: n_dof x 3,
+ *   dF_ddir: 3 x 3, dF_i/dd_j (row-major) with respect to the photon
+ *   direction d = -sun_dir/|sun_dir| (host).
+ * dF_dtheta is with respect to the clamped angles.  dF_ddir is computed when
+ * the pointer is non-NULL (SRP_F_GRAD_DIR); for it every primary
+ * ray keeps its triangle and its share of that triangle's visible area, whose
+ * projected size scales with c = -n.d of the primary hit; the specular chain
+ * follows d through its reflections.  d is varied as a free 3-vector; a
+ * rotation of the Sun direction or of the attitude takes the component
+ * orthogonal to d.  Any gradient pointer may be NULL.  Blocks until the
+ * results are on the host.  Errors as srp_eval; SRP_ERR_ARG for
+ * n_diffuse > 0 (the adjoint covers the specular chain only) and for a scene
+ * with 9*nodes + 6*materials + 9 > 960. */
 int srp_eval_grad(srp_scene *scene, const srp_eval_params *params, srp_result *out,
-                  double *dF_drho_s, double *dF_drho_d, double *dF_dtheta);
+                  double *dF_drho_s, double *dF_drho_d, double *dF_dtheta, double *dF_ddir);
 
 /* Batched form of srp_eval_grad.  grad_dev: device array, item k's gradients
  * at grad_dev + k*grad_stride doubles, laid out as rho_s (M x 3), rho_d
- * (M x 3), theta (J x 3) with that item's M and J; grad_stride must be at
- * least 3*(2M+J) for every item.  Stream-ordered like srp_eval_batch. */
+ * (M x 3), theta (J x 3), dF/dd (3 x 3, zeros unless the item's flags hold
+ * SRP_F_GRAD_DIR) with that item's M and J;
+ * grad_stride must be at least 3*(2M+J) + 9 for every item.  Stream-ordered
+ * like srp_eval_batch. */
 int srp_eval_grad_batch(const srp_batch_item *items, int64_t n_items, srp_result *out_dev,
                         double *grad_dev, int64_t grad_stride, void *hip_stream);
 

@@ -20,4 +20,6 @@ from .core import (  # noqa: F401
     threads,
     diffuse_set,
     record_slots,
+    shade_frozen_dir,
+    fd_dir_jacobian,
 )

@@ -66,8 +66,9 @@ def _load():
         _lib.orc_node_transforms.argtypes = [P, P, P]
         _lib.orc_threads.restype = C.c_int32
         _lib.orc_diffuse_set.argtypes = [C.c_int32, P]
+        _lib.orc_shade_frozen_dir.argtypes = [P, P, P, P, P, P, P]
         for f in ("orc_eval", "orc_shade_frozen", "orc_grid_of", "orc_articulate",
-                  "orc_node_transforms", "orc_diffuse_set"):
+                  "orc_node_transforms", "orc_diffuse_set", "orc_shade_frozen_dir"):
             getattr(_lib, f).restype = C.c_int
     return _lib
 
@@ -268,3 +269,34 @@ def _unchecked(scene, mats):
         return scene.with_mats(m)
     raise ValueError("finite-difference step leaves the admissible coefficient range; "
                      "use coefficients at least h inside [0,1]")
+
+
+def shade_frozen_dir(scene, n, bounces, grid: dict, ids, dnew, pressure=1.0, angles=None):
+    """Force of the recorded chains (ids (N*N, B+1)) when the photon direction
+    becomes dnew, each primary ray keeping its triangle and its share of the
+    triangle's visible area (scaled by c0(dnew)/c0(recorded))."""
+    lib = _load()
+    sr = _SceneRef(scene)
+    ids = np.ascontiguousarray(ids, dtype=np.int32).reshape(n * n, bounces + 1)
+    g = _grid_struct(grid)
+    dn = np.ascontiguousarray(dnew, dtype=np.float64)
+    out = _Result()
+    rc = lib.orc_shade_frozen_dir(C.byref(sr.c), _ptr(_angles(scene, angles)),
+                                  C.byref(_params(-grid["d"], pressure, n, bounces, (0, 0, 0))), C.byref(g),
+                                  _ptr(ids), _ptr(dn), C.byref(out))
+    if rc != 0:
+        raise ValueError(f"oracle shade failed ({rc})")
+    return np.array(out.force[:])
+
+
+def fd_dir_jacobian(scene, n, bounces, grid, ids, pressure=1.0, angles=None, h=1e-6):
+    """Central differences of shade_frozen_dir: J[i, j] = dF_i/dd_j at the
+    recorded photon direction, d varied as a free 3-vector."""
+    d0 = np.asarray(grid["d"], float)
+    J = np.zeros((3, 3))
+    for j in range(3):
+        e = np.zeros(3)
+        e[j] = h
+        J[:, j] = (shade_frozen_dir(scene, n, bounces, grid, ids, d0 + e, pressure, angles) -
+                   shade_frozen_dir(scene, n, bounces, grid, ids, d0 - e, pressure, angles)) / (2 * h)
+    return J

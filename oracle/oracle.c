@@ -800,3 +800,64 @@ int orc_shade_frozen(const orc_scene *S, const double *angles, const orc_params 
     free(wtri);
     return oom ? ORC_ERR_OOM : ORC_OK;
 }
+
+/* ------------------------------------------------------------ frozen visibility, new direction
+ * Force of the recorded chains (chain generations only, no diffuse fans) when
+ * the photon direction becomes dnew (any 3-vector, not normalised): every
+ * primary ray keeps its triangle and its share of that triangle's visible
+ * area, whose projected size scales with c0 = -n0.d, so the chain's force is
+ * multiplied by c0(dnew) / c0(g->d); the chain follows dnew through its
+ * specular reflections on the frozen triangles (d' = d - 2 (n.d) n) with the
+ * weights of the law.  The normal orientation is the one that faces the
+ * recorded direction.  At dnew = g->d this reproduces orc_shade_frozen's
+ * force.  Only the force is written (torque zero).
+ */
+int orc_shade_frozen_dir(const orc_scene *S, const double *angles, const orc_params *P, const orc_grid *g,
+                         const int32_t *ids, const double *dnew, orc_result *out)
+{
+    int rc = orc_validate(S);
+    if (rc) return rc;
+    if (!P || P->n < 1 || P->bounces < 0 || P->n_diffuse != 0 || !ids || !dnew || !out) return ORC_ERR_ARG;
+    double *wtri = (double *)malloc(sizeof(double) * 9 * (size_t)(S->nt + 1));
+    if (!wtri) return ORC_ERR_OOM;
+    orc_articulate(S, angles, wtri);
+    int64_t np = (int64_t)P->n * P->n;
+    int32_t G = P->bounces + 1;
+    pix_out *po = (pix_out *)malloc(sizeof(pix_out) * (size_t)(np + 1));
+    if (!po) { free(wtri); return ORC_ERR_OOM; }
+    double scale = P->pressure * g->a_pix;
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < np; ++k) {
+        ksum acc[3];
+        memset(acc, 0, sizeof acc);
+        memset(&po[k], 0, sizeof po[k]);
+        double dref[3] = {g->d[0], g->d[1], g->d[2]}, d[3] = {dnew[0], dnew[1], dnew[2]};
+        double w = 1.0, area = 1.0;
+        for (int32_t gen = 0; gen < G; ++gen) {
+            int32_t tri = ids[k * G + gen];
+            if (tri < 0) break;
+            double nf[3], n[3], nr[3], dF[3], dT[3], x[3] = {0, 0, 0}, zero[3] = {0, 0, 0};
+            tri_normal(wtri + 9 * (int64_t)tri, nf);
+            double cref = orient(nf, dref, nr);       /* orientation from the recorded ray */
+            for (int c = 0; c < 3; ++c) n[c] = nr[c];
+            double cth = -v_dot(n, d);
+            if (gen == 0) area = cth / cref;
+            int32_t m = S->tri_mat[tri];
+            double rs = S->mats[2 * m], rd = S->mats[2 * m + 1];
+            shade(scale, w * area, d, n, cth, rs, rd, NULL, x, zero, dF, dT);
+            for (int c = 0; c < 3; ++c) ks_add(&acc[c], dF[c]);
+            if (gen == 0) po[k].hits++;
+            for (int c = 0; c < 3; ++c) {
+                d[c] = d[c] + 2.0 * cth * n[c];
+                dref[c] = dref[c] + 2.0 * cref * n[c];
+            }
+            w *= rs;
+        }
+        for (int c = 0; c < 3; ++c) po[k].f[c] = ks_val(&acc[c]);
+    }
+    finish(S, P, g, po, np, out);
+    for (int c = 0; c < 3; ++c) out->torque[c] = 0.0;
+    free(po);
+    free(wtri);
+    return ORC_OK;
+}

@@ -62,6 +62,9 @@ int orc_eval(const orc_scene *S, const double *angles, const orc_params *P, int3
              int32_t *ids /* n_pix x R or NULL */, double *ts /* same or NULL */);
 int orc_shade_frozen(const orc_scene *S, const double *angles, const orc_params *P,
                      const orc_grid *g, const int32_t *ids /* N*N x R */, orc_result *out);
+int orc_shade_frozen_dir(const orc_scene *S, const double *angles, const orc_params *P,
+                         const orc_grid *g, const int32_t *ids /* N*N x (B+1) */, const double *dnew,
+                         orc_result *out);
 /* R = record slots per pixel: B + 1 chain generations, then B fans of K
  * diffuse rays (fan of generation g at slot B + 1 + g K). */
 int32_t orc_record_slots(const orc_params *P);

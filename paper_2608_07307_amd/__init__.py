@@ -22,14 +22,14 @@ def _load():
     return L.load()
 
 
-def params(sun_dir, n, bounces=0, pressure=1.0, ref=(0.0, 0.0, 0.0), count=False, diffuse=0):
+def params(sun_dir, n, bounces=0, pressure=1.0, ref=(0.0, 0.0, 0.0), count=False, diffuse=0, grad_dir=False):
     p = L.srp_eval_params()
     p.sun_dir[:] = [float(x) for x in sun_dir]
     p.pressure = float(pressure)
     p.n = int(n)
     p.bounces = int(bounces)
     p.ref[:] = [float(x) for x in ref]
-    p.flags = L.SRP_F_COUNT if count else 0
+    p.flags = (L.SRP_F_COUNT if count else 0) | (L.SRP_F_GRAD_DIR if grad_dir else 0)
     p.n_diffuse = int(diffuse)
     return p
 
@@ -124,17 +124,24 @@ def eval(scene: Scene, sun_dir, n, bounces=0, pressure=1.0, ref=(0, 0, 0), count
 
 
 def eval_grad(scene: Scene, sun_dir, n, bounces=0, pressure=1.0, ref=(0, 0, 0)) -> dict:
-    """srp_eval_grad: result plus dF/drho_s (M,3), dF/drho_d (M,3), dF/dtheta (J,3)."""
+    """srp_eval_grad: result plus dF/drho_s (M,3), dF/drho_d (M,3), dF/dtheta (J,3)
+    and dF/dd (3,3), d the photon direction."""
     lib = _load()
     p = params(sun_dir, n, bounces, pressure, ref)
     r = L.srp_result()
     gs = np.zeros((scene.n_mats, 3))
     gd = np.zeros((scene.n_mats, 3))
     gt = np.zeros((max(scene.n_dof, 1), 3))
-    L.check(lib.srp_eval_grad(scene.handle, C.byref(p), C.byref(r), L.ptr(gs), L.ptr(gd), L.ptr(gt)))
+    gdir = np.zeros((3, 3))
+    L.check(lib.srp_eval_grad(scene.handle, C.byref(p), C.byref(r), L.ptr(gs), L.ptr(gd), L.ptr(gt), L.ptr(gdir)))
     out = _result_dict(r)
-    out.update(rho_s=gs, rho_d=gd, theta=gt[: scene.n_dof])
+    out.update(rho_s=gs, rho_d=gd, theta=gt[: scene.n_dof], dir=gdir)
     return out
+
+
+def grad_size(scene: Scene) -> int:
+    """Gradient doubles of one evaluation: 3 (2M + J) + 9."""
+    return 3 * (2 * scene.n_mats + scene.n_dof) + 9
 
 
 def _items(entries):
@@ -172,11 +179,12 @@ def eval_batch(entries, out=None, stream=None):
 
 def eval_grad_batch(entries, out=None, grad=None, stream=None):
     """srp_eval_grad_batch.  Returns (results uint8 tensor, gradients float64
-    tensor (n, stride)) with stride = max over entries of 3*(2M+J)."""
+    tensor (n, stride)) with stride = max over entries of grad_size(scene):
+    rho_s (M x 3), rho_d (M x 3), theta (J x 3), dF/dd (3 x 3) per row."""
     import torch
     lib = _load()
     n = len(entries)
-    stride = max(3 * (2 * sc.n_mats + sc.n_dof) for sc, _, _ in entries)
+    stride = max(grad_size(sc) for sc, _, _ in entries)
     if out is None:
         out = torch.empty(n * RESULT_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
     if grad is None:
@@ -380,7 +388,7 @@ class Plan:
         n = len(entries)
         self.n = n
         self.out = torch.empty(n * RESULT_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
-        self.stride = max(3 * (2 * sc.n_mats + sc.n_dof) for sc, _, _ in entries)
+        self.stride = max(grad_size(sc) for sc, _, _ in entries)
         self.grad = torch.zeros((n, self.stride), dtype=torch.float64, device="cuda") if grad else None
         arr, keep = _items(entries)
         h = C.c_void_p()

@@ -23,6 +23,7 @@ EXPORTS = [
     "srp_rk78", "srp_propagate_rk78", "srp_propagate_spad_rk78",
 ]
 SRP_PLAN_GRAD = 1
+SRP_F_GRAD_DIR = 2
 
 
 class srp_material(C.Structure):
@@ -105,7 +106,7 @@ def load(path: str | None = None):
     lib.srp_set_panel_angles.argtypes = [V, V, I32]
     lib.srp_eval.argtypes = [V, C.POINTER(srp_eval_params), C.POINTER(srp_result), V, V]
     lib.srp_eval_batch.argtypes = [V, I64, V, V]
-    lib.srp_eval_grad.argtypes = [V, C.POINTER(srp_eval_params), C.POINTER(srp_result), V, V, V]
+    lib.srp_eval_grad.argtypes = [V, C.POINTER(srp_eval_params), C.POINTER(srp_result), V, V, V, V]
     lib.srp_eval_grad_batch.argtypes = [V, I64, V, V, I64, V]
     lib.srp_last_error.restype = C.c_char_p
     lib.srp_profile.argtypes = [C.c_int]

@@ -202,7 +202,7 @@ int check_params(const srp_eval_params *p) {
     double s = std::sqrt(p->sun_dir[0] * p->sun_dir[0] + p->sun_dir[1] * p->sun_dir[1] + p->sun_dir[2] * p->sun_dir[2]);
     if (!(s > 0) || !std::isfinite(s)) return fail(SRP_ERR_ARG, "zero sun_dir");
     if (!std::isfinite(p->pressure) || !finite3(p->ref)) return fail(SRP_ERR_ARG, "non-finite pressure or ref");
-    if (p->flags & ~(uint32_t)SRP_F_COUNT) return fail(SRP_ERR_ARG, "unknown flags");
+    if (p->flags & ~(uint32_t)(SRP_F_COUNT | SRP_F_GRAD_DIR)) return fail(SRP_ERR_ARG, "unknown flags");
     if (p->n_diffuse < 0 || p->n_diffuse > SRP_MAX_DIFFUSE)
         return fail(SRP_ERR_ARG, "n_diffuse must be in 0.." + std::to_string(SRP_MAX_DIFFUSE));
     return SRP_OK;
@@ -275,7 +275,7 @@ struct SlotRec {
 // pressures, references or hinge-angle values change.
 struct Layout {
     int64_t n = 0;
-    bool grad = false, count = false;
+    bool grad = false, count = false, dir = false;
     Schedule sch;
     std::vector<int64_t> chunk_base, patch_base;
     std::vector<int> tiles_x, tiles_y;
@@ -286,8 +286,18 @@ struct Layout {
     size_t o_desc = 0, o_cbase = 0, o_pbase = 0, o_win = 0, o_slots = 0, stage_bytes = 0;
     size_t o_patches = 0, o_counts = 0, o_gpart = 0, o_queue = 0, o_spill = 0, dev_bytes = 0;
     std::vector<size_t> gpart_off;
+    std::vector<int> grad_n;   // gradient partial doubles per chunk of each item (allocation and kernel)
     int grid = 1, wb = 1;
 };
+
+// Gradient partial slots per chunk: 9 per node (rotation sensitivities), 6
+// per material, and 9 for the photon-direction Jacobian when the item asks
+// for it (SRP_F_GRAD_DIR).
+int grad_slots(const srp_scene *sc, uint32_t flags) {
+    return 9 * sc->h.n_nodes + 6 * sc->h.n_mats + ((flags & SRP_F_GRAD_DIR) ? 9 : 0);
+}
+// Gradient outputs per evaluation: rho_s (M x 3), rho_d (M x 3), theta (J x 3), dF/dd (3 x 3).
+int64_t grad_out_size(const srp_scene *sc) { return 3 * (2 * (int64_t)sc->h.n_mats + sc->h.n_dof) + 9; }
 
 int check_items(const srp_batch_item *items, int64_t n, bool grad, const BatchOut &bo) {
     if (n > (1 << 30)) return fail(SRP_ERR_ARG, "too many items");
@@ -303,9 +313,9 @@ int check_items(const srp_batch_item *items, int64_t n, bool grad, const BatchOu
         if (grad && it.p.n_diffuse > 0)
             return fail(SRP_ERR_ARG, "item " + std::to_string(k) + ": the adjoint does not cover diffuse rays (n_diffuse must be 0)");
         if (grad) {
-            int gn = 9 * it.scene->h.n_nodes + 6 * it.scene->h.n_mats;
-            if (gn > MAX_GRAD_SLOTS) return fail(SRP_ERR_ARG, "gradient needs 9*nodes + 6*materials <= 960");
-            if (bo.d_grad && bo.grad_stride < 3 * (2 * it.scene->h.n_mats + it.scene->h.n_dof))
+            int gn = grad_slots(it.scene, it.p.flags);
+            if (gn > MAX_GRAD_SLOTS) return fail(SRP_ERR_ARG, "gradient needs 9*nodes + 6*materials + 9 <= 960");
+            if (bo.d_grad && bo.grad_stride < grad_out_size(it.scene))
                 return fail(SRP_ERR_ARG, "grad_stride too small");
         }
     }
@@ -365,11 +375,12 @@ int layout_build(const srp_batch_item *items, int64_t n, bool grad, Schedule for
         L.tiles_y[k] = (it.p.n + TILE - 1) / TILE;
         L.patch_base[k] = L.total_patches;
         L.total_patches += 4 * (int64_t)L.tiles_x[k] * L.tiles_y[k];
-        if (grad) L.max_grad_n = std::max(L.max_grad_n, 9 * it.scene->h.n_nodes + 6 * it.scene->h.n_mats);
+        if (grad) L.max_grad_n = std::max(L.max_grad_n, grad_slots(it.scene, it.p.flags));
+        L.dir |= grad && (it.p.flags & SRP_F_GRAD_DIR);
         L.max_wpts = std::max<int64_t>(L.max_wpts, (int64_t)it.scene->h.wpts.size());
     }
     L.patch_base[n] = L.total_patches;
-    int occ = trace_blocks_per_cu(L.count, grad, L.max_grad_n);
+    int occ = trace_blocks_per_cu(L.count, grad, L.dir, L.max_grad_n);
     L.sch = (force.ppc && force.bpc) ? force : pick_schedule(items, n, grad, L.total_patches, occ, L.max_grad_n);
     if (force.ppc) L.sch.ppc = force.ppc;
     if (force.bpc) L.sch.bpc = std::min(force.bpc, occ);
@@ -417,12 +428,13 @@ int layout_build(const srp_batch_item *items, int64_t n, bool grad, Schedule for
     L.o_counts = align_up(L.o_patches + sizeof(PatchOut) * L.total_patches);
     L.o_gpart = align_up(L.o_counts + (L.count ? sizeof(uint64_t) * 2 * L.total_patches : 0));
     L.gpart_off.assign(n, 0);
+    L.grad_n.assign(n, 0);
     size_t goff = L.o_gpart;
     if (grad)
         for (int64_t k = 0; k < n; ++k) {
             L.gpart_off[k] = goff;
-            int gn = 9 * items[k].scene->h.n_nodes + 6 * items[k].scene->h.n_mats;
-            goff = align_up(goff + sizeof(double) * gn * (L.chunk_base[k + 1] - L.chunk_base[k]));
+            L.grad_n[k] = grad_slots(items[k].scene, items[k].p.flags);
+            goff = align_up(goff + sizeof(double) * L.grad_n[k] * (L.chunk_base[k + 1] - L.chunk_base[k]));
         }
     // persistent grid: one chunk per wave at a time, at most bpc resident blocks per CU
     const int64_t waves = BLOCK / 64;
@@ -493,7 +505,7 @@ void staging_fill(const Layout &L, const srp_batch_item *items, const BatchOut &
         D.n_chunks = L.chunk_base[k + 1] - L.chunk_base[k];
         D.patch_base = L.patch_base[k];
         D.n_patches = L.patch_base[k + 1] - L.patch_base[k];
-        D.grad_n = L.grad ? 9 * sc->h.n_nodes + 6 * sc->h.n_mats : 0;
+        D.grad_n = L.grad ? L.grad_n[k] : 0;   // the per-chunk size the partials were allocated with
         D.grad_part = L.grad ? reinterpret_cast<double *>(Dv + L.gpart_off[k]) : nullptr;
         D.grad_out = (L.grad && bo.d_grad) ? bo.d_grad + k * bo.grad_stride : nullptr;
         D.hit_ids = (n == 1) ? bo.d_hit_ids : nullptr;
@@ -522,7 +534,7 @@ int enqueue(const Layout &L, char *Dv, const char *H, size_t copy_bytes, const B
         HIPCHK(hipEventRecord(ev.first, stream));
     }
     e = launch_trace(d_desc, d_cbase, (int)L.n, d_win, L.total_chunks, d_queue, d_spill, d_patches, d_counts, L.count,
-                     L.grad, L.grid, L.max_grad_n, stream);
+                     L.grad, L.dir, L.grid, L.max_grad_n, stream);
     if (e) return fail(SRP_ERR_DEVICE, std::string("trace kernel: ") + hipGetErrorString((hipError_t)e));
     if (profile) {
         HIPCHK(hipEventRecord(ev.second, stream));
@@ -646,7 +658,8 @@ int plan_refill(PlanImpl *P, const srp_batch_item *items, int64_t n, bool *compa
     if ((rc = layout_build(items, n, P->L.grad, P->L.sch, &L2))) return rc;
     const Layout &L = P->L;
     if (L2.n != L.n || L2.stage_bytes != L.stage_bytes || L2.dev_bytes > L.dev_bytes || L2.grid != L.grid ||
-        L2.wb != L.wb || L2.count != L.count || L2.max_grad_n != L.max_grad_n || L2.chunk_base != L.chunk_base ||
+        L2.wb != L.wb || L2.count != L.count || L2.dir != L.dir || L2.max_grad_n != L.max_grad_n ||
+        L2.grad_n != L.grad_n || L2.chunk_base != L.chunk_base ||
         L2.patch_base != L.patch_base || L2.o_patches != L.o_patches || L2.o_counts != L.o_counts ||
         L2.o_queue != L.o_queue || L2.o_spill != L.o_spill)
         return SRP_OK;
@@ -894,7 +907,7 @@ int srp_eval_grad_batch(const srp_batch_item *items, int64_t n_items, srp_result
 }
 
 int srp_eval_grad(srp_scene *scene, const srp_eval_params *params, srp_result *out, double *dF_drho_s,
-                  double *dF_drho_d, double *dF_dtheta) {
+                  double *dF_drho_d, double *dF_dtheta, double *dF_ddir) {
     g_err.clear();
     if (!scene || !params || !out) return fail(SRP_ERR_ARG, "null scene, params or out");
     int rc = check_params(params);
@@ -902,7 +915,7 @@ int srp_eval_grad(srp_scene *scene, const srp_eval_params *params, srp_result *o
     std::lock_guard<std::mutex> lk(g_ws.mu);
     if ((rc = ws_init())) return rc;
     const int M = scene->h.n_mats, J = scene->h.n_dof;
-    const size_t gsz = 3 * (size_t)(2 * M + J);
+    const size_t gsz = (size_t)grad_out_size(scene);
     static char *d_buf = nullptr;
     static size_t cap = 0;
     size_t need = sizeof(srp_result) + sizeof(double) * gsz + 256;
@@ -918,6 +931,8 @@ int srp_eval_grad(srp_scene *scene, const srp_eval_params *params, srp_result *o
         cap = need;
     }
     srp_batch_item it{scene, nullptr, *params};
+    if (dF_ddir) it.p.flags |= SRP_F_GRAD_DIR;
+    else it.p.flags &= ~(uint32_t)SRP_F_GRAD_DIR;
     BatchOut bo;
     bo.d_out = reinterpret_cast<srp_result *>(d_buf);
     bo.d_grad = reinterpret_cast<double *>(d_buf + 256);
@@ -931,6 +946,7 @@ int srp_eval_grad(srp_scene *scene, const srp_eval_params *params, srp_result *o
     if (dF_drho_s) std::memcpy(dF_drho_s, g.data(), sizeof(double) * 3 * M);
     if (dF_drho_d) std::memcpy(dF_drho_d, g.data() + 3 * M, sizeof(double) * 3 * M);
     if (dF_dtheta) std::memcpy(dF_dtheta, g.data() + 6 * M, sizeof(double) * 3 * J);
+    if (dF_ddir) std::memcpy(dF_ddir, g.data() + 6 * M + 3 * J, sizeof(double) * 9);
     if (out->status & SRP_STATUS_STACK) return fail(SRP_ERR_DEPTH, "traversal stack overflow");
     return SRP_OK;
 }
@@ -1021,7 +1037,7 @@ int srp_autotune(const srp_batch_item *items, int64_t n_items, int32_t flags, in
     double *d_grad = nullptr;
     int64_t stride = 0;
     for (int64_t k = 0; k < n_items; ++k)
-        if (items[k].scene) stride = std::max<int64_t>(stride, 3 * (2 * items[k].scene->h.n_mats + items[k].scene->h.n_dof));
+        if (items[k].scene) stride = std::max<int64_t>(stride, grad_out_size(items[k].scene));
     if (hipMalloc(&d_out, sizeof(srp_result) * n_items) != hipSuccess ||
         (grad && hipMalloc(&d_grad, sizeof(double) * std::max<int64_t>(stride, 1) * n_items) != hipSuccess)) {
         (void)hipGetLastError();
@@ -1035,13 +1051,14 @@ int srp_autotune(const srp_batch_item *items, int64_t n_items, int32_t flags, in
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
-    bool cnt = false;
+    bool cnt = false, dir = false;
     int mg = 0;
     for (int64_t k = 0; k < n_items; ++k) {
         cnt |= (items[k].p.flags & SRP_F_COUNT) != 0;
-        if (grad && items[k].scene) mg = std::max(mg, 9 * items[k].scene->h.n_nodes + 6 * items[k].scene->h.n_mats);
+        dir |= grad && (items[k].p.flags & SRP_F_GRAD_DIR);
+        if (grad && items[k].scene) mg = std::max(mg, grad_slots(items[k].scene, items[k].p.flags));
     }
-    int occ = trace_blocks_per_cu(cnt, grad, mg);
+    int occ = trace_blocks_per_cu(cnt, grad, dir, mg);
     Schedule best;
     double best_t = INFINITY;
     int64_t total_patches = 0;

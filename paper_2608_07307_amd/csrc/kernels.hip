@@ -164,7 +164,7 @@ __device__ __forceinline__ void fan_dir(const float n[3], const float4 l, float 
     for (int k = 0; k < 3; ++k) d[k] = l.x * t[k] + l.y * b[k] + l.z * n[k];
 }
 
-template <bool COUNT, bool GRAD>
+template <bool COUNT, bool GRAD, bool DIR>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(GRAD ? SRP_WPE_GRAD : SRP_WPE_FWD))) void k_trace(
     const EvalDesc *__restrict__ descs, const int64_t *__restrict__ chunk_base, int n_evals,
     const uint64_t *__restrict__ win, int grid_blocks, int64_t total_chunks, uint32_t *queue, uint32_t *spill,
@@ -414,6 +414,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(GRAD ? SR
                     int Kmax = K;
                     for (int m = 32; m >= 1; m >>= 1) Kmax = max(Kmax, __shfl_xor(Kmax, m, WAVE));
                     float A[9], Tn[3] = {0, 0, 0};
+                    float n0[3] = {0, 0, 0}, c0 = 1.0f;   // the primary hit's normal and cosine (DIR)
                     m3_zero(A);
                     for (int k = Kmax - 1; k >= 0; --k) {
                         const bool act = k < K;
@@ -444,6 +445,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(GRAD ? SR
                             }
                             const float cc = -(n[0] * d[0] + n[1] * d[1] + n[2] * d[2]);
                             const float sc = rs * cc + rd * (1.0f / 3.0f);
+                            if (DIR && k == 0) {
+                                for (int i = 0; i < 3; ++i) n0[i] = n[i];
+                                c0 = cc;
+                            }
                             // material terms
                             for (int i = 0; i < 3; ++i) {
                                 gmat[i] = w * (-d[i] - 2.0f * cc * n[i] + Tn[i]);
@@ -478,6 +483,16 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(GRAD ? SR
                         }
                         wave_scatter_add(gw, node, act, Hm, 9, 9);
                         wave_scatter_add(gw + 9 * gK, mat, act, gmat, 6, 6);
+                    }
+                    // Photon-direction Jacobian of the ray's whole chain, each primary ray
+                    // keeping its triangle and its share of that triangle's visible area
+                    // (the share's projected area scales with c = -n0.d):
+                    //   dF/dd = A - S n0^T / c0,  S = chain contribution per unit weight (Tn)
+                    if (DIR && (D.flags & SRP_F_GRAD_DIR)) {
+                        float Jd[9];
+                        for (int i = 0; i < 3; ++i)
+                            for (int j = 0; j < 3; ++j) Jd[3 * i + j] = A[3 * i + j] - Tn[i] * n0[j] / c0;
+                        wave_scatter_add(gw + 9 * gK + 6 * D.n_mats, 0, K > 0, Jd, 9, 9);
                     }
                 }
             }
@@ -687,6 +702,10 @@ __global__ __launch_bounds__(RBLOCK) void k_reduce(const EvalDesc *__restrict__ 
                 for (int i = 0; i < 3; ++i)
                     g[6 * M + 3 * j + i] = scale * (S[3 * i] * ax[0] + S[3 * i + 1] * ax[1] + S[3 * i + 2] * ax[2]);
             }
+            // photon-direction Jacobian dF_i/dd_j (row-major); zeros when the item
+            // did not ask for it (its partials then have no direction slots)
+            const bool has_dir = G >= 9 * K + 6 * M + 9;
+            for (int i = tid; i < 9; i += RBLOCK) g[6 * M + 3 * J + i] = has_dir ? scale * sg[9 * K + 6 * M + i] : 0.0;
         }
     }
 }
@@ -711,18 +730,21 @@ size_t trace_lds_bytes(bool grad, int lds_grad_doubles) {
 
 int launch_trace(const EvalDesc *d_desc, const int64_t *d_chunk_base, int n_evals, const uint64_t *d_win,
                  int64_t total_chunks, uint32_t *d_queue, uint32_t *d_spill, PatchOut *d_chunks,
-                 uint64_t *d_counts, bool count, bool grad, int grid_blocks, int lds_grad_doubles, void *stream) {
+                 uint64_t *d_counts, bool count, bool grad, bool dir, int grid_blocks, int lds_grad_doubles,
+                 void *stream) {
     if (total_chunks <= 0) return 0;
     const size_t lds = trace_lds_bytes(grad, lds_grad_doubles);
     const int lgd = grad ? lds_grad_doubles : 0;
     hipStream_t s = (hipStream_t)stream;
-#define SRP_LAUNCH_TRACE(C, G)                                                                                \
-    hipLaunchKernelGGL((k_trace<C, G>), dim3(grid_blocks), dim3(BLOCK), lds, s, d_desc, d_chunk_base, n_evals, \
+#define SRP_LAUNCH_TRACE(C, G, R)                                                                              \
+    hipLaunchKernelGGL((k_trace<C, G, R>), dim3(grid_blocks), dim3(BLOCK), lds, s, d_desc, d_chunk_base, n_evals, \
                        d_win, grid_blocks, total_chunks, d_queue, d_spill, d_chunks, d_counts, lgd)
-    if (count && grad) SRP_LAUNCH_TRACE(true, true);
-    else if (count) SRP_LAUNCH_TRACE(true, false);
-    else if (grad) SRP_LAUNCH_TRACE(false, true);
-    else SRP_LAUNCH_TRACE(false, false);
+    if (count && grad && dir) SRP_LAUNCH_TRACE(true, true, true);
+    else if (count && grad) SRP_LAUNCH_TRACE(true, true, false);
+    else if (count) SRP_LAUNCH_TRACE(true, false, false);
+    else if (grad && dir) SRP_LAUNCH_TRACE(false, true, true);
+    else if (grad) SRP_LAUNCH_TRACE(false, true, false);
+    else SRP_LAUNCH_TRACE(false, false, false);
 #undef SRP_LAUNCH_TRACE
     return check(hipGetLastError());
 }
@@ -744,14 +766,16 @@ int launch_reduce(const EvalDesc *d_desc, const int64_t *d_tile_base, int n_eval
     return check(hipGetLastError());
 }
 
-int trace_blocks_per_cu(bool count, bool grad, int lds_grad_doubles) {
+int trace_blocks_per_cu(bool count, bool grad, bool dir, int lds_grad_doubles) {
     const size_t lds = trace_lds_bytes(grad, lds_grad_doubles);
     int nb = 0;
     hipError_t e;
-    if (count && grad) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_trace<true, true>, BLOCK, lds);
-    else if (count) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_trace<true, false>, BLOCK, lds);
-    else if (grad) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_trace<false, true>, BLOCK, lds);
-    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_trace<false, false>, BLOCK, lds);
+    if (count && grad && dir) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_trace<true, true, true>, BLOCK, lds);
+    else if (count && grad) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_trace<true, true, false>, BLOCK, lds);
+    else if (count) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_trace<true, false, false>, BLOCK, lds);
+    else if (grad && dir) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_trace<false, true, true>, BLOCK, lds);
+    else if (grad) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_trace<false, true, false>, BLOCK, lds);
+    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_trace<false, false, false>, BLOCK, lds);
     if (e != hipSuccess || nb < 1) nb = 1;
     return nb;
 }

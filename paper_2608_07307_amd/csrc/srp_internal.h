@@ -212,12 +212,12 @@ int launch_window(const EvalDesc *d_desc, int n_evals, int blocks_x, uint64_t *d
 // d_spill: grid_blocks * BLOCK * STACK_SPILL words; chunk counts below 2^31.
 int launch_trace(const EvalDesc *d_desc, const int64_t *d_chunk_base, int n_evals,
                  const uint64_t *d_win, int64_t total_chunks, uint32_t *d_queue, uint32_t *d_spill,
-                 PatchOut *d_patches, uint64_t *d_counts, bool count, bool grad, int grid_blocks,
+                 PatchOut *d_patches, uint64_t *d_counts, bool count, bool grad, bool dir, int grid_blocks,
                  int lds_grad_doubles, void *stream);
 int launch_reduce(const EvalDesc *d_desc, const int64_t *d_patch_base, int n_evals,
                   const uint64_t *d_win, const PatchOut *d_patches, const uint64_t *d_counts,
                   bool count, bool grad, void *d_out, void *stream);
 // Resident blocks per compute unit of the trace kernel variant.
-int trace_blocks_per_cu(bool count, bool grad, int lds_grad_doubles);
+int trace_blocks_per_cu(bool count, bool grad, bool dir, int lds_grad_doubles);
 
 }  // namespace srp

@@ -15,6 +15,7 @@ from .scenes import (  # noqa: F401
     dihedral,
     icosphere,
     box_wing,
+    box_wing_2axis,
     procedural_spacecraft,
     procedural_sized,
     uneven_batch_specs,

@@ -282,6 +282,22 @@ def box_wing(rho_bus=(0.2, 0.4), rho_panel=(0.05, 0.1)) -> Scene:
     return b.build([rho_bus, rho_panel], name="box_wing")
 
 
+def box_wing_2axis(rho_bus=(0.2, 0.4), rho_panel=(0.05, 0.1), tess=1) -> Scene:
+    """The box-wing with two-axis wings: each 2 x 5 m panel turns about its
+    support axis (y, through (0, +-1.5, 0), +-90 deg), then folds about a hinge
+    across the wing (x, through the same point, +-45 deg); axes composed in
+    that order.  tess x tess quads per panel.  4 degrees of freedom."""
+    b = _Builder()
+    root = b.node()
+    b.box((0, 0, 0), (0.5, 0.5, 0.5), root, 0)
+    for s in (1.0, -1.0):
+        p = b.node(parent=root, is_panel=1, pivot=(0, 1.5 * s, 0), axes=[(0, 1, 0), (1, 0, 0)],
+                   lo=[-HALF_PI, -HALF_PI / 2], hi=[HALF_PI, HALF_PI / 2])
+        y0 = 1.5 if s > 0 else -6.5
+        b.quad_grid((-1, y0, 0), (2, 0, 0), (0, 5, 0), tess, tess, p, lambda a, c: 1 + 0 * a)
+    return b.build([rho_bus, rho_panel], name="box_wing_2axis")
+
+
 def _panel_chain(b, root, sign, axis_along, axis_across, root_dist, length, width,
                  n_segments, nx, ny, mat_fn, lim=HALF_PI):
     """A wing of `n_segments` rigid segments along +-axis_along.

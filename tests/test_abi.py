@@ -134,7 +134,7 @@ def test_null_arguments_rejected(lib):
     r = L.srp_result()
     p = L.srp_eval_params()
     assert lib.srp_eval(None, C.byref(p), C.byref(r), None, None) == -1
-    assert lib.srp_eval_grad(None, C.byref(p), C.byref(r), None, None, None) == -1
+    assert lib.srp_eval_grad(None, C.byref(p), C.byref(r), None, None, None, None) == -1
     assert lib.srp_set_panel_angles(None, None, 0) == -1
     assert lib.srp_set_materials(None, None, 0) == -1
     assert lib.srp_destroy_scene(None) == 0

@@ -184,6 +184,7 @@ def test_degenerate_cases(srp):
 @pytest.mark.parametrize("maker,n,B", [
     (lambda: synth.box_wing(), 96, 1),
     (lambda: synth.procedural_sized(23, 3000), 128, 2),
+    (lambda: synth.box_wing_2axis(tess=6), 96, 2),
 ])
 def test_adjoint_matches_finite_differences(srp, maker, n, B):
     """Hand-written adjoint (fixed visibility) against FP64 central finite
@@ -203,6 +204,12 @@ def test_adjoint_matches_finite_differences(srp, maker, n, B):
             err = np.abs(g[key] - fd[key]).max() / scale
             print(f"adjoint {mesh.name} seed={seed} {key}: max err / max |grad| = {err:.2e}", flush=True)
             assert err <= 1e-4, (key, g[key], fd[key])
+        # photon-direction Jacobian against central differences of the oracle's
+        # frozen re-shade at a moved direction
+        Jfd = oracle.fd_dir_jacobian(mesh, n, B, o.grid, o.ids, pressure=2.0, angles=ang)
+        err = np.abs(g["dir"] - Jfd).max() / np.abs(Jfd).max()
+        print(f"adjoint {mesh.name} seed={seed} dir: max err / max |J| = {err:.2e}", flush=True)
+        assert err <= 1e-4, (g["dir"], Jfd)
         assert np.array_equal(g["force"], rec["force"])
 
 
@@ -289,4 +296,95 @@ def test_schedules_plans_and_autotune(srp):
     print(f"autotune: patches/chunk {r} blocks/CU {b} {ms:.3f} ms", flush=True)
     assert r in (1, 2, 4, 8, 16, 32, 64) and b >= 1 and ms > 0
     assert srp.results_to_numpy(srp.eval_batch(entries)).tobytes() == ref.tobytes()
+    # the autotuner of the forward + adjoint launch (its own gradient buffer), then
+    # a gradient batch under the tuned schedule
+    rg, bg, msg = srp.autotune(entries, grad=True)
+    print(f"autotune (adjoint): patches/chunk {rg} blocks/CU {bg} {msg:.3f} ms", flush=True)
+    assert rg in (1, 2, 4, 8, 16, 32, 64) and bg >= 1 and msg > 0
+    res, grad = srp.eval_grad_batch(entries)
+    assert srp.results_to_numpy(res)["force"].tobytes() == ref["force"].tobytes()
+    assert np.isfinite(grad.cpu().numpy()).all()
     plan.close()
+
+
+def test_direction_jacobian_plate_closed_form(srp):
+    """A plate that fills its window: dF/dd = P A [-L n^T + c ((1-rs) I +
+    2 rs n n^T)], L = (1-rs) d - 2 (rs c + rd/3) n, c = -n.d (by hand)."""
+    rs, rd, P = 0.35, 0.25, 1.7
+    sun = np.array([0.3, -0.2, 1.0])
+    d = -sun / np.linalg.norm(sun)
+    h = np.array([0.0, 0.0, 1.0]) if abs(d[2]) < 0.9 else np.array([1.0, 0.0, 0.0])
+    u = np.cross(h, d)
+    u /= np.linalg.norm(u)
+    v = np.cross(d, u)
+    ev = 1.5 * (np.cos(0.6) * v + np.sin(0.6) * d)
+    mesh = synth.plate(origin=0.3 * u - 0.7 * v + 0.2 * d, eu=2.0 * u, ev=ev, rho=(rs, rd))
+    sc = srp.Scene(mesh)
+    g = srp.eval_grad(sc, sun, 32, bounces=1, pressure=P)
+    n = np.cross(u, ev)
+    n /= np.linalg.norm(n)
+    if n @ d > 0:
+        n = -n
+    c = -n @ d
+    L = (1 - rs) * d - 2 * (rs * c + rd / 3) * n
+    J = P * 3.0 * (-np.outer(L, n) + c * ((1 - rs) * np.eye(3) + 2 * rs * np.outer(n, n)))
+    np.testing.assert_allclose(g["dir"], J, rtol=2e-5, atol=2e-5 * np.abs(J).max())
+
+
+def test_autograd_sun_direction_and_attitude(srp):
+    """Sun-direction gradients through the autograd Function: the backward of
+    a loss equals the hand contraction of dF/dd with dd/ds; an attitude R(w)
+    composed in torch (F_inertial = R F(R^T s)) has a w-gradient that matches
+    central differences of the oracle's frozen re-shade at the rotated
+    direction."""
+    import torch
+    from paper_2608_07307_amd.autograd import srp_forces
+    mesh = synth.procedural_sized(42, 2500)
+    sc = srp.Scene(mesh)
+    th0 = np.linspace(-0.3, 0.4, mesh.n_dof)
+    rs = torch.tensor(mesh.mats[:, 0], dtype=torch.float64, device="cuda")
+    rd = torch.tensor(mesh.mats[:, 1], dtype=torch.float64, device="cuda")
+    th = torch.tensor(th0, dtype=torch.float64, device="cuda")
+    dirs = torch.tensor(synth.fibonacci_dirs(4) * 2.0, dtype=torch.float64, device="cuda", requires_grad=True)
+    F = srp_forces(rs, rd, th, sc, dirs, 96, bounces=1, pressure=3.0)
+    w = torch.tensor(np.random.default_rng(1).normal(size=(4, 3)), dtype=torch.float64, device="cuda")
+    (F * w).sum().backward()
+    sc.set_angles(th0)
+    for k in range(4):
+        s = dirs[k].detach().cpu().numpy()
+        g = srp.eval_grad(sc, s, 96, bounces=1, pressure=3.0)
+        sh = s / np.linalg.norm(s)
+        dds = -(np.eye(3) - np.outer(sh, sh)) / np.linalg.norm(s)
+        np.testing.assert_allclose(dirs.grad[k].cpu().numpy(), w[k].cpu().numpy() @ g["dir"] @ dds,
+                                   rtol=1e-12, atol=1e-15)
+    # attitude: body frame = R(omega)^T inertial; F_inertial = R F_body(R^T s)
+    s_in = np.array([0.4, -0.7, 0.6])
+
+    def rot(om):
+        th_ = torch.linalg.norm(om)
+        K = torch.zeros(3, 3, dtype=om.dtype, device=om.device)
+        K[0, 1], K[0, 2], K[1, 0], K[1, 2], K[2, 0], K[2, 1] = -om[2], om[1], om[2], -om[0], -om[1], om[0]
+        return torch.eye(3, dtype=om.dtype, device=om.device) + torch.sin(th_) / th_ * K + \
+            (1 - torch.cos(th_)) / th_ ** 2 * K @ K
+
+    om = torch.tensor([0.2, -0.1, 0.3], dtype=torch.float64, device="cuda", requires_grad=True)
+    R = rot(om)
+    s_body = (R.T @ torch.tensor(s_in, dtype=torch.float64, device="cuda")).reshape(1, 3)
+    Fb = srp_forces(rs, rd, th, sc, s_body, 96, bounces=1, pressure=3.0)
+    wi = torch.tensor([0.3, 1.0, -0.5], dtype=torch.float64, device="cuda")
+    ((R @ Fb[0]) * wi).sum().backward()
+    sb = s_body.detach().cpu().numpy()[0]
+    o = oracle.eval_srp(mesh, sb, 96, bounces=1, pressure=3.0, angles=th0, record=True)
+
+    def loss(om_np):
+        Rn = rot(torch.tensor(om_np, dtype=torch.float64)).numpy()
+        d_body = Rn.T @ (-s_in / np.linalg.norm(s_in))
+        Fbn = oracle.shade_frozen_dir(mesh, 96, 1, o.grid, o.ids, d_body, pressure=3.0, angles=th0)
+        return (Rn @ Fbn) @ wi.cpu().numpy()
+
+    hh = 1e-6
+    fd = np.array([(loss(om.detach().cpu().numpy() + hh * e) - loss(om.detach().cpu().numpy() - hh * e)) / (2 * hh)
+                   for e in np.eye(3)])
+    err = np.abs(om.grad.cpu().numpy() - fd).max() / np.abs(fd).max()
+    print(f"attitude gradient: autograd {om.grad.cpu().numpy()}, oracle FD {fd}, rel err {err:.2e}", flush=True)
+    assert err <= 2e-4

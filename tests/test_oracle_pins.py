@@ -413,3 +413,67 @@ def test_dihedral_chain_gradient_closed_form():
                                rtol=1e-8, atol=1e-10)
     np.testing.assert_allclose(g["rho_d"][0], A * P * np.sqrt(2) / 3 * (1 + rs) * d,
                                rtol=1e-8, atol=1e-10)
+
+
+def test_two_axis_joint_by_hand():
+    """Two-axis wing (support about y, then fold about x, both through the
+    wing root): a panel point moves by R_y(a) R_x(b) about the root; the fold
+    is limited to +-45 deg and the support to +-90 deg (clamped)."""
+    bw = synth.box_wing_2axis()
+    ang = np.array([0.7, -0.4, -0.3, 0.5])
+    X = oracle.node_transforms(bw, ang)
+    p = np.array([0.3, 4.0, 0.1])
+    for node, (a, b), piv in ((1, ang[:2], np.array([0, 1.5, 0])), (2, ang[2:], np.array([0, -1.5, 0]))):
+        np.testing.assert_allclose(X[node, :, :3] @ p + X[node, :, 3], _Ry(a) @ (_Rx(b) @ (p - piv)) + piv, atol=1e-14)
+    np.testing.assert_allclose(oracle.node_transforms(bw, [2.0, 1.5, -3.0, -0.9]),
+                               oracle.node_transforms(bw, [np.pi / 2, np.pi / 4, -np.pi / 2, -np.pi / 4]), atol=0)
+
+
+def test_two_axis_tracking_faces_the_sun():
+    """With a support and a fold axis, tracking outer to inner turns the
+    panel normal exactly onto the Sun (either face) whenever neither limit
+    binds; otherwise the result sits on a limit."""
+    from oracle import propagate as OP
+    bw = synth.box_wing_2axis()
+    rng = np.random.default_rng(12)
+    checked = 0
+    for _ in range(200):
+        s = rng.normal(size=3)
+        s /= np.linalg.norm(s)
+        ang = OP.sun_tracking(bw, s, np.zeros(4))
+        for node, j in ((1, 0), (2, 2)):
+            n = oracle.node_transforms(bw, ang)[node][:, :3] @ np.array([0.0, 0.0, 1.0])
+            inside = abs(ang[j]) < np.pi / 2 - 1e-9 and abs(ang[j + 1]) < np.pi / 4 - 1e-9
+            if inside:
+                assert abs(abs(n @ s) - 1) < 1e-12
+                checked += 1
+            else:
+                assert np.isclose(abs(ang[j]), np.pi / 2) or np.isclose(abs(ang[j + 1]), np.pi / 4)
+    assert checked > 50
+
+
+def test_frozen_direction_reshade_and_plate_jacobian():
+    """The frozen re-shade at a new photon direction gives back the recorded
+    force at the recorded direction; for a plate that fills its window (every
+    pixel hits, visible share 1) it is F(d) = P A c(d) L(d) with c = -n.d and
+    L = (1-rs) d - 2 (rs c + rd/3) n, whose Jacobian by hand is
+    dF/dd = P A [-L n^T + c ((1-rs) I + 2 rs n n^T)]."""
+    rs, rd, P = 0.35, 0.25, 1.7
+    sun = np.array([0.3, -0.2, 1.0])
+    sc, d, u, v = _aligned_plate(sun, 2.0, 1.5, 0.6, (rs, rd))
+    r = oracle.eval_srp(sc, sun, 32, bounces=1, pressure=P, record=True)
+    fr = oracle.shade_frozen(sc, sun, 32, 1, r.grid, r.ids, pressure=P)
+    np.testing.assert_allclose(oracle.shade_frozen_dir(sc, 32, 1, r.grid, r.ids, r.grid["d"], pressure=P), fr.force,
+                               rtol=1e-12)
+    W = sc.verts[sc.tris[0]]
+    n = np.cross(W[1] - W[0], W[2] - W[0])
+    n /= np.linalg.norm(n)
+    if n @ d > 0:
+        n = -n
+    c = -n @ d
+    A = 2.0 * 1.5
+    L = (1 - rs) * d - 2 * (rs * c + rd / 3) * n
+    np.testing.assert_allclose(r.force, P * A * c * L, rtol=1e-12)
+    J = P * A * (-np.outer(L, n) + c * ((1 - rs) * np.eye(3) + 2 * rs * np.outer(n, n)))
+    Jfd = oracle.fd_dir_jacobian(sc, 32, 1, r.grid, r.ids, pressure=P)
+    np.testing.assert_allclose(Jfd, J, rtol=1e-7, atol=1e-9 * np.abs(J).max())
