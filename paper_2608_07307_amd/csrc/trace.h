@@ -227,8 +227,15 @@ SRP_HD inline bool trace_closest(const TraceCtx &C, const float o[3], const floa
     if (C.root == REF_NONE) return true;
     const float wix = safe_inv(d[0]), wiy = safe_inv(d[1]), wiz = safe_inv(d[2]);
     const float woix = o[0] * wix, woiy = o[1] * wiy, woiz = o[2] * wiz;
-    Frame F;   // the current instance's frame
-    F.ix = F.iy = F.iz = F.oix = F.oiy = F.oiz = 0.0f;
+    // The level being traversed: its box-test constants (F.ix .. F.oiz) and its
+    // node array.  Entering an instance switches to the instance's frame and
+    // the bottom-level nodes; popping a top-level node switches back.  (Entries
+    // of the bottom level on the stack always belong to the current instance,
+    // so those are the only transitions.)
+    Frame F;
+    F.ix = wix; F.iy = wiy; F.iz = wiz;
+    F.oix = woix; F.oiy = woiy; F.oiz = woiz;
+    const BNode4 SRP_GLOBAL *nodes = C.tlas;
     int inst = -1;
     uint32_t visits = 0;
     bool overflow = false;
@@ -253,12 +260,11 @@ SRP_HD inline bool trace_closest(const TraceCtx &C, const float o[3], const floa
                 ld[1] = I.R[1] * d[0] + I.R[4] * d[1] + I.R[7] * d[2];
                 ld[2] = I.R[2] * d[0] + I.R[5] * d[1] + I.R[8] * d[2];
                 frame_setup(lo, ld, F);
+                nodes = C.blas;
                 ref = I.root;
             } else {
-                const bool tl = ref_type(ref) == REF_TLAS_NODE;
-                const NodeData4 N = load_node4((tl ? C.tlas : C.blas) + ref_index(ref));
-                const float ix = tl ? wix : F.ix, iy = tl ? wiy : F.iy, iz = tl ? wiz : F.iz;
-                const float oix = tl ? woix : F.oix, oiy = tl ? woiy : F.oiy, oiz = tl ? woiz : F.oiz;
+                const NodeData4 N = load_node4(nodes + ref_index(ref));
+                const float ix = F.ix, iy = F.iy, iz = F.iz, oix = F.oix, oiy = F.oiy, oiz = F.oiz;
                 float t[4] = {
                     box_enter(N.lx.x, N.ly.x, N.lz.x, N.hx.x, N.hy.x, N.hz.x, ix, iy, iz, oix, oiy, oiz, tmin, h.t),
                     box_enter(N.lx.y, N.ly.y, N.lz.y, N.hx.y, N.hy.y, N.hz.y, ix, iy, iz, oix, oiy, oiz, tmin, h.t),
@@ -297,6 +303,11 @@ SRP_HD inline bool trace_closest(const TraceCtx &C, const float o[3], const floa
                     ref = top;
                     --sp;
                     top = st_load(stack, sp - 1);
+                    if (ref_type(ref) == REF_TLAS_NODE) {
+                        F.ix = wix; F.iy = wiy; F.iz = wiz;
+                        F.oix = woix; F.oiy = woiy; F.oiz = woiz;
+                        nodes = C.tlas;
+                    }
                 } else {
                     ref = REF_NONE;
                 }
@@ -328,6 +339,11 @@ SRP_HD inline bool trace_closest(const TraceCtx &C, const float o[3], const floa
             ref = top;
             --sp;
             top = st_load(stack, sp - 1);
+            if (ref_type(ref) == REF_TLAS_NODE) {
+                F.ix = wix; F.iy = wiy; F.iz = wiz;
+                F.oix = woix; F.oiy = woiy; F.oiz = woiz;
+                nodes = C.tlas;
+            }
         } else {
             ref = REF_NONE;
         }
