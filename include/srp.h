@@ -385,7 +385,8 @@ int srp_propagate_spad_rk78(const srp_spad_grid *grid, const double *table, doub
                             const srp_rk78_opts *opts, double *traj, int64_t max_rows, int64_t *n_rows);
 
 /* Measurement hook (not part of an evaluation): srp_profile(1) starts timing
- * every trace-kernel launch with a pair of HIP events recorded on the launch
+ * every launch's ray-tracing kernels (the trace kernel, then the diffuse fan
+ * kernel when n_diffuse > 0) with a pair of HIP events recorded on the launch
  * stream, srp_profile(0) stops; both reset the totals.  srp_profile_read waits
  * for the recorded launches and returns the summed kernel time (ms) and the
  * launch count since the last reset. */

@@ -209,7 +209,7 @@ def profile(enable: bool):
 
 
 def profile_read():
-    """(summed trace-kernel milliseconds, launch count) since the last reset."""
+    """(summed milliseconds of the ray-tracing kernels, launch count) since the last reset."""
     ms, n = C.c_double(), C.c_int64()
     L.check(_load().srp_profile_read(C.byref(ms), C.byref(n)))
     return ms.value, n.value

@@ -278,16 +278,21 @@ struct Layout {
     bool grad = false, count = false, dir = false;
     Schedule sch;
     std::vector<int64_t> chunk_base, patch_base;
+    std::vector<int64_t> unit_base;   // first fan work unit of every item, then the total
+    std::vector<int64_t> fan_base;    // first fan partial slot of every item, then the total
     std::vector<int> tiles_x, tiles_y;
     std::vector<int> item_slot;
     std::vector<SlotRec> slots;
     int max_grad_n = 0;
-    int64_t total_chunks = 0, total_patches = 0, max_wpts = 0;
-    size_t o_desc = 0, o_cbase = 0, o_pbase = 0, o_win = 0, o_slots = 0, stage_bytes = 0;
-    size_t o_patches = 0, o_counts = 0, o_gpart = 0, o_queue = 0, o_spill = 0, dev_bytes = 0;
+    int64_t total_chunks = 0, total_patches = 0, max_wpts = 0, total_units = 0, total_fan_slots = 0;
+    size_t o_desc = 0, o_cbase = 0, o_pbase = 0, o_ubase = 0, o_fbase = 0, o_win = 0, o_slots = 0, stage_bytes = 0;
+    size_t o_patches = 0, o_counts = 0, o_emask = 0, o_fanout = 0, o_fancnt = 0, o_gpart = 0, o_queue = 0;
+    size_t o_spill = 0, dev_bytes = 0;
     std::vector<size_t> gpart_off;
+    std::vector<size_t> emit_off;   // emitter records of each item with diffuse fans (0: none)
     std::vector<int> grad_n;   // gradient partial doubles per chunk of each item (allocation and kernel)
-    int grid = 1, wb = 1;
+    int grid = 1, fan_grid = 0, fan_claim = 1, fan_parts = 0, wb = 1;
+    bool fans_inline = false;   // the trace kernel traces the fans itself (no fan launch)
 };
 
 // Gradient partial slots per chunk: 9 per node (rotation sensitivities), 6
@@ -390,9 +395,44 @@ int layout_build(const srp_batch_item *items, int64_t n, bool grad, Schedule for
         L.total_chunks += (L.patch_base[k + 1] - L.patch_base[k] + L.sch.ppc - 1) / L.sch.ppc;
     }
     L.chunk_base[n] = L.total_chunks;
+    // diffuse fans (forward only; emitters are chain hits of generation < bounces).
+    // Many patches with fans: the trace kernel traces each patch's fans right after
+    // its chains.  Few: a fan kernel follows, with fan_parts units per patch, doubled
+    // (up to MAX_FAN_PARTS) while the units stay within two per resident wave, so
+    // that a small batch still fills the GPU.  Both give the same bits.
+    int64_t fan_patches = 0;
+    for (int64_t k = 0; k < n; ++k)
+        if (!grad && items[k].p.bounces > 0 && items[k].p.n_diffuse > 0)
+            fan_patches += L.patch_base[k + 1] - L.patch_base[k];
+    if (fan_patches > 0) {
+        const int64_t resident = (int64_t)g_ws.n_cu * fan_blocks_per_cu(L.count) * (BLOCK / 64);
+        L.fans_inline = fan_patches >= 2 * resident;
+        if (!L.fans_inline) {
+            L.fan_parts = 1;
+            while (L.fan_parts < MAX_FAN_PARTS && fan_patches * (2 * L.fan_parts) <= 2 * resident) L.fan_parts *= 2;
+        }
+    }
+    // partial slots: one per pass of 64 tasks (emitter, slice of FAN_SLICE fan rays), at
+    // most bounces x ceil(n_diffuse / FAN_SLICE) per patch
+    L.unit_base.assign(n + 1, 0);
+    L.fan_base.assign(n + 1, 0);
+    for (int64_t k = 0; k < n; ++k) {
+        L.unit_base[k] = L.total_units;
+        L.fan_base[k] = L.total_fan_slots;
+        const srp_eval_params &p = items[k].p;
+        if (!grad && p.bounces > 0 && p.n_diffuse > 0) {
+            const int64_t np = L.patch_base[k + 1] - L.patch_base[k];
+            L.total_units += np * L.fan_parts;
+            L.total_fan_slots += np * p.bounces * ((p.n_diffuse + FAN_SLICE - 1) / FAN_SLICE);
+        }
+    }
+    L.unit_base[n] = L.total_units;
+    L.fan_base[n] = L.total_fan_slots;
     // the work counters are 32-bit and overshoot their range by at most one per wave
     if (L.total_chunks > ((int64_t)1 << 31))
         return fail(SRP_ERR_ARG, "batch too large: more than 2^31 chunks (split it or raise patches per chunk)");
+    if (L.total_units > ((int64_t)1 << 31))
+        return fail(SRP_ERR_ARG, "batch too large: more than 2^31 diffuse work units (split it)");
 
     // articulation slots: the scene's current slot, or one per distinct angle vector
     std::map<std::pair<const srp_scene *, std::vector<double>>, int> slot_of;
@@ -414,19 +454,37 @@ int layout_build(const srp_batch_item *items, int64_t n, bool grad, Schedule for
         slot_of.emplace(key, L.item_slot[k]);
     }
 
-    // staging (uploaded every launch): descs | chunk_base | patch_base | win | slots
+    // staging (uploaded every launch): descs | chunk_base | patch_base | unit_base | fan_base | win | slots
     L.o_desc = 0;
     L.o_cbase = align_up(sizeof(EvalDesc) * n);
     L.o_pbase = align_up(L.o_cbase + sizeof(int64_t) * (n + 1));
-    L.o_win = align_up(L.o_pbase + sizeof(int64_t) * (n + 1));
+    L.o_ubase = align_up(L.o_pbase + sizeof(int64_t) * (n + 1));
+    L.o_fbase = align_up(L.o_ubase + sizeof(int64_t) * (n + 1));
+    L.o_win = align_up(L.o_fbase + sizeof(int64_t) * (n + 1));
     L.o_slots = align_up(L.o_win + sizeof(uint64_t) * WIN_STRIDE * n);
     size_t off = L.o_slots;
     for (auto &s : L.slots) { s.off = off; off = align_up(off + s.L.bytes); }
     L.stage_bytes = off;
-    // device-only: patch partials | counts | gradient partials (per chunk)
+    // device-only: patch partials | counts | emitter masks | fan pass partials | their
+    // counts | emitter records (per item) | gradient partials (per chunk)
     L.o_patches = align_up(L.stage_bytes);
     L.o_counts = align_up(L.o_patches + sizeof(PatchOut) * L.total_patches);
-    L.o_gpart = align_up(L.o_counts + (L.count ? sizeof(uint64_t) * 2 * L.total_patches : 0));
+    L.o_emask = align_up(L.o_counts + (L.count ? sizeof(uint64_t) * 2 * L.total_patches : 0));
+    L.emit_off.assign(n, 0);
+    size_t eoff = L.o_emask;
+    if (L.total_fan_slots > 0) {
+        // masks: SRP_MAX_BOUNCES per patch of every item (only items with fans use theirs)
+        L.o_fanout = align_up(L.o_emask + sizeof(uint64_t) * SRP_MAX_BOUNCES * L.total_patches);
+        L.o_fancnt = align_up(L.o_fanout + sizeof(PatchOut) * L.total_fan_slots);
+        eoff = align_up(L.o_fancnt + (L.count ? sizeof(uint64_t) * 2 * L.total_fan_slots : 0));
+        for (int64_t k = 0; k < n; ++k) {
+            if (L.fan_base[k + 1] == L.fan_base[k]) continue;
+            L.emit_off[k] = eoff;
+            eoff = align_up(eoff + sizeof(FanRec) * 64 * (size_t)items[k].p.bounces *
+                                       (L.patch_base[k + 1] - L.patch_base[k]));
+        }
+    }
+    L.o_gpart = eoff;
     L.gpart_off.assign(n, 0);
     L.grad_n.assign(n, 0);
     size_t goff = L.o_gpart;
@@ -436,14 +494,24 @@ int layout_build(const srp_batch_item *items, int64_t n, bool grad, Schedule for
             L.grad_n[k] = grad_slots(items[k].scene, items[k].p.flags);
             goff = align_up(goff + sizeof(double) * L.grad_n[k] * (L.chunk_base[k + 1] - L.chunk_base[k]));
         }
-    // persistent grid: one chunk per wave at a time, at most bpc resident blocks per CU
+    // persistent grids: one chunk (fan unit) per wave at a time, at most bpc resident
+    // blocks per CU (the fan kernel: as many as fit)
     const int64_t waves = BLOCK / 64;
     L.grid = (int)std::max<int64_t>(1, std::min<int64_t>((L.total_chunks + waves - 1) / waves,
                                                          (int64_t)g_ws.n_cu * L.sch.bpc));
-    // the work counters, then the traversal stacks' spill area (per thread of the grid)
+    if (L.total_units > 0) {
+        L.fan_grid = (int)std::max<int64_t>(1, std::min<int64_t>((L.total_units + waves - 1) / waves,
+                                                                 (int64_t)g_ws.n_cu * fan_blocks_per_cu(L.count)));
+        // units per queue claim: the largest (up to 8) that still leaves >= 16 claims per
+        // resident wave (big batches: fewer counter updates; single evaluations: 1)
+        const int64_t resident = (int64_t)L.fan_grid * waves;
+        while (L.fan_claim < 8 && L.total_units / (2 * L.fan_claim) >= 16 * resident) L.fan_claim *= 2;
+    }
+    // the work counters (trace kernel's, then fan kernel's), then the traversal stacks'
+    // spill area (per thread of the larger grid: the kernels run one after the other)
     L.o_queue = align_up(goff);
-    L.o_spill = align_up(L.o_queue + sizeof(uint32_t) * N_QUEUES * QUEUE_STRIDE);
-    L.dev_bytes = align_up(L.o_spill + sizeof(uint32_t) * STACK_SPILL * (size_t)BLOCK * L.grid);
+    L.o_spill = align_up(L.o_queue + sizeof(uint32_t) * 2 * N_QUEUES * QUEUE_STRIDE);
+    L.dev_bytes = align_up(L.o_spill + sizeof(uint32_t) * STACK_SPILL * (size_t)BLOCK * std::max(L.grid, L.fan_grid));
     L.wb = (int)std::min<int64_t>(64, std::max<int64_t>(1, (L.max_wpts + 2047) / 2048));
     return SRP_OK;
 }
@@ -454,6 +522,8 @@ void staging_fill(const Layout &L, const srp_batch_item *items, const BatchOut &
     EvalDesc *desc = reinterpret_cast<EvalDesc *>(H + L.o_desc);
     std::memcpy(H + L.o_cbase, L.chunk_base.data(), sizeof(int64_t) * (n + 1));
     std::memcpy(H + L.o_pbase, L.patch_base.data(), sizeof(int64_t) * (n + 1));
+    std::memcpy(H + L.o_ubase, L.unit_base.data(), sizeof(int64_t) * (n + 1));
+    std::memcpy(H + L.o_fbase, L.fan_base.data(), sizeof(int64_t) * (n + 1));
     uint64_t *win = reinterpret_cast<uint64_t *>(H + L.o_win);
     for (int64_t k = 0; k < WIN_STRIDE * n; ++k) win[k] = enc_f64(INFINITY);
     for (auto &s : L.slots) slot_pack(s.s, s.L, H + s.off);
@@ -505,6 +575,12 @@ void staging_fill(const Layout &L, const srp_batch_item *items, const BatchOut &
         D.n_chunks = L.chunk_base[k + 1] - L.chunk_base[k];
         D.patch_base = L.patch_base[k];
         D.n_patches = L.patch_base[k + 1] - L.patch_base[k];
+        const bool fans = L.fan_base[k + 1] > L.fan_base[k];
+        D.emit = fans ? reinterpret_cast<FanRec *>(Dv + L.emit_off[k]) : nullptr;
+        D.emit_mask = fans ? reinterpret_cast<uint64_t *>(Dv + L.o_emask) + SRP_MAX_BOUNCES * D.patch_base : nullptr;
+        D.unit_base = L.unit_base[k];
+        D.n_parts = fans ? L.fan_parts : 0;
+        D.fan_base = L.fan_base[k];
         D.grad_n = L.grad ? L.grad_n[k] : 0;   // the per-chunk size the partials were allocated with
         D.grad_part = L.grad ? reinterpret_cast<double *>(Dv + L.gpart_off[k]) : nullptr;
         D.grad_out = (L.grad && bo.d_grad) ? bo.d_grad + k * bo.grad_stride : nullptr;
@@ -533,14 +609,30 @@ int enqueue(const Layout &L, char *Dv, const char *H, size_t copy_bytes, const B
         if (rc) return rc;
         HIPCHK(hipEventRecord(ev.first, stream));
     }
+    const int64_t *d_fbase = nullptr;
+    PatchOut *d_fan_out = nullptr;
+    uint64_t *d_fan_counts = nullptr;
+    if (L.total_fan_slots > 0) {
+        d_fbase = reinterpret_cast<const int64_t *>(Dv + L.o_fbase);
+        d_fan_out = reinterpret_cast<PatchOut *>(Dv + L.o_fanout);
+        d_fan_counts = L.count ? reinterpret_cast<uint64_t *>(Dv + L.o_fancnt) : nullptr;
+    }
     e = launch_trace(d_desc, d_cbase, (int)L.n, d_win, L.total_chunks, d_queue, d_spill, d_patches, d_counts, L.count,
-                     L.grad, L.dir, L.grid, L.max_grad_n, stream);
+                     L.grad, L.dir, L.grid, L.max_grad_n, L.fans_inline ? d_fan_out : nullptr,
+                     L.fans_inline ? d_fan_counts : nullptr, stream);
     if (e) return fail(SRP_ERR_DEVICE, std::string("trace kernel: ") + hipGetErrorString((hipError_t)e));
-    if (profile) {
+    if (L.total_units > 0) {
+        const int64_t *d_ubase = reinterpret_cast<const int64_t *>(Dv + L.o_ubase);
+        e = launch_fans(d_desc, d_ubase, (int)L.n, d_win, L.total_units, L.fan_claim, d_queue, d_spill, d_fan_out,
+                        d_fan_counts, L.count, L.fan_grid, stream);
+        if (e) return fail(SRP_ERR_DEVICE, std::string("fan kernel: ") + hipGetErrorString((hipError_t)e));
+    }
+    if (profile) {   // the ray-tracing kernels: trace, then fans
         HIPCHK(hipEventRecord(ev.second, stream));
         g_prof.pairs.push_back(ev);
     }
-    e = launch_reduce(d_desc, d_pbase, (int)L.n, d_win, d_patches, d_counts, L.count, L.grad, bo.d_out, stream);
+    e = launch_reduce(d_desc, d_pbase, (int)L.n, d_win, d_patches, d_counts, d_fbase, d_fan_out, d_fan_counts, L.count,
+                      L.grad, bo.d_out, stream);
     if (e) return fail(SRP_ERR_DEVICE, std::string("reduce kernel: ") + hipGetErrorString((hipError_t)e));
     if (bo.h_copy) HIPCHK(hipMemcpyAsync(bo.h_copy, bo.d_out, sizeof(srp_result) * L.n, hipMemcpyDeviceToHost, stream));
     return SRP_OK;
@@ -661,6 +753,10 @@ int plan_refill(PlanImpl *P, const srp_batch_item *items, int64_t n, bool *compa
         L2.wb != L.wb || L2.count != L.count || L2.dir != L.dir || L2.max_grad_n != L.max_grad_n ||
         L2.grad_n != L.grad_n || L2.chunk_base != L.chunk_base ||
         L2.patch_base != L.patch_base || L2.o_patches != L.o_patches || L2.o_counts != L.o_counts ||
+        L2.unit_base != L.unit_base || L2.fan_base != L.fan_base || L2.fan_grid != L.fan_grid ||
+        L2.fan_claim != L.fan_claim || L2.fan_parts != L.fan_parts || L2.fans_inline != L.fans_inline ||
+        L2.emit_off != L.emit_off ||
+        L2.o_emask != L.o_emask || L2.o_fanout != L.o_fanout || L2.o_fancnt != L.o_fancnt ||
         L2.o_queue != L.o_queue || L2.o_spill != L.o_spill)
         return SRP_OK;
     if (P->pending) HIPCHK(hipEventSynchronize(P->done));

@@ -55,9 +55,6 @@ __device__ __forceinline__ double wave_sum(double x) {
 // the last ones (a mirror reflection is its own inverse).
 constexpr uint32_t CHAIN_FLIP = 0x80000000u;
 
-// LDS words per lane of a pending diffuse fan (forward kernels).
-constexpr int FAN_WORDS = 7;
-
 // Adds per-lane vectors into per-wave LDS accumulators acc[key * stride + 0..n),
 // one wave-wide FP64 sum per distinct key (keys processed lowest lane first).
 __device__ void wave_scatter_add(double *acc, int key, bool active, const float *vals, int n, int stride) {
@@ -164,11 +161,160 @@ __device__ __forceinline__ void fan_dir(const float n[3], const float4 l, float 
     for (int k = 0; k < 3; ++k) d[k] = l.x * t[k] + l.y * b[k] + l.z * n[k];
 }
 
+// Takes the next work item from the per-XCD queues: queue r hands out items
+// r, r + N_QUEUES, r + 2 N_QUEUES, ... in order; a wave drains the queue of its
+// own XCD, then helps with the others; a relaxed load skips drained queues
+// without an atomic.  Lane 0 talks to the counters and broadcasts, so the
+// result is wave-uniform.  Returns -1 once every queue is drained.
+__device__ __forceinline__ int64_t take_work(uint32_t *queue, uint32_t &r, int &tried, int64_t &n_r, int64_t total,
+                                             int lane) {
+    int64_t c;
+    #pragma unroll 1
+    for (;;) {
+        uint32_t v = 0;
+        if (lane == 0) {
+            uint32_t *qr = queue + r * QUEUE_STRIDE;
+            v = __hip_atomic_load(qr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (v < (uint32_t)n_r) v = atomicAdd(qr, 1u);
+        }
+        c = (int64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+        if (c < n_r || tried == N_QUEUES) break;
+        r = (r + 1) & (N_QUEUES - 1);
+        ++tried;
+        n_r = (total - r + N_QUEUES - 1) / N_QUEUES;
+    }
+    return c < n_r ? (int64_t)r + c * N_QUEUES : -1;
+}
+
+// Position of the (j+1)-th set bit of m (j < popcount(m)).
+__device__ __forceinline__ int nth_set_bit(uint64_t m, int j) {
+    int pos = 0;
+    #pragma unroll
+    for (int w = 32; w >= 1; w >>= 1) {
+        const uint64_t low = m & ((1ull << w) - 1ull);
+        const int c = __popcll(low);
+        if (j >= c) {
+            j -= c;
+            m >>= w;
+            pos += w;
+        } else {
+            m = low;
+        }
+    }
+    return pos;
+}
+
+// The diffuse fans of one patch's recorded emitters.  The patch's fan work is
+// split into tasks (emitter, slice of FAN_SLICE consecutive fan-ray indices),
+// slice-major, packed 64 to a pass, so lanes idle only in the patch's last
+// pass.  Every pass writes its own partial sums (force, torque, diffuse rays
+// and hits) to its slot of the patch's B * ceil(K / FAN_SLICE) slots (passes
+// past the patch's tasks write zeros), so the result depends neither on the
+// schedule nor on which kernel, or how many work units, traced the passes.
+// This call traces passes pass0, pass0 + step, ...; m[g] = the patch's
+// emitters of generation g (bit = lane of the trace kernel's patch).
+template <bool COUNT>
+__device__ __forceinline__ void fan_passes(const EvalDesc &D, const TraceCtx &TC, int64_t p, uint64_t m0, uint64_t m1,
+                                           uint64_t m2, uint64_t m3, int pass0, int step, float tmin2,
+                                           LaneStack &stack, double *lacc, int lane, PatchOut *fan_out,
+                                           uint64_t *fan_counts) {
+    const int KD = D.n_diffuse, B = D.bounces, N = D.n;
+    const int S = (KD + FAN_SLICE - 1) / FAN_SLICE;
+    const int PM = B * S;               // pass slots per patch
+    const int R = B + 1 + B * KD;
+    const float4 *dset = reinterpret_cast<const float4 *>(D.dset);
+    // emitters packed in generation-then-lane order
+    const int c0 = __popcll(m0), c1 = c0 + __popcll(m1), c2 = c1 + __popcll(m2), total = c2 + __popcll(m3);
+    const int tasks = total * S;
+    const int tile = (int)(p >> 2), q = (int)(p & 3);
+    #pragma unroll 1
+    for (int pass = pass0; pass < PM; pass += step) {
+        const int64_t slot_out = D.fan_base + p * PM + pass;
+        uint32_t rays = 0, hits = 0, nbox = 0, ntri = 0, status = 0;
+        double tot[6] = {0, 0, 0, 0, 0, 0};
+        if (pass * WAVE < tasks) {
+            for (int k = 0; k < 6; ++k) lacc[k * BLOCK] = 0.0;
+            const int t = pass * WAVE + lane;
+            if (t < tasks) {
+                const int sl = t / total;
+                const int j = t - sl * total;
+                const int k0 = sl * FAN_SLICE, k1 = min(k0 + FAN_SLICE, KD);
+                const int g = j >= c0 ? (j >= c1 ? (j >= c2 ? 3 : 2) : 1) : 0;
+                const uint64_t mg = g == 0 ? m0 : g == 1 ? m1 : g == 2 ? m2 : m3;
+                const int base = g == 0 ? 0 : g == 1 ? c0 : g == 2 ? c1 : c2;
+                const int bl = nth_set_bit(mg, j - base);   // the emitting lane of the trace kernel's patch
+                const float4 SRP_GLOBAL *er =
+                    (const float4 SRP_GLOBAL *)(D.emit + ((size_t)(p * B + g) * WAVE + bl));
+                const float4 ea = er[0], eb = er[1];
+                const float x[3] = {ea.x, ea.y, ea.z}, n[3] = {eb.x, eb.y, eb.z};
+                const float wd = ea.w;
+                const int32_t excl = __float_as_int(eb.w);
+                const int px = (tile % D.tiles_x) * TILE + (q & 1) * PATCH + (bl & 7);
+                const int py = (tile / D.tiles_x) * TILE + (q >> 1) * PATCH + (bl >> 3);
+                const int64_t pix = (int64_t)py * N + px;
+                #pragma unroll 1
+                for (int k = k0; k < k1; ++k) {
+                    float d[3];
+                    fan_dir(n, dset[k], d);
+                    Hit h;
+                    if (!trace_closest<COUNT>(TC, x, d, tmin2, excl, stack, h, nbox, ntri)) {
+                        status |= SRP_STATUS_STACK;
+                        break;
+                    }
+                    ++rays;
+                    if (D.hit_ids) {
+                        const int64_t slot = pix * R + (B + 1 + g * KD + k);
+                        D.hit_ids[slot] = h.tri >= 0 ? h.id : -1;
+                        D.hit_t[slot] = h.tri >= 0 ? h.t : 0.0f;
+                    }
+                    if (h.tri >= 0) {
+                        ++hits;
+                        float nh[3], ch, rs, rd;
+                        int32_t id;
+                        hit_normal(TC, D, h, d, nh, ch, rs, rd, id);
+                        const float a = wd * (1.0f - rs), bb = -2.0f * wd * (rs * ch + rd * (1.0f / 3.0f));
+                        float f[3], y[3];
+                        for (int i = 0; i < 3; ++i) {
+                            f[i] = a * d[i] + bb * nh[i];
+                            y[i] = fmaf(h.t, d[i], x[i]);
+                        }
+                        deposit(lacc, f, y, D.ref);
+                    }
+                }
+            }
+            for (int k = 0; k < 6; ++k) tot[k] = wave_sum(lacc[k * BLOCK]);
+            for (int m = 32; m >= 1; m >>= 1) {
+                rays += __shfl_xor(rays, m, WAVE);
+                hits += __shfl_xor(hits, m, WAVE);
+                status |= __shfl_xor(status, m, WAVE);
+                if (COUNT) {
+                    nbox += __shfl_xor(nbox, m, WAVE);
+                    ntri += __shfl_xor(ntri, m, WAVE);
+                }
+            }
+        }
+        if (lane == 0) {
+            PatchOut co;
+            for (int k = 0; k < 6; ++k) co.f[k] = tot[k];
+            co.hits = 0;
+            co.sec = rays;
+            co.sec_hits = hits;
+            co.flags = status;
+            fan_out[slot_out] = co;
+            if (COUNT) {
+                fan_counts[2 * slot_out] = nbox;
+                fan_counts[2 * slot_out + 1] = ntri;
+            }
+        }
+    }
+}
+
 template <bool COUNT, bool GRAD, bool DIR>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(GRAD ? SRP_WPE_GRAD : SRP_WPE_FWD))) void k_trace(
     const EvalDesc *__restrict__ descs, const int64_t *__restrict__ chunk_base, int n_evals,
     const uint64_t *__restrict__ win, int grid_blocks, int64_t total_chunks, uint32_t *queue, uint32_t *spill,
-    PatchOut *__restrict__ patches, uint64_t *__restrict__ counts, int lds_grad_doubles) {
+    PatchOut *__restrict__ patches, uint64_t *__restrict__ counts, int lds_grad_doubles, int fans_inline,
+    PatchOut *__restrict__ fan_out, uint64_t *__restrict__ fan_counts) {
     extern __shared__ char smem[];
     const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid >> 6;
     LaneStack stack;
@@ -179,12 +325,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(GRAD ? SR
     // per-lane FP64 force/torque sums of the current patch (component k at [k * BLOCK]):
     // kept in LDS and updated with LDS adds, out of the traversal's registers
     double *lacc = reinterpret_cast<double *>(smem + sizeof(uint32_t) * STACK_LDS * BLOCK) + tid;
-    // adjoint only: the hit chains (hit k at [k * BLOCK]), then per-wave gradient sums;
-    // forward only: the pending diffuse fan (emitter normal, then the specular ray's
-    // direction and weight waiting for the fan to finish), word k at [k * BLOCK]
+    // adjoint only: the hit chains (hit k at [k * BLOCK]), then per-wave gradient sums
     uint32_t *lchain = reinterpret_cast<uint32_t *>(smem + sizeof(uint32_t) * STACK_LDS * BLOCK +
                                                     sizeof(double) * 6 * BLOCK) + tid;
-    float *lfan = reinterpret_cast<float *>(lchain);
     double *gw = reinterpret_cast<double *>(smem + sizeof(uint32_t) * STACK_LDS * BLOCK + sizeof(double) * 6 * BLOCK +
                                             sizeof(uint32_t) * MAX_CHAIN * BLOCK) +
                  (size_t)wv * lds_grad_doubles;
@@ -208,23 +351,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(GRAD ? SR
     bool empty = true;
     #pragma unroll 1
     for (;;) {
-        int64_t c;
-        #pragma unroll 1
-        for (;;) {
-            uint32_t v = 0;
-            if (lane == 0) {
-                uint32_t *qr = queue + r * QUEUE_STRIDE;
-                v = __hip_atomic_load(qr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if (v < (uint32_t)n_r) v = atomicAdd(qr, 1u);
-            }
-            c = (int64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)v);
-            if (c < n_r || tried == N_QUEUES) break;
-            r = (r + 1) & (N_QUEUES - 1);
-            ++tried;
-            n_r = (total_chunks - r + N_QUEUES - 1) / N_QUEUES;
-        }
-        if (c >= n_r) break;   // every queue drained
-        c = r + c * N_QUEUES;
+        const int64_t c = take_work(queue, r, tried, n_r, total_chunks, lane);
+        if (c < 0) break;   // every queue drained
 
         if (c < cur_begin || c >= cur_end) {
             // evaluation owning chunk c (chunk_base is increasing; chunk_base[n_evals] = total)
@@ -283,10 +411,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(GRAD ? SR
             const int py = (tile / D.tiles_x) * TILE + (q >> 1) * PATCH + (lane >> 3);
             for (int k = 0; k < 6; ++k) lacc[k * BLOCK] = 0.0;
             // hit counts packed in 10-bit fields (primary hits, specular secondary rays and
-            // their hits; a patch sums at most 64 * SRP_MAX_BOUNCES of each), diffuse rays and
-            // their hits in 16-bit fields (at most 64 * SRP_MAX_BOUNCES * SRP_MAX_DIFFUSE), the
-            // status separately
-            uint32_t hcnt = 0, dcnt = 0, nbox = 0, ntri = 0, status = 0;
+            // their hits; a patch sums at most 64 * SRP_MAX_BOUNCES of each), the status
+            // separately (the diffuse rays are counted by the fan kernel)
+            uint32_t hcnt = 0, nbox = 0, ntri = 0, status = 0;
+            uint64_t em[SRP_MAX_BOUNCES] = {};   // the patch's fan emitters per generation
             {
                 const bool inside = px < N && py < N;
                 const bool valid = !empty && inside;
@@ -294,6 +422,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(GRAD ? SR
                 int K = 0;
                 float d[3] = {dd[0], dd[1], dd[2]}, w = 1.0f;   // the current ray's direction and weight
                 bool cont = false;                              // the last chain hit spawned a specular ray
+                uint32_t emitted = 0;                           // generations whose hit emitted a fan
                 if (inside && D.hit_ids) {   // rays that are not traced or miss stay "no hit"
                     for (int s = 0; s < R; ++s) {
                         D.hit_ids[pix * R + s] = -1;
@@ -305,53 +434,13 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(GRAD ? SR
                     for (int k = 0; k < 3; ++k) o[k] = fmaf((float)py, sv[k], fmaf((float)px, su[k], o0[k]));
                     float tmin = 0.0f;
                     int32_t excl = -1;
-                    // One loop traces the lane's specular chain and, after an emitting hit, its
-                    // fan of diffuse rays, then resumes the chain: lanes without a fan keep
-                    // following their chains while others trace fan rays.
-                    int gen = 0;   // chain generation (of the emitting hit while its fan is traced)
-                    int fk = -1;   // fan ray being traced; -1 while the chain is
+                    int gen = 0;   // chain generation
                     #pragma unroll 1
                     for (;;) {
                         Hit h;
                         if (!trace_closest<COUNT>(TC, o, d, tmin, excl, stack, h, nbox, ntri)) {
                             status |= SRP_STATUS_STACK;
                             break;
-                        }
-                        if (!GRAD && fk >= 0) {
-                            // diffuse ray: deposits at its first hit and spawns nothing
-                            if (D.hit_ids) {
-                                const int64_t slot = pix * R + (B + 1 + gen * KD + fk);
-                                D.hit_ids[slot] = h.tri >= 0 ? h.id : -1;
-                                D.hit_t[slot] = h.tri >= 0 ? h.t : 0.0f;
-                            }
-                            dcnt += 1u;
-                            if (h.tri >= 0) {
-                                dcnt += 1u << 16;
-                                float n[3], c, rs, rd;
-                                int32_t id;
-                                hit_normal(TC, D, h, d, n, c, rs, rd, id);
-                                const float a = w * (1.0f - rs), b = -2.0f * w * (rs * c + rd * (1.0f / 3.0f));
-                                float f[3], x[3];
-                                for (int k = 0; k < 3; ++k) {
-                                    f[k] = a * d[k] + b * n[k];
-                                    x[k] = fmaf(h.t, d[k], o[k]);
-                                }
-                                deposit(lacc, f, x, D.ref);
-                            }
-                            if (++fk < KD) {
-                                const float fn[3] = {lfan[0], lfan[BLOCK], lfan[2 * BLOCK]};
-                                fan_dir(fn, dset[fk], d);
-                                continue;
-                            }
-                            // fan done: the emitting hit's specular ray, if it spawned one
-                            fk = -1;
-                            const float cw = lfan[6 * BLOCK];
-                            if (!(cw > 0.0f)) break;
-                            for (int k = 0; k < 3; ++k) d[k] = lfan[(3 + k) * BLOCK];
-                            w = cw;
-                            ++gen;
-                            hcnt += 1u << 10;
-                            continue;
                         }
                         if (D.hit_ids) {
                             D.hit_ids[pix * R + gen] = h.tri >= 0 ? h.id : -1;
@@ -365,9 +454,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(GRAD ? SR
                         const bool emit = !GRAD && KD > 0 && gen < B && rd > 0.0f;
                         const bool spec = gen < B && rs > 0.0f;
                         const float a = w * (1.0f - rs);
-                        float f[3], x[3], ft[3] = {0, 0, 0}, fb[3] = {0, 0, 0};
+                        float f[3], x[3];
                         if (emit) {
                             // the fan's exact mean direction replaces the Lambertian 2/3 n recoil
+                            float ft[3], fb[3];
                             fan_frame(n, ft, fb);
                             const float4 m = dset[KD];
                             const float b = -2.0f * w * rs * cth - w * rd * m.z, e = -w * rd;
@@ -378,33 +468,37 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(GRAD ? SR
                         }
                         for (int k = 0; k < 3; ++k) x[k] = fmaf(h.t, d[k], o[k]);
                         deposit(lacc, f, x, D.ref);
+                        if (emit) {
+                            // the fan kernel traces this hit's diffuse rays from its record
+                            // (slot gen * 64 + lane of the patch's region)
+                            float4 SRP_GLOBAL *er = (float4 SRP_GLOBAL *)(D.emit + ((size_t)(pt * B + gen) * WAVE + lane));
+                            er[0] = make_float4(x[0], x[1], x[2], w * rd / (float)KD);
+                            er[1] = make_float4(n[0], n[1], n[2], __int_as_float(id));
+                            emitted |= 1u << gen;
+                        }
                         if (GRAD) lchain[K * BLOCK] = (uint32_t)h.tri | (flip ? CHAIN_FLIP : 0u);
                         ++K;
                         cont = false;
-                        if (!emit && !spec) break;
+                        if (!spec) break;
                         for (int k = 0; k < 3; ++k) {
                             o[k] = x[k];
                             d[k] = fmaf(2.0f * cth, n[k], d[k]);   // the specular direction
                         }
+                        w *= rs;
                         tmin = tmin2;
                         excl = id;
-                        if (emit) {
-                            // keep the emitter normal and the pending specular ray, trace fan ray 0
-                            for (int k = 0; k < 3; ++k) {
-                                lfan[k * BLOCK] = n[k];
-                                lfan[(3 + k) * BLOCK] = d[k];
-                            }
-                            lfan[6 * BLOCK] = spec ? w * rs : 0.0f;
-                            w = w * rd / (float)KD;
-                            fk = 0;
-                            const float4 l = dset[0];
-                            for (int k = 0; k < 3; ++k) d[k] = l.x * ft[k] + l.y * fb[k] + l.z * n[k];
-                            continue;
-                        }
-                        w *= rs;
                         ++gen;
                         cont = true;
                         hcnt += 1u << 10;
+                    }
+                }
+                if (!GRAD && KD > 0) {
+                    // which slots of the patch's emitter region hold records, per generation
+                    #pragma unroll
+                    for (int g = 0; g < SRP_MAX_BOUNCES; ++g) {
+                        if (g >= B) break;
+                        em[g] = __ballot((emitted >> g) & 1u);
+                        if (lane == 0) D.emit_mask[(size_t)pt * B + g] = em[g];
                     }
                 }
                 if (GRAD) {
@@ -504,15 +598,13 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(GRAD ? SR
                 for (int k = 0; k < 6; ++k) tot[k] = wave_sum(lacc[k * BLOCK]);
             for (int m = 32; m >= 1; m >>= 1) {
                 hcnt += __shfl_xor(hcnt, m, WAVE);
-                if (!GRAD) dcnt += __shfl_xor(dcnt, m, WAVE);
                 status |= __shfl_xor(status, m, WAVE);
                 if (COUNT) {
                     nbox += __shfl_xor(nbox, m, WAVE);
                     ntri += __shfl_xor(ntri, m, WAVE);
                 }
             }
-            const uint32_t cnts[6] = {hcnt & 1023u, ((hcnt >> 10) & 1023u) + (dcnt & 0xffffu),
-                                      (hcnt >> 20) + (dcnt >> 16), nbox, ntri, status};
+            const uint32_t cnts[6] = {hcnt & 1023u, (hcnt >> 10) & 1023u, hcnt >> 20, nbox, ntri, status};
             if (lane == 0) {
                 PatchOut co;
                 for (int k = 0; k < 6; ++k) co.f[k] = tot[k];
@@ -527,11 +619,75 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(GRAD ? SR
                     counts[2 * t + 1] = cnts[4];
                 }
             }
+            if (!GRAD && KD > 0 && fans_inline) {
+                // the patch's fans right away, from the records its lanes just wrote
+                __threadfence_block();
+                fan_passes<COUNT>(D, TC, pt, em[0], em[1], em[2], em[3], 0, 1, tmin2, stack, lacc, lane, fan_out,
+                                  fan_counts);
+            }
         }
         if (GRAD) {
             wave_lds_fence();
             double *dst = D.grad_part + (size_t)kc * D.grad_n;
             for (int i = lane; i < D.grad_n; i += WAVE) dst[i] = gw[i];
+        }
+    }
+}
+
+// Fan work of the trace kernel's recorded emitters as a separate launch, for
+// batches too small to fill the GPU with whole patches: unit = one of V parts
+// of a patch (passes v, v + V, ...), V chosen by the host (up to
+// MAX_FAN_PARTS).  Persistent waves and work queues as in k_trace; a claim
+// takes `per_claim` consecutive units.
+template <bool COUNT>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(SRP_WPE_FWD))) void k_fans(
+    const EvalDesc *__restrict__ descs, const int64_t *__restrict__ unit_base, int n_evals,
+    const uint64_t *__restrict__ win, int grid_blocks, int64_t total_units, int per_claim, uint32_t *queue,
+    uint32_t *spill, PatchOut *__restrict__ fan_out, uint64_t *__restrict__ fan_counts) {
+    extern __shared__ char smem[];
+    const int tid = threadIdx.x, lane = tid & (WAVE - 1);
+    LaneStack stack;
+    stack.ring = reinterpret_cast<uint32_t *>(smem) + tid;
+    stack.stride = BLOCK;
+    stack.spill = (uint32_t SRP_GLOBAL *)spill + (size_t)blockIdx.x * BLOCK + tid;
+    stack.sstride = grid_blocks * BLOCK;
+    double *lacc = reinterpret_cast<double *>(smem + sizeof(uint32_t) * STACK_LDS * BLOCK) + tid;
+
+    uint32_t r = __builtin_amdgcn_s_getreg((HWREG_XCC_ID << 0) | (0 << 6) | (3 << 11)) & (N_QUEUES - 1);
+    int tried = 1;
+    const int64_t n_claims = (total_units + per_claim - 1) / per_claim;
+    int64_t n_r = (n_claims - r + N_QUEUES - 1) / N_QUEUES;
+    int cur = -1;
+    int64_t cur_begin = 0, cur_end = -1;
+    float tmin2 = 0.0f;
+    #pragma unroll 1
+    for (;;) {
+        const int64_t b = take_work(queue, r, tried, n_r, n_claims, lane);
+        if (b < 0) break;
+        const int64_t c_end = min((b + 1) * per_claim, total_units);
+        #pragma unroll 1
+        for (int64_t c = b * per_claim; c < c_end; ++c) {
+            if (c < cur_begin || c >= cur_end) {
+                int lo = (cur >= 0 && c >= cur_end) ? cur : 0, hi = n_evals - 1;
+                while (lo < hi) {
+                    int mid = (lo + hi + 1) >> 1;
+                    if (unit_base[mid] <= c) lo = mid; else hi = mid - 1;
+                }
+                cur = lo;
+                cur_begin = unit_base[lo];
+                cur_end = unit_base[lo + 1];
+                const uint64_t *W = win + (size_t)lo * WIN_STRIDE;
+                const double wu = -dec_f64(W[1]) - dec_f64(W[0]), wv_ = -dec_f64(W[3]) - dec_f64(W[2]);
+                tmin2 = uniform_f32((float)(1e-6 * fmax(wu, wv_)));
+            }
+            const EvalDesc &D = descs[cur];
+            const int64_t u = c - D.unit_base;
+            const int V = D.n_parts, B = D.bounces;
+            const int64_t p = u / V;            // the patch
+            const int v = (int)(u - p * V);     // which of its parts
+            const uint64_t *em = D.emit_mask + (size_t)p * B;
+            const uint64_t m0 = em[0], m1 = B > 1 ? em[1] : 0ull, m2 = B > 2 ? em[2] : 0ull, m3 = B > 3 ? em[3] : 0ull;
+            fan_passes<COUNT>(D, trace_ctx(D), p, m0, m1, m2, m3, v, V, tmin2, stack, lacc, lane, fan_out, fan_counts);
         }
     }
 }
@@ -543,8 +699,8 @@ constexpr int WBLOCK = 256;   // threads per block of the window kernel
 __global__ __launch_bounds__(WBLOCK) void k_window(const EvalDesc *__restrict__ descs, uint64_t *win, int blocks_x,
                                                   uint32_t *queue) {
     const EvalDesc &D = descs[blockIdx.y];
-    // the trace kernel's work counters start at zero
-    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < N_QUEUES) queue[threadIdx.x * QUEUE_STRIDE] = 0u;
+    // the trace and fan kernels' work counters start at zero
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < 2 * N_QUEUES) queue[threadIdx.x * QUEUE_STRIDE] = 0u;
     double mn[5] = {INFINITY, INFINITY, INFINITY, INFINITY, INFINITY};
     const int64_t stride = (int64_t)blocks_x * WBLOCK;
     for (int64_t i = (int64_t)blockIdx.x * WBLOCK + threadIdx.x; i < D.n_wpts; i += stride) {
@@ -585,7 +741,10 @@ __global__ __launch_bounds__(RBLOCK) void k_reduce(const EvalDesc *__restrict__ 
                                                 const int64_t *__restrict__ patch_base,
                                                 const uint64_t *__restrict__ win,
                                                 const PatchOut *__restrict__ patches,
-                                                const uint64_t *__restrict__ counts, srp_result *out) {
+                                                const uint64_t *__restrict__ counts,
+                                                const int64_t *__restrict__ fan_base,
+                                                const PatchOut *__restrict__ fan_out,
+                                                const uint64_t *__restrict__ fan_counts, srp_result *out) {
     const int e = blockIdx.x, tid = threadIdx.x, lane = tid & (WAVE - 1), wid = tid >> 6;
     const EvalDesc &D = descs[e];
     // patch partials: per-thread strided sums, wave butterflies, waves in order
@@ -601,6 +760,18 @@ __global__ __launch_bounds__(RBLOCK) void k_reduce(const EvalDesc *__restrict__ 
         cn[2] += co.sec_hits;
         st |= co.flags;
         if (COUNT) { cn[3] += counts[2 * c]; cn[4] += counts[2 * c + 1]; }
+    }
+    // then the fan kernel's pass partials (diffuse rays), also in a fixed order
+    if (!GRAD && fan_base) {
+        const int64_t u0 = fan_base[e], u1 = fan_base[e + 1];
+        for (int64_t c = u0 + tid; c < u1; c += RBLOCK) {
+            const PatchOut &co = fan_out[c];
+            for (int k = 0; k < 6; ++k) f[k] += co.f[k];
+            cn[1] += co.sec;
+            cn[2] += co.sec_hits;
+            st |= co.flags;
+            if (COUNT) { cn[3] += fan_counts[2 * c]; cn[4] += fan_counts[2 * c + 1]; }
+        }
     }
     for (int k = 0; k < 6; ++k) f[k] = wave_sum(f[k]);
     for (int m = 32; m >= 1; m >>= 1) {
@@ -724,21 +895,22 @@ int launch_window(const EvalDesc *d_desc, int n_evals, int blocks_x, uint64_t *d
 
 size_t trace_lds_bytes(bool grad, int lds_grad_doubles) {
     return sizeof(uint32_t) * STACK_LDS * BLOCK + sizeof(double) * 6 * BLOCK +
-           (grad ? sizeof(uint32_t) * MAX_CHAIN * BLOCK + sizeof(double) * (BLOCK / 64) * lds_grad_doubles
-                 : sizeof(float) * FAN_WORDS * BLOCK);
+           (grad ? sizeof(uint32_t) * MAX_CHAIN * BLOCK + sizeof(double) * (BLOCK / 64) * lds_grad_doubles : 0);
 }
 
 int launch_trace(const EvalDesc *d_desc, const int64_t *d_chunk_base, int n_evals, const uint64_t *d_win,
                  int64_t total_chunks, uint32_t *d_queue, uint32_t *d_spill, PatchOut *d_chunks,
                  uint64_t *d_counts, bool count, bool grad, bool dir, int grid_blocks, int lds_grad_doubles,
-                 void *stream) {
+                 PatchOut *d_fan_out, uint64_t *d_fan_counts, void *stream) {
     if (total_chunks <= 0) return 0;
     const size_t lds = trace_lds_bytes(grad, lds_grad_doubles);
     const int lgd = grad ? lds_grad_doubles : 0;
+    const int fans_inline = (!grad && d_fan_out) ? 1 : 0;
     hipStream_t s = (hipStream_t)stream;
 #define SRP_LAUNCH_TRACE(C, G, R)                                                                              \
     hipLaunchKernelGGL((k_trace<C, G, R>), dim3(grid_blocks), dim3(BLOCK), lds, s, d_desc, d_chunk_base, n_evals, \
-                       d_win, grid_blocks, total_chunks, d_queue, d_spill, d_chunks, d_counts, lgd)
+                       d_win, grid_blocks, total_chunks, d_queue, d_spill, d_chunks, d_counts, lgd, fans_inline,  \
+                       d_fan_out, d_fan_counts)
     if (count && grad && dir) SRP_LAUNCH_TRACE(true, true, true);
     else if (count && grad) SRP_LAUNCH_TRACE(true, true, false);
     else if (count) SRP_LAUNCH_TRACE(true, false, false);
@@ -749,20 +921,38 @@ int launch_trace(const EvalDesc *d_desc, const int64_t *d_chunk_base, int n_eval
     return check(hipGetLastError());
 }
 
+int launch_fans(const EvalDesc *d_desc, const int64_t *d_unit_base, int n_evals, const uint64_t *d_win,
+                int64_t total_units, int per_claim, uint32_t *d_queue, uint32_t *d_spill, PatchOut *d_fan_out,
+                uint64_t *d_fan_counts, bool count, int grid_blocks, void *stream) {
+    if (total_units <= 0) return 0;
+    if (per_claim < 1) return (int)hipErrorInvalidValue;
+    const size_t lds = trace_lds_bytes(false, 0);   // the same ring and accumulators as the forward trace
+    hipStream_t s = (hipStream_t)stream;
+    uint32_t *q = d_queue + N_QUEUES * QUEUE_STRIDE;   // the fan kernel's own counters
+    if (count)
+        hipLaunchKernelGGL((k_fans<true>), dim3(grid_blocks), dim3(BLOCK), lds, s, d_desc, d_unit_base, n_evals, d_win,
+                           grid_blocks, total_units, per_claim, q, d_spill, d_fan_out, d_fan_counts);
+    else
+        hipLaunchKernelGGL((k_fans<false>), dim3(grid_blocks), dim3(BLOCK), lds, s, d_desc, d_unit_base, n_evals, d_win,
+                           grid_blocks, total_units, per_claim, q, d_spill, d_fan_out, d_fan_counts);
+    return check(hipGetLastError());
+}
+
 int launch_reduce(const EvalDesc *d_desc, const int64_t *d_tile_base, int n_evals, const uint64_t *d_win,
-                  const PatchOut *d_chunks, const uint64_t *d_counts, bool count, bool grad, void *d_out,
+                  const PatchOut *d_chunks, const uint64_t *d_counts, const int64_t *d_fan_base,
+                  const PatchOut *d_fan_out, const uint64_t *d_fan_counts, bool count, bool grad, void *d_out,
                   void *stream) {
     if (n_evals <= 0) return 0;
     hipStream_t s = (hipStream_t)stream;
     srp_result *out = (srp_result *)d_out;
-    if (count && grad)
-        hipLaunchKernelGGL((k_reduce<true, true>), dim3(n_evals), dim3(RBLOCK), 0, s, d_desc, d_tile_base, d_win, d_chunks, d_counts, out);
-    else if (count)
-        hipLaunchKernelGGL((k_reduce<true, false>), dim3(n_evals), dim3(RBLOCK), 0, s, d_desc, d_tile_base, d_win, d_chunks, d_counts, out);
-    else if (grad)
-        hipLaunchKernelGGL((k_reduce<false, true>), dim3(n_evals), dim3(RBLOCK), 0, s, d_desc, d_tile_base, d_win, d_chunks, d_counts, out);
-    else
-        hipLaunchKernelGGL((k_reduce<false, false>), dim3(n_evals), dim3(RBLOCK), 0, s, d_desc, d_tile_base, d_win, d_chunks, d_counts, out);
+#define SRP_LAUNCH_REDUCE(C, G)                                                                                  \
+    hipLaunchKernelGGL((k_reduce<C, G>), dim3(n_evals), dim3(RBLOCK), 0, s, d_desc, d_tile_base, d_win, d_chunks, \
+                       d_counts, d_fan_base, d_fan_out, d_fan_counts, out)
+    if (count && grad) SRP_LAUNCH_REDUCE(true, true);
+    else if (count) SRP_LAUNCH_REDUCE(true, false);
+    else if (grad) SRP_LAUNCH_REDUCE(false, true);
+    else SRP_LAUNCH_REDUCE(false, false);
+#undef SRP_LAUNCH_REDUCE
     return check(hipGetLastError());
 }
 
@@ -776,6 +966,15 @@ int trace_blocks_per_cu(bool count, bool grad, bool dir, int lds_grad_doubles) {
     else if (grad && dir) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_trace<false, true, true>, BLOCK, lds);
     else if (grad) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_trace<false, true, false>, BLOCK, lds);
     else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_trace<false, false, false>, BLOCK, lds);
+    if (e != hipSuccess || nb < 1) nb = 1;
+    return nb;
+}
+
+int fan_blocks_per_cu(bool count) {
+    const size_t lds = trace_lds_bytes(false, 0);
+    int nb = 0;
+    hipError_t e = count ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fans<true>, BLOCK, lds)
+                         : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fans<false>, BLOCK, lds);
     if (e != hipSuccess || nb < 1) nb = 1;
     return nb;
 }

@@ -93,6 +93,25 @@ struct alignas(64) PatchOut {
     uint32_t hits, sec, sec_hits, flags;
 };
 
+// A fan emitter (a chain hit that emits diffuse rays), written by the trace
+// kernel at slot gen * 64 + lane of its patch's region and read by the fan
+// kernel: hit point, weight w rho_d / K of each diffuse ray, oriented normal,
+// original index of the hit triangle (excluded from the fan's rays).
+struct alignas(16) FanRec {
+    float x[3];
+    float wd;
+    float n[3];
+    int32_t id;
+};
+static_assert(sizeof(FanRec) == 32, "FanRec is 32 bytes");
+
+// Diffuse rays per fan task: the fan kernel's lane task is one emitter times
+// one slice of FAN_SLICE consecutive fan-ray indices.
+constexpr int FAN_SLICE = 4;
+static_assert(SRP_MAX_BOUNCES == 4, "fan emitter masks: four generations");
+// Most work units per patch of the fan kernel.
+constexpr int MAX_FAN_PARTS = 8;
+
 // One evaluation, as the kernels see it.
 struct alignas(64) EvalDesc {
     // scene
@@ -131,11 +150,17 @@ struct alignas(64) EvalDesc {
     double *grad_part;      // n_chunks x grad_n (gradient partials)
     double *grad_out;       // 3*(2M+J) final gradient or null
     const float *dset;      // n_diffuse > 0: the diffuse set, 4 floats per ray (x, y, z, 0), then its mean
+    FanRec *emit;           // n_diffuse > 0, forward: emitter records, n_patches x bounces x 64
+    uint64_t *emit_mask;    // which of them are filled: n_patches x bounces masks of 64 lanes
+    int64_t unit_base;      // first fan work unit of this evaluation (n_patches x n_parts units)
+    int32_t n_parts;        // fan work units per patch (V); 0 without fans
+    int32_t pad2_;
+    int64_t fan_base;       // first fan partial slot (n_patches x bounces x ceil(n_diffuse / FAN_SLICE))
 };
 
 // The host writes these records and the kernels read them: both compilation
 // passes (host and gfx950) must agree on every offset.
-static_assert(sizeof(EvalDesc) == 320, "EvalDesc layout");
+static_assert(sizeof(EvalDesc) == 384, "EvalDesc layout");
 static_assert(offsetof(EvalDesc, tris) == 0, "EvalDesc layout");
 static_assert(offsetof(EvalDesc, blas) == 8, "EvalDesc layout");
 static_assert(offsetof(EvalDesc, mats) == 16, "EvalDesc layout");
@@ -173,6 +198,11 @@ static_assert(offsetof(EvalDesc, hit_t) == 280, "EvalDesc layout");
 static_assert(offsetof(EvalDesc, grad_part) == 288, "EvalDesc layout");
 static_assert(offsetof(EvalDesc, grad_out) == 296, "EvalDesc layout");
 static_assert(offsetof(EvalDesc, dset) == 304, "EvalDesc layout");
+static_assert(offsetof(EvalDesc, emit) == 312, "EvalDesc layout");
+static_assert(offsetof(EvalDesc, emit_mask) == 320, "EvalDesc layout");
+static_assert(offsetof(EvalDesc, unit_base) == 328, "EvalDesc layout");
+static_assert(offsetof(EvalDesc, n_parts) == 336, "EvalDesc layout");
+static_assert(offsetof(EvalDesc, fan_base) == 344, "EvalDesc layout");
 static_assert(sizeof(PatchOut) == 64, "PatchOut layout");
 static_assert(offsetof(PatchOut, f) == 0, "PatchOut layout");
 static_assert(offsetof(PatchOut, hits) == 48, "PatchOut layout");
@@ -203,21 +233,33 @@ SRP_HD inline double dec_f64(uint64_t e) {
 constexpr int WIN_STRIDE = 8;
 
 // Kernel launchers (kernels.hip)
-// Work queues of the trace kernel: N_QUEUES counters QUEUE_STRIDE words apart
+// Work queues of the trace kernel (and, after them, of the fan kernel): N_QUEUES
+// counters QUEUE_STRIDE words apart
 // (launch_window zeroes them).
 constexpr int N_QUEUES = 8;
 constexpr int QUEUE_STRIDE = 64;
 int launch_window(const EvalDesc *d_desc, int n_evals, int blocks_x, uint64_t *d_win, uint32_t *d_queue,
                   void *stream);
 // d_spill: grid_blocks * BLOCK * STACK_SPILL words; chunk counts below 2^31.
+// d_fan_out (forward, diffuse rays on): the trace kernel also traces every
+// patch's diffuse fans into their partial slots (no fan launch follows).
 int launch_trace(const EvalDesc *d_desc, const int64_t *d_chunk_base, int n_evals,
                  const uint64_t *d_win, int64_t total_chunks, uint32_t *d_queue, uint32_t *d_spill,
                  PatchOut *d_patches, uint64_t *d_counts, bool count, bool grad, bool dir, int grid_blocks,
-                 int lds_grad_doubles, void *stream);
+                 int lds_grad_doubles, PatchOut *d_fan_out, uint64_t *d_fan_counts, void *stream);
+// Diffuse fans of the recorded emitters: one work unit per patch and fan slice
+// (d_unit_base: first unit of every evaluation, then the total); uses the
+// second set of queue counters and the same spill area as the trace kernel.
+int launch_fans(const EvalDesc *d_desc, const int64_t *d_unit_base, int n_evals, const uint64_t *d_win,
+                int64_t total_units, int per_claim, uint32_t *d_queue, uint32_t *d_spill, PatchOut *d_fan_out,
+                uint64_t *d_fan_counts, bool count, int grid_blocks, void *stream);
 int launch_reduce(const EvalDesc *d_desc, const int64_t *d_patch_base, int n_evals,
                   const uint64_t *d_win, const PatchOut *d_patches, const uint64_t *d_counts,
+                  const int64_t *d_fan_base, const PatchOut *d_fan_out, const uint64_t *d_fan_counts,
                   bool count, bool grad, void *d_out, void *stream);
 // Resident blocks per compute unit of the trace kernel variant.
 int trace_blocks_per_cu(bool count, bool grad, bool dir, int lds_grad_doubles);
+// Resident blocks per compute unit of the fan kernel variant.
+int fan_blocks_per_cu(bool count);
 
 }  // namespace srp

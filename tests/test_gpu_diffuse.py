@@ -143,6 +143,39 @@ def test_adjoint_rejects_fans(srp):
         srp.eval(sc, (0, 0, 1), 32, bounces=1, diffuse=65)
 
 
+def test_fan_work_split_gives_the_same_bits(srp):
+    """The fans are traced by the trace kernel itself for big batches and by a
+    separate fan launch, with a patch's passes split over 8, 4, 2 or 1 work
+    units, for small ones (the split follows the batch size): every item's
+    force, torque and ray and test counts are bitwise the same in batches of
+    1, 2, 6 and 13 (the ~50k-triangle spacecraft, ragged 200^2 grid, B = 2,
+    K = 16)."""
+    mesh, dirs, angles, _, B, K = synth.diffuse_batch(13)
+    sc = srp.Scene(mesh)
+    keys = ("force", "torque")
+    cnts = ("n_hits", "n_secondary", "n_secondary_hits", "n_box_tests", "n_tri_tests")
+    ref = None
+    for E in (1, 2, 6, 13):
+        entries = [(sc, angles[k], srp.params(dirs[k], 200, B, count=True, diffuse=K)) for k in range(E)]
+        r = srp.results_to_numpy(srp.eval_batch(entries)).copy()
+        assert (r["status"] == 0).all()
+        if ref is None:
+            ref = r
+            continue
+        for k in range(min(E, len(ref))):
+            for f in keys:
+                assert r[k][f].tobytes() == ref[k][f].tobytes(), (E, k, f)
+            for f in cnts:
+                assert r[k][f] == ref[k][f], (E, k, f)
+        ref = r
+    # without counting (the other kernel variants) the forces are the same bits too
+    for E in (1, 13):
+        entries = [(sc, angles[k], srp.params(dirs[k], 200, B, diffuse=K)) for k in range(E)]
+        r = srp.results_to_numpy(srp.eval_batch(entries)).copy()
+        for k in range(E):
+            assert r[k]["force"].tobytes() == ref[k]["force"].tobytes(), (E, k)
+
+
 def test_paper_setting_batch(srp):
     """The ~50k-triangle spacecraft at the paper's ray-traced setting (256^2,
     two secondary levels, 16 diffuse rays), 64 attitudes in one launch: every
