@@ -288,7 +288,8 @@ struct Layout {
     size_t o_desc = 0, o_cbase = 0, o_pbase = 0, o_ubase = 0, o_fbase = 0, o_win = 0, o_slots = 0, stage_bytes = 0;
     size_t o_patches = 0, o_counts = 0, o_emask = 0, o_fanout = 0, o_fancnt = 0, o_gpart = 0, o_queue = 0;
     size_t o_spill = 0, dev_bytes = 0;
-    std::vector<size_t> gpart_off;
+    std::vector<size_t> gpart_off, gslice_off;
+    std::vector<int> n_gslices;   // gradient range sums per item (first reduction stage)
     std::vector<size_t> emit_off;   // emitter records of each item with diffuse fans (0: none)
     std::vector<int> grad_n;   // gradient partial doubles per chunk of each item (allocation and kernel)
     int grid = 1, fan_grid = 0, fan_claim = 1, fan_parts = 0, wb = 1;
@@ -487,12 +488,20 @@ int layout_build(const srp_batch_item *items, int64_t n, bool grad, Schedule for
     L.o_gpart = eoff;
     L.gpart_off.assign(n, 0);
     L.grad_n.assign(n, 0);
+    L.gslice_off.assign(n, 0);
+    L.n_gslices.assign(n, 0);
     size_t goff = L.o_gpart;
     if (grad)
         for (int64_t k = 0; k < n; ++k) {
+            const int64_t nc = L.chunk_base[k + 1] - L.chunk_base[k];
             L.gpart_off[k] = goff;
             L.grad_n[k] = grad_slots(items[k].scene, items[k].p.flags);
-            goff = align_up(goff + sizeof(double) * L.grad_n[k] * (L.chunk_base[k + 1] - L.chunk_base[k]));
+            goff = align_up(goff + sizeof(double) * L.grad_n[k] * nc);
+            // range sums of about 256 chunks each (at most MAX_GSLICES): a function of the
+            // item's own chunk count, so an item's gradient does not depend on its batch
+            L.n_gslices[k] = (int)std::min<int64_t>(MAX_GSLICES, std::max<int64_t>(1, nc / 256));
+            L.gslice_off[k] = goff;
+            goff = align_up(goff + sizeof(double) * L.grad_n[k] * L.n_gslices[k]);
         }
     // persistent grids: one chunk (fan unit) per wave at a time, at most bpc resident
     // blocks per CU (the fan kernel: as many as fit)
@@ -583,6 +592,8 @@ void staging_fill(const Layout &L, const srp_batch_item *items, const BatchOut &
         D.fan_base = L.fan_base[k];
         D.grad_n = L.grad ? L.grad_n[k] : 0;   // the per-chunk size the partials were allocated with
         D.grad_part = L.grad ? reinterpret_cast<double *>(Dv + L.gpart_off[k]) : nullptr;
+        D.n_gslices = L.grad ? L.n_gslices[k] : 0;
+        D.gslice = L.grad ? reinterpret_cast<double *>(Dv + L.gslice_off[k]) : nullptr;
         D.grad_out = (L.grad && bo.d_grad) ? bo.d_grad + k * bo.grad_stride : nullptr;
         D.hit_ids = (n == 1) ? bo.d_hit_ids : nullptr;
         D.hit_t = (n == 1) ? bo.d_hit_t : nullptr;

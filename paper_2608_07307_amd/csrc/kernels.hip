@@ -818,36 +818,14 @@ __global__ __launch_bounds__(RBLOCK) void k_reduce(const EvalDesc *__restrict__ 
         out[e] = r;
     }
     if (GRAD) {
-        // sum the chunk partials per component, then assemble.  The chunks are
-        // split into P contiguous slices (P threads per component when the
-        // components fit the block several times); each slice is summed with
-        // four interleaved accumulators and the slices are added in order, so
-        // the result depends only on the batch layout.
+        // the range sums of the chunk partials (k_grad_slices), added in order,
+        // then assembled
         const int G = D.grad_n, K = D.n_nodes, M = D.n_mats, J = D.n_dof;
         __shared__ double sg[MAX_GRAD_SLOTS];
-        __shared__ double sl[RBLOCK];
-        const double *gp = D.grad_part;
-        const int64_t NC = D.n_chunks;
-        const int P = (G > 0 && G <= RBLOCK) ? RBLOCK / G : 1;
-        auto slice_sum = [&](int i, int64_t c0, int64_t c1) {
-            double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-            int64_t c = c0;
-            for (; c + 8 <= c1; c += 8)
-                for (int u = 0; u < 8; ++u) a[u] += gp[(size_t)(c + u) * G + i];
-            for (; c < c1; ++c) a[0] += gp[(size_t)c * G + i];
-            return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
-        };
-        if (P > 1) {
-            const int i = tid % G, p = tid / G;
-            if (p < P) sl[p * G + i] = slice_sum(i, NC * p / P, NC * (p + 1) / P);
-            __syncthreads();
-            for (int j = tid; j < G; j += RBLOCK) {
-                double t = 0.0;
-                for (int q = 0; q < P; ++q) t += sl[q * G + j];
-                sg[j] = t;
-            }
-        } else {
-            for (int j = tid; j < G; j += RBLOCK) sg[j] = slice_sum(j, 0, NC);
+        for (int j = tid; j < G; j += RBLOCK) {
+            double t = 0.0;
+            for (int q = 0; q < D.n_gslices; ++q) t += D.gslice[(size_t)q * G + j];
+            sg[j] = t;
         }
         __syncthreads();
         double *g = D.grad_out;
@@ -878,6 +856,45 @@ __global__ __launch_bounds__(RBLOCK) void k_reduce(const EvalDesc *__restrict__ 
             const bool has_dir = G >= 9 * K + 6 * M + 9;
             for (int i = tid; i < 9; i += RBLOCK) g[6 * M + 3 * J + i] = has_dir ? scale * sg[9 * K + 6 * M + i] : 0.0;
         }
+    }
+}
+
+// Gradient partials, first stage: block (q, e) sums the chunk partials of
+// evaluation e in the q-th of n_gslices contiguous chunk ranges (ranges
+// NC q / Q .. NC (q + 1) / Q).  Inside a block the range is split again into P
+// contiguous slices (P threads per component when the components fit the
+// block several times), each summed with eight interleaved accumulators, and
+// the slices are added in order: the result depends only on the batch layout.
+__global__ __launch_bounds__(RBLOCK) void k_grad_slices(const EvalDesc *__restrict__ descs) {
+    const int q = blockIdx.x, e = blockIdx.y, tid = threadIdx.x;
+    const EvalDesc &D = descs[e];
+    const int Q = D.n_gslices;
+    if (q >= Q) return;
+    const int G = D.grad_n;
+    const double *gp = D.grad_part;
+    const int64_t NC = D.n_chunks, r0 = NC * q / Q, r1 = NC * (q + 1) / Q;
+    const int P = (G > 0 && G <= RBLOCK) ? RBLOCK / G : 1;
+    __shared__ double sl[RBLOCK];
+    auto slice_sum = [&](int i, int64_t c0, int64_t c1) {
+        double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        int64_t c = c0;
+        for (; c + 8 <= c1; c += 8)
+            for (int u = 0; u < 8; ++u) a[u] += gp[(size_t)(c + u) * G + i];
+        for (; c < c1; ++c) a[0] += gp[(size_t)c * G + i];
+        return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+    };
+    double *out = D.gslice + (size_t)q * G;
+    if (P > 1) {
+        const int i = tid % G, p = tid / G;
+        if (p < P) sl[p * G + i] = slice_sum(i, r0 + (r1 - r0) * p / P, r0 + (r1 - r0) * (p + 1) / P);
+        __syncthreads();
+        for (int j = tid; j < G; j += RBLOCK) {
+            double t = 0.0;
+            for (int k = 0; k < P; ++k) t += sl[k * G + j];
+            out[j] = t;
+        }
+    } else {
+        for (int j = tid; j < G; j += RBLOCK) out[j] = slice_sum(j, r0, r1);
     }
 }
 
@@ -945,6 +962,7 @@ int launch_reduce(const EvalDesc *d_desc, const int64_t *d_tile_base, int n_eval
     if (n_evals <= 0) return 0;
     hipStream_t s = (hipStream_t)stream;
     srp_result *out = (srp_result *)d_out;
+    if (grad) hipLaunchKernelGGL(k_grad_slices, dim3(MAX_GSLICES, n_evals), dim3(RBLOCK), 0, s, d_desc);
 #define SRP_LAUNCH_REDUCE(C, G)                                                                                  \
     hipLaunchKernelGGL((k_reduce<C, G>), dim3(n_evals), dim3(RBLOCK), 0, s, d_desc, d_tile_base, d_win, d_chunks, \
                        d_counts, d_fan_base, d_fan_out, d_fan_counts, out)

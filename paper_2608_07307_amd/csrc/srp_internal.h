@@ -110,6 +110,8 @@ static_assert(sizeof(FanRec) == 32, "FanRec is 32 bytes");
 constexpr int FAN_SLICE = 4;
 static_assert(SRP_MAX_BOUNCES == 4, "fan emitter masks: four generations");
 // Most work units per patch of the fan kernel.
+// Most gradient range sums per evaluation (separate blocks, summed in order).
+constexpr int MAX_GSLICES = 16;
 constexpr int MAX_FAN_PARTS = 8;
 
 // One evaluation, as the kernels see it.
@@ -154,8 +156,9 @@ struct alignas(64) EvalDesc {
     uint64_t *emit_mask;    // which of them are filled: n_patches x bounces masks of 64 lanes
     int64_t unit_base;      // first fan work unit of this evaluation (n_patches x n_parts units)
     int32_t n_parts;        // fan work units per patch (V); 0 without fans
-    int32_t pad2_;
+    int32_t n_gslices;      // gradient: contiguous chunk ranges summed by separate blocks
     int64_t fan_base;       // first fan partial slot (n_patches x bounces x ceil(n_diffuse / FAN_SLICE))
+    double *gslice;         // gradient: n_gslices x grad_n range sums
 };
 
 // The host writes these records and the kernels read them: both compilation
@@ -202,7 +205,9 @@ static_assert(offsetof(EvalDesc, emit) == 312, "EvalDesc layout");
 static_assert(offsetof(EvalDesc, emit_mask) == 320, "EvalDesc layout");
 static_assert(offsetof(EvalDesc, unit_base) == 328, "EvalDesc layout");
 static_assert(offsetof(EvalDesc, n_parts) == 336, "EvalDesc layout");
+static_assert(offsetof(EvalDesc, n_gslices) == 340, "EvalDesc layout");
 static_assert(offsetof(EvalDesc, fan_base) == 344, "EvalDesc layout");
+static_assert(offsetof(EvalDesc, gslice) == 352, "EvalDesc layout");
 static_assert(sizeof(PatchOut) == 64, "PatchOut layout");
 static_assert(offsetof(PatchOut, f) == 0, "PatchOut layout");
 static_assert(offsetof(PatchOut, hits) == 48, "PatchOut layout");
