@@ -53,7 +53,8 @@ int fail(int code, const std::string &msg) {
 size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) & ~(a - 1); }
 
 // Per-process workspace: one growing device buffer, one pinned staging
-// buffer, the library stream and the completion event of the last batch.
+// buffer, the library stream, and the upload and completion events of the
+// last batch.
 struct Workspace {
     std::mutex mu;
     bool init = false;
@@ -66,7 +67,8 @@ struct Workspace {
     srp_result *h_res = nullptr;   // pinned result readback
     size_t h_res_cap = 0;
     hipStream_t stream = nullptr;
-    hipEvent_t done = nullptr;
+    hipEvent_t done = nullptr;     // the last batch's device work finished
+    hipEvent_t copied = nullptr;   // its staging image was uploaded
     bool pending = false;
     float *d_dset = nullptr;       // diffuse direction sets, K = 1..SRP_MAX_DIFFUSE
 };
@@ -142,6 +144,7 @@ int ws_init() {
     HIPCHK(hipDeviceGetAttribute(&g_ws.n_cu, hipDeviceAttributeMultiprocessorCount, g_ws.device));
     HIPCHK(hipStreamCreateWithFlags(&g_ws.stream, hipStreamNonBlocking));
     HIPCHK(hipEventCreateWithFlags(&g_ws.done, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&g_ws.copied, hipEventDisableTiming));
     {
         const std::vector<float> t = diffuse_sets();
         if (hipMalloc(&g_ws.d_dset, t.size() * sizeof(float)) != hipSuccess) {
@@ -602,8 +605,9 @@ void staging_fill(const Layout &L, const srp_batch_item *items, const BatchOut &
 
 // Upload + window + trace + reduce (+ optional result copy) on `stream`.
 int enqueue(const Layout &L, char *Dv, const char *H, size_t copy_bytes, const BatchOut &bo, hipStream_t stream,
-            bool profile) {
+            bool profile, hipEvent_t copied = nullptr) {
     HIPCHK(hipMemcpyAsync(Dv, H, copy_bytes, hipMemcpyHostToDevice, stream));
+    if (copied) HIPCHK(hipEventRecord(copied, stream));
     const EvalDesc *d_desc = reinterpret_cast<const EvalDesc *>(Dv + L.o_desc);
     const int64_t *d_cbase = reinterpret_cast<const int64_t *>(Dv + L.o_cbase);
     const int64_t *d_pbase = reinterpret_cast<const int64_t *>(Dv + L.o_pbase);
@@ -668,10 +672,16 @@ int run_batch(const srp_batch_item *items, int64_t n, bool grad, const BatchOut 
         if ((rc = run_batch(items, h, grad, bo, stream, force))) return rc;
         return run_batch(items + h, n - h, grad, b2, stream, force);
     }
-    if ((rc = ws_wait())) return rc;   // staging and workspace reuse
-    if ((rc = ws_reserve(L.dev_bytes, L.stage_bytes))) return rc;
+    if (g_ws.pending) {
+        // the pinned staging image may be rewritten once the last batch's upload is
+        // done (the host prepares this batch while that one runs); the device
+        // workspace is reused on `stream` only after the last batch finished
+        HIPCHK(hipEventSynchronize(g_ws.copied));
+        HIPCHK(hipStreamWaitEvent(stream, g_ws.done, 0));
+    }
+    if ((rc = ws_reserve(L.dev_bytes, L.stage_bytes))) return rc;   // (waits for the last batch to grow)
     staging_fill(L, items, bo, g_ws.h_stage, g_ws.d_buf);
-    if ((rc = enqueue(L, g_ws.d_buf, g_ws.h_stage, L.stage_bytes, bo, stream, g_prof.on))) return rc;
+    if ((rc = enqueue(L, g_ws.d_buf, g_ws.h_stage, L.stage_bytes, bo, stream, g_prof.on, g_ws.copied))) return rc;
     HIPCHK(hipEventRecord(g_ws.done, stream));
     g_ws.pending = true;
     return SRP_OK;
