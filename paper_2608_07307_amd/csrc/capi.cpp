@@ -288,11 +288,11 @@ struct Layout {
     std::vector<SlotRec> slots;
     int max_grad_n = 0;
     int64_t total_chunks = 0, total_patches = 0, max_wpts = 0, total_units = 0, total_fan_slots = 0;
-    size_t o_desc = 0, o_cbase = 0, o_pbase = 0, o_ubase = 0, o_fbase = 0, o_win = 0, o_slots = 0, stage_bytes = 0;
+    size_t o_desc = 0, o_cbase = 0, o_ubase = 0, o_win = 0, o_slots = 0, stage_bytes = 0;
     size_t o_patches = 0, o_counts = 0, o_emask = 0, o_fanout = 0, o_fancnt = 0, o_gpart = 0, o_queue = 0;
     size_t o_spill = 0, dev_bytes = 0;
-    std::vector<size_t> gpart_off, gslice_off;
-    std::vector<int> n_gslices;   // gradient range sums per item (first reduction stage)
+    std::vector<size_t> gpart_off, gslice_off, pslice_off;
+    std::vector<int> n_slices;    // reduction range sums per item (first stage)
     std::vector<size_t> emit_off;   // emitter records of each item with diffuse fans (0: none)
     std::vector<int> grad_n;   // gradient partial doubles per chunk of each item (allocation and kernel)
     int grid = 1, fan_grid = 0, fan_claim = 1, fan_parts = 0, wb = 1;
@@ -458,13 +458,11 @@ int layout_build(const srp_batch_item *items, int64_t n, bool grad, Schedule for
         slot_of.emplace(key, L.item_slot[k]);
     }
 
-    // staging (uploaded every launch): descs | chunk_base | patch_base | unit_base | fan_base | win | slots
+    // staging (uploaded every launch): descs | chunk_base | unit_base | win | slots
     L.o_desc = 0;
     L.o_cbase = align_up(sizeof(EvalDesc) * n);
-    L.o_pbase = align_up(L.o_cbase + sizeof(int64_t) * (n + 1));
-    L.o_ubase = align_up(L.o_pbase + sizeof(int64_t) * (n + 1));
-    L.o_fbase = align_up(L.o_ubase + sizeof(int64_t) * (n + 1));
-    L.o_win = align_up(L.o_fbase + sizeof(int64_t) * (n + 1));
+    L.o_ubase = align_up(L.o_cbase + sizeof(int64_t) * (n + 1));
+    L.o_win = align_up(L.o_ubase + sizeof(int64_t) * (n + 1));
     L.o_slots = align_up(L.o_win + sizeof(uint64_t) * WIN_STRIDE * n);
     size_t off = L.o_slots;
     for (auto &s : L.slots) { s.off = off; off = align_up(off + s.L.bytes); }
@@ -492,20 +490,25 @@ int layout_build(const srp_batch_item *items, int64_t n, bool grad, Schedule for
     L.gpart_off.assign(n, 0);
     L.grad_n.assign(n, 0);
     L.gslice_off.assign(n, 0);
-    L.n_gslices.assign(n, 0);
+    L.pslice_off.assign(n, 0);
+    L.n_slices.assign(n, 0);
     size_t goff = L.o_gpart;
-    if (grad)
-        for (int64_t k = 0; k < n; ++k) {
-            const int64_t nc = L.chunk_base[k + 1] - L.chunk_base[k];
-            L.gpart_off[k] = goff;
-            L.grad_n[k] = grad_slots(items[k].scene, items[k].p.flags);
-            goff = align_up(goff + sizeof(double) * L.grad_n[k] * nc);
-            // range sums of about 256 chunks each (at most MAX_GSLICES): a function of the
-            // item's own chunk count, so an item's gradient does not depend on its batch
-            L.n_gslices[k] = (int)std::min<int64_t>(MAX_GSLICES, std::max<int64_t>(1, nc / 256));
-            L.gslice_off[k] = goff;
-            goff = align_up(goff + sizeof(double) * L.grad_n[k] * L.n_gslices[k]);
-        }
+    for (int64_t k = 0; k < n; ++k) {
+        // the reduction's first stage: range sums of about 1,024 patches each (at most
+        // MAX_SLICES), a function of the item's own size, so an item's results do not
+        // depend on its batch
+        const int64_t np = L.patch_base[k + 1] - L.patch_base[k];
+        L.n_slices[k] = (int)std::min<int64_t>(MAX_SLICES, std::max<int64_t>(1, np / 1024));
+        L.pslice_off[k] = goff;
+        goff = align_up(goff + sizeof(SliceOut) * L.n_slices[k]);
+        if (!grad) continue;
+        const int64_t nc = L.chunk_base[k + 1] - L.chunk_base[k];
+        L.gpart_off[k] = goff;
+        L.grad_n[k] = grad_slots(items[k].scene, items[k].p.flags);
+        goff = align_up(goff + sizeof(double) * L.grad_n[k] * nc);
+        L.gslice_off[k] = goff;
+        goff = align_up(goff + sizeof(double) * L.grad_n[k] * L.n_slices[k]);
+    }
     // persistent grids: one chunk (fan unit) per wave at a time, at most bpc resident
     // blocks per CU (the fan kernel: as many as fit)
     const int64_t waves = BLOCK / 64;
@@ -533,9 +536,7 @@ void staging_fill(const Layout &L, const srp_batch_item *items, const BatchOut &
     const int64_t n = L.n;
     EvalDesc *desc = reinterpret_cast<EvalDesc *>(H + L.o_desc);
     std::memcpy(H + L.o_cbase, L.chunk_base.data(), sizeof(int64_t) * (n + 1));
-    std::memcpy(H + L.o_pbase, L.patch_base.data(), sizeof(int64_t) * (n + 1));
     std::memcpy(H + L.o_ubase, L.unit_base.data(), sizeof(int64_t) * (n + 1));
-    std::memcpy(H + L.o_fbase, L.fan_base.data(), sizeof(int64_t) * (n + 1));
     uint64_t *win = reinterpret_cast<uint64_t *>(H + L.o_win);
     for (int64_t k = 0; k < WIN_STRIDE * n; ++k) win[k] = enc_f64(INFINITY);
     for (auto &s : L.slots) slot_pack(s.s, s.L, H + s.off);
@@ -595,7 +596,8 @@ void staging_fill(const Layout &L, const srp_batch_item *items, const BatchOut &
         D.fan_base = L.fan_base[k];
         D.grad_n = L.grad ? L.grad_n[k] : 0;   // the per-chunk size the partials were allocated with
         D.grad_part = L.grad ? reinterpret_cast<double *>(Dv + L.gpart_off[k]) : nullptr;
-        D.n_gslices = L.grad ? L.n_gslices[k] : 0;
+        D.n_slices = L.n_slices[k];
+        D.pslice = reinterpret_cast<SliceOut *>(Dv + L.pslice_off[k]);
         D.gslice = L.grad ? reinterpret_cast<double *>(Dv + L.gslice_off[k]) : nullptr;
         D.grad_out = (L.grad && bo.d_grad) ? bo.d_grad + k * bo.grad_stride : nullptr;
         D.hit_ids = (n == 1) ? bo.d_hit_ids : nullptr;
@@ -610,7 +612,6 @@ int enqueue(const Layout &L, char *Dv, const char *H, size_t copy_bytes, const B
     if (copied) HIPCHK(hipEventRecord(copied, stream));
     const EvalDesc *d_desc = reinterpret_cast<const EvalDesc *>(Dv + L.o_desc);
     const int64_t *d_cbase = reinterpret_cast<const int64_t *>(Dv + L.o_cbase);
-    const int64_t *d_pbase = reinterpret_cast<const int64_t *>(Dv + L.o_pbase);
     uint64_t *d_win = reinterpret_cast<uint64_t *>(Dv + L.o_win);
     PatchOut *d_patches = reinterpret_cast<PatchOut *>(Dv + L.o_patches);
     uint64_t *d_counts = L.count ? reinterpret_cast<uint64_t *>(Dv + L.o_counts) : nullptr;
@@ -624,11 +625,9 @@ int enqueue(const Layout &L, char *Dv, const char *H, size_t copy_bytes, const B
         if (rc) return rc;
         HIPCHK(hipEventRecord(ev.first, stream));
     }
-    const int64_t *d_fbase = nullptr;
     PatchOut *d_fan_out = nullptr;
     uint64_t *d_fan_counts = nullptr;
     if (L.total_fan_slots > 0) {
-        d_fbase = reinterpret_cast<const int64_t *>(Dv + L.o_fbase);
         d_fan_out = reinterpret_cast<PatchOut *>(Dv + L.o_fanout);
         d_fan_counts = L.count ? reinterpret_cast<uint64_t *>(Dv + L.o_fancnt) : nullptr;
     }
@@ -646,8 +645,8 @@ int enqueue(const Layout &L, char *Dv, const char *H, size_t copy_bytes, const B
         HIPCHK(hipEventRecord(ev.second, stream));
         g_prof.pairs.push_back(ev);
     }
-    e = launch_reduce(d_desc, d_pbase, (int)L.n, d_win, d_patches, d_counts, d_fbase, d_fan_out, d_fan_counts, L.count,
-                      L.grad, bo.d_out, stream);
+    e = launch_reduce(d_desc, (int)L.n, d_win, d_patches, d_counts, d_fan_out, d_fan_counts, L.count, L.grad, bo.d_out,
+                      stream);
     if (e) return fail(SRP_ERR_DEVICE, std::string("reduce kernel: ") + hipGetErrorString((hipError_t)e));
     if (bo.h_copy) HIPCHK(hipMemcpyAsync(bo.h_copy, bo.d_out, sizeof(srp_result) * L.n, hipMemcpyDeviceToHost, stream));
     return SRP_OK;

@@ -734,36 +734,48 @@ __global__ __launch_bounds__(WBLOCK) void k_window(const EvalDesc *__restrict__ 
     }
 }
 
-constexpr int RBLOCK = 1024;   // threads per block of the reduce kernel (one block per evaluation)
+constexpr int RBLOCK = 1024;   // threads per block of the reduction kernels
 
+// Reduction, first stage: block (q, e) sums the q-th of n_slices contiguous
+// ranges of evaluation e's patch partials (patches np q / Q .. np (q + 1) / Q),
+// then the same range of its fan pass slots, with per-thread strided sums,
+// wave butterflies and the waves in order; with GRAD also the q-th range of its
+// per-chunk gradient partials (the range split again into P contiguous slices,
+// P threads per component when the components fit the block several times,
+// each summed with eight interleaved accumulators, the slices added in order).
+// Q depends only on the evaluation's own size, so every result depends only on
+// the evaluation (and, for gradients, on the patches per chunk), not on the
+// batch around it.
 template <bool COUNT, bool GRAD>
-__global__ __launch_bounds__(RBLOCK) void k_reduce(const EvalDesc *__restrict__ descs,
-                                                const int64_t *__restrict__ patch_base,
-                                                const uint64_t *__restrict__ win,
+__global__ __launch_bounds__(RBLOCK) void k_slices(const EvalDesc *__restrict__ descs,
                                                 const PatchOut *__restrict__ patches,
                                                 const uint64_t *__restrict__ counts,
-                                                const int64_t *__restrict__ fan_base,
                                                 const PatchOut *__restrict__ fan_out,
-                                                const uint64_t *__restrict__ fan_counts, srp_result *out) {
-    const int e = blockIdx.x, tid = threadIdx.x, lane = tid & (WAVE - 1), wid = tid >> 6;
+                                                const uint64_t *__restrict__ fan_counts) {
+    const int q = blockIdx.x, e = blockIdx.y, tid = threadIdx.x, lane = tid & (WAVE - 1), wid = tid >> 6;
     const EvalDesc &D = descs[e];
-    // patch partials: per-thread strided sums, wave butterflies, waves in order
-    const int64_t c0 = patch_base[e], c1 = patch_base[e + 1];
+    const int Q = D.n_slices;
+    if (q >= Q) return;
     double f[6] = {0, 0, 0, 0, 0, 0};
     unsigned long long cn[5] = {0, 0, 0, 0, 0};
     uint32_t st = 0;
-    for (int64_t c = c0 + tid; c < c1; c += RBLOCK) {
-        const PatchOut &co = patches[c];
-        for (int k = 0; k < 6; ++k) f[k] += co.f[k];
-        cn[0] += co.hits;
-        cn[1] += co.sec;
-        cn[2] += co.sec_hits;
-        st |= co.flags;
-        if (COUNT) { cn[3] += counts[2 * c]; cn[4] += counts[2 * c + 1]; }
+    {
+        const int64_t np = D.n_patches;
+        const int64_t c0 = D.patch_base + np * q / Q, c1 = D.patch_base + np * (q + 1) / Q;
+        for (int64_t c = c0 + tid; c < c1; c += RBLOCK) {
+            const PatchOut &co = patches[c];
+            for (int k = 0; k < 6; ++k) f[k] += co.f[k];
+            cn[0] += co.hits;
+            cn[1] += co.sec;
+            cn[2] += co.sec_hits;
+            st |= co.flags;
+            if (COUNT) { cn[3] += counts[2 * c]; cn[4] += counts[2 * c + 1]; }
+        }
     }
-    // then the fan kernel's pass partials (diffuse rays), also in a fixed order
-    if (!GRAD && fan_base) {
-        const int64_t u0 = fan_base[e], u1 = fan_base[e + 1];
+    if (!GRAD && D.emit) {
+        // the fan pass slots (diffuse rays): B ceil(K / FAN_SLICE) per patch
+        const int64_t nf = D.n_patches * D.bounces * ((D.n_diffuse + FAN_SLICE - 1) / FAN_SLICE);
+        const int64_t u0 = D.fan_base + nf * q / Q, u1 = D.fan_base + nf * (q + 1) / Q;
         for (int64_t c = u0 + tid; c < u1; c += RBLOCK) {
             const PatchOut &co = fan_out[c];
             for (int k = 0; k < 6; ++k) f[k] += co.f[k];
@@ -787,6 +799,54 @@ __global__ __launch_bounds__(RBLOCK) void k_reduce(const EvalDesc *__restrict__ 
         ss[wid] = st;
     }
     __syncthreads();
+    if (tid == 0) {
+        SliceOut o = {};
+        for (int w = 0; w < RBLOCK / WAVE; ++w) {
+            for (int k = 0; k < 6; ++k) o.f[k] += sf[w][k];
+            for (int k = 0; k < 5; ++k) o.cnt[k] += sc[w][k];
+            o.flags |= ss[w];
+        }
+        D.pslice[q] = o;
+    }
+    if (GRAD) {
+        const int G = D.grad_n;
+        const double *gp = D.grad_part;
+        const int64_t NC = D.n_chunks, r0 = NC * q / Q, r1 = NC * (q + 1) / Q;
+        const int P = (G > 0 && G <= RBLOCK) ? RBLOCK / G : 1;
+        __shared__ double sl[RBLOCK];
+        auto slice_sum = [&](int i, int64_t a0, int64_t a1) {
+            double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            int64_t c = a0;
+            for (; c + 8 <= a1; c += 8)
+                for (int u = 0; u < 8; ++u) a[u] += gp[(size_t)(c + u) * G + i];
+            for (; c < a1; ++c) a[0] += gp[(size_t)c * G + i];
+            return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+        };
+        double *gs = D.gslice + (size_t)q * G;
+        if (P > 1) {
+            const int i = tid % G, p = tid / G;
+            if (p < P) sl[p * G + i] = slice_sum(i, r0 + (r1 - r0) * p / P, r0 + (r1 - r0) * (p + 1) / P);
+            __syncthreads();
+            for (int j = tid; j < G; j += RBLOCK) {
+                double t = 0.0;
+                for (int k = 0; k < P; ++k) t += sl[k * G + j];
+                gs[j] = t;
+            }
+        } else {
+            for (int j = tid; j < G; j += RBLOCK) gs[j] = slice_sum(j, r0, r1);
+        }
+    }
+}
+
+// Reduction, second stage (one block per evaluation): the first stage's
+// range sums added in order, scaled to newtons; with GRAD the gradient range
+// sums likewise, then assembled per material and hinge DOF.
+template <bool COUNT, bool GRAD>
+__global__ __launch_bounds__(RBLOCK) void k_reduce(const EvalDesc *__restrict__ descs,
+                                                const uint64_t *__restrict__ win, srp_result *out) {
+    const int e = blockIdx.x, tid = threadIdx.x;
+    const EvalDesc &D = descs[e];
+    const int Q = D.n_slices;
     const uint64_t *W = win + (size_t)e * WIN_STRIDE;
     const double umin = dec_f64(W[0]), umax = -dec_f64(W[1]);
     const double vmin = dec_f64(W[2]), vmax = -dec_f64(W[3]);
@@ -797,10 +857,11 @@ __global__ __launch_bounds__(RBLOCK) void k_reduce(const EvalDesc *__restrict__ 
         double F[6] = {0, 0, 0, 0, 0, 0};
         unsigned long long N[5] = {0, 0, 0, 0, 0};
         uint32_t S = 0;
-        for (int w = 0; w < RBLOCK / WAVE; ++w) {
-            for (int k = 0; k < 6; ++k) F[k] += sf[w][k];
-            for (int k = 0; k < 5; ++k) N[k] += sc[w][k];
-            S |= ss[w];
+        for (int q = 0; q < Q; ++q) {
+            const SliceOut &o = D.pslice[q];
+            for (int k = 0; k < 6; ++k) F[k] += o.f[k];
+            for (int k = 0; k < 5; ++k) N[k] += o.cnt[k];
+            S |= o.flags;
         }
         srp_result r;
         for (int k = 0; k < 3; ++k) {
@@ -818,13 +879,11 @@ __global__ __launch_bounds__(RBLOCK) void k_reduce(const EvalDesc *__restrict__ 
         out[e] = r;
     }
     if (GRAD) {
-        // the range sums of the chunk partials (k_grad_slices), added in order,
-        // then assembled
         const int G = D.grad_n, K = D.n_nodes, M = D.n_mats, J = D.n_dof;
         __shared__ double sg[MAX_GRAD_SLOTS];
         for (int j = tid; j < G; j += RBLOCK) {
             double t = 0.0;
-            for (int q = 0; q < D.n_gslices; ++q) t += D.gslice[(size_t)q * G + j];
+            for (int q = 0; q < Q; ++q) t += D.gslice[(size_t)q * G + j];
             sg[j] = t;
         }
         __syncthreads();
@@ -856,45 +915,6 @@ __global__ __launch_bounds__(RBLOCK) void k_reduce(const EvalDesc *__restrict__ 
             const bool has_dir = G >= 9 * K + 6 * M + 9;
             for (int i = tid; i < 9; i += RBLOCK) g[6 * M + 3 * J + i] = has_dir ? scale * sg[9 * K + 6 * M + i] : 0.0;
         }
-    }
-}
-
-// Gradient partials, first stage: block (q, e) sums the chunk partials of
-// evaluation e in the q-th of n_gslices contiguous chunk ranges (ranges
-// NC q / Q .. NC (q + 1) / Q).  Inside a block the range is split again into P
-// contiguous slices (P threads per component when the components fit the
-// block several times), each summed with eight interleaved accumulators, and
-// the slices are added in order: the result depends only on the batch layout.
-__global__ __launch_bounds__(RBLOCK) void k_grad_slices(const EvalDesc *__restrict__ descs) {
-    const int q = blockIdx.x, e = blockIdx.y, tid = threadIdx.x;
-    const EvalDesc &D = descs[e];
-    const int Q = D.n_gslices;
-    if (q >= Q) return;
-    const int G = D.grad_n;
-    const double *gp = D.grad_part;
-    const int64_t NC = D.n_chunks, r0 = NC * q / Q, r1 = NC * (q + 1) / Q;
-    const int P = (G > 0 && G <= RBLOCK) ? RBLOCK / G : 1;
-    __shared__ double sl[RBLOCK];
-    auto slice_sum = [&](int i, int64_t c0, int64_t c1) {
-        double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        int64_t c = c0;
-        for (; c + 8 <= c1; c += 8)
-            for (int u = 0; u < 8; ++u) a[u] += gp[(size_t)(c + u) * G + i];
-        for (; c < c1; ++c) a[0] += gp[(size_t)c * G + i];
-        return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
-    };
-    double *out = D.gslice + (size_t)q * G;
-    if (P > 1) {
-        const int i = tid % G, p = tid / G;
-        if (p < P) sl[p * G + i] = slice_sum(i, r0 + (r1 - r0) * p / P, r0 + (r1 - r0) * (p + 1) / P);
-        __syncthreads();
-        for (int j = tid; j < G; j += RBLOCK) {
-            double t = 0.0;
-            for (int k = 0; k < P; ++k) t += sl[k * G + j];
-            out[j] = t;
-        }
-    } else {
-        for (int j = tid; j < G; j += RBLOCK) out[j] = slice_sum(j, r0, r1);
     }
 }
 
@@ -955,17 +975,18 @@ int launch_fans(const EvalDesc *d_desc, const int64_t *d_unit_base, int n_evals,
     return check(hipGetLastError());
 }
 
-int launch_reduce(const EvalDesc *d_desc, const int64_t *d_tile_base, int n_evals, const uint64_t *d_win,
-                  const PatchOut *d_chunks, const uint64_t *d_counts, const int64_t *d_fan_base,
-                  const PatchOut *d_fan_out, const uint64_t *d_fan_counts, bool count, bool grad, void *d_out,
-                  void *stream) {
+int launch_reduce(const EvalDesc *d_desc, int n_evals, const uint64_t *d_win, const PatchOut *d_patches,
+                  const uint64_t *d_counts, const PatchOut *d_fan_out, const uint64_t *d_fan_counts, bool count,
+                  bool grad, void *d_out, void *stream) {
     if (n_evals <= 0) return 0;
     hipStream_t s = (hipStream_t)stream;
     srp_result *out = (srp_result *)d_out;
-    if (grad) hipLaunchKernelGGL(k_grad_slices, dim3(MAX_GSLICES, n_evals), dim3(RBLOCK), 0, s, d_desc);
-#define SRP_LAUNCH_REDUCE(C, G)                                                                                  \
-    hipLaunchKernelGGL((k_reduce<C, G>), dim3(n_evals), dim3(RBLOCK), 0, s, d_desc, d_tile_base, d_win, d_chunks, \
-                       d_counts, d_fan_base, d_fan_out, d_fan_counts, out)
+#define SRP_LAUNCH_REDUCE(C, G)                                                                                 \
+    do {                                                                                                        \
+        hipLaunchKernelGGL((k_slices<C, G>), dim3(MAX_SLICES, n_evals), dim3(RBLOCK), 0, s, d_desc, d_patches,  \
+                           d_counts, d_fan_out, d_fan_counts);                                                  \
+        hipLaunchKernelGGL((k_reduce<C, G>), dim3(n_evals), dim3(RBLOCK), 0, s, d_desc, d_win, out);            \
+    } while (0)
     if (count && grad) SRP_LAUNCH_REDUCE(true, true);
     else if (count) SRP_LAUNCH_REDUCE(true, false);
     else if (grad) SRP_LAUNCH_REDUCE(false, true);

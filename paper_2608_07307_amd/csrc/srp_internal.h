@@ -110,9 +110,20 @@ static_assert(sizeof(FanRec) == 32, "FanRec is 32 bytes");
 constexpr int FAN_SLICE = 4;
 static_assert(SRP_MAX_BOUNCES == 4, "fan emitter masks: four generations");
 // Most work units per patch of the fan kernel.
-// Most gradient range sums per evaluation (separate blocks, summed in order).
-constexpr int MAX_GSLICES = 16;
+// Most range sums per evaluation in the reduction's first stage (separate
+// blocks, added in order by the second).
+constexpr int MAX_SLICES = 16;
 constexpr int MAX_FAN_PARTS = 8;
+
+// A range sum of an evaluation's patch (and fan) partials: force and torque
+// (FP64, before scaling), hit and test counts, status flags.
+struct alignas(16) SliceOut {
+    double f[6];
+    uint64_t cnt[5];   // primary hits, secondary rays, secondary hits, box tests, triangle tests
+    uint32_t flags;
+    uint32_t pad_;
+};
+static_assert(sizeof(SliceOut) == 96, "SliceOut is 96 bytes");
 
 // One evaluation, as the kernels see it.
 struct alignas(64) EvalDesc {
@@ -156,9 +167,10 @@ struct alignas(64) EvalDesc {
     uint64_t *emit_mask;    // which of them are filled: n_patches x bounces masks of 64 lanes
     int64_t unit_base;      // first fan work unit of this evaluation (n_patches x n_parts units)
     int32_t n_parts;        // fan work units per patch (V); 0 without fans
-    int32_t n_gslices;      // gradient: contiguous chunk ranges summed by separate blocks
+    int32_t n_slices;       // reduction: contiguous ranges summed by separate blocks (1..MAX_SLICES)
     int64_t fan_base;       // first fan partial slot (n_patches x bounces x ceil(n_diffuse / FAN_SLICE))
-    double *gslice;         // gradient: n_gslices x grad_n range sums
+    double *gslice;         // gradient: n_slices x grad_n range sums
+    SliceOut *pslice;       // n_slices range sums of the patch (and fan) partials
 };
 
 // The host writes these records and the kernels read them: both compilation
@@ -205,9 +217,10 @@ static_assert(offsetof(EvalDesc, emit) == 312, "EvalDesc layout");
 static_assert(offsetof(EvalDesc, emit_mask) == 320, "EvalDesc layout");
 static_assert(offsetof(EvalDesc, unit_base) == 328, "EvalDesc layout");
 static_assert(offsetof(EvalDesc, n_parts) == 336, "EvalDesc layout");
-static_assert(offsetof(EvalDesc, n_gslices) == 340, "EvalDesc layout");
+static_assert(offsetof(EvalDesc, n_slices) == 340, "EvalDesc layout");
 static_assert(offsetof(EvalDesc, fan_base) == 344, "EvalDesc layout");
 static_assert(offsetof(EvalDesc, gslice) == 352, "EvalDesc layout");
+static_assert(offsetof(EvalDesc, pslice) == 360, "EvalDesc layout");
 static_assert(sizeof(PatchOut) == 64, "PatchOut layout");
 static_assert(offsetof(PatchOut, f) == 0, "PatchOut layout");
 static_assert(offsetof(PatchOut, hits) == 48, "PatchOut layout");
@@ -258,10 +271,9 @@ int launch_trace(const EvalDesc *d_desc, const int64_t *d_chunk_base, int n_eval
 int launch_fans(const EvalDesc *d_desc, const int64_t *d_unit_base, int n_evals, const uint64_t *d_win,
                 int64_t total_units, int per_claim, uint32_t *d_queue, uint32_t *d_spill, PatchOut *d_fan_out,
                 uint64_t *d_fan_counts, bool count, int grid_blocks, void *stream);
-int launch_reduce(const EvalDesc *d_desc, const int64_t *d_patch_base, int n_evals,
-                  const uint64_t *d_win, const PatchOut *d_patches, const uint64_t *d_counts,
-                  const int64_t *d_fan_base, const PatchOut *d_fan_out, const uint64_t *d_fan_counts,
-                  bool count, bool grad, void *d_out, void *stream);
+int launch_reduce(const EvalDesc *d_desc, int n_evals, const uint64_t *d_win, const PatchOut *d_patches,
+                  const uint64_t *d_counts, const PatchOut *d_fan_out, const uint64_t *d_fan_counts, bool count,
+                  bool grad, void *d_out, void *stream);
 // Resident blocks per compute unit of the trace kernel variant.
 int trace_blocks_per_cu(bool count, bool grad, bool dir, int lds_grad_doubles);
 // Resident blocks per compute unit of the fan kernel variant.
