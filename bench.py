@@ -34,10 +34,12 @@ BOX_OPS, TRI_OPS = 10, 30             # algorithmic lane-ops per ray-box / ray-t
 TRAFFIC = os.path.join(ROOT, "profiles", "k_trace_grad_traffic.json")
 
 
-def measured_traffic():
+def measured_traffic(schedule):
     """HBM bytes per launch of the adjoint trace kernel from the committed
     FETCH_SIZE / WRITE_SIZE counter runs, or None when the kernel sources have
-    changed since those counters were taken."""
+    changed since those counters were taken or this run's schedule (patches per
+    chunk, blocks per CU: the gradient partials are per chunk) is not the one
+    they were taken with."""
     import hashlib
     try:
         with open(TRAFFIC) as f:
@@ -46,7 +48,9 @@ def measured_traffic():
         for src in rec["sources"]:
             with open(os.path.join(ROOT, src), "rb") as f:
                 h.update(f.read())
-        return rec["traffic_bytes_per_launch"] if h.hexdigest() == rec["sources_sha256"] else None
+        if h.hexdigest() != rec["sources_sha256"] or rec.get("schedule") != schedule:
+            return None
+        return rec["traffic_bytes_per_launch"]
     except (OSError, KeyError, ValueError):
         return None
 
@@ -206,6 +210,16 @@ def main():
     d_dt = (t1 - t0) / args.steps
     d_kern = d_ms / 1e3 / max(d_launches, 1)
     assert (srp.results_to_numpy(out)["status"] == 0).all()
+    # one evaluation at a time, as a propagator calls it (srp_eval: host round trip
+    # and result readback included; the scene at the first attitude's angles)
+    scene.set_angles(angles[0])
+    for k in range(3):
+        srp.eval(scene, dirs[k], dN, bounces=dB, diffuse=dK)
+    n_single = min(E, 32)
+    t0 = time.perf_counter()
+    for k in range(n_single):
+        srp.eval(scene, dirs[k], dN, bounces=dB, diffuse=dK)
+    single_ms = (time.perf_counter() - t0) / n_single * 1e3
     paper_setting = {
         "workload": f"same mesh and {E} attitudes, {dN}x{dN} rays, {dB} secondary levels, "
                     f"{dK} diffuse rays per emitting hit, batched forward",
@@ -214,8 +228,10 @@ def main():
         "rays_per_batch": d_rays,
         "kernel_ms": round(d_kern * 1e3, 4),
         "lane_op_frac": round(d_work / d_kern / PEAK_LANE_OPS, 4),
+        "single_eval_ms": round(single_ms, 4),
     }
-    log(f"paper setting (N={dN}, B={dB}, K={dK}): {E / d_dt:.1f} evals/s, {d_rays / d_dt / 1e9:.2f} Grays/s")
+    log(f"paper setting (N={dN}, B={dB}, K={dK}): {E / d_dt:.1f} evals/s, {d_rays / d_dt / 1e9:.2f} Grays/s; "
+        f"one evaluation {single_ms:.3f} ms")
 
     # SPAD (precomputed table + interpolation) against direct ray tracing during
     # propagation: the paper's 20 x 10 grids (plain and shifted by 5 deg) built at
@@ -374,7 +390,7 @@ def main():
             "peak": round(peak, 4),
             "unit": "Tlane-op/s",
             "frac": round(achieved / peak, 4),
-            "traffic": measured_traffic(),
+            "traffic": measured_traffic({"patches_per_chunk": tune[0], "blocks_per_cu": tune[1]}),
             "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "kernel": "k_trace<GRAD> (forward + adjoint)",
             "work_per_launch": {"box_tests": n_box, "tri_tests": n_tri,
