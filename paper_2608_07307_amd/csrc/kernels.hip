@@ -42,10 +42,29 @@ constexpr int HWREG_XCC_ID = 20;   // hardware register holding the wave's XCD (
 #endif
 constexpr int MAX_CHAIN = SRP_MAX_BOUNCES + 1;
 
+// x from another lane of the same 16-lane row (data-parallel primitive move,
+// one per 32-bit half).  Every lane of the wave must be active.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double readlane_f64(double x, int lane) {
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), lane),
+                            __builtin_amdgcn_readlane(__double2loint(x), lane));
+}
+
+// The sum of x over the wave's 64 lanes, returned to every lane, in a fixed
+// order: quads (lane ^ 1, then lane ^ 2), the four quads of each row (row
+// rotations by 4 and 8), then the four rows' totals as read from their first
+// lanes, ((r0 + r1) + (r2 + r3)).  Every lane of the wave must be active.
 __device__ __forceinline__ double wave_sum(double x) {
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m, WAVE);
-    return x;
+    x += dpp_f64<0xB1>(x);    // quad_perm (1, 0, 3, 2)
+    x += dpp_f64<0x4E>(x);    // quad_perm (2, 3, 0, 1)
+    x += dpp_f64<0x124>(x);   // row_ror 4
+    x += dpp_f64<0x128>(x);   // row_ror 8
+    return (readlane_f64(x, 0) + readlane_f64(x, 16)) + (readlane_f64(x, 32) + readlane_f64(x, 48));
 }
 
 // The adjoint keeps one word per hit of a lane's chain in LDS: the triangle's
