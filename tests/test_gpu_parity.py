@@ -143,6 +143,46 @@ def test_batch_matches_single_and_is_deterministic(srp):
     assert out.tobytes() == out2.tobytes()
 
 
+def test_back_to_back_batches_on_different_streams(srp):
+    """Consecutive launches through the library's shared workspace on three
+    streams, with no synchronisation between them: the host prepares each
+    launch while the previous one runs and the library orders it after that
+    one on the device, so every result (forward and adjoint) is bitwise its
+    reference taken alone."""
+    import torch
+    mesh = synth.procedural_sized(23, 4000)
+    sc = srp.Scene(mesh)
+    dirs = synth.random_dirs(2300, 24)
+
+    def batch(k0, n, B):
+        return [(sc, np.full(mesh.n_dof, 0.05 * (k % 5) - 0.1), srp.params(dirs[k], n, B)) for k in range(k0, k0 + 8)]
+
+    fa, fb, ga = batch(0, 160, 2), batch(8, 96, 1), batch(16, 128, 2)
+    ref_a = srp.results_to_numpy(srp.eval_batch(fa)).copy()
+    ref_b = srp.results_to_numpy(srp.eval_batch(fb)).copy()
+    r, g = srp.eval_grad_batch(ga)
+    ref_g, ref_gr = srp.results_to_numpy(r).copy(), g.cpu().numpy().copy()
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream() for _ in range(3)]
+    outs = []
+    for rep in range(3):
+        oa = torch.empty(len(fa) * srp.RESULT_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+        ob = torch.empty_like(oa)
+        og = torch.empty_like(oa)
+        gg = torch.zeros_like(g)
+        torch.cuda.synchronize()
+        srp.eval_batch(fa, oa, streams[0])
+        srp.eval_batch(fb, ob, streams[1])
+        srp.eval_grad_batch(ga, og, gg, streams[2])
+        outs.append((oa, ob, og, gg))
+    torch.cuda.synchronize()
+    for oa, ob, og, gg in outs:
+        assert srp.results_to_numpy(oa).tobytes() == ref_a.tobytes()
+        assert srp.results_to_numpy(ob).tobytes() == ref_b.tobytes()
+        assert srp.results_to_numpy(og).tobytes() == ref_g.tobytes()
+        assert gg.cpu().numpy().tobytes() == ref_gr.tobytes()
+
+
 @pytest.mark.parametrize("n", [1, 2, 17, 100, 257])
 def test_ragged_and_tiny_grids(srp, n):
     """Grid sizes that are not multiples of the 16-pixel tile, down to one ray."""
