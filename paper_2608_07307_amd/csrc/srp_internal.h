@@ -26,7 +26,6 @@ constexpr uint32_t REF_BLAS_NODE = 0u;
 constexpr uint32_t REF_BLAS_LEAF = 1u;
 constexpr uint32_t REF_TLAS_NODE = 2u;
 constexpr uint32_t REF_TLAS_LEAF = 3u;
-constexpr uint32_t REF_EXIT = 0xFFFFFFFEu;  // stack marker: leave the current instance
 constexpr uint32_t REF_NONE = 0xFFFFFFFFu;
 constexpr int LEAF_MAX = 8;
 constexpr int STACK_DEPTH = 64;             // per-lane traversal stack entries (the build checks each hierarchy's worst case)
