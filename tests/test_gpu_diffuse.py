@@ -176,6 +176,33 @@ def test_fan_work_split_gives_the_same_bits(srp):
             assert r[k]["force"].tobytes() == ref[k]["force"].tobytes(), (E, k)
 
 
+def test_inline_fans_in_a_mixed_batch(srp):
+    """A batch big enough for the trace kernel to trace the fans itself, mixing
+    two scenes, K in {0, 1, 5, 16, 64} and B in {0, 1, 2, 4}: every item is
+    bitwise its single evaluation (which traces the fans in a separate
+    launch), counts included."""
+    m1, m2 = synth.box_wing(), synth.procedural_sized(26, 3000)
+    s1, s2 = srp.Scene(m1), srp.Scene(m2)
+    dirs = synth.random_dirs(2601, 16)
+    Ks, Bs = (0, 1, 5, 16, 64), (0, 1, 2, 4)
+    specs = []
+    for k in range(16):
+        sc, m = (s1, m1) if k % 2 == 0 else (s2, m2)
+        ang = np.full(m.n_dof, 0.2 * (k % 3) - 0.2)
+        specs.append((sc, m, ang, 256, Bs[k % 4], Ks[k % 5]))
+    entries = [(sc, ang, srp.params(dirs[k], n, B, count=True, diffuse=K))
+               for k, (sc, m, ang, n, B, K) in enumerate(specs)]
+    r = srp.results_to_numpy(srp.eval_batch(entries)).copy()
+    assert (r["status"] == 0).all()
+    for k, (sc, m, ang, n, B, K) in enumerate(specs):
+        sc.set_angles(ang)
+        g = srp.eval(sc, dirs[k], n, bounces=B, count=True, diffuse=K)
+        assert g["force"].tobytes() == r[k]["force"].tobytes(), k
+        assert g["torque"].tobytes() == r[k]["torque"].tobytes(), k
+        for f in ("n_hits", "n_secondary", "n_secondary_hits", "n_box_tests", "n_tri_tests"):
+            assert g[f] == r[k][f], (k, f)
+
+
 def test_paper_setting_batch(srp):
     """The ~50k-triangle spacecraft at the paper's ray-traced setting (256^2,
     two secondary levels, 16 diffuse rays), 64 attitudes in one launch: every
