@@ -249,7 +249,8 @@ int srp_plan_destroy(srp_plan *plan);
 int srp_set_schedule(int32_t patches_per_chunk, int32_t blocks_per_cu);
 
 /* Times the batch under candidate schedules (patches per chunk 1..64 in powers
- * of two, full and half occupancy) and keeps the fastest for batches of the
+ * of two, full and half occupancy; the best of four timed runs after a
+ * warm-up each) and keeps the fastest for batches of the
  * same size class (total primary rays to a power of two, bounce count,
  * gradient flag).  Outputs the choice and its time (ms); any output pointer
  * may be NULL.  Blocks.  Errors as srp_eval_batch. */

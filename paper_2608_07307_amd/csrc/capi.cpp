@@ -1202,7 +1202,7 @@ int srp_autotune(const srp_batch_item *items, int64_t n_items, int32_t flags, in
     if (cands.empty()) cands.push_back(pick_schedule(items, n_items, grad, total_patches, occ, mg));
     for (const Schedule &sc : cands) {
         double tmin = INFINITY;
-        for (int rep = 0; rep < 3 && rc == 0; ++rep) {
+        for (int rep = 0; rep < 5 && rc == 0; ++rep) {   // one warm-up, the best of four
             if ((rc = run_batch(items, n_items, grad, bo, g_ws.stream, sc))) break;
             HIPCHK(hipStreamSynchronize(g_ws.stream));
             g_ws.pending = false;
