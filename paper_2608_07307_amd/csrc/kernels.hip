@@ -55,6 +55,39 @@ __device__ __forceinline__ double readlane_f64(double x, int lane) {
                             __builtin_amdgcn_readlane(__double2loint(x), lane));
 }
 
+// Wave-wide sum, OR and maximum of 32-bit integers, returned to every lane
+// (quads, then rows by rotation, then the rows' first lanes).  Every lane of
+// the wave must be active.
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, 0xF, 0xF, false);
+}
+__device__ __forceinline__ uint32_t rows_u32(uint32_t x, int k) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)x, k);
+}
+__device__ __forceinline__ uint32_t wave_add_u32(uint32_t x) {
+    x += dpp_u32<0xB1>(x);
+    x += dpp_u32<0x4E>(x);
+    x += dpp_u32<0x124>(x);
+    x += dpp_u32<0x128>(x);
+    return rows_u32(x, 0) + rows_u32(x, 16) + rows_u32(x, 32) + rows_u32(x, 48);
+}
+__device__ __forceinline__ uint32_t wave_or_u32(uint32_t x) {
+    x |= dpp_u32<0xB1>(x);
+    x |= dpp_u32<0x4E>(x);
+    x |= dpp_u32<0x124>(x);
+    x |= dpp_u32<0x128>(x);
+    return rows_u32(x, 0) | rows_u32(x, 16) | rows_u32(x, 32) | rows_u32(x, 48);
+}
+__device__ __forceinline__ int wave_max_i32(int x) {
+    x = max(x, (int)dpp_u32<0xB1>((uint32_t)x));
+    x = max(x, (int)dpp_u32<0x4E>((uint32_t)x));
+    x = max(x, (int)dpp_u32<0x124>((uint32_t)x));
+    x = max(x, (int)dpp_u32<0x128>((uint32_t)x));
+    return max(max((int)rows_u32((uint32_t)x, 0), (int)rows_u32((uint32_t)x, 16)),
+               max((int)rows_u32((uint32_t)x, 32), (int)rows_u32((uint32_t)x, 48)));
+}
+
 // The sum of x over the wave's 64 lanes, returned to every lane, in a fixed
 // order: quads (lane ^ 1, then lane ^ 2), the four quads of each row (row
 // rotations by 4 and 8), then the four rows' totals as read from their first
@@ -302,14 +335,12 @@ __device__ __forceinline__ void fan_passes(const EvalDesc &D, const TraceCtx &TC
                 }
             }
             for (int k = 0; k < 6; ++k) tot[k] = wave_sum(lacc[k * BLOCK]);
-            for (int m = 32; m >= 1; m >>= 1) {
-                rays += __shfl_xor(rays, m, WAVE);
-                hits += __shfl_xor(hits, m, WAVE);
-                status |= __shfl_xor(status, m, WAVE);
-                if (COUNT) {
-                    nbox += __shfl_xor(nbox, m, WAVE);
-                    ntri += __shfl_xor(ntri, m, WAVE);
-                }
+            rays = wave_add_u32(rays);
+            hits = wave_add_u32(hits);
+            status = wave_or_u32(status);
+            if (COUNT) {
+                nbox = wave_add_u32(nbox);
+                ntri = wave_add_u32(ntri);
             }
         }
         if (lane == 0) {
@@ -524,8 +555,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(GRAD ? SR
                     // Reverse sweep over the chain at fixed visibility.
                     //   A  = d(sum of later contributions)/d(incoming direction)   (3x3)
                     //   Tn = later contributions divided by the weight after this hit
-                    int Kmax = K;
-                    for (int m = 32; m >= 1; m >>= 1) Kmax = max(Kmax, __shfl_xor(Kmax, m, WAVE));
+                    const int Kmax = wave_max_i32(K);
                     float A[9], Tn[3] = {0, 0, 0};
                     float n0[3] = {0, 0, 0}, c0 = 1.0f;   // the primary hit's normal and cosine (DIR)
                     m3_zero(A);
@@ -610,18 +640,16 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(GRAD ? SR
                 }
             }
 
-            // the patch's sums: wave butterfly (every lane ends with the total), lane 0
+            // the patch's sums: wave reductions (every lane ends with the total), lane 0
             // stores; a patch without a hit has zero sums (secondary hits need a primary)
             double tot[6] = {0, 0, 0, 0, 0, 0};
             if (__ballot((hcnt & 1023u) != 0))
                 for (int k = 0; k < 6; ++k) tot[k] = wave_sum(lacc[k * BLOCK]);
-            for (int m = 32; m >= 1; m >>= 1) {
-                hcnt += __shfl_xor(hcnt, m, WAVE);
-                status |= __shfl_xor(status, m, WAVE);
-                if (COUNT) {
-                    nbox += __shfl_xor(nbox, m, WAVE);
-                    ntri += __shfl_xor(ntri, m, WAVE);
-                }
+            hcnt = wave_add_u32(hcnt);
+            status = wave_or_u32(status);
+            if (COUNT) {
+                nbox = wave_add_u32(nbox);
+                ntri = wave_add_u32(ntri);
             }
             const uint32_t cnts[6] = {hcnt & 1023u, (hcnt >> 10) & 1023u, hcnt >> 20, nbox, ntri, status};
             if (lane == 0) {
