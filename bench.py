@@ -55,6 +55,77 @@ def measured_traffic(schedule):
         return None
 
 
+def _log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def time_config(srp, torch, name, stream, steps):
+    """Throughput of one of the other batch workloads: the box-wing at 128^2
+    (c1, 1,024 attitudes), the 32,768-evaluation SPAD table at 512^2 (c3), the
+    uneven 64-scene batch (c4), the 1M-triangle batch of 256 attitudes at
+    2048^2 with the adjoint (c5).  Autotuned, one warm-up call, `steps` timed
+    calls (a call runs as consecutive sub-batches when its workspace would
+    pass 2 GB); ray and test counts from one counting call."""
+    import synth
+    grad = False
+    if name == "c1":
+        mesh = synth.box_wing()
+        sc = srp.Scene(mesh)
+        E, n, B = 1024, 128, 0
+        dirs = synth.fibonacci_dirs(E)
+        rng = np.random.default_rng(1001)
+        angles = rng.uniform(-np.pi / 2, np.pi / 2, size=(E, mesh.n_dof))
+        items = [(sc, angles[k], dirs[k], n) for k in range(E)]
+        desc = f"box-wing ({mesh.n_tris} tris), {E} attitudes, {n}x{n} rays, B={B}"
+    elif name == "c3":
+        mesh, dirs, angles, n, B = synth.c3_spad()
+        sc = srp.Scene(mesh)
+        items = [(sc, angles[k], dirs[k], n) for k in range(len(dirs))]
+        desc = f"SPAD table: {mesh.n_tris}-triangle spacecraft, {len(dirs)} attitudes, {n}x{n} rays, B={B}"
+    elif name == "c4":
+        specs, B = synth.c4_uneven()
+        scenes = [srp.Scene(m) for m, _, _, _ in specs]
+        items = [(scenes[k], a, s_, n_) for k, (m, a, s_, n_) in enumerate(specs)]
+        tris = [m.n_tris for m, _, _, _ in specs]
+        desc = (f"uneven batch: {len(specs)} scenes of {min(tris)}..{max(tris)} triangles, "
+                f"grids {min(x[3] for x in specs)}..{max(x[3] for x in specs)}, B={B}")
+    elif name == "c5":
+        mesh, dirs, angles, n, B = synth.c5_batch()
+        sc = srp.Scene(mesh)
+        items = [(sc, angles[k], dirs[k], n) for k in range(len(dirs))]
+        grad = True
+        desc = (f"greebled spacecraft ({mesh.n_tris} tris, {mesh.n_dof} hinge DOF), {len(dirs)} attitudes, "
+                f"{n}x{n} rays, B={B}, forward + adjoint")
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    entries = [(s_, a, srp.params(d, n_, B)) for s_, a, d, n_ in items]
+    E = len(entries)
+    cnt = srp.results_to_numpy(srp.eval_batch([(s_, a, srp.params(d, n_, B, count=True)) for s_, a, d, n_ in items]))
+    rays = int(cnt["n_rays"].sum() + cnt["n_secondary"].sum())
+    work = BOX_OPS * int(cnt["n_box_tests"].sum()) + TRI_OPS * int(cnt["n_tri_tests"].sum())
+    tune = srp.autotune(entries, grad=grad)
+    run = (lambda: srp.eval_grad_batch(entries, None, None, stream)) if grad else (lambda: srp.eval_batch(entries, None, stream))
+    out = run()
+    torch.cuda.synchronize()
+    srp.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = run()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    ms, launches = srp.profile_read()
+    srp.profile(False)
+    res = srp.results_to_numpy(out[0] if grad else out)
+    assert (res["status"] == 0).all()
+    kern = ms / 1e3 / steps   # the ray-tracing kernels of one call (of all its sub-batches)
+    _log(f"{name}: {E / dt:.1f} evals/s, {rays / dt / 1e9:.2f} Grays/s, kernels {kern * 1e3:.2f} ms of "
+        f"{dt * 1e3:.2f} ms per call ({launches // steps} launches)")
+    return {"workload": desc, "evals": E, "evals_per_s": round(E / dt, 2), "grays_per_s": round(rays / dt / 1e9, 3),
+            "rays_per_call": rays, "ms_per_call": round(dt * 1e3, 3), "kernel_ms": round(kern * 1e3, 3),
+            "launches_per_call": launches // steps, "lane_op_frac": round(work / kern / PEAK_LANE_OPS, 4),
+            "schedule": {"patches_per_chunk": tune[0], "blocks_per_cu": tune[1]}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -73,6 +144,8 @@ def main():
     ap.add_argument("--p2", type=int, default=1,
                     help="20-revolution propagation timing (0: skip, 1: fixed panels, 2: also tracking panels)")
     ap.add_argument("--p2-revs", type=int, default=20)
+    ap.add_argument("--configs", default="",
+                    help="also time these other workloads, comma-separated from c1,c3,c4,c5 (off by default)")
     ap.add_argument("--p2-rtol", type=float, default=1e-9)
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="also run a device copy of this many MiB (calibrates memory counters)")
@@ -400,6 +473,9 @@ def main():
         },
         "cpu_baseline": cpu,
     }
+    if args.configs:
+        line["configs"] = {c: time_config(srp, torch, c, stream, max(1, min(args.steps, 3)))
+                           for c in args.configs.split(",") if c}
     print(json.dumps(line), flush=True)
 
 
