@@ -34,21 +34,32 @@ BOX_OPS, TRI_OPS = 10, 30             # algorithmic lane-ops per ray-box / ray-t
 TRAFFIC = os.path.join(ROOT, "profiles", "k_trace_grad_traffic.json")
 
 
+def source_digest(paths):
+    """SHA-256 of the code in `paths` (relative to the repository root) with
+    // comments, trailing blanks and empty lines removed: a comment edit does
+    not invalidate counters taken on the same code."""
+    import hashlib
+    import re
+    h = hashlib.sha256()
+    for src in paths:
+        with open(os.path.join(ROOT, src), encoding="utf-8") as f:
+            for line in f:
+                code = re.sub(r"//.*$", "", line).rstrip()
+                if code:
+                    h.update(code.encode() + b"\n")
+    return h.hexdigest()
+
+
 def measured_traffic(schedule):
     """HBM bytes per launch of the adjoint trace kernel from the committed
     FETCH_SIZE / WRITE_SIZE counter runs, or None when the kernel sources have
     changed since those counters were taken or this run's schedule (patches per
     chunk, blocks per CU: the gradient partials are per chunk) is not the one
     they were taken with."""
-    import hashlib
     try:
         with open(TRAFFIC) as f:
             rec = json.load(f)
-        h = hashlib.sha256()
-        for src in rec["sources"]:
-            with open(os.path.join(ROOT, src), "rb") as f:
-                h.update(f.read())
-        if h.hexdigest() != rec["sources_sha256"] or rec.get("schedule") != schedule:
+        if source_digest(rec["sources"]) != rec["code_sha256"] or rec.get("schedule") != schedule:
             return None
         return rec["traffic_bytes_per_launch"]
     except (OSError, KeyError, ValueError):

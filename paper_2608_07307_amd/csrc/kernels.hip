@@ -10,12 +10,19 @@
 //             the kinematic-tree nodes, rigid instance transform, bottom level
 //             in rest-pose coordinates) with a per-lane stack (LDS ring, global
 //             spill); watertight FP32 triangle test; momentum law at each hit;
-//             specular secondary rays iteratively; FP64 per-lane sums, wave
-//             butterfly, one partial per patch (no floating-point atomics, so
-//             results do not depend on scheduling).  The GRAD variant also
-//             differentiates each ray's hit chain at fixed visibility.
-//   k_reduce  per evaluation, sums its patch partials in a fixed order, scales by
-//             P * A_pix and writes the srp_result (and the gradients).
+//             specular secondary rays iteratively; FP64 per-lane sums, a wave
+//             reduction, one partial per patch (no floating-point atomics, so
+//             results do not depend on scheduling).  With diffuse rays a chain
+//             hit that emits a fan writes an emitter record; for big batches
+//             the kernel then traces the patch's fan passes itself.  The GRAD
+//             variant also differentiates each ray's hit chain at fixed
+//             visibility.
+//   k_fans    small diffuse batches: the patches' fan passes as a separate
+//             persistent launch, each patch split into several work units.
+//   k_slices  per evaluation, up to 16 blocks each summing a contiguous range of
+//             its patch, fan-pass and gradient partials in a fixed order.
+//   k_reduce  per evaluation, adds the ranges in order, scales by P * A_pix and
+//             writes the srp_result (and assembles the gradients).
 //
 // The per-pixel structure, the iterative secondary rays and the GPU-side
 // reduction follow Sec. 4.3 of the paper; the articulation follows Sec. 4.4.
