@@ -183,9 +183,10 @@ def test_back_to_back_batches_on_different_streams(srp):
         assert gg.cpu().numpy().tobytes() == ref_gr.tobytes()
 
 
-@pytest.mark.parametrize("n", [1, 2, 17, 100, 257])
+@pytest.mark.parametrize("n", [1, 2, 17, 100, 257, 600, 1030])
 def test_ragged_and_tiny_grids(srp, n):
-    """Grid sizes that are not multiples of the 16-pixel tile, down to one ray."""
+    """Grid sizes that are not multiples of the 16-pixel tile, down to one ray;
+    600 and 1030 also split the reduction's first stage into 5 and 16 ranges."""
     mesh = synth.box_wing()
     sc = srp.Scene(mesh)
     sun = synth.random_dirs(2300 + n)[0]
