@@ -109,7 +109,7 @@ def time_config(srp, torch, name, stream, steps):
                 f"{n}x{n} rays, B={B}, forward + adjoint")
     else:
         raise SystemExit(f"unknown workload {name}")
-    entries = [(s_, a, srp.params(d, n_, B)) for s_, a, d, n_ in items]
+    entries = srp.Batch([(s_, a, srp.params(d, n_, B)) for s_, a, d, n_ in items])   # marshalled once
     E = len(entries)
     cnt = srp.results_to_numpy(srp.eval_batch([(s_, a, srp.params(d, n_, B, count=True)) for s_, a, d, n_ in items]))
     rays = int(cnt["n_rays"].sum() + cnt["n_secondary"].sum())

@@ -14,7 +14,7 @@ import numpy as np
 from . import _lib as L
 from ._lib import RESULT_DTYPE, SRP_F_COUNT, SrpError  # noqa: F401
 
-__all__ = ["Scene", "params", "eval", "eval_grad", "eval_batch", "eval_grad_batch",
+__all__ = ["Scene", "params", "eval", "eval_grad", "Batch", "eval_batch", "eval_grad_batch",
            "SrpError", "RESULT_DTYPE"]
 
 
@@ -144,6 +144,27 @@ def grad_size(scene: Scene) -> int:
     return 3 * (2 * scene.n_mats + scene.n_dof) + 9
 
 
+class Batch:
+    """A batch marshalled once into its srp_batch_item array, for repeated
+    launches (eval_batch / eval_grad_batch accept it in place of the entry
+    list).  Holds the scenes and angle arrays the items point to."""
+
+    def __init__(self, entries):
+        self.entries = list(entries)
+        self.arr, self.keep = _items(self.entries)
+
+    def __len__(self):
+        return len(self.entries)
+
+
+def _marshalled(entries):
+    """(item array, objects it points into, n) for an entry list or a Batch."""
+    if isinstance(entries, Batch):
+        return entries.arr, entries.keep, len(entries)
+    arr, keep = _items(entries)
+    return arr, keep, len(entries)
+
+
 def _items(entries):
     """entries: list of (scene, angles or None, params)."""
     arr = (L.srp_batch_item * len(entries))()
@@ -163,34 +184,34 @@ def _items(entries):
 
 
 def eval_batch(entries, out=None, stream=None):
-    """srp_eval_batch.  entries: list of (scene, angles or None, params).
-    Returns a uint8 device tensor of len(entries) srp_result records (use
-    results_to_numpy to read it); stream-ordered on `stream` (torch stream)."""
+    """srp_eval_batch.  entries: list of (scene, angles or None, params), or a
+    Batch.  Returns a uint8 device tensor of len(entries) srp_result records
+    (use results_to_numpy to read it); stream-ordered on `stream` (torch
+    stream)."""
     import torch
     lib = _load()
-    n = len(entries)
+    arr, keep, n = _marshalled(entries)
     if out is None:
         out = torch.empty(n * RESULT_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
     s = stream if stream is not None else torch.cuda.current_stream()
-    arr, keep = _items(entries)
     L.check(lib.srp_eval_batch(arr, n, C.c_void_p(out.data_ptr()), C.c_void_p(s.cuda_stream)))
     return out
 
 
 def eval_grad_batch(entries, out=None, grad=None, stream=None):
-    """srp_eval_grad_batch.  Returns (results uint8 tensor, gradients float64
+    """srp_eval_grad_batch (entries: a list as for eval_batch, or a Batch).  Returns (results uint8 tensor, gradients float64
     tensor (n, stride)) with stride = max over entries of grad_size(scene):
     rho_s (M x 3), rho_d (M x 3), theta (J x 3), dF/dd (3 x 3) per row."""
     import torch
     lib = _load()
-    n = len(entries)
-    stride = max(grad_size(sc) for sc, _, _ in entries)
+    arr, keep, n = _marshalled(entries)
     if out is None:
         out = torch.empty(n * RESULT_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
     if grad is None:
+        lst = entries.entries if isinstance(entries, Batch) else entries
+        stride = max(grad_size(sc) for sc, _, _ in lst)
         grad = torch.zeros((n, stride), dtype=torch.float64, device="cuda")
     s = stream if stream is not None else torch.cuda.current_stream()
-    arr, keep = _items(entries)
     L.check(lib.srp_eval_grad_batch(arr, n, C.c_void_p(out.data_ptr()),
                                     C.c_void_p(grad.data_ptr()), grad.shape[1],
                                     C.c_void_p(s.cuda_stream)))
@@ -372,10 +393,11 @@ def set_schedule(patches_per_chunk=0, blocks_per_cu=0):
 
 
 def autotune(entries, grad=False):
-    """srp_autotune over a batch; returns (patches_per_chunk, blocks_per_cu, ms)."""
-    arr, keep = _items(entries)
+    """srp_autotune over a batch (entry list or Batch); returns
+    (patches_per_chunk, blocks_per_cu, ms)."""
+    arr, keep, n = _marshalled(entries)
     r, b, ms = C.c_int32(), C.c_int32(), C.c_double()
-    L.check(_load().srp_autotune(arr, len(entries), L.SRP_PLAN_GRAD if grad else 0, C.byref(r),
+    L.check(_load().srp_autotune(arr, n, L.SRP_PLAN_GRAD if grad else 0, C.byref(r),
                                  C.byref(b), C.byref(ms)))
     return r.value, b.value, ms.value
 

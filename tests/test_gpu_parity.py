@@ -135,7 +135,11 @@ def test_batch_matches_single_and_is_deterministic(srp):
         singles.append(srp.eval(sc, sun, n, bounces=B))
     out = srp.results_to_numpy(srp.eval_batch(entries))
     out2 = srp.results_to_numpy(srp.eval_batch(entries))
+    prebuilt = srp.Batch(entries)   # marshalled once, launched twice
+    out3 = srp.results_to_numpy(srp.eval_batch(prebuilt))
+    out4 = srp.results_to_numpy(srp.eval_batch(prebuilt))
     torch.cuda.synchronize()
+    assert out3.tobytes() == out.tobytes() and out4.tobytes() == out.tobytes()
     for k, s in enumerate(singles):
         assert np.array_equal(out[k]["force"], s["force"]), k
         assert np.array_equal(out[k]["torque"], s["torque"]), k
