@@ -203,6 +203,32 @@ def test_inline_fans_in_a_mixed_batch(srp):
             assert g[f] == r[k][f], (k, f)
 
 
+def test_plans_with_fans(srp):
+    """Captured launches (graph replays) of diffuse batches at the paper's
+    setting, small (a separate fan launch) and big (fans inside the trace
+    kernel): every replay, with eager launches and synchronisations between
+    them, is bitwise the eager result, and so is a replay after an update with
+    other directions and angles."""
+    import torch
+    mesh, dirs, angles, n, B, K = synth.diffuse_batch(32)
+    sc = srp.Scene(mesh)
+    for E in (2, 16):
+        entries = [(sc, angles[k], srp.params(dirs[k], n, B, diffuse=K)) for k in range(E)]
+        ref = srp.results_to_numpy(srp.eval_batch(entries)).copy()
+        plan = srp.Plan(entries)
+        for _ in range(3):
+            got = srp.results_to_numpy(plan.launch()).copy()
+            torch.cuda.synchronize()
+            assert got.tobytes() == ref.tobytes(), E
+            assert srp.results_to_numpy(srp.eval_batch(entries)).tobytes() == ref.tobytes(), E
+        entries2 = [(sc, angles[16 + k], srp.params(dirs[16 + k], n, B, diffuse=K)) for k in range(E)]
+        plan.update(entries2)
+        got2 = srp.results_to_numpy(plan.launch()).copy()
+        ref2 = srp.results_to_numpy(srp.eval_batch(entries2))
+        assert got2.tobytes() == ref2.tobytes(), E
+        plan.close()
+
+
 def test_paper_setting_batch(srp):
     """The ~50k-triangle spacecraft at the paper's ray-traced setting (256^2,
     two secondary levels, 16 diffuse rays), 64 attitudes in one launch: every
