@@ -9,7 +9,7 @@
  * hit (self-shadowing, Sec. 1), applying the absorbed / specular / diffuse
  * momentum-transfer law of the hit facet's material, following specular
  * secondary rays iteratively (Sec. 4.3), and reducing everything on the GPU to
- * a total force and torque (GPU-side reduction, Sec. 4.3 and Sec. 7.2).
+ * a total force and torque (GPU-side reduction, Sec. 4.3 and Sec. 8.2).
  * Articulated solar panels follow the paper's rooted kinematic tree
  * G = (N, E, L) with edge labels (pivot, axes, intervals) (Sec. 4.4.1) and the
  * clamp-to-interval rule of the panel update (Sec. 4.4.2).
@@ -384,6 +384,56 @@ int srp_propagate_rk78(srp_scene *scene, const srp_orbit_params *op, const doubl
 int srp_propagate_spad_rk78(const srp_spad_grid *grid, const double *table, double p_table,
                             const srp_orbit_params *op, const double *y0, double t0, double t1,
                             const srp_rk78_opts *opts, double *traj, int64_t max_rows, int64_t *n_rows);
+
+/* ---- N-plate model: the analytical model of Sec. 1, one of the strategies
+ * compared in Sec. 6.1 and 7.1 ----
+ *
+ * The spacecraft as flat plates, each lit on the side its normal points to
+ * (or on either side when two-sided), with no shadowing and no secondary
+ * rays.  Per lit plate, with s the unit Sun direction, d = -s the photon
+ * direction, n the plate normal turned towards the Sun and c = n . s > 0:
+ *   F = P A c [(1 - rho_s) d - 2 (rho_s c + rho_d / 3) n],
+ *   tau = (center - ref) x F.
+ * Body frame throughout. */
+typedef struct {
+    double normal[3];  /* unit; a one-sided plate is lit only when normal . s > 0 */
+    double center[3];  /* area-weighted centroid (torque lever) */
+    double area;       /* m^2, > 0 */
+    double rho_s, rho_d;
+    int32_t two_sided; /* 1: lit from either side */
+    int32_t reserved;
+} srp_plate;
+
+/* The plates of a scene at `angles` (NULL = its current angles; clamped as in
+ * srp_set_panel_angles): the articulated triangles grouped by node, material
+ * and normal direction (normals equal to 1e-6 per component share a plate);
+ * the triangle winding gives the normal; plates of panel nodes are
+ * two-sided (single-layer panels), the others one-sided (closed bodies wound
+ * outward).  Zero-area triangles are skipped.  plates: caller-owned,
+ * max_plates entries; *n_plates = plates needed (written also when
+ * max_plates is too small, with SRP_ERR_ARG).  Host only. */
+int srp_nplate_from_scene(srp_scene *scene, const double *angles, srp_plate *plates, int32_t max_plates,
+                          int32_t *n_plates);
+
+/* N-plate force and torque for Sun direction sun_dir (body frame, need not
+ * be unit) at pressure P (N/m^2) about ref.  force, torque: 3 doubles each.
+ * Host only.  Errors: SRP_ERR_ARG (null pointer, n_plates < 0, a zero or
+ * non-finite sun_dir, a plate with a non-unit normal, a non-positive area or
+ * reflectivities outside [0, 1]). */
+int srp_nplate_eval(const srp_plate *plates, int32_t n_plates, const double *sun_dir, double pressure,
+                    const double *ref, double *force, double *torque);
+
+/* Two-body + N-plate SRP propagation with the attitude fixed (the body frame
+ * is the inertial frame, the Sun direction at r is -r / |r|, the pressure
+ * op->p_ref (op->r_ref / |r|)^2; op->n, bounces, n_diffuse and ref unused;
+ * track_sun must be 0): srp_rk4 with step h (traj as srp_rk4), or srp_rk78
+ * from t0 to t1 (traj, max_rows, n_rows as srp_rk78).  Host only.  Errors:
+ * SRP_ERR_ARG, or those of the integrator. */
+int srp_propagate_nplate(const srp_plate *plates, int32_t n_plates, const srp_orbit_params *op, const double *y0,
+                         double t0, double h, int64_t n_steps, double *traj);
+int srp_propagate_nplate_rk78(const srp_plate *plates, int32_t n_plates, const srp_orbit_params *op,
+                              const double *y0, double t0, double t1, const srp_rk78_opts *opts, double *traj,
+                              int64_t max_rows, int64_t *n_rows);
 
 /* Measurement hook (not part of an evaluation): srp_profile(1) starts timing
  * every launch's ray-tracing kernels (the trace kernel, then the diffuse fan

@@ -7,7 +7,7 @@ the 8th-order weights and q <= 7 for the embedded 7th-order ones; the
 conditions sum_i b_i a_ij c_j^(q-1) = 1/(q (q + 1)) for q <= 7), the
 integrator by order-8 convergence on an eccentric Kepler orbit, the step
 control by the accuracy it reaches on the paper's reference orbit (a = 0.557 AU,
-e = 0.682, Sec. 5.2), and the two-body + cannonball SRP closed form."""
+e = 0.682, Sec. 5.1), and the two-body + cannonball SRP closed form."""
 from fractions import Fraction as Fr
 
 import numpy as np
