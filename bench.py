@@ -348,6 +348,13 @@ def main():
             tr = srp.propagate_spad(G, tabs[name], P1AU, y0, 0.0, h, steps, MU_SUN, MASS, P1AU, AU)
             spad_s[name] = time.perf_counter() - t0
             sep[name] = float(np.linalg.norm(tr[-1, 1:4] - direct[-1, 1:4]) / 1e3)
+        # the N-plate model of the same craft (plates of the articulated mesh, no
+        # shadowing, no secondary rays) over the same revolution
+        plates = srp.nplate_from_scene(scene, angles[0])
+        t0 = time.perf_counter()
+        tr = srp.propagate_nplate(plates, y0, 0.0, h, steps, MU_SUN, MASS, P1AU, AU)
+        nplate_s = time.perf_counter() - t0
+        sep["nplate"] = float(np.linalg.norm(tr[-1, 1:4] - direct[-1, 1:4]) / 1e3)
         kep = srp.propagate_spad(grids["20x10"], 0.0 * tabs["20x10"], P1AU, y0, 0.0, h, steps, MU_SUN, MASS,
                                  P1AU, AU)
         # interpolation error per evaluation along the orbit plane (elevation 0, 1 deg steps)
@@ -359,22 +366,26 @@ def main():
         interp_err = {name: round(float(np.sqrt(np.mean([np.sum((srp.spad_interp(G, tabs[name], S[k])[:3] - ref_f[k]) ** 2)
                                                           for k in range(360)])) / scale), 5)
                       for name, G in grids.items()}
+        interp_err["nplate"] = round(float(np.sqrt(np.mean([np.sum((srp.nplate_eval(plates, S[k], P1AU)["force"]
+                                                                   - ref_f[k]) ** 2) for k in range(360)])) / scale), 5)
         spad = {
             "workload": f"{mesh.n_tris}-triangle spacecraft, {dN}x{dN} rays, {dB} secondary levels, {dK} diffuse "
                         f"rays; orbit C (a = 0.388 AU, e = 0), one revolution, {steps} RK4 steps, "
                         f"mass {MASS:.0f} kg, fixed attitude",
             "table_nodes": 200,
+            "n_plates": len(plates),
             "table_build_ms": {k: round(v, 3) for k, v in build_ms.items()},
             "direct_ms_per_step": round(direct_s / steps * 1e3, 4),
             "direct_evals": st["n_evals"],
             "spad_us_per_step": {k: round(v / steps * 1e6, 3) for k, v in spad_s.items()},
+            "nplate_us_per_step": round(nplate_s / steps * 1e6, 3),
             "interp_rms_rel_err_el0": interp_err,
             "final_separation_km": {k: round(v, 4) for k, v in sep.items()},
             "srp_displacement_km": round(float(np.linalg.norm(kep[-1, 1:4] - direct[-1, 1:4]) / 1e3), 3),
         }
         log(f"SPAD: table {build_ms['20x10']:.1f} ms, direct {direct_s / steps * 1e3:.2f} ms/step, "
             f"SPAD {spad_s['20x10'] / steps * 1e6:.1f} us/step, separation 20x10 {sep['20x10']:.3f} km, "
-            f"20x10S {sep['20x10S']:.3f} km (SRP displacement {spad['srp_displacement_km']} km); "
+            f"20x10S {sep['20x10S']:.3f} km, N-plate {sep['nplate']:.3f} km (SRP displacement {spad['srp_displacement_km']} km); "
             f"interpolation rms error {interp_err}")
 
     # 20 revolutions of the paper's reference orbit (a = 0.557 AU, e = 0.682,
@@ -411,7 +422,11 @@ def main():
                                           P1AU, AU)
             p2[f"spad_{name}_s"] = round(time.perf_counter() - t0, 4)
             sep2[name] = float(np.linalg.norm(tr2[-1, 1:4] - finals["fixed_panels"]) / 1e3)
-        p2["final_separation_km"] = {f"spad_{k}": round(v, 3) for k, v in sep2.items()}
+        t0 = time.perf_counter()
+        tr2 = srp.propagate_nplate_rk78(plates, y2, 0.0, args.p2_revs * T2, opts, MU_SUN, MASS, P1AU, AU)
+        p2["nplate_s"] = round(time.perf_counter() - t0, 4)
+        sep2["nplate"] = float(np.linalg.norm(tr2[-1, 1:4] - finals["fixed_panels"]) / 1e3)
+        p2["final_separation_km"] = {(k if k == "nplate" else f"spad_{k}"): round(v, 3) for k, v in sep2.items()}
         if "tracking_panels" in finals:
             p2["final_separation_km"]["tracking_vs_fixed_panels"] = round(
                 float(np.linalg.norm(finals["tracking_panels"] - finals["fixed_panels"]) / 1e3), 3)

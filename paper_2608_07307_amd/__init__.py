@@ -15,6 +15,7 @@ from . import _lib as L
 from ._lib import RESULT_DTYPE, SRP_F_COUNT, SrpError  # noqa: F401
 
 __all__ = ["Scene", "params", "eval", "eval_grad", "Batch", "eval_batch", "eval_grad_batch",
+           "PLATE_DTYPE", "nplate_from_scene", "nplate_eval", "propagate_nplate", "propagate_nplate_rk78",
            "SrpError", "RESULT_DTYPE"]
 
 
@@ -385,6 +386,68 @@ def propagate_spad(grid, table, p_table, y0, t0, h, n_steps, mu, mass, p_ref, r_
     L.check(_load().srp_propagate_spad(C.byref(grid), L.ptr(t), float(p_table), C.byref(op), L.ptr(y), float(t0),
                                        float(h), int(n_steps), L.ptr(traj)))
     return traj
+
+
+PLATE_DTYPE = np.dtype([("normal", "<f8", 3), ("center", "<f8", 3), ("area", "<f8"), ("rho_s", "<f8"),
+                        ("rho_d", "<f8"), ("two_sided", "<i4"), ("reserved", "<i4")])
+
+
+def _plates(plates) -> np.ndarray:
+    a = np.ascontiguousarray(plates, dtype=PLATE_DTYPE)
+    return a
+
+
+def nplate_from_scene(scene: Scene, angles=None) -> np.ndarray:
+    """srp_nplate_from_scene: the scene's plates (PLATE_DTYPE records) at
+    `angles` (None = its current angles)."""
+    lib = _load()
+    a = None if angles is None else np.ascontiguousarray(angles, dtype=np.float64)
+    n = C.c_int32(0)
+    rc = lib.srp_nplate_from_scene(scene.handle, L.ptr(a) if a is not None else None, None, 0, C.byref(n))
+    if rc != 0 and n.value == 0:
+        L.check(rc)
+    out = np.zeros(n.value, PLATE_DTYPE)
+    L.check(lib.srp_nplate_from_scene(scene.handle, L.ptr(a) if a is not None else None,
+                                      out.ctypes.data if n.value else None, n.value, C.byref(n)))
+    return out
+
+
+def nplate_eval(plates, sun_dir, pressure=1.0, ref=(0.0, 0.0, 0.0)) -> dict:
+    """srp_nplate_eval: N-plate force and torque."""
+    p = _plates(plates)
+    s = np.ascontiguousarray(sun_dir, dtype=np.float64)
+    r = np.ascontiguousarray(ref, dtype=np.float64)
+    f, t = np.zeros(3), np.zeros(3)
+    L.check(_load().srp_nplate_eval(p.ctypes.data if len(p) else None, len(p), L.ptr(s), float(pressure),
+                                    L.ptr(r), L.ptr(f), L.ptr(t)))
+    return dict(force=f, torque=t)
+
+
+def propagate_nplate(plates, y0, t0, h, n_steps, mu, mass, p_ref, r_ref):
+    """srp_propagate_nplate: RK4 two-body + N-plate SRP, attitude fixed.
+    Returns traj (n_steps+1, 7)."""
+    p = _plates(plates)
+    op = L.srp_orbit_params(float(mu), float(mass), float(p_ref), float(r_ref), 0, 0, 0, 0,
+                            (C.c_double * 3)(0.0, 0.0, 0.0))
+    y = np.ascontiguousarray(y0, dtype=np.float64)
+    traj = np.zeros((n_steps + 1, 7))
+    L.check(_load().srp_propagate_nplate(p.ctypes.data if len(p) else None, len(p), C.byref(op), L.ptr(y),
+                                         float(t0), float(h), int(n_steps), L.ptr(traj)))
+    return traj
+
+
+def propagate_nplate_rk78(plates, y0, t0, t1, opts, mu, mass, p_ref, r_ref, max_rows=1 << 16):
+    """srp_propagate_nplate_rk78.  Returns rows (t, r, v) of the accepted steps."""
+    p = _plates(plates)
+    op = L.srp_orbit_params(float(mu), float(mass), float(p_ref), float(r_ref), 0, 0, 0, 0,
+                            (C.c_double * 3)(0.0, 0.0, 0.0))
+    y = np.ascontiguousarray(y0, dtype=np.float64)
+    traj = np.zeros((max_rows, 7))
+    rows = C.c_int64(0)
+    L.check(_load().srp_propagate_nplate_rk78(p.ctypes.data if len(p) else None, len(p), C.byref(op), L.ptr(y),
+                                              float(t0), float(t1), C.byref(opts), L.ptr(traj), int(max_rows),
+                                              C.byref(rows)))
+    return traj[:rows.value].copy()
 
 
 def set_schedule(patches_per_chunk=0, blocks_per_cu=0):

@@ -21,6 +21,7 @@ EXPORTS = [
     "srp_plan_create", "srp_plan_update", "srp_plan_launch", "srp_plan_destroy",
     "srp_set_schedule", "srp_autotune", "srp_spad_build", "srp_spad_interp", "srp_propagate_spad",
     "srp_rk78", "srp_propagate_rk78", "srp_propagate_spad_rk78",
+    "srp_nplate_from_scene", "srp_nplate_eval", "srp_propagate_nplate", "srp_propagate_nplate_rk78",
 ]
 SRP_PLAN_GRAD = 1
 SRP_F_GRAD_DIR = 2
@@ -62,6 +63,11 @@ class srp_orbit_params(C.Structure):
 class srp_spad_grid(C.Structure):
     _fields_ = [("n_az", C.c_int32), ("n_el", C.c_int32), ("az0", C.c_double), ("el0", C.c_double),
                 ("daz", C.c_double), ("del_", C.c_double)]
+
+
+class srp_plate(C.Structure):
+    _fields_ = [("normal", C.c_double * 3), ("center", C.c_double * 3), ("area", C.c_double),
+                ("rho_s", C.c_double), ("rho_d", C.c_double), ("two_sided", C.c_int32), ("reserved", C.c_int32)]
 
 
 class srp_rk78_opts(C.Structure):
@@ -131,6 +137,12 @@ def load(path: str | None = None):
                                             V, C.c_double, C.c_double, C.POINTER(srp_rk78_opts), V, I64,
                                             C.POINTER(C.c_int64)]
     lib.srp_spad_interp.argtypes = [C.POINTER(srp_spad_grid), V, V, V]
+    lib.srp_nplate_from_scene.argtypes = [V, V, V, C.c_int32, C.POINTER(C.c_int32)]
+    lib.srp_nplate_eval.argtypes = [V, C.c_int32, V, C.c_double, V, V, V]
+    lib.srp_propagate_nplate.argtypes = [V, C.c_int32, C.POINTER(srp_orbit_params), V, C.c_double, C.c_double,
+                                         I64, V]
+    lib.srp_propagate_nplate_rk78.argtypes = [V, C.c_int32, C.POINTER(srp_orbit_params), V, C.c_double,
+                                              C.c_double, C.POINTER(srp_rk78_opts), V, I64, C.POINTER(C.c_int64)]
     lib.srp_propagate_spad.argtypes = [C.POINTER(srp_spad_grid), V, C.c_double, C.POINTER(srp_orbit_params), V,
                                        C.c_double, C.c_double, I64, V]
     for f in ("srp_build_scene", "srp_destroy_scene", "srp_set_materials",
@@ -139,7 +151,8 @@ def load(path: str | None = None):
               "srp_sun_tracking_angles", "srp_rk4", "srp_propagate", "srp_plan_create",
               "srp_plan_update", "srp_plan_launch", "srp_plan_destroy", "srp_set_schedule",
               "srp_autotune", "srp_spad_build", "srp_spad_interp", "srp_propagate_spad", "srp_rk78",
-              "srp_propagate_rk78", "srp_propagate_spad_rk78"):
+              "srp_propagate_rk78", "srp_propagate_spad_rk78", "srp_nplate_from_scene", "srp_nplate_eval",
+              "srp_propagate_nplate", "srp_propagate_nplate_rk78"):
         getattr(lib, f).restype = C.c_int
     _lib = lib
     return lib

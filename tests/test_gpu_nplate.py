@@ -1,0 +1,81 @@
+"""The library's plates of a built scene (srp_nplate_from_scene: the
+articulated triangles grouped by node, material and normal) against the
+oracle's one-plate-per-triangle N-plate model: equal forces and torques for
+many Sun directions (the model is linear in the plates), the box-wing's eight
+plates (six bus faces, two two-sided panels), and the N-plate trajectory
+against the ray-traced one at the paper's ray-traced setting."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import nplate as NP
+
+pytestmark = pytest.mark.gpu
+
+P = 4.56e-6
+
+
+@pytest.fixture(scope="module")
+def srp():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2608_07307_amd as m
+    return m
+
+
+def test_box_wing_plates(srp):
+    m = synth.box_wing()
+    sc = srp.Scene(m)
+    ang = np.array([0.7, -0.4])
+    pl = srp.nplate_from_scene(sc, ang)
+    assert len(pl) == 8
+    assert int(pl["two_sided"].sum()) == 2
+    np.testing.assert_allclose(np.sort(pl["area"]), [1, 1, 1, 1, 1, 1, 10, 10], rtol=1e-6)
+
+
+@pytest.mark.parametrize("maker", [synth.box_wing, lambda: synth.box_wing_2axis(tess=3),
+                                   lambda: synth.procedural_spacecraft(seed=2)])
+def test_plates_match_oracle(srp, maker):
+    m = maker()
+    sc = srp.Scene(m)
+    rng = np.random.default_rng(61)
+    ang = rng.uniform(-0.6, 0.6, size=m.n_dof)
+    pl = srp.nplate_from_scene(sc, ang)
+    ref_pl = NP.plates(m, ang)
+    assert len(pl) <= len(ref_pl)
+    for s in synth.random_dirs(6101, 12):
+        got = srp.nplate_eval(pl, s, P, (0.2, -0.1, 0.3))
+        F, T = NP.force(ref_pl, s, P, (0.2, -0.1, 0.3))
+        sc_f = max(np.abs(F).max(), 1e-30)
+        np.testing.assert_allclose(got["force"], F, rtol=2e-6, atol=2e-6 * sc_f)
+        np.testing.assert_allclose(got["torque"], T, rtol=2e-6, atol=2e-6 * max(np.abs(T).max(), sc_f))
+    # the scene's current angles when none are given
+    sc.set_angles(ang)
+    again = srp.nplate_from_scene(sc)
+    assert again.tobytes() == pl.tobytes()
+
+
+def test_nplate_against_ray_traced_trajectory(srp):
+    """One revolution of orbit C (0.388 AU, circular) with the attitude fixed:
+    the N-plate trajectory of the ~50k-triangle craft ends closer to the
+    ray-traced one than the pure two-body orbit does (the model captures the
+    bulk of the pressure) but not on it: without shadowing its force in the
+    orbit plane is 24-57 % larger than the FP64 ray tracer's at 64^2 rays and
+    two secondary levels."""
+    AU, MU = 1.495978707e11, 1.32712440018e20
+    mesh, _, angles, n, B, K = synth.diffuse_batch(1)
+    sc = srp.Scene(mesh)
+    a = 0.388 * AU
+    y0 = np.array([a, 0, 0, 0, np.sqrt(MU / a), 0])
+    steps = 120
+    h = 2 * np.pi * np.sqrt(a ** 3 / MU) / steps
+    sc.set_angles(angles[0])
+    direct, _ = srp.propagate(sc, y0, 0.0, h, steps, MU, 1000.0, P, AU, 64, bounces=B)
+    pl = srp.nplate_from_scene(sc)
+    npl = srp.propagate_nplate(pl, y0, 0.0, h, steps, MU, 1000.0, P, AU)
+    kep = srp.propagate_nplate(np.zeros(0, srp.PLATE_DTYPE), y0, 0.0, h, steps, MU, 1000.0, P, AU)
+    d_np = np.linalg.norm(npl[-1, 1:4] - direct[-1, 1:4])
+    d_kep = np.linalg.norm(kep[-1, 1:4] - direct[-1, 1:4])
+    print(f"one revolution: N-plate {d_np / 1e3:.3f} km, two-body {d_kep / 1e3:.3f} km from the ray-traced orbit",
+          flush=True)
+    assert 0 < d_np < d_kep
