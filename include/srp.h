@@ -406,7 +406,9 @@ typedef struct {
 
 /* The plates of a scene at `angles` (NULL = its current angles; clamped as in
  * srp_set_panel_angles): the articulated triangles grouped by node, material
- * and normal direction (normals equal to 1e-6 per component share a plate);
+ * and normal direction (normals equal to 1e-6 per component share a plate;
+ * the grouping is made once, by srp_build_scene, in each node's frame, and
+ * the plates move rigidly with their nodes);
  * the triangle winding gives the normal; plates of panel nodes are
  * two-sided (single-layer panels), the others one-sided (closed bodies wound
  * outward).  Zero-area triangles are skipped.  plates: caller-owned,

@@ -3,7 +3,6 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <array>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -850,6 +849,7 @@ int srp_build_scene(const double *verts, int64_t n_verts, const int32_t *tris, i
         rc = scene_build(verts, n_verts, tris, n_tris, tri_material, tri_node, mats, n_mats, nodes, n_nodes, &sc->h,
                          &g_err);
         if (!rc) rc = slot_build(sc->h, nullptr, &sc->cur, &g_err);
+        if (!rc) plates_build(&sc->h);
     } catch (const std::bad_alloc &) {
         rc = fail(SRP_ERR_OOM, "host allocation failed");
     }
@@ -937,59 +937,23 @@ int srp_nplate_from_scene(srp_scene *scene, const double *angles, srp_plate *pla
         if (rc) return rc;
         slot = &own;
     }
-    // group the articulated triangles by node, material and normal (components
-    // rounded to 1e-6); accumulate area, area-weighted normal and centroid
-    struct Acc {
-        double area = 0, n[3] = {0, 0, 0}, c[3] = {0, 0, 0};
-        int32_t node = 0, mat = 0, first_id = 0;
-    };
-    std::map<std::array<int64_t, 5>, size_t> key_of;
-    std::vector<Acc> acc;
-    for (const TriRec &T : scene->h.tris) {
-        const double *X = slot->xf.data() + 12 * (size_t)T.node;
-        const float *v[3] = {T.v0, T.v1, T.v2};
-        double w[3][3];
-        for (int k = 0; k < 3; ++k)
-            for (int i = 0; i < 3; ++i)
-                w[k][i] = X[3 * i] * v[k][0] + X[3 * i + 1] * v[k][1] + X[3 * i + 2] * v[k][2] + X[9 + i];
-        const double e1[3] = {w[1][0] - w[0][0], w[1][1] - w[0][1], w[1][2] - w[0][2]};
-        const double e2[3] = {w[2][0] - w[0][0], w[2][1] - w[0][1], w[2][2] - w[0][2]};
-        const double cr[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
-        const double len = std::sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
-        if (!(len > 0)) continue;   // zero-area triangle
-        const double a = 0.5 * len, nu[3] = {cr[0] / len, cr[1] / len, cr[2] / len};
-        const std::array<int64_t, 5> key = {T.node, T.mat, std::llround(nu[0] * 1e6), std::llround(nu[1] * 1e6),
-                                            std::llround(nu[2] * 1e6)};
-        auto f = key_of.find(key);
-        if (f == key_of.end()) {
-            f = key_of.emplace(key, acc.size()).first;
-            acc.emplace_back();
-            acc.back().node = T.node;
-            acc.back().mat = T.mat;
-            acc.back().first_id = T.id;
-        }
-        Acc &P = acc[f->second];
-        P.area += a;
-        P.first_id = std::min(P.first_id, T.id);
-        for (int i = 0; i < 3; ++i) {
-            P.n[i] += a * nu[i];
-            P.c[i] += a * (w[0][i] + w[1][i] + w[2][i]) / 3.0;
-        }
-    }
-    // plates in the order of their first triangle in the caller's mesh
-    std::sort(acc.begin(), acc.end(), [](const Acc &x, const Acc &y) { return x.first_id < y.first_id; });
-    if (acc.size() > (size_t)INT32_MAX) return fail(SRP_ERR_ARG, "too many plates");
-    *n_plates = (int32_t)acc.size();
-    if ((int64_t)acc.size() > max_plates)
-        return fail(SRP_ERR_ARG, "max_plates too small: " + std::to_string(acc.size()) + " plates");
-    for (size_t k = 0; k < acc.size(); ++k) {
-        const Acc &P = acc[k];
+    // the scene's plates, moved rigidly with their nodes
+    const std::vector<PlateLocal> &pl = scene->h.plates;
+    if (pl.size() > (size_t)INT32_MAX) return fail(SRP_ERR_ARG, "too many plates");
+    *n_plates = (int32_t)pl.size();
+    if ((int64_t)pl.size() > max_plates)
+        return fail(SRP_ERR_ARG, "max_plates too small: " + std::to_string(pl.size()) + " plates");
+    for (size_t k = 0; k < pl.size(); ++k) {
+        const PlateLocal &P = pl[k];
+        const double *X = slot->xf.data() + 12 * (size_t)P.node;
         srp_plate &q = plates[k];
-        const double nl = std::sqrt(P.n[0] * P.n[0] + P.n[1] * P.n[1] + P.n[2] * P.n[2]);
+        double nw[3];
         for (int i = 0; i < 3; ++i) {
-            q.normal[i] = P.n[i] / nl;
-            q.center[i] = P.c[i] / P.area;
+            nw[i] = X[3 * i] * P.n[0] + X[3 * i + 1] * P.n[1] + X[3 * i + 2] * P.n[2];
+            q.center[i] = X[3 * i] * P.c[0] + X[3 * i + 1] * P.c[1] + X[3 * i + 2] * P.c[2] + X[9 + i];
         }
+        const double nl = std::sqrt(nw[0] * nw[0] + nw[1] * nw[1] + nw[2] * nw[2]);
+        for (int i = 0; i < 3; ++i) q.normal[i] = nw[i] / nl;
         q.area = P.area;
         q.rho_s = scene->h.mats[2 * (size_t)P.mat];
         q.rho_d = scene->h.mats[2 * (size_t)P.mat + 1];

@@ -24,6 +24,15 @@ struct NodeInfo {
     double n0[3] = {0, 0, 0};           // area-weighted rest-pose normal (unit, or 0 if none)
 };
 
+// One plate of the N-plate model in its node's frame: the node's triangles of
+// one material whose unit normals agree to 1e-6 (rounded components), merged;
+// n is the area-weighted sum of their unit normals, c their area-weighted
+// centroid.  Articulation moves a plate rigidly with its node.
+struct PlateLocal {
+    double n[3] = {0, 0, 0}, c[3] = {0, 0, 0}, area = 0;
+    int32_t node = 0, mat = 0;
+};
+
 // Host image of one articulation slot (see srp_internal.h for the layout).
 struct SlotHost {
     std::vector<Inst> inst;
@@ -52,6 +61,7 @@ struct SceneHost {
     std::vector<BNode4> blas;
     std::vector<WPoint> wpts;
     std::vector<int32_t> parent;
+    std::vector<PlateLocal> plates; // N-plate model, in the order of each plate's first triangle
     double pad = 0;                 // box padding (metres)
     int max_blas_depth = 0;
 };
@@ -69,5 +79,9 @@ int validate_materials(const srp_material *mats, int32_t n_mats, std::string *er
 // angle to its interval (Sec. 4.4.2 step 4), and builds the instances, the
 // top-level hierarchy and the world hinge axes.
 int slot_build(const SceneHost &S, const double *angles, SlotHost *out, std::string *err);
+
+// Fills S->plates from S->tris (which the library frees once they are on the
+// device).
+void plates_build(SceneHost *S);
 
 }  // namespace srp

@@ -7,6 +7,8 @@
 // flat-plate law
 //   F = P A c [(1 - rho_s) d - 2 (rho_s c + rho_d / 3) n],  tau = (x - ref) x F.
 // Host code; the propagation uses the library's RK4 / RK7(8) integrators.
+#include <algorithm>
+#include <array>
 #include <cmath>
 #include <string>
 
@@ -92,6 +94,69 @@ int check_orbit(const srp_orbit_params *op) {
 }
 
 }  // namespace
+
+namespace srp {
+
+void plates_build(SceneHost *S) {
+    // per triangle: area, unit normal and centroid in its node's frame, and a
+    // grouping key (node, material, normal rounded to 1e-6)
+    struct Tri {
+        std::array<int64_t, 5> key;
+        int32_t id;
+        double a, n[3], c[3];
+    };
+    std::vector<Tri> t;
+    t.reserve(S->tris.size());
+    for (const TriRec &T : S->tris) {
+        double e1[3], e2[3];
+        for (int i = 0; i < 3; ++i) {
+            e1[i] = (double)T.v1[i] - (double)T.v0[i];
+            e2[i] = (double)T.v2[i] - (double)T.v0[i];
+        }
+        const double cr[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+                              e1[0] * e2[1] - e1[1] * e2[0]};
+        const double len = std::sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
+        if (!(len > 0)) continue;   // zero-area triangle
+        Tri q;
+        q.id = T.id;
+        q.a = 0.5 * len;
+        for (int i = 0; i < 3; ++i) {
+            q.n[i] = cr[i] / len;
+            q.c[i] = ((double)T.v0[i] + (double)T.v1[i] + (double)T.v2[i]) / 3.0;
+        }
+        q.key = {T.node, T.mat, std::llround(q.n[0] * 1e6), std::llround(q.n[1] * 1e6), std::llround(q.n[2] * 1e6)};
+        t.push_back(q);
+    }
+    // groups are runs of equal keys; within a group the sums run in triangle
+    // order, so the result does not depend on the leaf order
+    std::sort(t.begin(), t.end(), [](const Tri &x, const Tri &y) { return x.key != y.key ? x.key < y.key : x.id < y.id; });
+    std::vector<std::pair<int32_t, PlateLocal>> g;   // (first triangle, plate)
+    for (size_t k = 0; k < t.size(); ++k) {
+        if (k == 0 || t[k].key != t[k - 1].key) {
+            PlateLocal P;
+            P.node = (int32_t)t[k].key[0];
+            P.mat = (int32_t)t[k].key[1];
+            g.emplace_back(t[k].id, P);
+        }
+        PlateLocal &P = g.back().second;
+        P.area += t[k].a;
+        for (int i = 0; i < 3; ++i) {
+            P.n[i] += t[k].a * t[k].n[i];
+            P.c[i] += t[k].a * t[k].c[i];
+        }
+    }
+    std::sort(g.begin(), g.end(), [](const std::pair<int32_t, PlateLocal> &x, const std::pair<int32_t, PlateLocal> &y) {
+        return x.first < y.first;
+    });
+    S->plates.clear();
+    S->plates.reserve(g.size());
+    for (auto &e : g) {
+        for (int i = 0; i < 3; ++i) e.second.c[i] /= e.second.area;
+        S->plates.push_back(e.second);
+    }
+}
+
+}  // namespace srp
 
 extern "C" {
 
