@@ -368,6 +368,34 @@ def main():
                       for name, G in grids.items()}
         interp_err["nplate"] = round(float(np.sqrt(np.mean([np.sum((srp.nplate_eval(plates, S[k], P1AU)["force"]
                                                                    - ref_f[k]) ** 2) for k in range(360)])) / scale), 5)
+        # the paper's four orbits (Sec. 6.1 table: a in AU, e; angles zero), one
+        # revolution from perihelion each, adaptive RK7(8): ray-traced SRP per
+        # stage against the SPAD tables and the N-plate model, each integrated
+        # with the same step control
+        orbit_set = {"C": (0.388, 0.0), "E(S)": (0.388, 0.881), "E(M)": (0.437, 0.786), "E(L)": (0.557, 0.682)}
+        per_orbit = {}
+        for oname, (a_au, ecc) in orbit_set.items():
+            ao = a_au * AU
+            rp = ao * (1 - ecc)
+            yo = np.array([rp, 0, 0, 0, np.sqrt(MU_SUN * (1 + ecc) / rp), 0])
+            To = 2 * np.pi * np.sqrt(ao ** 3 / MU_SUN)
+            oo = srp.rk78_opts(To / 100, True, args.p2_rtol, [args.p2_rtol * AU] * 3 + [args.p2_rtol * 1e5] * 3)
+            t0 = time.perf_counter()
+            dtr, dst = srp.propagate_rk78(scene, yo, 0.0, To, oo, MU_SUN, MASS, P1AU, AU, dN, bounces=dB,
+                                          angles0=angles[0], diffuse=dK)
+            d_s = time.perf_counter() - t0
+            end = dtr[-1, 1:4]
+            ends = {name: srp.propagate_spad_rk78(G, tabs[name], P1AU, yo, 0.0, To, oo, MU_SUN, MASS, P1AU,
+                                                  AU)[-1, 1:4] for name, G in grids.items()}
+            ends["nplate"] = srp.propagate_nplate_rk78(plates, yo, 0.0, To, oo, MU_SUN, MASS, P1AU, AU)[-1, 1:4]
+            two_body = srp.propagate_nplate_rk78(plates[:0], yo, 0.0, To, oo, MU_SUN, MASS, P1AU, AU)[-1, 1:4]
+            per_orbit[oname] = {
+                "direct_s": round(d_s, 3), "direct_evals": dst["n_evals"], "steps": len(dtr) - 1,
+                "final_separation_km": {k: round(float(np.linalg.norm(v - end) / 1e3), 3) for k, v in ends.items()},
+                "srp_displacement_km": round(float(np.linalg.norm(two_body - end) / 1e3), 3)}
+            log(f"orbit {oname}: direct {d_s:.2f} s ({dst['n_evals']} evaluations), separations (km) "
+                f"{per_orbit[oname]['final_separation_km']}, SRP displacement "
+                f"{per_orbit[oname]['srp_displacement_km']} km")
         spad = {
             "workload": f"{mesh.n_tris}-triangle spacecraft, {dN}x{dN} rays, {dB} secondary levels, {dK} diffuse "
                         f"rays; orbit C (a = 0.388 AU, e = 0), one revolution, {steps} RK4 steps, "
@@ -382,6 +410,7 @@ def main():
             "interp_rms_rel_err_el0": interp_err,
             "final_separation_km": {k: round(v, 4) for k, v in sep.items()},
             "srp_displacement_km": round(float(np.linalg.norm(kep[-1, 1:4] - direct[-1, 1:4]) / 1e3), 3),
+            "orbits_one_revolution_rk78": per_orbit,
         }
         log(f"SPAD: table {build_ms['20x10']:.1f} ms, direct {direct_s / steps * 1e3:.2f} ms/step, "
             f"SPAD {spad_s['20x10'] / steps * 1e6:.1f} us/step, separation 20x10 {sep['20x10']:.3f} km, "
