@@ -40,7 +40,18 @@ struct Frame {
     float oix, oiy, oiz;   // o / d
     float mx[3], my[3], mz[3];
     float cx, cy, cz;
+    int nx, ny, nz;        // float4 index of the near-plane array per axis in a node
 };
+
+// Near-plane arrays of a 4-wide node for a direction with inverse (ix, iy, iz):
+// lo (0, 1, 2) where the component is positive, hi (3, 4, 5) where negative;
+// the far plane's index is the near one's XOR 3, 5, 7.  With lo <= hi and a
+// monotone rounded fma, the near plane gives min(t_lo, t_hi) exactly.
+SRP_HD inline void near_planes(float ix, float iy, float iz, int &nx, int &ny, int &nz) {
+    nx = ix < 0.0f ? 3 : 0;
+    ny = iy < 0.0f ? 4 : 1;
+    nz = iz < 0.0f ? 5 : 2;
+}
 
 SRP_HD inline void frame_setup(const float o[3], const float d[3], Frame &F) {
     F.ix = safe_inv(d[0]);
@@ -49,6 +60,7 @@ SRP_HD inline void frame_setup(const float o[3], const float d[3], Frame &F) {
     F.oix = o[0] * F.ix;
     F.oiy = o[1] * F.iy;
     F.oiz = o[2] * F.iz;
+    near_planes(F.ix, F.iy, F.iz, F.nx, F.ny, F.nz);
     onb(d, F.mx, F.my);
     F.mz[0] = d[0]; F.mz[1] = d[1]; F.mz[2] = d[2];
     F.cx = F.mx[0] * o[0] + F.mx[1] * o[1] + F.mx[2] * o[2];
@@ -56,15 +68,13 @@ SRP_HD inline void frame_setup(const float o[3], const float d[3], Frame &F) {
     F.cz = F.mz[0] * o[0] + F.mz[1] * o[1] + F.mz[2] * o[2];
 }
 
-// Slab test of one box against [tmin, tmax]; returns entry distance or +inf.
-SRP_HD inline float box_enter(float lx, float ly, float lz, float hx, float hy, float hz,
-                                           float ix, float iy, float iz, float oix, float oiy, float oiz,
-                                           float tmin, float tmax) {
-    float t0x = fmaf(lx, ix, -oix), t1x = fmaf(hx, ix, -oix);
-    float t0y = fmaf(ly, iy, -oiy), t1y = fmaf(hy, iy, -oiy);
-    float t0z = fmaf(lz, iz, -oiz), t1z = fmaf(hz, iz, -oiz);
-    float tn = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), tmin));
-    float tf = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fminf(fmaxf(t0z, t1z), tmax));
+// Slab test of one box against [tmin, tmax] with its planes already ordered
+// per axis (near, far); returns the entry distance or T_INF.
+SRP_HD inline float box_enter(float nx, float ny, float nz, float fx, float fy, float fz,
+                              float ix, float iy, float iz, float oix, float oiy, float oiz,
+                              float tmin, float tmax) {
+    float tn = fmaxf(fmaxf(fmaf(nx, ix, -oix), fmaf(ny, iy, -oiy)), fmaxf(fmaf(nz, iz, -oiz), tmin));
+    float tf = fminf(fminf(fmaf(fx, ix, -oix), fmaf(fy, iy, -oiy)), fminf(fmaf(fz, iz, -oiz), tmax));
     return tn <= tf ? tn : T_INF;
 }
 
@@ -137,24 +147,6 @@ SRP_HD inline TraceCtx trace_ctx(const EvalDesc &D) {
     c.inst = (const Inst SRP_GLOBAL *)D.inst;
     c.root = D.root_ref;
     return c;
-}
-
-struct NodeData4 {
-    float4 lx, ly, lz, hx, hy, hz;
-    uint4 r;
-};
-
-SRP_HD inline NodeData4 load_node4(const BNode4 SRP_GLOBAL *n) {
-    const float4 SRP_GLOBAL *q = (const float4 SRP_GLOBAL *)n;
-    NodeData4 v;
-    v.lx = q[0];
-    v.ly = q[1];
-    v.lz = q[2];
-    v.hx = q[3];
-    v.hy = q[4];
-    v.hz = q[5];
-    v.r = ((const uint4 SRP_GLOBAL *)n)[6];
-    return v;
 }
 
 // Orders (t[i], r[i]) so that t[i] <= t[j] for i < j (five compare-exchanges).
@@ -235,6 +227,7 @@ SRP_HD inline bool trace_closest(const TraceCtx &C, const float o[3], const floa
     Frame F;
     F.ix = wix; F.iy = wiy; F.iz = wiz;
     F.oix = woix; F.oiy = woiy; F.oiz = woiz;
+    near_planes(wix, wiy, wiz, F.nx, F.ny, F.nz);
     const BNode4 SRP_GLOBAL *nodes = C.tlas;
     int inst = -1;
     uint32_t visits = 0;
@@ -263,14 +256,17 @@ SRP_HD inline bool trace_closest(const TraceCtx &C, const float o[3], const floa
                 nodes = C.blas;
                 ref = I.root;
             } else {
-                const NodeData4 N = load_node4(nodes + ref_index(ref));
+                const float4 SRP_GLOBAL *q = (const float4 SRP_GLOBAL *)(nodes + ref_index(ref));
+                const float4 NX = q[F.nx], NY = q[F.ny], NZ = q[F.nz];
+                const float4 FX = q[F.nx ^ 3], FY = q[F.ny ^ 5], FZ = q[F.nz ^ 7];
+                const uint4 NR = ((const uint4 SRP_GLOBAL *)q)[6];
                 const float ix = F.ix, iy = F.iy, iz = F.iz, oix = F.oix, oiy = F.oiy, oiz = F.oiz;
                 float t[4] = {
-                    box_enter(N.lx.x, N.ly.x, N.lz.x, N.hx.x, N.hy.x, N.hz.x, ix, iy, iz, oix, oiy, oiz, tmin, h.t),
-                    box_enter(N.lx.y, N.ly.y, N.lz.y, N.hx.y, N.hy.y, N.hz.y, ix, iy, iz, oix, oiy, oiz, tmin, h.t),
-                    box_enter(N.lx.z, N.ly.z, N.lz.z, N.hx.z, N.hy.z, N.hz.z, ix, iy, iz, oix, oiy, oiz, tmin, h.t),
-                    box_enter(N.lx.w, N.ly.w, N.lz.w, N.hx.w, N.hy.w, N.hz.w, ix, iy, iz, oix, oiy, oiz, tmin, h.t)};
-                uint32_t r[4] = {N.r.x, N.r.y, N.r.z, N.r.w};
+                    box_enter(NX.x, NY.x, NZ.x, FX.x, FY.x, FZ.x, ix, iy, iz, oix, oiy, oiz, tmin, h.t),
+                    box_enter(NX.y, NY.y, NZ.y, FX.y, FY.y, FZ.y, ix, iy, iz, oix, oiy, oiz, tmin, h.t),
+                    box_enter(NX.z, NY.z, NZ.z, FX.z, FY.z, FZ.z, ix, iy, iz, oix, oiy, oiz, tmin, h.t),
+                    box_enter(NX.w, NY.w, NZ.w, FX.w, FY.w, FZ.w, ix, iy, iz, oix, oiy, oiz, tmin, h.t)};
+                uint32_t r[4] = {NR.x, NR.y, NR.z, NR.w};
                 if (COUNT) nbox += (r[0] != REF_NONE) + (r[1] != REF_NONE) + (r[2] != REF_NONE) + (r[3] != REF_NONE);
                 sort4(t, r);
                 const int hits = (t[0] != T_INF) + (t[1] != T_INF) + (t[2] != T_INF) + (t[3] != T_INF);
@@ -306,6 +302,7 @@ SRP_HD inline bool trace_closest(const TraceCtx &C, const float o[3], const floa
                     if (ref_type(ref) == REF_TLAS_NODE) {
                         F.ix = wix; F.iy = wiy; F.iz = wiz;
                         F.oix = woix; F.oiy = woiy; F.oiz = woiz;
+                        near_planes(wix, wiy, wiz, F.nx, F.ny, F.nz);
                         nodes = C.tlas;
                     }
                 } else {
@@ -342,6 +339,7 @@ SRP_HD inline bool trace_closest(const TraceCtx &C, const float o[3], const floa
             if (ref_type(ref) == REF_TLAS_NODE) {
                 F.ix = wix; F.iy = wiy; F.iz = wiz;
                 F.oix = woix; F.oiy = woiy; F.oiz = woiz;
+                near_planes(wix, wiy, wiz, F.nx, F.ny, F.nz);
                 nodes = C.tlas;
             }
         } else {
