@@ -417,6 +417,18 @@ typedef struct {
 int srp_nplate_from_scene(srp_scene *scene, const double *angles, srp_plate *plates, int32_t max_plates,
                           int32_t *n_plates);
 
+/* The same plates straight from the arrays srp_build_scene takes (same
+ * meaning, layout and validation), at `angles` (NULL = all zero; clamped),
+ * without building a scene: for callers that want the N-plate model of a
+ * mesh, also on a machine without a GPU.  plates, max_plates and *n_plates as
+ * srp_nplate_from_scene.  Host only.  Errors: those of srp_build_scene's
+ * validation (SRP_ERR_ARG, SRP_ERR_DEPTH), SRP_ERR_OOM, SRP_ERR_ARG for
+ * max_plates. */
+int srp_nplate_from_mesh(const double *verts, int64_t n_verts, const int32_t *tris, int64_t n_tris,
+                         const int32_t *tri_material, const int32_t *tri_node, const srp_material *mats,
+                         int32_t n_mats, const srp_node *nodes, int32_t n_nodes, const double *angles,
+                         srp_plate *plates, int32_t max_plates, int32_t *n_plates);
+
 /* N-plate force and torque for Sun direction sun_dir (body frame, need not
  * be unit) at pressure P (N/m^2) about ref.  force, torque: 3 doubles each.
  * Host only.  Errors: SRP_ERR_ARG (null pointer, n_plates < 0, a zero or

@@ -15,7 +15,7 @@ from . import _lib as L
 from ._lib import RESULT_DTYPE, SRP_F_COUNT, SrpError  # noqa: F401
 
 __all__ = ["Scene", "params", "eval", "eval_grad", "Batch", "eval_batch", "eval_grad_batch",
-           "PLATE_DTYPE", "nplate_from_scene", "nplate_eval", "propagate_nplate", "propagate_nplate_rk78",
+           "PLATE_DTYPE", "nplate_from_scene", "nplate_from_mesh", "nplate_eval", "propagate_nplate", "propagate_nplate_rk78",
            "SrpError", "RESULT_DTYPE"]
 
 
@@ -41,6 +41,28 @@ def record_slots(bounces, diffuse=0):
     return int(bounces) + 1 + int(bounces) * int(diffuse)
 
 
+def _mesh_arrays(mesh):
+    """The arrays srp_build_scene takes, from a mesh object (see Scene)."""
+    verts = np.ascontiguousarray(mesh.verts, dtype=np.float64)
+    tris = np.ascontiguousarray(mesh.tris, dtype=np.int32)
+    tm = np.ascontiguousarray(mesh.tri_mat, dtype=np.int32)
+    tn = np.ascontiguousarray(mesh.tri_node, dtype=np.int32)
+    mats = (L.srp_material * len(mesh.mats))(*[L.srp_material(float(a), float(b)) for a, b in mesh.mats])
+    K = len(mesh.parent)
+    nodes = (L.srp_node * K)()
+    for k in range(K):
+        nd = nodes[k]
+        nd.parent = int(mesh.parent[k])
+        nd.is_panel = int(mesh.is_panel[k])
+        nd.pivot[:] = [float(x) for x in mesh.pivot[k]]
+        nd.n_axes = int(mesh.n_axes[k])
+        for a in range(3):
+            nd.axis[a][:] = [float(x) for x in mesh.axes[k][a]]
+        nd.lo[:] = [float(x) for x in mesh.lo[k]]
+        nd.hi[:] = [float(x) for x in mesh.hi[k]]
+    return verts, tris, tm, tn, mats, nodes
+
+
 class Scene:
     """A scene built by srp_build_scene from mesh, materials and tree arrays.
 
@@ -50,23 +72,8 @@ class Scene:
 
     def __init__(self, mesh):
         lib = _load()
-        verts = np.ascontiguousarray(mesh.verts, dtype=np.float64)
-        tris = np.ascontiguousarray(mesh.tris, dtype=np.int32)
-        tm = np.ascontiguousarray(mesh.tri_mat, dtype=np.int32)
-        tn = np.ascontiguousarray(mesh.tri_node, dtype=np.int32)
-        mats = (L.srp_material * len(mesh.mats))(*[L.srp_material(float(a), float(b)) for a, b in mesh.mats])
-        K = len(mesh.parent)
-        nodes = (L.srp_node * K)()
-        for k in range(K):
-            nd = nodes[k]
-            nd.parent = int(mesh.parent[k])
-            nd.is_panel = int(mesh.is_panel[k])
-            nd.pivot[:] = [float(x) for x in mesh.pivot[k]]
-            nd.n_axes = int(mesh.n_axes[k])
-            for a in range(3):
-                nd.axis[a][:] = [float(x) for x in mesh.axes[k][a]]
-            nd.lo[:] = [float(x) for x in mesh.lo[k]]
-            nd.hi[:] = [float(x) for x in mesh.hi[k]]
+        verts, tris, tm, tn, mats, nodes = _mesh_arrays(mesh)
+        K = len(nodes)
         h = C.c_void_p()
         L.check(lib.srp_build_scene(L.ptr(verts), verts.shape[0], L.ptr(tris), tris.shape[0],
                                     L.ptr(tm), L.ptr(tn), mats, len(mesh.mats), nodes, K,
@@ -409,6 +416,23 @@ def nplate_from_scene(scene: Scene, angles=None) -> np.ndarray:
     out = np.zeros(n.value, PLATE_DTYPE)
     L.check(lib.srp_nplate_from_scene(scene.handle, L.ptr(a) if a is not None else None,
                                       out.ctypes.data if n.value else None, n.value, C.byref(n)))
+    return out
+
+
+def nplate_from_mesh(mesh, angles=None) -> np.ndarray:
+    """srp_nplate_from_mesh: the plates srp_nplate_from_scene would give for
+    this mesh at `angles` (None = all zero), without a scene or a GPU."""
+    lib = _load()
+    verts, tris, tm, tn, mats, nodes = _mesh_arrays(mesh)
+    a = None if angles is None else np.ascontiguousarray(angles, dtype=np.float64)
+    args = (L.ptr(verts), verts.shape[0], L.ptr(tris), tris.shape[0], L.ptr(tm), L.ptr(tn), mats, len(mesh.mats),
+            nodes, len(nodes), L.ptr(a) if a is not None else None)
+    n = C.c_int32(0)
+    rc = lib.srp_nplate_from_mesh(*args, None, 0, C.byref(n))
+    if rc != 0 and n.value == 0:
+        L.check(rc)
+    out = np.zeros(n.value, PLATE_DTYPE)
+    L.check(lib.srp_nplate_from_mesh(*args, out.ctypes.data if n.value else None, n.value, C.byref(n)))
     return out
 
 

@@ -21,7 +21,8 @@ EXPORTS = [
     "srp_plan_create", "srp_plan_update", "srp_plan_launch", "srp_plan_destroy",
     "srp_set_schedule", "srp_autotune", "srp_spad_build", "srp_spad_interp", "srp_propagate_spad",
     "srp_rk78", "srp_propagate_rk78", "srp_propagate_spad_rk78",
-    "srp_nplate_from_scene", "srp_nplate_eval", "srp_propagate_nplate", "srp_propagate_nplate_rk78",
+    "srp_nplate_from_scene", "srp_nplate_from_mesh", "srp_nplate_eval", "srp_propagate_nplate",
+    "srp_propagate_nplate_rk78",
 ]
 SRP_PLAN_GRAD = 1
 SRP_F_GRAD_DIR = 2
@@ -138,6 +139,8 @@ def load(path: str | None = None):
                                             C.POINTER(C.c_int64)]
     lib.srp_spad_interp.argtypes = [C.POINTER(srp_spad_grid), V, V, V]
     lib.srp_nplate_from_scene.argtypes = [V, V, V, C.c_int32, C.POINTER(C.c_int32)]
+    lib.srp_nplate_from_mesh.argtypes = [V, I64, V, I64, V, V, V, I32, V, I32, V, V, C.c_int32,
+                                         C.POINTER(C.c_int32)]
     lib.srp_nplate_eval.argtypes = [V, C.c_int32, V, C.c_double, V, V, V]
     lib.srp_propagate_nplate.argtypes = [V, C.c_int32, C.POINTER(srp_orbit_params), V, C.c_double, C.c_double,
                                          I64, V]
@@ -152,7 +155,7 @@ def load(path: str | None = None):
               "srp_plan_update", "srp_plan_launch", "srp_plan_destroy", "srp_set_schedule",
               "srp_autotune", "srp_spad_build", "srp_spad_interp", "srp_propagate_spad", "srp_rk78",
               "srp_propagate_rk78", "srp_propagate_spad_rk78", "srp_nplate_from_scene", "srp_nplate_eval",
-              "srp_propagate_nplate", "srp_propagate_nplate_rk78"):
+              "srp_nplate_from_mesh", "srp_propagate_nplate", "srp_propagate_nplate_rk78"):
         getattr(lib, f).restype = C.c_int
     _lib = lib
     return lib

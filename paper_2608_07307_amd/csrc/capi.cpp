@@ -943,23 +943,7 @@ int srp_nplate_from_scene(srp_scene *scene, const double *angles, srp_plate *pla
     *n_plates = (int32_t)pl.size();
     if ((int64_t)pl.size() > max_plates)
         return fail(SRP_ERR_ARG, "max_plates too small: " + std::to_string(pl.size()) + " plates");
-    for (size_t k = 0; k < pl.size(); ++k) {
-        const PlateLocal &P = pl[k];
-        const double *X = slot->xf.data() + 12 * (size_t)P.node;
-        srp_plate &q = plates[k];
-        double nw[3];
-        for (int i = 0; i < 3; ++i) {
-            nw[i] = X[3 * i] * P.n[0] + X[3 * i + 1] * P.n[1] + X[3 * i + 2] * P.n[2];
-            q.center[i] = X[3 * i] * P.c[0] + X[3 * i + 1] * P.c[1] + X[3 * i + 2] * P.c[2] + X[9 + i];
-        }
-        const double nl = std::sqrt(nw[0] * nw[0] + nw[1] * nw[1] + nw[2] * nw[2]);
-        for (int i = 0; i < 3; ++i) q.normal[i] = nw[i] / nl;
-        q.area = P.area;
-        q.rho_s = scene->h.mats[2 * (size_t)P.mat];
-        q.rho_d = scene->h.mats[2 * (size_t)P.mat + 1];
-        q.two_sided = scene->h.nodes[P.node].is_panel ? 1 : 0;
-        q.reserved = 0;
-    }
+    plates_world(scene->h, *slot, plates);
     return SRP_OK;
 }
 

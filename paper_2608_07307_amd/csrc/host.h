@@ -84,4 +84,7 @@ int slot_build(const SceneHost &S, const double *angles, SlotHost *out, std::str
 // device).
 void plates_build(SceneHost *S);
 
+// S's plates moved by the node transforms of `slot` into out[0 .. S.plates.size()).
+void plates_world(const SceneHost &S, const SlotHost &slot, srp_plate *out);
+
 }  // namespace srp

@@ -9,7 +9,9 @@
 // Host code; the propagation uses the library's RK4 / RK7(8) integrators.
 #include <algorithm>
 #include <array>
+#include <climits>
 #include <cmath>
+#include <new>
 #include <string>
 
 #include "host.h"
@@ -156,9 +158,61 @@ void plates_build(SceneHost *S) {
     }
 }
 
+void plates_world(const SceneHost &S, const SlotHost &slot, srp_plate *out) {
+    for (size_t k = 0; k < S.plates.size(); ++k) {
+        const PlateLocal &P = S.plates[k];
+        const double *X = slot.xf.data() + 12 * (size_t)P.node;
+        srp_plate &q = out[k];
+        double nw[3];
+        for (int i = 0; i < 3; ++i) {
+            nw[i] = X[3 * i] * P.n[0] + X[3 * i + 1] * P.n[1] + X[3 * i + 2] * P.n[2];
+            q.center[i] = X[3 * i] * P.c[0] + X[3 * i + 1] * P.c[1] + X[3 * i + 2] * P.c[2] + X[9 + i];
+        }
+        const double nl = std::sqrt(nw[0] * nw[0] + nw[1] * nw[1] + nw[2] * nw[2]);
+        for (int i = 0; i < 3; ++i) q.normal[i] = nw[i] / nl;
+        q.area = P.area;
+        q.rho_s = S.mats[2 * (size_t)P.mat];
+        q.rho_d = S.mats[2 * (size_t)P.mat + 1];
+        q.two_sided = S.nodes[P.node].is_panel ? 1 : 0;
+        q.reserved = 0;
+    }
+}
+
 }  // namespace srp
 
 extern "C" {
+
+int srp_nplate_from_mesh(const double *verts, int64_t n_verts, const int32_t *tris, int64_t n_tris,
+                         const int32_t *tri_material, const int32_t *tri_node, const srp_material *mats,
+                         int32_t n_mats, const srp_node *nodes, int32_t n_nodes, const double *angles,
+                         srp_plate *plates, int32_t max_plates, int32_t *n_plates) {
+    if (!n_plates || (max_plates > 0 && !plates) || max_plates < 0) {
+        set_error("null plates or count");
+        return SRP_ERR_ARG;
+    }
+    std::string err;
+    try {
+        SceneHost h;
+        int rc = scene_build(verts, n_verts, tris, n_tris, tri_material, tri_node, mats, n_mats, nodes, n_nodes, &h,
+                             &err);
+        SlotHost slot;
+        if (!rc) rc = slot_build(h, angles, &slot, &err);
+        if (rc) { set_error(err); return rc; }
+        plates_build(&h);
+        if (h.plates.size() > (size_t)INT32_MAX) { set_error("too many plates"); return SRP_ERR_ARG; }
+        *n_plates = (int32_t)h.plates.size();
+        if ((int64_t)h.plates.size() > max_plates) {
+            set_error("max_plates too small: " + std::to_string(h.plates.size()) + " plates");
+            return SRP_ERR_ARG;
+        }
+        plates_world(h, slot, plates);
+    } catch (const std::bad_alloc &) {
+        set_error("host allocation failed");
+        return SRP_ERR_OOM;
+    }
+    return SRP_OK;
+}
+
 
 int srp_nplate_eval(const srp_plate *plates, int32_t n_plates, const double *sun_dir, double pressure,
                     const double *ref, double *force, double *torque) {

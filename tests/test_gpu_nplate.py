@@ -53,6 +53,8 @@ def test_plates_match_oracle(srp, maker):
     sc.set_angles(ang)
     again = srp.nplate_from_scene(sc)
     assert again.tobytes() == pl.tobytes()
+    # the same plates without a scene
+    assert srp.nplate_from_mesh(m, ang).tobytes() == pl.tobytes()
 
 
 def test_nplate_against_ray_traced_trajectory(srp):
