@@ -60,7 +60,7 @@ def _load():
         _lib = C.CDLL(_SO)
         P = C.c_void_p
         _lib.orc_eval.argtypes = [P, P, P, C.c_int32, P, C.c_int64, P, P, P]
-        _lib.orc_shade_frozen.argtypes = [P, P, P, P, P, P]
+        _lib.orc_shade_frozen.argtypes = [P, P, P, P, P, P, P]
         _lib.orc_grid_of.argtypes = [P, P, P, P]
         _lib.orc_articulate.argtypes = [P, P, P]
         _lib.orc_node_transforms.argtypes = [P, P, P]
@@ -210,15 +210,18 @@ def node_transforms(scene, angles=None) -> np.ndarray:
 
 
 def shade_frozen(scene, sun_dir, n, bounces, grid: dict, ids, pressure=1.0, ref=(0, 0, 0),
-                 angles=None, diffuse=0) -> OracleResult:
+                 angles=None, diffuse=0, angles_ref=None) -> OracleResult:
     """Fixed-visibility re-shade of recorded rays (ids shape
-    (N*N, record_slots(bounces, diffuse)))."""
+    (N*N, record_slots(bounces, diffuse))).  With angles_ref (the angles the
+    ids were recorded at) every primary ray keeps its share of its triangle's
+    visible surface: its contribution scales with c0(angles)/c0(angles_ref)."""
     lib = _load()
     sr = _SceneRef(scene)
     ids = np.ascontiguousarray(ids, dtype=np.int32).reshape(n * n, record_slots(bounces, diffuse))
     g = _grid_struct(grid)
     out = _Result()
-    rc = lib.orc_shade_frozen(C.byref(sr.c), _ptr(_angles(scene, angles)),
+    aref = None if angles_ref is None else _angles(scene, angles_ref)
+    rc = lib.orc_shade_frozen(C.byref(sr.c), _ptr(_angles(scene, angles)), _ptr(aref),
                               C.byref(_params(sun_dir, pressure, n, bounces, ref, diffuse)), C.byref(g),
                               _ptr(ids), C.byref(out))
     if rc != 0:
@@ -232,12 +235,15 @@ def fd_gradients(scene, sun_dir, n, bounces, grid, ids, pressure=1.0, angles=Non
                  which=("rho_s", "rho_d", "theta"), theta_idx=None, diffuse=0):
     """Central finite differences (FP64) of the fixed-visibility force with
     respect to each material's rho_s and rho_d and each hinge angle (or the
-    hinges listed in theta_idx).  Returns dict name -> array (count, 3)."""
+    hinges listed in theta_idx).  Every primary ray keeps its triangle and
+    its share of that triangle's visible surface (shade_frozen with
+    angles_ref = the recorded angles).  Returns dict name -> array (count, 3)."""
     ang = np.zeros(scene.n_dof) if angles is None else np.asarray(angles, float).copy()
     out = {}
 
     def F(sc, a):
-        return shade_frozen(sc, sun_dir, n, bounces, grid, ids, pressure, (0, 0, 0), a, diffuse).force
+        return shade_frozen(sc, sun_dir, n, bounces, grid, ids, pressure, (0, 0, 0), a, diffuse,
+                            angles_ref=ang).force
 
     for col, name in ((0, "rho_s"), (1, "rho_d")):
         if name not in which:

@@ -716,9 +716,18 @@ int orc_grid_of(const orc_scene *S, const double *angles, const orc_params *P, o
  * rays with the planes of its frozen triangles.  At the angles the ids were
  * recorded with this reproduces orc_eval; perturbing angles or materials gives
  * the fixed-visibility variation whose derivative the adjoint computes.
+ *
+ * angles_ref (may be NULL): the angles the ids were recorded at.  With it,
+ * every primary ray keeps its share of its triangle's visible surface, so the
+ * projected area it carries scales with the primary cosine:
+ * the pixel's whole contribution is multiplied by c0(angles) / c0(angles_ref),
+ * c0 = |n0 . d| of its primary triangle (the same convention as the direction
+ * re-shade below).  For a fully visible plate this makes the variation the
+ * flat-plate law's own, P A cos(theta) [...], including the cos(theta)
+ * prefactor.  Without it the pixel area is held (factor 1).
  */
-int orc_shade_frozen(const orc_scene *S, const double *angles, const orc_params *P, const orc_grid *g,
-                     const int32_t *ids, orc_result *out)
+int orc_shade_frozen(const orc_scene *S, const double *angles, const double *angles_ref, const orc_params *P,
+                     const orc_grid *g, const int32_t *ids, orc_result *out)
 {
     int rc = orc_validate(S);
     if (rc) return rc;
@@ -726,10 +735,16 @@ int orc_shade_frozen(const orc_scene *S, const double *angles, const orc_params 
     double *wtri = (double *)malloc(sizeof(double) * 9 * (size_t)(S->nt + 1));
     if (!wtri) return ORC_ERR_OOM;
     orc_articulate(S, angles, wtri);
+    double *wref = NULL;
+    if (angles_ref) {
+        wref = (double *)malloc(sizeof(double) * 9 * (size_t)(S->nt + 1));
+        if (!wref) { free(wtri); return ORC_ERR_OOM; }
+        orc_articulate(S, angles_ref, wref);
+    }
     int64_t np = (int64_t)P->n * P->n;
     int32_t G = orc_record_slots(P), K = P->n_diffuse;
     pix_out *po = (pix_out *)malloc(sizeof(pix_out) * (size_t)(np + 1));
-    if (!po) { free(wtri); return ORC_ERR_OOM; }
+    if (!po) { free(wref); free(wtri); return ORC_ERR_OOM; }
     double scale = P->pressure * g->a_pix;
     int oom = 0;
 #pragma omp parallel
@@ -755,6 +770,12 @@ int orc_shade_frozen(const orc_scene *S, const double *angles, const orc_params 
                 const double *tv = wtri + 9 * (int64_t)tri;
                 double nf[3], nn[3], dF[3], dT[3], r0[3], m[3];
                 tri_normal(tv, nf);
+                if (gen == 0 && wref) {
+                    /* the share of the primary triangle's surface: projected area ~ c0 */
+                    double nr[3], ns[3], nrr[3];
+                    tri_normal(wref + 9 * (int64_t)tri, nr);
+                    w = orient(nf, d, ns) / orient(nr, d, nrr);
+                }
                 v_sub(tv, o, r0);
                 double t = v_dot(r0, nf) / v_dot(d, nf);
                 double x[3] = {o[0] + t * d[0], o[1] + t * d[1], o[2] + t * d[2]};
@@ -797,6 +818,7 @@ int orc_shade_frozen(const orc_scene *S, const double *angles, const orc_params 
     }
     if (!oom) finish(S, P, g, po, np, out);
     free(po);
+    free(wref);
     free(wtri);
     return oom ? ORC_ERR_OOM : ORC_OK;
 }

@@ -60,8 +60,9 @@ int orc_grid_of(const orc_scene *S, const double *angles, const orc_params *P, o
 int orc_eval(const orc_scene *S, const double *angles, const orc_params *P, int32_t use_bvh,
              const int64_t *pixels, int64_t n_pixels, orc_result *out,
              int32_t *ids /* n_pix x R or NULL */, double *ts /* same or NULL */);
-int orc_shade_frozen(const orc_scene *S, const double *angles, const orc_params *P,
-                     const orc_grid *g, const int32_t *ids /* N*N x R */, orc_result *out);
+int orc_shade_frozen(const orc_scene *S, const double *angles, const double *angles_ref /* or NULL */,
+                     const orc_params *P, const orc_grid *g, const int32_t *ids /* N*N x R */,
+                     orc_result *out);
 int orc_shade_frozen_dir(const orc_scene *S, const double *angles, const orc_params *P,
                          const orc_grid *g, const int32_t *ids /* N*N x (B+1) */, const double *dnew,
                          orc_result *out);

@@ -225,14 +225,16 @@ def cube(half=0.5, rho=(0.3, 0.2), center=(0, 0, 0)) -> Scene:
     return b.build([rho], name="cube")
 
 
-def dihedral(L=1.0, H=1.0, rho=(1.0, 0.0)) -> Scene:
+def dihedral(L=1.0, H=1.0, rho=(1.0, 0.0), rho_b=None) -> Scene:
     """Two L x H faces meeting at 90 deg along the x axis: face A in z=0
-    (y in [0,H]), face B in y=0 (z in [0,H]); the corner opens towards +y+z."""
+    (y in [0,H]), face B in y=0 (z in [0,H]); the corner opens towards +y+z.
+    Face B takes material rho_b (material 1) when given, else face A's."""
     b = _Builder()
     root = b.node()
     b.quad_grid((0, 0, 0), (L, 0, 0), (0, H, 0), 1, 1, root, lambda a, c: 0 * a)
-    b.quad_grid((0, 0, 0), (L, 0, 0), (0, 0, H), 1, 1, root, lambda a, c: 0 * a)
-    return b.build([rho], name="dihedral")
+    mb = 0 if rho_b is None else 1
+    b.quad_grid((0, 0, 0), (L, 0, 0), (0, 0, H), 1, 1, root, lambda a, c: 0 * a + mb)
+    return b.build([rho] if rho_b is None else [rho, rho_b], name="dihedral")
 
 
 def icosphere(R=1.0, subdiv=3, rho=(0.3, 0.2)) -> Scene:

@@ -317,28 +317,70 @@ def test_frozen_shade_reproduces_eval():
     assert s.n_hits == r.n_hits and s.n_secondary_hits == r.n_secondary_hits
 
 
+def _hinged_plate_force_and_gradient(rs, rd, P, t, A):
+    """Flat-plate law of the hinged plate lit along d = -z, written out by
+    hand: n(t) = R_y(t) z faces the Sun, c = cos t, so
+        F(t)  = P A c [(1-rs) d - 2 (rs c + rd/3) n],
+        dF/dt = P A [c' ((1-rs) d - 2 (rs c + rd/3) n) - 2 c (rs c' n + (rs c + rd/3) n')],
+    with c' = -sin t and n' = y x n = (cos t, 0, -sin t)."""
+    d = np.array([0.0, 0.0, -1.0])
+    n = np.array([np.sin(t), 0.0, np.cos(t)])
+    c, cp = np.cos(t), -np.sin(t)
+    npr = np.array([np.cos(t), 0.0, -np.sin(t)])
+    law = (1 - rs) * d - 2 * (rs * c + rd / 3) * n
+    F = P * A * c * law
+    dF = P * A * (cp * law - 2 * c * (rs * cp * n + (rs * c + rd / 3) * npr))
+    return F, dF, d, n, c
+
+
 def test_flat_plate_gradients_closed_form():
-    """Fixed visibility keeps A_proj = N^2 A_pix.  For the hinged plate with
-    F = P A_proj [(1-rs) d - 2 (rs c + rd/3) n], n(t) = R_y(t) z, n' = a x n
-    (a = y), c = -n.d, c' = -d.(a x n):
-        dF/drs = P A_proj (-d - 2 c n),     dF/drd = -(2/3) P A_proj n,
-        dF/dt  = -2 P A_proj [rs c' n + (rs c + rd/3) (a x n)]."""
-    rs, rd, P, t = 0.35, 0.2, 1.9, 0.45
+    """Fixed visibility for the hinged plate (every pixel hits it): each ray
+    keeps its share of the plate's surface, so the frozen variation is the
+    flat-plate law's own, F(t) = P A cos t [...].  The coefficient terms at
+    fixed t are dF/drs = P A c (-d - 2 c n) and dF/drd = -(2/3) P A c n; the
+    hinge term is the derivative of F(t) including its cos t prefactor
+    (_hinged_plate_force_and_gradient).  The same closed form is the central
+    difference of the full evaluation re-traced at t +- h (window and pixel
+    area re-fitted), which ties the convention to the true force."""
+    rs, rd, P = 0.35, 0.2, 1.9
     sc = synth.hinged_plate(2.0, 3.0, rho=(rs, rd))
     sun = np.array([0.0, 0.0, 1.0])
-    d = -sun
-    r = oracle.eval_srp(sc, sun, 16, bounces=1, pressure=P, angles=[t], record=True)
-    g = oracle.fd_gradients(sc, sun, 16, 1, r.grid, r.ids, pressure=P, angles=[t])
-    A = 16 * 16 * r.grid["a_pix"]
-    a = np.array([0.0, 1.0, 0.0])
-    n = np.array([np.sin(t), 0.0, np.cos(t)])
-    c = -(n @ d)
-    axn = np.cross(a, n)
-    cp = -(d @ axn)
-    np.testing.assert_allclose(g["rho_s"][0], P * A * (-d - 2 * c * n), rtol=1e-8, atol=1e-9)
-    np.testing.assert_allclose(g["rho_d"][0], -2 / 3 * P * A * n, rtol=1e-8, atol=1e-9)
-    np.testing.assert_allclose(g["theta"][0], -2 * P * A * (rs * cp * n + (rs * c + rd / 3) * axn),
-                               rtol=1e-6, atol=1e-8)
+    for t in (0.45, -0.8, 1.1):
+        F, dF, d, n, c = _hinged_plate_force_and_gradient(rs, rd, P, t, 6.0)
+        r = oracle.eval_srp(sc, sun, 16, bounces=1, pressure=P, angles=[t], record=True)
+        np.testing.assert_allclose(r.force, F, rtol=1e-12, atol=1e-13)
+        g = oracle.fd_gradients(sc, sun, 16, 1, r.grid, r.ids, pressure=P, angles=[t])
+        np.testing.assert_allclose(g["rho_s"][0], P * 6.0 * c * (-d - 2 * c * n), rtol=1e-8, atol=1e-9)
+        np.testing.assert_allclose(g["rho_d"][0], -2 / 3 * P * 6.0 * c * n, rtol=1e-8, atol=1e-9)
+        np.testing.assert_allclose(g["theta"][0], dF, rtol=1e-7, atol=1e-8 * np.abs(dF).max())
+        h = 1e-5
+        fp = oracle.eval_srp(sc, sun, 16, bounces=1, pressure=P, angles=[t + h]).force
+        fm = oracle.eval_srp(sc, sun, 16, bounces=1, pressure=P, angles=[t - h]).force
+        np.testing.assert_allclose((fp - fm) / (2 * h), dF, rtol=1e-7, atol=1e-8 * np.abs(dF).max())
+
+
+def test_frozen_share_is_one_at_the_recorded_angles():
+    """With the recorded angles as reference the surface-share factor is
+    exactly 1, so the re-shade gives the plain re-shade's force and torque
+    bitwise.  A lone plate recorded head-on (t = 0) and turned by dt keeps
+    every ray on it, each with its share of the surface, so the frozen force
+    is the flat-plate law at dt, cos(dt) prefactor included."""
+    sc = synth.procedural_sized(13, 3000)
+    ang = np.linspace(-0.7, 0.6, sc.n_dof)
+    sun = synth.random_dirs(93)[0]
+    r = oracle.eval_srp(sc, sun, 48, bounces=2, angles=ang, record=True)
+    a = oracle.shade_frozen(sc, sun, 48, 2, r.grid, r.ids, angles=ang)
+    b = oracle.shade_frozen(sc, sun, 48, 2, r.grid, r.ids, angles=ang, angles_ref=ang)
+    assert np.array_equal(a.force, b.force) and np.array_equal(a.torque, b.torque)
+    # a lone plate lit head-on (t = 0), turned by dt under frozen visibility:
+    # F(dt) = P A cos(dt) [(1-rs) d - 2 (rs cos dt + rd/3) n(dt)] exactly
+    rs, rd = 0.3, 0.25
+    hp = synth.hinged_plate(2.0, 3.0, rho=(rs, rd))
+    rr = oracle.eval_srp(hp, (0, 0, 1), 12, bounces=0, angles=[0.0], record=True)
+    for dt in (0.2, -0.5):
+        F, _, _, _, _ = _hinged_plate_force_and_gradient(rs, rd, 1.0, dt, 6.0)
+        got = oracle.shade_frozen(hp, (0, 0, 1), 12, 0, rr.grid, rr.ids, angles=[dt], angles_ref=[0.0])
+        np.testing.assert_allclose(got.force, F, rtol=1e-12, atol=1e-13)
 
 
 def test_paper_material_tables():
@@ -413,6 +455,88 @@ def test_dihedral_chain_gradient_closed_form():
                                rtol=1e-8, atol=1e-10)
     np.testing.assert_allclose(g["rho_d"][0], A * P * np.sqrt(2) / 3 * (1 + rs) * d,
                                rtol=1e-8, atol=1e-10)
+
+
+def _dihedral_chains(rho_a, rho_b):
+    """The dihedral's two ray families written out by hand (d0 = -(0,1,1)/sqrt2,
+    face A in z = 0 with n_A = +z and material rho_a, face B in y = 0 with
+    n_B = +y and material rho_b, both normals facing the rays, c = 1/sqrt2 at
+    every hit).  Family A hits A first, reflects along R_A d0 = (0,-1,1)/sqrt2
+    onto B at the mirrored point; family B likewise.  With
+    law(d, n, rs, rd) = (1-rs) d - 2 (rs c(d) + rd/3) n, c(d) = -n.d, the
+    per-unit-weight terms of each family's two hits are
+        A1 = law(d0, n_A, rho_a),  A2 = rs_a law(R_A d0, n_B, rho_b),
+        B1 = law(d0, n_B, rho_b),  B2 = rs_b law(R_B d0, n_A, rho_a)."""
+    nA, nB = np.array([0.0, 0.0, 1.0]), np.array([0.0, 1.0, 0.0])
+    d0 = -np.array([0.0, 1.0, 1.0]) / np.sqrt(2)
+
+    def law(d, n, rho):
+        rs, rd = rho
+        return (1 - rs) * d - 2 * (rs * (-(n @ d)) + rd / 3) * n
+
+    RA, RB = np.eye(3) - 2 * np.outer(nA, nA), np.eye(3) - 2 * np.outer(nB, nB)
+    return dict(nA=nA, nB=nB, d0=d0, RA=RA, RB=RB,
+                A1=law(d0, nA, rho_a), A2=rho_a[0] * law(RA @ d0, nB, rho_b),
+                B1=law(d0, nB, rho_b), B2=rho_b[0] * law(RB @ d0, nA, rho_a))
+
+
+@pytest.mark.parametrize("bounces", [0, 1, 2])
+def test_dihedral_torque_off_axis(bounces):
+    """Torque of both hits about an off-axis point, faces of different
+    materials (so the two families do not mirror each other).  Each family
+    covers half the window (N even: the faces' projections meet on a pixel
+    edge), so each carries P W/2, W = sqrt2 L H.  Family A's primary hits are
+    spread evenly over face A (mean = its centre c_A = (L/2, H/2, 0)) and its
+    secondary hits are their mirror images on face B (mean c_B =
+    (L/2, 0, H/2)); family B the other way round.  So
+        tau = P W/2 [(c_A - r) x A1 + (c_B - r) x A2 + (c_B - r) x B1 + (c_A - r) x B2]
+    (A2 = B2 = 0 without a bounce).  A lever arm taken at the wrong hit, or
+    at the primary point for the bounce, fails this."""
+    rho_a, rho_b, L, H, P = (0.55, 0.25), (0.2, 0.5), 1.3, 0.7, 1.7
+    sc = synth.dihedral(L, H, rho_a, rho_b)
+    sun = np.array([0.0, 1.0, 1.0]) / np.sqrt(2)
+    ref = np.array([0.3, -0.8, 1.1])
+    r = oracle.eval_srp(sc, sun, 40, bounces=bounces, pressure=P, ref=ref)
+    ch = _dihedral_chains(rho_a, rho_b)
+    cA, cB = np.array([L / 2, H / 2, 0.0]), np.array([L / 2, 0.0, H / 2])
+    k = 1.0 if bounces else 0.0
+    W = np.sqrt(2) * L * H
+    tau = P * W / 2 * (np.cross(cA - ref, ch["A1"]) + k * np.cross(cB - ref, ch["A2"]) +
+                       np.cross(cB - ref, ch["B1"]) + k * np.cross(cA - ref, ch["B2"]))
+    F = P * W / 2 * (ch["A1"] + k * ch["A2"] + ch["B1"] + k * ch["B2"])
+    np.testing.assert_allclose(r.force, F, rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(r.torque, tau, rtol=1e-11, atol=1e-11 * np.abs(tau).max())
+
+
+@pytest.mark.parametrize("bounces", [1, 2])
+def test_dihedral_direction_jacobian(bounces):
+    """dF/dd through the two-hit chain, by hand.  At fixed visibility a ray of
+    family A carries (c_A(d)/c) [law(d, n_A, rho_a) + rs_a law(R_A d, n_B, rho_b)]
+    per unit P A_pix (its share of face A scales with c_A(d) = -n_A.d), so at d0
+        J_A = -(A1 + A2) n_A^T / c + D_a(n_A) + rs_a D_b(n_B) R_A,
+    with D(n) = d law/dd = (1-rs) I + 2 rs n n^T for that face's material and
+    d(R_A d)/dd = R_A; J_B the same with A and B swapped; J = P W/2 (J_A + J_B).
+    The oracle's central differences of its frozen re-shade at moved
+    directions must agree.  A reflection taken about the wrong normal, a
+    reflected direction not carried to the second hit, or a share factor that
+    does not follow d, fails this."""
+    rho_a, rho_b, L, H, P = (0.45, 0.3), (0.6, 0.15), 1.1, 0.8, 1.3
+    sc = synth.dihedral(L, H, rho_a, rho_b)
+    sun = np.array([0.0, 1.0, 1.0]) / np.sqrt(2)
+    r = oracle.eval_srp(sc, sun, 20, bounces=bounces, pressure=P, record=True)
+    ch = _dihedral_chains(rho_a, rho_b)
+    nA, nB, RA, RB = ch["nA"], ch["nB"], ch["RA"], ch["RB"]
+    c = 1 / np.sqrt(2)
+    I3 = np.eye(3)
+
+    def D(n, rho):
+        return (1 - rho[0]) * I3 + 2 * rho[0] * np.outer(n, n)
+
+    JA = -np.outer(ch["A1"] + ch["A2"], nA) / c + D(nA, rho_a) + rho_a[0] * D(nB, rho_b) @ RA
+    JB = -np.outer(ch["B1"] + ch["B2"], nB) / c + D(nB, rho_b) + rho_b[0] * D(nA, rho_a) @ RB
+    J = P * np.sqrt(2) * L * H / 2 * (JA + JB)
+    Jfd = oracle.fd_dir_jacobian(sc, 20, bounces, r.grid, r.ids, pressure=P)
+    np.testing.assert_allclose(Jfd, J, rtol=1e-7, atol=1e-8 * np.abs(J).max())
 
 
 def test_two_axis_joint_by_hand():
