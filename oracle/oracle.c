@@ -718,13 +718,19 @@ int orc_grid_of(const orc_scene *S, const double *angles, const orc_params *P, o
  * the fixed-visibility variation whose derivative the adjoint computes.
  *
  * angles_ref (may be NULL): the angles the ids were recorded at.  With it,
- * every primary ray keeps its share of its triangle's visible surface, so the
- * projected area it carries scales with the primary cosine:
- * the pixel's whole contribution is multiplied by c0(angles) / c0(angles_ref),
- * c0 = |n0 . d| of its primary triangle (the same convention as the direction
- * re-shade below).  For a fully visible plate this makes the variation the
- * flat-plate law's own, P A cos(theta) [...], including the cos(theta)
- * prefactor.  Without it the pixel area is held (factor 1).
+ * the recorded state is held as the direction re-shade below holds it:
+ *   - every hit keeps the face the recorded ray met (the normal's orientation
+ *     is taken from the recorded chain, followed through the triangles at
+ *     angles_ref), so the law varies smoothly even where a bounce meets its
+ *     triangle near edge-on;
+ *   - every primary ray keeps its share of its triangle's visible surface, so
+ *     the projected area it carries scales with the primary cosine: the
+ *     pixel's whole contribution is multiplied by c0(angles) / c0(angles_ref),
+ *     c0 = -n0 . d with that orientation.
+ * For a fully visible plate the variation is then the flat-plate law's own,
+ * P A cos(theta) [...], including the cos(theta) prefactor.  Diffuse fan rays
+ * are re-shaded as without it.  Without angles_ref the pixel area is held
+ * (factor 1) and each hit faces the ray it is re-shaded with.
  */
 int orc_shade_frozen(const orc_scene *S, const double *angles, const double *angles_ref, const orc_params *P,
                      const orc_grid *g, const int32_t *ids, orc_result *out)
@@ -764,22 +770,30 @@ int orc_shade_frozen(const orc_scene *S, const double *angles, const double *ang
             memset(acc, 0, sizeof acc);
             memset(&po[k], 0, sizeof po[k]);
             double w = 1.0;
+            double dref[3] = {g->d[0], g->d[1], g->d[2]};   /* the recorded chain's direction */
             for (int32_t gen = 0; gen <= P->bounces; ++gen) {
                 int32_t tri = ids[k * G + gen];
                 if (tri < 0) break;
                 const double *tv = wtri + 9 * (int64_t)tri;
                 double nf[3], nn[3], dF[3], dT[3], r0[3], m[3];
                 tri_normal(tv, nf);
-                if (gen == 0 && wref) {
-                    /* the share of the primary triangle's surface: projected area ~ c0 */
-                    double nr[3], ns[3], nrr[3];
+                double cth;
+                if (wref) {
+                    /* the face the recorded ray met, and (primary) the surface share */
+                    double nr[3], nro[3];
                     tri_normal(wref + 9 * (int64_t)tri, nr);
-                    w = orient(nf, d, ns) / orient(nr, d, nrr);
+                    double cref = orient(nr, dref, nro);
+                    double sgn = v_dot(nro, nr) > 0 ? 1.0 : -1.0;
+                    for (int c = 0; c < 3; ++c) nn[c] = sgn * nf[c];
+                    cth = -v_dot(nn, d);
+                    if (gen == 0) w = cth / cref;
+                    for (int c = 0; c < 3; ++c) dref[c] += 2.0 * cref * nro[c];
+                } else {
+                    cth = orient(nf, d, nn);
                 }
                 v_sub(tv, o, r0);
                 double t = v_dot(r0, nf) / v_dot(d, nf);
                 double x[3] = {o[0] + t * d[0], o[1] + t * d[1], o[2] + t * d[2]};
-                double cth = orient(nf, d, nn);
                 int32_t mt = S->tri_mat[tri];
                 double rs = S->mats[2 * mt], rd = S->mats[2 * mt + 1];
                 int emit = gen < P->bounces && K > 0 && rd > 0.0;

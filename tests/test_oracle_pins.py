@@ -383,6 +383,39 @@ def test_frozen_share_is_one_at_the_recorded_angles():
         np.testing.assert_allclose(got.force, F, rtol=1e-12, atol=1e-13)
 
 
+def test_frozen_share_holds_the_face_met():
+    """Fixed visibility holds the face each recorded ray met.  A plate hinged
+    about y, lit from s = (sin a, 0, cos a) (a = -0.3), has c(t) = n(t).s =
+    cos(t - a); recorded at t = 1.2 (c = 0.071) and re-shaded at t = 1.35 it
+    has turned past edge-on (c = -0.079).  With the recorded face held, the
+    frozen force is the flat-plate law continued through edge-on,
+    P A c(t) [(1-rs) d - 2 (rs c(t) + rd/3) n(t)] with n(t) = R_y(t) z and
+    c(t) < 0, and the central difference across edge-on is its derivative
+    (re-orienting the normal toward the ray would flip the rd term and put a
+    kink at edge-on)."""
+    rs, rd, P, a = 0.3, 0.25, 1.4, -0.3
+    sc = synth.hinged_plate(2.0, 3.0, rho=(rs, rd))
+    sun = np.array([np.sin(a), 0.0, np.cos(a)])
+    d = -sun
+
+    def law(t):
+        n = np.array([np.sin(t), 0.0, np.cos(t)])
+        c = np.cos(t - a)
+        return P * 6.0 * c * ((1 - rs) * d - 2 * (rs * c + rd / 3) * n)
+
+    r = oracle.eval_srp(sc, sun, 16, bounces=0, pressure=P, angles=[1.2], record=True)
+    assert r.n_hits == 256
+    np.testing.assert_allclose(r.force, law(1.2), rtol=1e-11, atol=1e-13)
+    for t in (1.35, 1.27):
+        got = oracle.shade_frozen(sc, sun, 16, 0, r.grid, r.ids, pressure=P, angles=[t], angles_ref=[1.2])
+        np.testing.assert_allclose(got.force, law(t), rtol=1e-11, atol=1e-13)
+    h = 1e-4
+    t0 = np.pi / 2 + a            # exactly edge-on
+    fd = (oracle.shade_frozen(sc, sun, 16, 0, r.grid, r.ids, pressure=P, angles=[t0 + h], angles_ref=[1.2]).force -
+          oracle.shade_frozen(sc, sun, 16, 0, r.grid, r.ids, pressure=P, angles=[t0 - h], angles_ref=[1.2]).force)
+    np.testing.assert_allclose(fd / (2 * h), (law(t0 + 1e-6) - law(t0 - 1e-6)) / 2e-6, rtol=1e-6, atol=1e-9)
+
+
 def test_paper_material_tables():
     """The printed optical coefficients satisfy p_s + p_d + p_a = 1 for every
     part; the oracle accepts them and rejects a row with rs + rd > 1."""
