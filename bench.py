@@ -158,6 +158,8 @@ def main():
     ap.add_argument("--configs", default="",
                     help="also time these other workloads, comma-separated from c1,c3,c4,c5 (off by default)")
     ap.add_argument("--p2-rtol", type=float, default=1e-9)
+    ap.add_argument("--c2-prop-steps", type=int, default=1440,
+                    help="RK4 steps of 60 s of the headline workload's propagation leg (0: skip)")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="also run a device copy of this many MiB (calibrates memory counters)")
     args = ap.parse_args()
@@ -461,24 +463,62 @@ def main():
                 float(np.linalg.norm(finals["tracking_panels"] - finals["fixed_panels"]) / 1e3), 3)
         log(f"P2 separations (km): {p2['final_separation_km']}")
 
+    # the propagation leg of the headline workload: 1,000 kg on the circular 1 AU
+    # orbit, attitude inertially fixed, RK4 at 60 s steps for one day (4 SRP
+    # evaluations per step at the headline's 1024^2 rays and 2 bounces), the
+    # wing roots tracking the Sun at every stage
+    c2prop = None
+    if args.c2_prop_steps > 0:
+        AU, MU_SUN, MASS, P0 = 1.495978707e11, 1.32712440018e20, 1000.0, 1361.0 / 299792458.0
+        y0 = np.array([AU, 0.0, 0.0, 0.0, np.sqrt(MU_SUN / AU), 0.0])
+        srp.propagate(scene, y0, 0.0, 60.0, 2, MU_SUN, MASS, P0, AU, N, bounces=B, track_sun=True)   # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tr, st = srp.propagate(scene, y0, 0.0, 60.0, args.c2_prop_steps, MU_SUN, MASS, P0, AU, N, bounces=B,
+                               track_sun=True)
+        prop_s = time.perf_counter() - t0
+        kep = srp.propagate_nplate(srp.nplate_from_scene(scene)[:0], y0, 0.0, 60.0, args.c2_prop_steps, MU_SUN,
+                                   MASS, P0, AU)   # no plates: two-body RK4 on the same steps
+        c2prop = {
+            "workload": f"{mesh.n_tris}-triangle spacecraft, 1000 kg, circular 1 AU orbit, RK4, 60 s steps, "
+                        f"{args.c2_prop_steps} steps ({args.c2_prop_steps * 60 / 86400:.3g} day), {N}x{N} rays, "
+                        f"{B} bounces, sun-tracking wing roots, one srp_eval per stage",
+            "steps": args.c2_prop_steps, "evals": st["n_evals"], "total_s": round(prop_s, 3),
+            "ms_per_eval": round(prop_s / st["n_evals"] * 1e3, 4),
+            "srp_share": round(st["srp_seconds"] / prop_s, 4),
+            "srp_displacement_m": round(float(np.linalg.norm(tr[-1, 1:4] - kep[-1, 1:4])), 3)}
+        log(f"c2 propagation: {args.c2_prop_steps} RK4 steps, {st['n_evals']} evaluations in {prop_s:.2f} s "
+            f"({c2prop['ms_per_eval']} ms each), SRP displacement {c2prop['srp_displacement_m']} m")
+
     # oracle on a bounded sample (CPU baseline and parity of the sampled items)
     cpu = None
     parity = None
     if args.cpu_samples > 0:
         import oracle
-        errs = []
+        errs, gerrs = [], {"rho_s": [], "rho_d": [], "theta": []}
+        g_host = grad.cpu().numpy()
+        M, J = mesh.n_mats, mesh.n_dof
         t0 = time.perf_counter()
+        fds = []
         for k in range(args.cpu_samples):
             o = oracle.eval_srp(mesh, dirs[k], N, bounces=B, angles=angles[k], record=True)
-            oracle.fd_gradients(mesh, dirs[k], N, B, o.grid, o.ids, angles=angles[k])
+            fds.append(oracle.fd_gradients(mesh, dirs[k], N, B, o.grid, o.ids, angles=angles[k]))
             errs.append(float(np.linalg.norm(res[k]["force"] - o.force) / np.linalg.norm(o.force)))
         t1 = time.perf_counter()
+        for k, fd in enumerate(fds):
+            blocks = {"rho_s": g_host[k, :3 * M].reshape(M, 3), "rho_d": g_host[k, 3 * M:6 * M].reshape(M, 3),
+                      "theta": g_host[k, 6 * M:6 * M + 3 * J].reshape(J, 3)}
+            for key, gk in blocks.items():
+                gerrs[key].append(float(np.abs(gk - fd[key]).max() / np.abs(fd[key]).max()))
         cpu = {"value": round(args.cpu_samples / (t1 - t0), 4), "unit": "evals/s",
                "cores": oracle.threads(), "kind": "oracle",
                "sample": f"{args.cpu_samples} of the {E} batch items: FP64 forward (oracle BVH) + "
                          f"central-difference gradient ({2 * (2 * mesh.n_mats + mesh.n_dof)} "
                          f"fixed-visibility re-shades), {N}x{N} rays, B={B}"}
-        parity = {"max_rel_force_err": max(errs), "items_checked": args.cpu_samples}
+        parity = {"max_rel_force_err": max(errs), "items_checked": args.cpu_samples,
+                  "max_rel_grad_err": {k: max(v) for k, v in gerrs.items()},
+                  "grad_err_definition": "per block: max |adjoint - oracle central difference (h = 1e-4, "
+                                         "oracle's own hits)| / max |oracle central difference|"}
         log(f"oracle: {cpu['value']} evals/s on {cpu['cores']} threads; parity {max(errs):.2e}")
 
     achieved = work / kern_s / 1e12
@@ -511,6 +551,7 @@ def main():
         "paper_setting": paper_setting,
         "spad": spad,
         "p2": p2,
+        "c2_propagation": c2prop,
         "parity": parity,
         "roofline": {
             "bound": "alu",

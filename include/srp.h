@@ -26,8 +26,10 @@
  *   - Device: the library uses the HIP device current at srp_build_scene;
  *     a scene's calls are ordered on the stream given (or the null stream).
  *     Calls on one scene must not overlap from several host threads.
- *   - Precision: rays, traversal and intersection in FP32; every sum of
- *     force, torque and gradient contributions in FP64.
+ *   - Precision: rays, traversal and intersection in FP32; force and torque
+ *     contributions are summed in FP64.  The adjoint's per-hit gradient
+ *     terms are first summed over a wavefront in FP32 (at most 64 terms per
+ *     sum) and then accumulated in FP64 across hits and patches.
  */
 #ifndef SRP_MI355X_H
 #define SRP_MI355X_H
@@ -191,15 +193,19 @@ int srp_eval_batch(const srp_batch_item *items, int64_t n_items, srp_result *out
                    void *hip_stream);
 
 /* One evaluation plus the gradient of the force at fixed visibility (hit
- * triangles of every generation, window, pixel area and ray origins frozen):
+ * triangles of every generation, the face of each that the ray met, window
+ * and ray origins frozen; every primary ray keeps its triangle and its share
+ * of that triangle's visible surface, whose projected area scales with
+ * c0 = -n0.d of the primary hit):
  *   dF_drho_s: n_mats x 3, dF_drho_d: n_mats x 3, dF_dtheta: n_dof x 3,
  *   dF_ddir: 3 x 3, dF_i/dd_j (row-major) with respect to the photon
  *   direction d = -sun_dir/|sun_dir| (host).
- * dF_dtheta is with respect to the clamped angles.  dF_ddir is computed when
- * the pointer is non-NULL (SRP_F_GRAD_DIR); for it every primary
- * ray keeps its triangle and its share of that triangle's visible area, whose
- * projected size scales with c = -n.d of the primary hit; the specular chain
- * follows d through its reflections.  d is varied as a free 3-vector; a
+ * dF_dtheta is with respect to the clamped angles; a turned primary
+ * triangle changes its rays' projected area with c0 (for a fully visible
+ * plate the result is the derivative of the flat-plate law
+ * P A cos(theta) [...]), and the specular chain follows the turned normals.
+ * dF_ddir is computed when the pointer is non-NULL (SRP_F_GRAD_DIR); the
+ * specular chain follows d through its reflections.  d is varied as a free 3-vector; a
  * rotation of the Sun direction or of the attitude takes the component
  * orthogonal to d.  Any gradient pointer may be NULL.  Blocks until the
  * results are on the host.  Errors as srp_eval; SRP_ERR_ARG for

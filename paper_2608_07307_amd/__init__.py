@@ -404,11 +404,20 @@ def _plates(plates) -> np.ndarray:
     return a
 
 
+def _angle_vector(angles, n_dof) -> np.ndarray:
+    """Hinge angles as a contiguous FP64 vector of exactly n_dof entries (the
+    library reads that many)."""
+    a = np.ascontiguousarray(angles, dtype=np.float64).reshape(-1)
+    if a.shape[0] != n_dof:
+        raise SrpError(-1, f"expected {n_dof} hinge angles, got {a.shape[0]}")
+    return a
+
+
 def nplate_from_scene(scene: Scene, angles=None) -> np.ndarray:
     """srp_nplate_from_scene: the scene's plates (PLATE_DTYPE records) at
     `angles` (None = its current angles)."""
     lib = _load()
-    a = None if angles is None else np.ascontiguousarray(angles, dtype=np.float64)
+    a = None if angles is None else _angle_vector(angles, scene.n_dof)
     n = C.c_int32(0)
     rc = lib.srp_nplate_from_scene(scene.handle, L.ptr(a) if a is not None else None, None, 0, C.byref(n))
     if rc != 0 and n.value == 0:
@@ -424,7 +433,7 @@ def nplate_from_mesh(mesh, angles=None) -> np.ndarray:
     this mesh at `angles` (None = all zero), without a scene or a GPU."""
     lib = _load()
     verts, tris, tm, tn, mats, nodes = _mesh_arrays(mesh)
-    a = None if angles is None else np.ascontiguousarray(angles, dtype=np.float64)
+    a = None if angles is None else _angle_vector(angles, int(np.asarray(mesh.n_axes).sum()))
     args = (L.ptr(verts), verts.shape[0], L.ptr(tris), tris.shape[0], L.ptr(tm), L.ptr(tn), mats, len(mesh.mats),
             nodes, len(nodes), L.ptr(a) if a is not None else None)
     n = C.c_int32(0)

@@ -630,6 +630,16 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(GRAD ? SR
                                     e += 2.0f * cc * A[3 * i + j] - 2.0f * an * d[j];
                                     G[3 * i + j] = e;
                                 }
+                            if (k == 0) {
+                                // the primary ray keeps its share of the triangle's visible surface,
+                                // whose projected area scales with c0 = -n0.d: the whole chain's
+                                // contribution S (per unit weight) adds dF/dn0 = -S d^T / c0
+                                float S[3];
+                                for (int i = 0; i < 3; ++i) S[i] = (1.0f - rs) * d[i] - 2.0f * sc * n[i] + rs * Tn[i];
+                                const float ws = w / cc;
+                                for (int i = 0; i < 3; ++i)
+                                    for (int j = 0; j < 3; ++j) G[3 * i + j] -= ws * S[i] * d[j];
+                            }
                             // H = -G [n]x
                             for (int i = 0; i < 3; ++i) {
                                 const float g0 = G[3 * i], g1 = G[3 * i + 1], g2 = G[3 * i + 2];

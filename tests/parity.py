@@ -131,3 +131,62 @@ def check_report(rep, strict=True):
         allow = F_TOL + 4.0 * flips / max(rep["hits_orc"], 1)
         assert rep["f_err"] <= allow, rep
         assert rep["t_err"] <= allow, rep
+
+
+# Adjoint tolerances (FP32 per-ray terms, FP64 sums), each gradient block
+# (rho_s, rho_d, theta, dir) measured against its own largest entry:
+#   G_TOL_VM  against central differences of the oracle's re-shade of the
+#             GPU's recorded hits (visibility matched: only arithmetic differs);
+#   G_TOL     against central differences of the oracle's re-shade of its own
+#             recorded hits, beyond what the rays whose hits differ carry.  A
+#             primary ray keeps its share of its triangle's surface, so on a
+#             grazing triangle (small c0 = -n0.d) it carries a hinge term
+#             ~ 1/c0; the few silhouette rays that flip between FP32 and FP64
+#             (all inside the edge band) can then move a small block by more
+#             than G_TOL.  Their share is exactly the difference of the two
+#             central differences (the re-shade is a sum over pixels), as for
+#             the force, whose plain error is allowed what the flipped rays carry.
+G_TOL = 1e-4
+G_TOL_VM = 1e-5
+
+
+def block_err(got, ref):
+    """max |got - ref| / max |ref| over one gradient block (0 when both vanish)."""
+    got, ref = np.asarray(got, float), np.asarray(ref, float)
+    den = np.abs(ref).max() if ref.size else 0.0
+    num = np.abs(got - ref).max() if ref.size else 0.0
+    if den == 0.0:
+        return 0.0 if num == 0.0 else float("inf")
+    return float(num / den)
+
+
+def _fd(mesh, sun, n, bounces, grid, ids, pressure, angles, theta_idx, dir_jacobian, keys):
+    fd = oracle.fd_gradients(mesh, sun, n, bounces, grid, ids, pressure=pressure, angles=angles,
+                             which=keys, theta_idx=theta_idx)
+    if dir_jacobian:
+        fd["dir"] = oracle.fd_dir_jacobian(mesh, n, bounces, grid, ids, pressure=pressure, angles=angles)
+    return fd
+
+
+def grad_report(got, mesh, sun, n, bounces, grid, ids_orc, ids_gpu, pressure=1.0, angles=None, theta_idx=None,
+                dir_jacobian=False, keys=("rho_s", "rho_d", "theta")):
+    """Per-block comparison of the GPU's gradient blocks `got` (dict) with the
+    oracle's central differences on its own recorded ids (`own`), on the
+    GPU's (`vm`), and the share of the rays whose ids differ (`flip`: the two
+    central differences against each other).  Returns {block: (own, vm, flip)}."""
+    fo = _fd(mesh, sun, n, bounces, grid, ids_orc, pressure, angles, theta_idx, dir_jacobian, keys)
+    same = np.array_equal(np.asarray(ids_orc), np.asarray(ids_gpu))
+    fg = fo if same else _fd(mesh, sun, n, bounces, grid, ids_gpu, pressure, angles, theta_idx, dir_jacobian, keys)
+    rep = {}
+    for k in fo:
+        g = got[k] if (k != "theta" or theta_idx is None) else np.asarray(got[k])[list(theta_idx)]
+        rep[k] = (block_err(g, fo[k]), block_err(g, fg[k]), block_err(fg[k], fo[k]))
+    return rep
+
+
+def check_grads(rep):
+    """Visibility matched within G_TOL_VM; on the oracle's hits within G_TOL
+    beyond the flipped rays' share."""
+    for k, (own, vm, flip) in rep.items():
+        assert vm <= G_TOL_VM, (k, rep)
+        assert own <= G_TOL + flip, (k, rep)

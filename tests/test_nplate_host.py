@@ -130,3 +130,14 @@ def test_plates_from_mesh_errors(srp):
     m.tri_mat[0] = 99
     with pytest.raises(SrpError):
         srp.nplate_from_mesh(m)
+
+
+def test_plates_from_mesh_rejects_wrong_angle_count(srp):
+    """The library reads n_dof angles: a shorter (or longer) vector is an
+    error raised before the call, not an out-of-bounds read."""
+    from paper_2608_07307_amd import SrpError
+    m = synth.box_wing()
+    for bad in ([0.1], [0.1, 0.2, 0.3], np.zeros((1, 1))):
+        with pytest.raises(SrpError):
+            srp.nplate_from_mesh(m, bad)
+    assert len(srp.nplate_from_mesh(m, [0.1, -0.2])) > 0
