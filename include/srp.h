@@ -214,6 +214,25 @@ int srp_eval_batch(const srp_batch_item *items, int64_t n_items, srp_result *out
 int srp_eval_grad(srp_scene *scene, const srp_eval_params *params, srp_result *out,
                   double *dF_drho_s, double *dF_drho_d, double *dF_dtheta, double *dF_ddir);
 
+/* srp_eval_batch for callers that cannot allocate memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * kernels and the same results, bitwise, but the call makes no device or
+ * pinned-host allocation (no hipMalloc, hipHostMalloc, hipFree).  Its device
+ * workspace is a fixed array of SRP_NOALLOC_SCRATCH_BYTES per GPU, held by
+ * every GPU the library runs on until the process ends; its host staging
+ * image is a fixed buffer of SRP_NOALLOC_STAGE_BYTES.  A batch whose
+ * workspace does not fit (after reducing the persistent grid) or whose
+ * staging image exceeds the buffer is rejected with SRP_ERR_ARG and a
+ * message giving both sizes; it is never split.  Every call on one GPU uses
+ * that GPU's array: calls ordered on one stream are safe, calls that overlap
+ * on one GPU (other streams, other threads' streams) race and give wrong
+ * results.  The array keeps the last call's contents; the launch sequence
+ * rewrites everything it reads (counters are zeroed by its first kernel).
+ * Items, out_dev and errors as srp_eval_batch; stream-ordered on hip_stream. */
+#define SRP_NOALLOC_SCRATCH_BYTES (64ll << 20)
+#define SRP_NOALLOC_STAGE_BYTES (4ll << 20)
+int srp_eval_batch_noalloc(const srp_batch_item *items, int64_t n_items, srp_result *out_dev, void *hip_stream);
+
 /* Batched form of srp_eval_grad.  grad_dev: device array, item k's gradients
  * at grad_dev + k*grad_stride doubles, laid out as rho_s (M x 3), rho_d
  * (M x 3), theta (J x 3), dF/dd (3 x 3, zeros unless the item's flags hold

@@ -206,6 +206,20 @@ def eval_batch(entries, out=None, stream=None):
     return out
 
 
+def eval_batch_noalloc(entries, out=None, stream=None):
+    """srp_eval_batch_noalloc: srp_eval_batch through the library's fixed
+    per-GPU workspace (the call allocates nothing; batches that do not fit are
+    rejected).  Same arguments and result as eval_batch."""
+    import torch
+    lib = _load()
+    arr, keep, n = _marshalled(entries)
+    if out is None:
+        out = torch.empty(n * RESULT_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+    s = stream if stream is not None else torch.cuda.current_stream()
+    L.check(lib.srp_eval_batch_noalloc(arr, n, C.c_void_p(out.data_ptr()), C.c_void_p(s.cuda_stream)))
+    return out
+
+
 def eval_grad_batch(entries, out=None, grad=None, stream=None):
     """srp_eval_grad_batch (entries: a list as for eval_batch, or a Batch).  Returns (results uint8 tensor, gradients float64
     tensor (n, stride)) with stride = max over entries of grad_size(scene):

@@ -15,7 +15,7 @@ SRP_MAX_N, SRP_MAX_BOUNCES, SRP_MAX_NODES, SRP_MAX_MATS, SRP_MAX_DIFFUSE = 8192,
 
 EXPORTS = [
     "srp_build_scene", "srp_destroy_scene", "srp_scene_n_dof", "srp_set_materials",
-    "srp_set_panel_angles", "srp_eval", "srp_eval_batch", "srp_eval_grad",
+    "srp_set_panel_angles", "srp_eval", "srp_eval_batch", "srp_eval_batch_noalloc", "srp_eval_grad",
     "srp_eval_grad_batch", "srp_last_error", "srp_profile", "srp_profile_read",
     "srp_sun_tracking_angles", "srp_rk4", "srp_propagate",
     "srp_plan_create", "srp_plan_update", "srp_plan_launch", "srp_plan_destroy",
@@ -113,6 +113,7 @@ def load(path: str | None = None):
     lib.srp_set_panel_angles.argtypes = [V, V, I32]
     lib.srp_eval.argtypes = [V, C.POINTER(srp_eval_params), C.POINTER(srp_result), V, V]
     lib.srp_eval_batch.argtypes = [V, I64, V, V]
+    lib.srp_eval_batch_noalloc.argtypes = [V, I64, V, V]
     lib.srp_eval_grad.argtypes = [V, C.POINTER(srp_eval_params), C.POINTER(srp_result), V, V, V, V]
     lib.srp_eval_grad_batch.argtypes = [V, I64, V, V, I64, V]
     lib.srp_last_error.restype = C.c_char_p
@@ -149,7 +150,7 @@ def load(path: str | None = None):
     lib.srp_propagate_spad.argtypes = [C.POINTER(srp_spad_grid), V, C.c_double, C.POINTER(srp_orbit_params), V,
                                        C.c_double, C.c_double, I64, V]
     for f in ("srp_build_scene", "srp_destroy_scene", "srp_set_materials",
-              "srp_set_panel_angles", "srp_eval", "srp_eval_batch", "srp_eval_grad",
+              "srp_set_panel_angles", "srp_eval", "srp_eval_batch", "srp_eval_batch_noalloc", "srp_eval_grad",
               "srp_eval_grad_batch", "srp_profile", "srp_profile_read",
               "srp_sun_tracking_angles", "srp_rk4", "srp_propagate", "srp_plan_create",
               "srp_plan_update", "srp_plan_launch", "srp_plan_destroy", "srp_set_schedule",

@@ -154,6 +154,9 @@ int ws_init() {
         }
         HIPCHK(hipMemcpy(g_ws.d_dset, t.data(), t.size() * sizeof(float), hipMemcpyHostToDevice));
     }
+    // the fixed workspace of srp_eval_batch_noalloc on this device
+    int e = noalloc_scratch_init();
+    if (e) return fail(SRP_ERR_DEVICE, std::string("scratch address lookup: ") + hipGetErrorString((hipError_t)e));
     g_ws.init = true;
     return SRP_OK;
 }
@@ -686,6 +689,34 @@ int run_batch(const srp_batch_item *items, int64_t n, bool grad, const BatchOut 
     return SRP_OK;
 }
 
+// Host staging image of srp_eval_batch_noalloc (descriptors, chunk bases,
+// window slots, articulation slots): a fixed buffer, uploaded from pageable
+// memory (the copy has consumed it when hipMemcpyAsync returns).
+constexpr size_t NOALLOC_STAGE_BYTES = (size_t)4 << 20;
+alignas(256) char g_noalloc_stage[NOALLOC_STAGE_BYTES];
+
+// Shrinks the persistent grids of L until its device workspace fits `cap`
+// bytes (only the traversal stacks' spill area depends on the grid size);
+// fails when even one block does not fit.
+int layout_fit(Layout *Lp, size_t cap) {
+    Layout &L = *Lp;
+    const size_t per_block = sizeof(uint32_t) * STACK_SPILL * (size_t)BLOCK;
+    if (L.o_spill + per_block > cap)
+        return fail(SRP_ERR_ARG, "batch too large for the fixed workspace: it needs " +
+                                     std::to_string(L.o_spill + per_block) + " bytes of the " +
+                                     std::to_string(cap) + " available (split it)");
+    const int max_blocks = (int)std::min<size_t>((cap - L.o_spill) / per_block, 1 << 30);
+    if (L.grid > max_blocks) L.grid = max_blocks;
+    if (L.fan_grid > max_blocks) {
+        L.fan_grid = max_blocks;
+        const int64_t resident = (int64_t)L.fan_grid * (BLOCK / 64);
+        L.fan_claim = 1;
+        while (L.fan_claim < 8 && L.total_units / (2 * L.fan_claim) >= 16 * resident) L.fan_claim *= 2;
+    }
+    L.dev_bytes = align_up(L.o_spill + per_block * (size_t)std::max(L.grid, L.fan_grid));
+    return SRP_OK;
+}
+
 }  // namespace
 
 // A captured launch sequence (upload, window, trace, reduce, result copy)
@@ -1028,6 +1059,30 @@ int srp_eval_batch(const srp_batch_item *items, int64_t n_items, srp_result *out
     BatchOut bo;
     bo.d_out = out_dev;
     return run_batch(items, n_items, false, bo, (hipStream_t)hip_stream);
+}
+
+int srp_eval_batch_noalloc(const srp_batch_item *items, int64_t n_items, srp_result *out_dev, void *hip_stream) {
+    g_err.clear();
+    if (n_items < 0 || (n_items > 0 && (!items || !out_dev))) return fail(SRP_ERR_ARG, "null items or out_dev");
+    if (n_items == 0) return SRP_OK;
+    std::lock_guard<std::mutex> lk(g_ws.mu);
+    // every item's scene was built, so the library is initialised on its device
+    // (scratch address looked up); nothing here allocates
+    if (!g_ws.init) return fail(SRP_ERR_ARG, "no scene has been built");
+    char *scr = noalloc_scratch(g_ws.device);
+    if (!scr) return fail(SRP_ERR_DEVICE, "no scratch address for this device");
+    BatchOut bo;
+    bo.d_out = out_dev;
+    int rc = check_items(items, n_items, false, bo);
+    if (rc) return rc;
+    Layout L;
+    if ((rc = layout_build(items, n_items, false, Schedule(), &L))) return rc;
+    if ((rc = layout_fit(&L, NOALLOC_SCRATCH_BYTES))) return rc;
+    if (L.stage_bytes > NOALLOC_STAGE_BYTES)
+        return fail(SRP_ERR_ARG, "batch too large for the fixed staging area: " + std::to_string(L.stage_bytes) +
+                                     " bytes of " + std::to_string(NOALLOC_STAGE_BYTES) + " (split it)");
+    staging_fill(L, items, bo, g_noalloc_stage, scr);
+    return enqueue(L, scr, g_noalloc_stage, L.stage_bytes, bo, (hipStream_t)hip_stream, false);
 }
 
 int srp_eval_grad_batch(const srp_batch_item *items, int64_t n_items, srp_result *out_dev, double *grad_dev,

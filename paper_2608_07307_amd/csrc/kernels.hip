@@ -1003,6 +1003,30 @@ int check(hipError_t e) { return e == hipSuccess ? 0 : (int)e; }
 
 }  // namespace
 
+// The device workspace of srp_eval_batch_noalloc.  Its name is a host-side
+// stand-in in host code: only the address looked up on each device is passed
+// to kernels and copies.
+static __device__ __align__(256) char scratch[NOALLOC_SCRATCH_BYTES];
+
+static char *g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+int noalloc_scratch_init() {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return (int)e;
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return (int)hipErrorInvalidDevice;
+    if (g_scratch_ptr[dev]) return 0;
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return (int)e;
+    g_scratch_ptr[dev] = static_cast<char *>(p);
+    return 0;
+}
+
+char *noalloc_scratch(int device) {
+    return (device >= 0 && device < NOALLOC_MAX_DEVICES) ? g_scratch_ptr[device] : nullptr;
+}
+
 int launch_window(const EvalDesc *d_desc, int n_evals, int blocks_x, uint64_t *d_win, uint32_t *d_queue,
                   void *stream) {
     if (n_evals <= 0) return 0;

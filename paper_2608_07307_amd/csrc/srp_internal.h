@@ -278,4 +278,14 @@ int trace_blocks_per_cu(bool count, bool grad, bool dir, int lds_grad_doubles);
 // Resident blocks per compute unit of the fan kernel variant.
 int fan_blocks_per_cu(bool count);
 
+// Fixed device workspace of the entry point that allocates nothing: a
+// file-scope static device array in kernels.hip, NOALLOC_SCRATCH_BYTES per
+// GPU, held until the process ends.  noalloc_scratch_init looks up its address
+// on the current device (once per device; the library's init calls it);
+// noalloc_scratch returns that address (nullptr before the lookup).
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)64 << 20;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+int noalloc_scratch_init();
+char *noalloc_scratch(int device);
+
 }  // namespace srp
