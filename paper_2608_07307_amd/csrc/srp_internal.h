@@ -28,7 +28,10 @@ constexpr uint32_t REF_TLAS_NODE = 2u;
 constexpr uint32_t REF_TLAS_LEAF = 3u;
 constexpr uint32_t REF_NONE = 0xFFFFFFFFu;
 constexpr int LEAF_MAX = 8;
-constexpr int STACK_DEPTH = 64;             // per-lane traversal stack entries (the build checks each hierarchy's worst case)
+#ifndef SRP_STACK_DEPTH
+#define SRP_STACK_DEPTH 64                  // (a host build of the traversal may lower it to check overflow reporting)
+#endif
+constexpr int STACK_DEPTH = SRP_STACK_DEPTH;   // per-lane traversal stack entries (the build checks each hierarchy's worst case)
 #ifndef SRP_STACK_LDS
 #define SRP_STACK_LDS 16                    // (a host build may shrink it to exercise the spill path)
 #endif

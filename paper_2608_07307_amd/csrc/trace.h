@@ -208,10 +208,12 @@ SRP_HD inline uint32_t st_load(const LaneStack &S, int e) {
 // steps.  The descent loop has a single exit (stack overflow and the visit
 // bound are reported after it).  Returns false only when the stack or the
 // visit bound is exceeded (corrupted data).
+// (steps, deepest: optional instrumentation of a host build, the node and
+// leaf visits and the most entries the stack held.)
 template <bool COUNT>
 SRP_HD inline bool trace_closest(const TraceCtx &C, const float o[3], const float d[3], float tmin,
                                  int32_t exclude_id, const LaneStack &stack, Hit &h, uint32_t &nbox,
-                                 uint32_t &ntri, uint32_t *steps = nullptr) {
+                                 uint32_t &ntri, uint32_t *steps = nullptr, int *deepest = nullptr) {
     h.t = T_INF;
     h.tri = -1;
     h.inst = -1;
@@ -293,6 +295,7 @@ SRP_HD inline bool trace_closest(const TraceCtx &C, const float o[3], const floa
                         }
                     }
                 }
+                if (deepest && sp > *deepest) *deepest = sp;
                 if (hits > 0) {
                     ref = r[0];   // descend into the nearest
                 } else if (sp > 0) {
