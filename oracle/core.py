@@ -49,7 +49,8 @@ class _Result(C.Structure):
     _fields_ = [("force", C.c_double * 3), ("torque", C.c_double * 3), ("n_rays", C.c_int64),
                 ("n_hits", C.c_int64), ("n_secondary", C.c_int64),
                 ("n_secondary_hits", C.c_int64), ("n_diffuse", C.c_int64),
-                ("n_diffuse_hits", C.c_int64), ("grid", _Grid)]
+                ("n_diffuse_hits", C.c_int64), ("n_box_tests", C.c_int64), ("n_tri_tests", C.c_int64),
+                ("grid", _Grid)]
 
 
 def _load():
@@ -116,6 +117,8 @@ class OracleResult:
     ts: np.ndarray | None = None
     n_diffuse: int = 0
     n_diffuse_hits: int = 0
+    n_box_tests: int = 0
+    n_tri_tests: int = 0
 
 
 def _grid_dict(g: _Grid) -> dict:
@@ -163,7 +166,7 @@ def eval_srp(scene, sun_dir, n, bounces=0, pressure=1.0, ref=(0, 0, 0), angles=N
         raise ValueError(f"oracle eval failed ({rc})")
     return OracleResult(np.array(out.force[:]), np.array(out.torque[:]), out.n_rays, out.n_hits,
                         out.n_secondary, out.n_secondary_hits, _grid_dict(out.grid), ids, ts,
-                        out.n_diffuse, out.n_diffuse_hits)
+                        out.n_diffuse, out.n_diffuse_hits, out.n_box_tests, out.n_tri_tests)
 
 
 def diffuse_set(K) -> np.ndarray:

@@ -420,14 +420,17 @@ static int box_hit(const bnode *n, const double *o, const double *d, double tmin
     return 1;
 }
 
-/* Closest hit along o + t d with t > tmin, skipping triangle `exclude`. */
+/* Closest hit along o + t d with t > tmin, skipping triangle `exclude`.
+ * cnt (may be NULL) accumulates the box and triangle tests made (a count of
+ * work only: the result does not depend on it). */
 static void closest_hit(const bvh *B, const double *wtri, int64_t nt, const double *o, const double *d,
-                        double tmin, int64_t exclude, double *best_t, int64_t *best)
+                        double tmin, int64_t exclude, double *best_t, int64_t *best, int64_t *cnt)
 {
     *best_t = INFINITY;
     *best = -1;
     if (!B) {
         for (int64_t t = 0; t < nt; ++t) consider(o, d, wtri, t, tmin, exclude, best_t, best);
+        if (cnt) cnt[1] += nt;
         return;
     }
     if (B->nn == 0) return;
@@ -436,8 +439,10 @@ static void closest_hit(const bvh *B, const double *wtri, int64_t nt, const doub
     stack[sp++] = 0;
     while (sp) {
         const bnode *n = &B->n[stack[--sp]];
+        if (cnt) cnt[0]++;
         if (!box_hit(n, o, d, tmin, *best_t)) continue;
         if (n->count) {
+            if (cnt) cnt[1] += n->count;
             for (int64_t k = n->first; k < n->first + n->count; ++k)
                 consider(o, d, wtri, B->idx[k], tmin, exclude, best_t, best);
         } else {
@@ -549,7 +554,7 @@ int32_t orc_record_slots(const orc_params *P)
 }
 
 /* ------------------------------------------------------------ evaluation */
-typedef struct { double f[6]; int64_t hits, sec, sec_hits, dif, dif_hits; } pix_out;
+typedef struct { double f[6]; int64_t hits, sec, sec_hits, dif, dif_hits, tests[2]; } pix_out;
 
 static void trace_pixel(const orc_scene *S, const double *wtri, const bvh *B, const orc_params *P,
                         const orc_grid *g, int64_t pix, pix_out *po, int32_t *ids, double *ts,
@@ -568,7 +573,7 @@ static void trace_pixel(const orc_scene *S, const double *wtri, const bvh *B, co
     for (int32_t gen = 0; gen <= P->bounces; ++gen) {
         double bt;
         int64_t bi;
-        closest_hit(B, wtri, S->nt, o, d, tmin, exclude, &bt, &bi);
+        closest_hit(B, wtri, S->nt, o, d, tmin, exclude, &bt, &bi, po->tests);
         if (bi < 0) break;
         if (ids) ids[gen] = (int32_t)bi;
         if (ts) ts[gen] = bt;
@@ -592,7 +597,7 @@ static void trace_pixel(const orc_scene *S, const double *wtri, const bvh *B, co
                 int64_t ei;
                 po->sec++;
                 po->dif++;
-                closest_hit(B, wtri, S->nt, x, e, 1e-6 * g->L, bi, &et, &ei);
+                closest_hit(B, wtri, S->nt, x, e, 1e-6 * g->L, bi, &et, &ei, po->tests);
                 int32_t slot = P->bounces + 1 + gen * K + k;
                 if (ei < 0) continue;
                 if (ids) ids[slot] = (int32_t)ei;
@@ -632,6 +637,8 @@ static void finish(const orc_scene *S, const orc_params *P, const orc_grid *g, c
         out->n_secondary_hits += po[k].sec_hits;
         out->n_diffuse += po[k].dif;
         out->n_diffuse_hits += po[k].dif_hits;
+        out->n_box_tests += po[k].tests[0];
+        out->n_tri_tests += po[k].tests[1];
     }
     for (int c = 0; c < 3; ++c) { out->force[c] = ks_val(&acc[c]); out->torque[c] = ks_val(&acc[3 + c]); }
     out->n_rays = np;

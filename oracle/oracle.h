@@ -48,6 +48,7 @@ typedef struct {
     double force[3], torque[3];
     int64_t n_rays, n_hits, n_secondary, n_secondary_hits;
     int64_t n_diffuse, n_diffuse_hits;   /* the diffuse part of the secondary counts */
+    int64_t n_box_tests, n_tri_tests;    /* work of the evaluation (orc_eval only): box and triangle tests */
     orc_grid grid;
 } orc_result;
 
