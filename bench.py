@@ -109,7 +109,8 @@ def time_config(srp, torch, name, stream, steps):
                 f"{n}x{n} rays, B={B}, forward + adjoint")
     else:
         raise SystemExit(f"unknown workload {name}")
-    entries = srp.Batch([(s_, a, srp.params(d, n_, B)) for s_, a, d, n_ in items])   # marshalled once
+    plain_items = [(s_, a, srp.params(d, n_, B)) for s_, a, d, n_ in items]
+    entries = srp.Batch(plain_items)   # marshalled once
     E = len(entries)
     cnt = srp.results_to_numpy(srp.eval_batch([(s_, a, srp.params(d, n_, B, count=True)) for s_, a, d, n_ in items]))
     rays = int(cnt["n_rays"].sum() + cnt["n_secondary"].sum())
@@ -129,12 +130,36 @@ def time_config(srp, torch, name, stream, steps):
     res = srp.results_to_numpy(out[0] if grad else out)
     assert (res["status"] == 0).all()
     kern = ms / 1e3 / steps   # the ray-tracing kernels of one call (of all its sub-batches)
+    rec = {"workload": desc, "evals": E}
+    if name == "c4":
+        # the uneven batch as a captured graph (upload, window, trace, reduction), replayed
+        plan = srp.Plan(plain_items)
+        ref = res.tobytes()
+        pout = plan.launch(stream)
+        torch.cuda.synchronize()
+        assert srp.results_to_numpy(pout).tobytes() == ref, "plan replay differs from the direct batch"
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            pout = plan.launch(stream)
+        torch.cuda.synchronize()
+        dt_plan = (time.perf_counter() - t0) / steps
+        assert srp.results_to_numpy(pout).tobytes() == ref
+        plan.close()
+        _log(f"{name} (graph replays): {E / dt_plan:.1f} evals/s, {dt_plan * 1e3:.2f} ms per replay "
+             f"(direct call {dt * 1e3:.2f} ms)")
+        rec.update(path="srp_plan (captured graph replay); kernel_ms from a profiled direct call of the same batch",
+                   evals_per_s=round(E / dt_plan, 2), grays_per_s=round(rays / dt_plan / 1e9, 3),
+                   ms_per_call=round(dt_plan * 1e3, 3), direct_ms_per_call=round(dt * 1e3, 3))
+    else:
+        rec.update(path="srp_eval_grad_batch" if grad else "srp_eval_batch",
+                   evals_per_s=round(E / dt, 2), grays_per_s=round(rays / dt / 1e9, 3), ms_per_call=round(dt * 1e3, 3))
     _log(f"{name}: {E / dt:.1f} evals/s, {rays / dt / 1e9:.2f} Grays/s, kernels {kern * 1e3:.2f} ms of "
         f"{dt * 1e3:.2f} ms per call ({launches // steps} launches)")
-    return {"workload": desc, "evals": E, "evals_per_s": round(E / dt, 2), "grays_per_s": round(rays / dt / 1e9, 3),
-            "rays_per_call": rays, "ms_per_call": round(dt * 1e3, 3), "kernel_ms": round(kern * 1e3, 3),
-            "launches_per_call": launches // steps, "lane_op_frac": round(work / kern / PEAK_LANE_OPS, 4),
-            "schedule": {"patches_per_chunk": tune[0], "blocks_per_cu": tune[1]}}
+    rec.update(rays_per_call=rays, kernel_ms=round(kern * 1e3, 3), launches_per_call=launches // steps,
+               lane_op_frac=round(work / kern / PEAK_LANE_OPS, 4),
+               tests_per_ray=round((int(cnt["n_box_tests"].sum()) + int(cnt["n_tri_tests"].sum())) / rays, 2),
+               schedule={"patches_per_chunk": tune[0], "blocks_per_cu": tune[1]})
+    return rec
 
 
 def main():
@@ -155,8 +180,8 @@ def main():
     ap.add_argument("--p2", type=int, default=1,
                     help="20-revolution propagation timing (0: skip, 1: fixed panels, 2: also tracking panels)")
     ap.add_argument("--p2-revs", type=int, default=20)
-    ap.add_argument("--configs", default="",
-                    help="also time these other workloads, comma-separated from c1,c3,c4,c5 (off by default)")
+    ap.add_argument("--configs", default="c1,c3,c4,c5",
+                    help="also time these other workloads, comma-separated from c1,c3,c4,c5 ('' to skip)")
     ap.add_argument("--p2-rtol", type=float, default=1e-9)
     ap.add_argument("--c2-prop-steps", type=int, default=1440,
                     help="RK4 steps of 60 s of the headline workload's propagation leg (0: skip)")
@@ -499,9 +524,10 @@ def main():
         g_host = grad.cpu().numpy()
         M, J = mesh.n_mats, mesh.n_dof
         t0 = time.perf_counter()
-        fds = []
+        fds, orcs = [], []
         for k in range(args.cpu_samples):
             o = oracle.eval_srp(mesh, dirs[k], N, bounces=B, angles=angles[k], record=True)
+            orcs.append(o)
             fds.append(oracle.fd_gradients(mesh, dirs[k], N, B, o.grid, o.ids, angles=angles[k]))
             errs.append(float(np.linalg.norm(res[k]["force"] - o.force) / np.linalg.norm(o.force)))
         t1 = time.perf_counter()
@@ -510,19 +536,43 @@ def main():
                       "theta": g_host[k, 6 * M:6 * M + 3 * J].reshape(J, 3)}
             for key, gk in blocks.items():
                 gerrs[key].append(float(np.abs(gk - fd[key]).max() / np.abs(fd[key]).max()))
+        # primary ids of the sampled items (their single recorded evaluations, bitwise the
+        # batch's) against the oracle's: rays that differ must lie in the edge band
+        sys.path.insert(0, os.path.join(ROOT, "tests"))
+        from parity import classify_primary
+        band, mism, outside = [], 0, 0
+        for k, o in enumerate(orcs):
+            scene.set_angles(angles[k])
+            single = srp.eval(scene, dirs[k], N, bounces=B, record=True)
+            assert np.array_equal(single["force"], res[k]["force"])
+            m_, out_, frac_ = classify_primary(mesh, angles[k], o.grid, N, o.ids[:, 0], single["ids"][:, 0])
+            band.append(frac_)
+            mism += m_
+            outside += out_
+        orc_tests = sum(o.n_box_tests + o.n_tri_tests for o in orcs) / sum(o.n_rays + o.n_secondary for o in orcs)
         cpu = {"value": round(args.cpu_samples / (t1 - t0), 4), "unit": "evals/s",
                "cores": oracle.threads(), "kind": "oracle",
                "sample": f"{args.cpu_samples} of the {E} batch items: FP64 forward (oracle BVH) + "
                          f"central-difference gradient ({2 * (2 * mesh.n_mats + mesh.n_dof)} "
                          f"fixed-visibility re-shades), {N}x{N} rays, B={B}"}
         parity = {"max_rel_force_err": max(errs), "items_checked": args.cpu_samples,
+                  "primary_ids_differing": mism, "primary_ids_differing_outside_edge_band": outside,
+                  "edge_band_fraction": max(band),
+                  "edge_band_definition": "fraction of primary rays whose GPU and oracle hits differ inside the "
+                                          "edge band (image-plane distance to an edge of either triangle, or "
+                                          "depth difference, <= 1e-6 L)",
                   "max_rel_grad_err": {k: max(v) for k, v in gerrs.items()},
                   "grad_err_definition": "per block: max |adjoint - oracle central difference (h = 1e-4, "
                                          "oracle's own hits)| / max |oracle central difference|"}
-        log(f"oracle: {cpu['value']} evals/s on {cpu['cores']} threads; parity {max(errs):.2e}")
+        cpu["oracle_bvh_tests_per_ray"] = round(orc_tests, 2)
+        log(f"oracle: {cpu['value']} evals/s on {cpu['cores']} threads; parity {max(errs):.2e}; "
+            f"edge band {max(band):.2e}; oracle BVH {orc_tests:.1f} tests/ray")
 
     achieved = work / kern_s / 1e12
     peak = PEAK_LANE_OPS / 1e12
+    vp = srp.valu_peak()
+    log(f"measured FMA-loop peak: {vp['lane_fma_per_s'] / 1e12:.2f} T lane-FMA/s at {vp['shader_ghz']:.3f} GHz "
+        f"on {vp['n_cu']} CUs")
     line = {
         "metric": "SRP evals/sec and Grays/s at 1024^2 rays, batched+adjoint vs plain, at 1e-5 rel force err",
         "value": round(value, 3),
@@ -559,8 +609,19 @@ def main():
             "peak": round(peak, 4),
             "unit": "Tlane-op/s",
             "frac": round(achieved / peak, 4),
+            "peak_definition": "256 CUs x 64 lanes x 2.4 GHz: one non-packed VALU lane-op per lane per cycle",
+            "frac_vs_packed_peak": round(achieved / (2 * peak), 4),
+            "packed_peak_definition": "157.3 TFLOP/s FP32 = 78.6 T packed lane-FMA/s (packed FP32 is not used here)",
+            "measured_peak": {"lane_fma_per_s_T": round(vp["lane_fma_per_s"] / 1e12, 4),
+                              "shader_ghz": round(vp["shader_ghz"], 4), "n_cu": vp["n_cu"],
+                              "frac": round(achieved * 1e12 / vp["lane_fma_per_s"], 4),
+                              "how": "srp_valu_peak: 8 waves per SIMD, 8 independent v_fma_f32 chains per lane"},
+            "tests_per_ray": round((n_box + n_tri) / rays_total, 2),
             "traffic": measured_traffic({"patches_per_chunk": tune[0], "blocks_per_cu": tune[1]}),
             "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "traffic_source": "not measured by this run: the committed counter record "
+                              "profiles/k_trace_grad_traffic.json, used only while its kernel-code digest "
+                              "and schedule match this run (null otherwise)",
             "kernel": "k_trace<GRAD> (forward + adjoint)",
             "work_per_launch": {"box_tests": n_box, "tri_tests": n_tri,
                                 "lane_ops": work, "ops_per_box": BOX_OPS, "ops_per_tri": TRI_OPS},

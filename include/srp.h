@@ -484,6 +484,17 @@ int srp_profile(int enable);
 int srp_profile_read(double *trace_ms, int64_t *launches);
 
 /* Thread-local message of the last error ("" if none). */
+/* ---- measurement ---- */
+
+/* The measured issue rate of non-packed FP32 fused multiply-adds on the
+ * current GPU: a kernel of 8 waves per SIMD, each lane running 8 independent
+ * FMA chains, timed with HIP events after a warm-up launch.  Writes the
+ * lane-FMAs per second (*lane_fma_per_s), the shader clock the timed launch
+ * ran at (*shader_ghz: its clock counter over its constant-rate wall clock)
+ * and the compute-unit count (*n_cu).  Allocates and frees a few MB of
+ * device memory; SRP_ERR_DEVICE on a HIP failure. */
+int srp_valu_peak(double *lane_fma_per_s, double *shader_ghz, int32_t *n_cu);
+
 const char *srp_last_error(void);
 
 #ifdef __cplusplus

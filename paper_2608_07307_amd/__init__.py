@@ -206,6 +206,14 @@ def eval_batch(entries, out=None, stream=None):
     return out
 
 
+def valu_peak() -> dict:
+    """srp_valu_peak: measured non-packed FP32 FMA issue rate (lane-FMAs/s),
+    the shader clock it ran at (GHz) and the compute-unit count."""
+    r, g, n = C.c_double(0), C.c_double(0), C.c_int32(0)
+    L.check(_load().srp_valu_peak(C.byref(r), C.byref(g), C.byref(n)))
+    return dict(lane_fma_per_s=r.value, shader_ghz=g.value, n_cu=n.value)
+
+
 def eval_batch_noalloc(entries, out=None, stream=None):
     """srp_eval_batch_noalloc: srp_eval_batch through the library's fixed
     per-GPU workspace (the call allocates nothing; batches that do not fit are

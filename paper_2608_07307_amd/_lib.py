@@ -22,7 +22,7 @@ EXPORTS = [
     "srp_set_schedule", "srp_autotune", "srp_spad_build", "srp_spad_interp", "srp_propagate_spad",
     "srp_rk78", "srp_propagate_rk78", "srp_propagate_spad_rk78",
     "srp_nplate_from_scene", "srp_nplate_from_mesh", "srp_nplate_eval", "srp_propagate_nplate",
-    "srp_propagate_nplate_rk78",
+    "srp_propagate_nplate_rk78", "srp_valu_peak",
 ]
 SRP_PLAN_GRAD = 1
 SRP_F_GRAD_DIR = 2
@@ -114,6 +114,7 @@ def load(path: str | None = None):
     lib.srp_eval.argtypes = [V, C.POINTER(srp_eval_params), C.POINTER(srp_result), V, V]
     lib.srp_eval_batch.argtypes = [V, I64, V, V]
     lib.srp_eval_batch_noalloc.argtypes = [V, I64, V, V]
+    lib.srp_valu_peak.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(I32)]
     lib.srp_eval_grad.argtypes = [V, C.POINTER(srp_eval_params), C.POINTER(srp_result), V, V, V, V]
     lib.srp_eval_grad_batch.argtypes = [V, I64, V, V, I64, V]
     lib.srp_last_error.restype = C.c_char_p
