@@ -76,7 +76,7 @@ def time_config(srp, torch, name, stream, steps):
     uneven 64-scene batch (c4), the 1M-triangle batch of 256 attitudes at
     2048^2 with the adjoint (c5).  Autotuned, one warm-up call, `steps` timed
     calls (a call runs as consecutive sub-batches when its workspace would
-    pass 2 GB); ray and test counts from one counting call."""
+    pass 16 GiB); ray and test counts from one counting call."""
     import synth
     grad = False
     if name == "c1":

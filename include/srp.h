@@ -185,7 +185,7 @@ int srp_eval(srp_scene *scene, const srp_eval_params *params, srp_result *out,
  * written in stream order on hip_stream (a hipStream_t; NULL = null stream).
  * The call returns once the work is queued; host inputs may be reused then.
  * A batch whose device workspace (about 64 bytes per 8x8-pixel patch, plus
- * gradient partials) would exceed 2 GiB runs as consecutive sub-batches; the
+ * gradient partials) would exceed 16 GiB runs as consecutive sub-batches; the
  * call may then block while earlier sub-batches run.  Results are bitwise
  * independent of scheduling and of that split.  Errors as srp_eval, checked
  * for every item before anything is queued. */
@@ -269,13 +269,17 @@ int srp_plan_destroy(srp_plan *plan);
  * unit of the persistent grid (1..64, capped at the kernel's occupancy);
  * 0 = automatic (autotuned value for the batch's size class if any, else a
  * heuristic).  Forces and torques do not depend on the schedule (every patch
- * keeps its own partial sum); gradients are deterministic per schedule.
- * Errors: SRP_ERR_ARG (out of range). */
+ * keeps its own partial sum).  The adjoint's chunks are fixed groups of an
+ * evaluation's patches (8 to 64, the smallest power of two whose gradient
+ * partials for that evaluation fit 8 MiB), so it takes only the blocks per
+ * CU from the schedule and its gradients do not depend on the schedule
+ * either.  Errors: SRP_ERR_ARG (out of range). */
 int srp_set_schedule(int32_t patches_per_chunk, int32_t blocks_per_cu);
 
 /* Times the batch under candidate schedules (patches per chunk 1..64 in powers
- * of two, full and half occupancy; the best of four timed runs after a
- * warm-up each) and keeps the fastest for batches of the
+ * of two, full and half occupancy; with SRP_PLAN_GRAD the occupancy only, the
+ * adjoint's chunks being its evaluations' fixed patch groups; the best of four
+ * timed runs after a warm-up each) and keeps the fastest for batches of the
  * same size class (total primary rays to a power of two, bounce count,
  * gradient flag).  Outputs the choice and its time (ms); any output pointer
  * may be NULL.  Blocks.  Errors as srp_eval_batch. */

@@ -298,6 +298,7 @@ struct Layout {
     std::vector<int> n_slices;    // reduction range sums per item (first stage)
     std::vector<size_t> emit_off;   // emitter records of each item with diffuse fans (0: none)
     std::vector<int> grad_n;   // gradient partial doubles per chunk of each item (allocation and kernel)
+    std::vector<int> item_ppc;   // patches per chunk of each item (the adjoint: its gradient group)
     int grid = 1, fan_grid = 0, fan_claim = 1, fan_parts = 0, wb = 1;
     bool fans_inline = false;   // the trace kernel traces the fans itself (no fan launch)
 };
@@ -334,18 +335,22 @@ int check_items(const srp_batch_item *items, int64_t n, bool grad, const BatchOu
     return SRP_OK;
 }
 
-// Gradient partials are per chunk: a launch keeps them under this many bytes
-// by raising the patches per chunk; a batch whose whole device workspace
-// would exceed WORKSPACE_CAP runs as consecutive sub-batches.
-constexpr size_t GRAD_PART_CAP = (size_t)256 << 20;
-constexpr size_t WORKSPACE_CAP = (size_t)2 << 30;
+// The adjoint's gradient partials are per chunk, and an adjoint chunk is a
+// fixed group of an evaluation's patches whose size depends on that
+// evaluation alone (grad_group), never on the schedule: gradient bits then do
+// not depend on the autotuner, the blocks per CU or the batch around an
+// evaluation.  The group is the smallest power of two from GRAD_GROUP_MIN up
+// to MAX_PPC patches whose partials for the evaluation fit GRAD_PART_EVAL
+// bytes.  A batch whose whole device workspace would exceed WORKSPACE_CAP
+// runs as consecutive sub-batches.
+constexpr int GRAD_GROUP_MIN = 8;
+constexpr size_t GRAD_PART_EVAL = (size_t)8 << 20;
+constexpr size_t WORKSPACE_CAP = (size_t)16 << 30;   // of the MI355X's 288 GB: the 32,768-evaluation table at 512^2 (8.6 GB of patch partials) runs as one launch
 
-// Smallest power-of-two patches per chunk (<= MAX_PPC) whose gradient partials fit GRAD_PART_CAP.
-int min_ppc_for_grad(int64_t total_patches, int max_grad_n) {
-    int ppc = 1;
-    while (ppc < MAX_PPC && (size_t)((total_patches + ppc - 1) / ppc) * max_grad_n * sizeof(double) > GRAD_PART_CAP)
-        ppc *= 2;
-    return ppc;
+int grad_group(int64_t n_patches, int grad_n) {
+    int g = GRAD_GROUP_MIN;
+    while (g < MAX_PPC && (size_t)((n_patches + g - 1) / g) * grad_n * sizeof(double) > GRAD_PART_EVAL) g *= 2;
+    return g;
 }
 
 Schedule pick_schedule(const srp_batch_item *items, int64_t n, bool grad, int64_t total_patches, int occ,
@@ -366,7 +371,6 @@ Schedule pick_schedule(const srp_batch_item *items, int64_t n, bool grad, int64_
         s.ppc = 1;
         while (s.ppc < 4 && total_patches / (2 * s.ppc) >= 16 * resident) s.ppc *= 2;
     }
-    if (grad) s.ppc = std::max(s.ppc, min_ppc_for_grad(total_patches, max_grad_n));
     s.bpc = std::max(1, std::min(s.bpc, occ));
     return s;
 }
@@ -396,10 +400,14 @@ int layout_build(const srp_batch_item *items, int64_t n, bool grad, Schedule for
     L.sch = (force.ppc && force.bpc) ? force : pick_schedule(items, n, grad, L.total_patches, occ, L.max_grad_n);
     if (force.ppc) L.sch.ppc = force.ppc;
     if (force.bpc) L.sch.bpc = std::min(force.bpc, occ);
-    if (grad) L.sch.ppc = std::max(L.sch.ppc, min_ppc_for_grad(L.total_patches, L.max_grad_n));
+    // patches per chunk: the schedule's for the forward launch, each evaluation's
+    // own gradient group for the adjoint
+    L.item_ppc.assign(n, L.sch.ppc);
     for (int64_t k = 0; k < n; ++k) {
+        const int64_t np = L.patch_base[k + 1] - L.patch_base[k];
+        if (grad) L.item_ppc[k] = grad_group(np, grad_slots(items[k].scene, items[k].p.flags));
         L.chunk_base[k] = L.total_chunks;
-        L.total_chunks += (L.patch_base[k + 1] - L.patch_base[k] + L.sch.ppc - 1) / L.sch.ppc;
+        L.total_chunks += (np + L.item_ppc[k] - 1) / L.item_ppc[k];
     }
     L.chunk_base[n] = L.total_chunks;
     // diffuse fans (forward only; emitters are chain hits of generation < bounces).
@@ -586,7 +594,7 @@ void staging_fill(const Layout &L, const srp_batch_item *items, const BatchOut &
         D.dset = it.p.n_diffuse > 0 ? g_ws.d_dset + 4 * dset_entry(it.p.n_diffuse) : nullptr;
         D.tiles_x = L.tiles_x[k];
         D.tiles_y = L.tiles_y[k];
-        D.ppc = L.sch.ppc;
+        D.ppc = L.item_ppc[k];
         D.chunk_base = L.chunk_base[k];
         D.n_chunks = L.chunk_base[k + 1] - L.chunk_base[k];
         D.patch_base = L.patch_base[k];
@@ -1261,19 +1269,20 @@ int srp_autotune(const srp_batch_item *items, int64_t n_items, int32_t flags, in
         total_patches += 4 * t * t;
     }
     // candidates: patches per chunk 1..64 (powers of two) that give every
-    // resident wave at least one chunk and at most 64 (the gradient partials
-    // are per chunk), at full and half occupancy
+    // resident wave at least one chunk and at most 64, at full and half
+    // occupancy; the adjoint's chunks are its evaluations' gradient groups, so
+    // only the occupancy is tuned for it
     std::vector<Schedule> cands;
     for (int b : {occ, std::max(1, occ / 2)}) {
         const int64_t resident = (int64_t)g_ws.n_cu * b * (BLOCK / 64);
         for (int ppc = 1; ppc <= MAX_PPC; ppc *= 2) {
             const int64_t chunks = (total_patches + ppc - 1) / ppc;
-            if ((chunks < resident && ppc > 1) || chunks > 64 * resident) continue;
-            if (grad && ppc < min_ppc_for_grad(total_patches, mg)) continue;
+            if (!grad && ((chunks < resident && ppc > 1) || chunks > 64 * resident)) continue;
             Schedule sc;
-            sc.ppc = ppc;
+            sc.ppc = grad ? GRAD_GROUP_MIN : ppc;
             sc.bpc = b;
             cands.push_back(sc);
+            if (grad) break;
         }
         if (b == 1) break;
     }

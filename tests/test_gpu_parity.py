@@ -338,9 +338,11 @@ def test_autograd_function(srp):
 
 def test_schedules_plans_and_autotune(srp):
     """Forces are bitwise identical under every schedule (per-patch partial
-    sums); a captured plan replays bitwise the direct batch, also after an
-    update with new Sun directions and angles; the autotuner returns a valid
-    schedule that is then used."""
+    sums), and so are gradients (per fixed patch group of each evaluation),
+    which also equal each item's gradients in a batch of its own; a captured plan
+    replays bitwise the direct batch, also after an update with new Sun
+    directions and angles; the autotuner returns a valid schedule that is
+    then used."""
     import torch
     mesh = synth.procedural_sized(51, 5000)
     sc = srp.Scene(mesh)
@@ -353,7 +355,22 @@ def test_schedules_plans_and_autotune(srp):
         srp.set_schedule(ppc, bpc)
         got = srp.results_to_numpy(srp.eval_batch(entries))
         assert got.tobytes() == ref.tobytes(), (ppc, bpc)
+    # gradients: the adjoint's chunks are fixed patch groups of each evaluation,
+    # so the gradient bits do not depend on the schedule either, and a batch
+    # item's gradients are bitwise its single evaluation's
+    gref = None
+    for ppc, bpc in ((1, 1), (8, 0), (64, 4), (0, 0), (2, 3)):
+        srp.set_schedule(ppc, bpc)
+        gres, grad = srp.eval_grad_batch(entries)
+        g = grad.cpu().numpy()
+        assert srp.results_to_numpy(gres)["force"].tobytes() == ref["force"].tobytes()
+        if gref is None:
+            gref = g.copy()
+        assert g.tobytes() == gref.tobytes(), (ppc, bpc)
     srp.set_schedule(0, 0)
+    for k in (0, 7, 23):
+        _, g1 = srp.eval_grad_batch([entries[k]])
+        assert g1.cpu().numpy()[0].tobytes() == gref[k].tobytes(), k
     plan = srp.Plan(entries)
     for _ in range(3):
         out = srp.results_to_numpy(plan.launch())
