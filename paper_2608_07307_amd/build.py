@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsrp_mi355x.so")
-SOURCES = ["kernels.hip", "peak.hip", "scene.cpp", "capi.cpp", "propagate.cpp", "spad.cpp", "nplate.cpp"]
+SOURCES = ["kernels.hip", "articulate.hip", "peak.hip", "scene.cpp", "capi.cpp", "propagate.cpp", "spad.cpp", "nplate.cpp"]
 ARCH = "gfx950"
 
 

@@ -1,0 +1,160 @@
+// Articulation slots on the GPU (Sec. 4.4.2 steps 1, 4 and 5 as rigid
+// instance transforms; Sec. 4.4.1 for the tree): one thread per slot composes
+// the node transforms down the kinematic tree in FP64, writes the instances
+// and world hinge axes, and refits the scene's fixed top-level topology to the
+// instances' world boxes.  The host computes the cosine and sine of every
+// clamped angle (the same library calls as its own slot build); everything
+// after that is the host build's sequence of separately rounded FP64
+// operations (contraction is off in this file and in the host's), so a slot
+// built here holds the same bits as one built on the host for the same
+// angles.
+#include <hip/hip_runtime.h>
+
+#include "srp.h"
+#include "srp_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace srp {
+namespace {
+
+constexpr int ART_BLOCK = 64;
+
+// std::min and std::max as the host build calls them (the first argument on ties)
+template <typename T>
+__device__ inline T lmin(T a, T b) { return (b < a) ? b : a; }
+template <typename T>
+__device__ inline T lmax(T a, T b) { return (a < b) ? b : a; }
+
+__device__ inline void mat3_mul(const double *A, const double *B, double *C) {
+    double T[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) T[3 * i + j] = A[3 * i] * B[j] + A[3 * i + 1] * B[3 + j] + A[3 * i + 2] * B[6 + j];
+    for (int i = 0; i < 9; ++i) C[i] = T[i];
+}
+
+__device__ inline void mat3_vec(const double *A, const double *x, double *y) {
+    double t[3];
+    for (int i = 0; i < 3; ++i) t[i] = A[3 * i] * x[0] + A[3 * i + 1] * x[1] + A[3 * i + 2] * x[2];
+    for (int i = 0; i < 3; ++i) y[i] = t[i];
+}
+
+// Rotation by the angle of cosine c and sine s about the unit axis u (Rodrigues).
+__device__ inline void rot_unit(const double *u, double c, double s, double *R) {
+    const double x = u[0], y = u[1], z = u[2], C = 1 - c;
+    R[0] = c + x * x * C;
+    R[1] = x * y * C - z * s;
+    R[2] = x * z * C + y * s;
+    R[3] = y * x * C + z * s;
+    R[4] = c + y * y * C;
+    R[5] = y * z * C - x * s;
+    R[6] = z * x * C - y * s;
+    R[7] = z * y * C + x * s;
+    R[8] = c + z * z * C;
+}
+
+// The instance's top-level box: its padded rest-pose box's eight corners under
+// X, their extremes grown by the padding and rounded outward to FP32.
+__device__ inline void inst_box(const ArtNode &nd, const double *X, double pad, float lo[3], float hi[3]) {
+    double l[3] = {INFINITY, INFINITY, INFINITY}, h[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int c = 0; c < 8; ++c) {
+        const double p[3] = {(c & 1) ? nd.bhi[0] : nd.blo[0], (c & 2) ? nd.bhi[1] : nd.blo[1],
+                             (c & 4) ? nd.bhi[2] : nd.blo[2]};
+        double w[3];
+        mat3_vec(X, p, w);
+        for (int a = 0; a < 3; ++a) {
+            w[a] += X[9 + a];
+            l[a] = lmin(l[a], w[a]);
+            h[a] = lmax(h[a], w[a]);
+        }
+    }
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = nextafterf((float)(l[a] - pad), -INFINITY);
+        hi[a] = nextafterf((float)(h[a] + pad), INFINITY);
+    }
+}
+
+__global__ __launch_bounds__(ART_BLOCK) void k_articulate(const ArtJob *__restrict__ jobs, int n_jobs) {
+    const int j = blockIdx.x * ART_BLOCK + threadIdx.x;
+    if (j >= n_jobs) return;
+    const ArtJob J = jobs[j];
+    // node transforms, parents first (node order is a topological order)
+    for (int k = 0; k < J.n_nodes; ++k) {
+        const ArtNode &nd = J.nodes[k];
+        double X[12];
+        if (k == 0) {
+            for (int c = 0; c < 12; ++c) X[c] = (c == 0 || c == 4 || c == 8) ? 1.0 : 0.0;
+        } else {
+            double Pm[12];
+            for (int c = 0; c < 12; ++c) Pm[c] = J.xf[12 * nd.parent + c];
+            double prefix[9], Rl[9];
+            for (int c = 0; c < 9; ++c) {
+                prefix[c] = Pm[c];   // R_parent * R(a_0) ... R(a_{i-1})
+                Rl[c] = (c == 0 || c == 4 || c == 8) ? 1.0 : 0.0;
+            }
+            for (int a = 0; a < nd.n_axes; ++a) {
+                const int q = nd.dof_offset + a;
+                double w[3];
+                mat3_vec(prefix, nd.axis[a], w);
+                for (int c = 0; c < 3; ++c) J.axw[3 * q + c] = w[c];
+                J.dof_node[q] = k;
+                double Ra[9];
+                rot_unit(nd.unit[a], J.cs[2 * q], J.cs[2 * q + 1], Ra);
+                mat3_mul(Rl, Ra, Rl);
+                mat3_mul(prefix, Ra, prefix);
+            }
+            // local: x -> Rl (x - p) + p ; world: R_par * local + t_par
+            double Rp[3], tl[3], tw[3];
+            mat3_vec(Rl, nd.pivot, Rp);
+            for (int c = 0; c < 3; ++c) tl[c] = nd.pivot[c] - Rp[c];
+            mat3_vec(Pm, tl, tw);
+            mat3_mul(Pm, Rl, X);
+            for (int c = 0; c < 3; ++c) X[9 + c] = tw[c] + Pm[9 + c];
+        }
+        for (int c = 0; c < 12; ++c) J.xf[12 * k + c] = X[c];
+        Inst I;
+        for (int c = 0; c < 9; ++c) I.R[c] = (float)X[c];
+        for (int c = 0; c < 3; ++c) I.t[c] = (float)X[9 + c];
+        I.root = nd.blas_root;
+        I.node = k;
+        I.pad[0] = I.pad[1] = 0.0f;
+        J.inst[k] = I;
+    }
+    // refit, children before parents: an instance leaf takes its world box, an
+    // inner child the union of its node's non-empty boxes
+    for (int i = J.n_tlas - 1; i >= 0; --i) {
+        BNode4 nd = J.topo[i];
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t r = nd.ref[k];
+            if (r == REF_NONE) continue;
+            float lo[3], hi[3];
+            if (ref_type(r) == REF_TLAS_LEAF) {
+                const uint32_t q = ref_index(r);
+                inst_box(J.nodes[q], J.xf + 12 * q, J.pad, lo, hi);
+            } else {
+                const BNode4 &c = J.tlas[ref_index(r)];
+                for (int a = 0; a < 3; ++a) { lo[a] = INFINITY; hi[a] = -INFINITY; }
+                for (int m = 0; m < 4; ++m) {
+                    if (c.ref[m] == REF_NONE) continue;
+                    lo[0] = lmin(lo[0], c.lox[m]); hi[0] = lmax(hi[0], c.hix[m]);
+                    lo[1] = lmin(lo[1], c.loy[m]); hi[1] = lmax(hi[1], c.hiy[m]);
+                    lo[2] = lmin(lo[2], c.loz[m]); hi[2] = lmax(hi[2], c.hiz[m]);
+                }
+            }
+            nd.lox[k] = lo[0]; nd.loy[k] = lo[1]; nd.loz[k] = lo[2];
+            nd.hix[k] = hi[0]; nd.hiy[k] = hi[1]; nd.hiz[k] = hi[2];
+        }
+        J.tlas[i] = nd;
+    }
+}
+
+}  // namespace
+
+int launch_articulate(const ArtJob *d_jobs, int n_jobs, void *stream) {
+    if (n_jobs <= 0) return 0;
+    hipLaunchKernelGGL(k_articulate, dim3((n_jobs + ART_BLOCK - 1) / ART_BLOCK), dim3(ART_BLOCK), 0,
+                       (hipStream_t)stream, d_jobs, n_jobs);
+    return (int)hipGetLastError();
+}
+
+}  // namespace srp

@@ -7,6 +7,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <unordered_map>
 #include <new>
 #include <string>
 #include <vector>
@@ -25,6 +26,8 @@ struct srp_scene {
     float *d_mats = nullptr;
     WPoint *d_wpts = nullptr;
     int32_t *d_parent = nullptr;
+    ArtNode *d_art = nullptr;      // the tree as the articulation kernel reads it
+    BNode4 *d_topo = nullptr;      // top-level topology (references; boxes refitted per slot)
     char *d_slot = nullptr;        // current articulation slot
     SlotLayout slot_L{};
     SlotHost cur;
@@ -270,11 +273,15 @@ uint64_t tune_key(const srp_batch_item *items, int64_t n, bool grad) {
            (grad ? 1u : 0u);
 }
 
+// A batch's articulation slot: built on the device by k_articulate from the
+// angles of its first item (`item`); `next` chains slots of equal angle hash.
 struct SlotRec {
     const srp_scene *sc;
-    SlotHost s;
+    int64_t item;
+    int next;
+    size_t cs_off;   // its cosines and sines: doubles from Layout::o_cs
     SlotLayout L;
-    size_t off;
+    size_t off;      // device offset of the slot
 };
 
 // Everything about a batch that does not change when only Sun directions,
@@ -291,11 +298,13 @@ struct Layout {
     std::vector<SlotRec> slots;
     int max_grad_n = 0;
     int64_t total_chunks = 0, total_patches = 0, max_wpts = 0, total_units = 0, total_fan_slots = 0;
-    size_t o_desc = 0, o_cbase = 0, o_ubase = 0, o_win = 0, o_slots = 0, stage_bytes = 0;
+    size_t o_desc = 0, o_cbase = 0, o_ubase = 0, o_win = 0, o_seval = 0, o_jobs = 0, o_cs = 0, stage_bytes = 0;
+    size_t o_slots = 0, total_cs = 0;
     size_t o_patches = 0, o_counts = 0, o_emask = 0, o_fanout = 0, o_fancnt = 0, o_gpart = 0, o_queue = 0;
     size_t o_spill = 0, dev_bytes = 0;
     std::vector<size_t> gpart_off, gslice_off, pslice_off;
     std::vector<int> n_slices;    // reduction range sums per item (first stage)
+    std::vector<int64_t> slice_base;   // first range sum of every item, then the total
     std::vector<size_t> emit_off;   // emitter records of each item with diffuse fans (0: none)
     std::vector<int> grad_n;   // gradient partial doubles per chunk of each item (allocation and kernel)
     std::vector<int> item_ppc;   // patches per chunk of each item (the adjoint: its gradient group)
@@ -396,6 +405,17 @@ int layout_build(const srp_batch_item *items, int64_t n, bool grad, Schedule for
         L.max_wpts = std::max<int64_t>(L.max_wpts, (int64_t)it.scene->h.wpts.size());
     }
     L.patch_base[n] = L.total_patches;
+    // the reduction's first stage: range sums of about 1,024 patches each (at most
+    // MAX_SLICES), a function of the item's own size, so an item's results do not
+    // depend on its batch
+    L.n_slices.assign(n, 0);
+    L.slice_base.assign(n + 1, 0);
+    for (int64_t k = 0; k < n; ++k) {
+        const int64_t np = L.patch_base[k + 1] - L.patch_base[k];
+        L.n_slices[k] = (int)std::min<int64_t>(MAX_SLICES, std::max<int64_t>(1, np / 1024));
+        L.slice_base[k + 1] = L.slice_base[k] + L.n_slices[k];
+    }
+    if (L.slice_base[n] > INT32_MAX) return fail(SRP_ERR_ARG, "batch too large: more than 2^31 range sums (split it)");
     int occ = trace_blocks_per_cu(L.count, grad, L.dir, L.max_grad_n);
     L.sch = (force.ppc && force.bpc) ? force : pick_schedule(items, n, grad, L.total_patches, occ, L.max_grad_n);
     if (force.ppc) L.sch.ppc = force.ppc;
@@ -449,38 +469,61 @@ int layout_build(const srp_batch_item *items, int64_t n, bool grad, Schedule for
     if (L.total_units > ((int64_t)1 << 31))
         return fail(SRP_ERR_ARG, "batch too large: more than 2^31 diffuse work units (split it)");
 
-    // articulation slots: the scene's current slot, or one per distinct angle vector
-    std::map<std::pair<const srp_scene *, std::vector<double>>, int> slot_of;
+    // articulation slots: the scene's current slot, or one per distinct angle
+    // vector (equal bits), built on the device
+    std::unordered_map<uint64_t, int> head;   // angle hash -> newest slot with it
     L.item_slot.assign(n, -1);
     for (int64_t k = 0; k < n; ++k) {
         const srp_batch_item &it = items[k];
         if (!it.angles) continue;
-        std::vector<double> a(it.angles, it.angles + it.scene->h.n_dof);
-        auto key = std::make_pair((const srp_scene *)it.scene, a);
-        auto f = slot_of.find(key);
-        if (f != slot_of.end()) { L.item_slot[k] = f->second; continue; }
-        SlotRec r;
-        r.sc = it.scene;
-        int rc = slot_build(it.scene->h, a.data(), &r.s, &g_err);
-        if (rc) return rc;
-        r.L = slot_layout(it.scene->h.n_nodes, std::max<int>(it.scene->h.n_nodes, 1), it.scene->h.n_dof);
-        L.slots.push_back(std::move(r));
-        L.item_slot[k] = (int)L.slots.size() - 1;
-        slot_of.emplace(key, L.item_slot[k]);
+        const int J = it.scene->h.n_dof;
+        uint64_t h = 1469598103934665603ull;   // FNV-1a over the scene address and the angle bytes
+        auto mix = [&h](const void *p, size_t len) {
+            const unsigned char *b = static_cast<const unsigned char *>(p);
+            for (size_t i = 0; i < len; ++i) h = (h ^ b[i]) * 1099511628211ull;
+        };
+        mix(&it.scene, sizeof it.scene);
+        mix(it.angles, sizeof(double) * J);
+        auto f = head.find(h);
+        int found = -1;
+        for (int q = (f == head.end()) ? -1 : f->second; q >= 0; q = L.slots[q].next)
+            if (L.slots[q].sc == it.scene && std::memcmp(items[L.slots[q].item].angles, it.angles, sizeof(double) * J) == 0) {
+                found = q;
+                break;
+            }
+        if (found < 0) {
+            SlotRec r;
+            r.sc = it.scene;
+            r.item = k;
+            r.next = (f == head.end()) ? -1 : f->second;
+            r.cs_off = L.total_cs;
+            L.total_cs += 2 * (size_t)J;
+            r.L = it.scene->slot_L;
+            r.off = 0;
+            L.slots.push_back(r);
+            found = (int)L.slots.size() - 1;
+            head[h] = found;
+        }
+        L.item_slot[k] = found;
     }
 
-    // staging (uploaded every launch): descs | chunk_base | unit_base | win | slots
+    // staging (uploaded every launch): descs | chunk_base | unit_base | win |
+    // evaluation of every range sum | articulation jobs | their cosines and sines
     L.o_desc = 0;
     L.o_cbase = align_up(sizeof(EvalDesc) * n);
     L.o_ubase = align_up(L.o_cbase + sizeof(int64_t) * (n + 1));
     L.o_win = align_up(L.o_ubase + sizeof(int64_t) * (n + 1));
-    L.o_slots = align_up(L.o_win + sizeof(uint64_t) * WIN_STRIDE * n);
+    L.o_seval = align_up(L.o_win + sizeof(uint64_t) * WIN_STRIDE * n);
+    L.o_jobs = align_up(L.o_seval + sizeof(uint32_t) * L.slice_base[n]);
+    L.o_cs = align_up(L.o_jobs + sizeof(ArtJob) * L.slots.size());
+    L.stage_bytes = align_up(L.o_cs + sizeof(double) * L.total_cs);
+    // device-only: articulation slots | patch partials | counts | emitter masks
+    L.o_slots = L.stage_bytes;
     size_t off = L.o_slots;
-    for (auto &s : L.slots) { s.off = off; off = align_up(off + s.L.bytes); }
-    L.stage_bytes = off;
-    // device-only: patch partials | counts | emitter masks | fan pass partials | their
-    // counts | emitter records (per item) | gradient partials (per chunk)
-    L.o_patches = align_up(L.stage_bytes);
+    for (auto &sl : L.slots) { sl.off = off; off = align_up(off + sl.L.bytes); }
+    // ... | fan pass partials | their counts | emitter records (per item) |
+    // gradient partials (per chunk)
+    L.o_patches = align_up(off);
     L.o_counts = align_up(L.o_patches + sizeof(PatchOut) * L.total_patches);
     L.o_emask = align_up(L.o_counts + (L.count ? sizeof(uint64_t) * 2 * L.total_patches : 0));
     L.emit_off.assign(n, 0);
@@ -502,14 +545,8 @@ int layout_build(const srp_batch_item *items, int64_t n, bool grad, Schedule for
     L.grad_n.assign(n, 0);
     L.gslice_off.assign(n, 0);
     L.pslice_off.assign(n, 0);
-    L.n_slices.assign(n, 0);
     size_t goff = L.o_gpart;
     for (int64_t k = 0; k < n; ++k) {
-        // the reduction's first stage: range sums of about 1,024 patches each (at most
-        // MAX_SLICES), a function of the item's own size, so an item's results do not
-        // depend on its batch
-        const int64_t np = L.patch_base[k + 1] - L.patch_base[k];
-        L.n_slices[k] = (int)std::min<int64_t>(MAX_SLICES, std::max<int64_t>(1, np / 1024));
         L.pslice_off[k] = goff;
         goff = align_up(goff + sizeof(SliceOut) * L.n_slices[k]);
         if (!grad) continue;
@@ -550,7 +587,40 @@ void staging_fill(const Layout &L, const srp_batch_item *items, const BatchOut &
     std::memcpy(H + L.o_ubase, L.unit_base.data(), sizeof(int64_t) * (n + 1));
     uint64_t *win = reinterpret_cast<uint64_t *>(H + L.o_win);
     for (int64_t k = 0; k < WIN_STRIDE * n; ++k) win[k] = enc_f64(INFINITY);
-    for (auto &s : L.slots) slot_pack(s.s, s.L, H + s.off);
+    uint32_t *seval = reinterpret_cast<uint32_t *>(H + L.o_seval);
+    for (int64_t k = 0; k < n; ++k)
+        for (int64_t q = L.slice_base[k]; q < L.slice_base[k + 1]; ++q) seval[q] = (uint32_t)k;
+    ArtJob *jobs = reinterpret_cast<ArtJob *>(H + L.o_jobs);
+    double *cs = reinterpret_cast<double *>(H + L.o_cs);
+    for (size_t q = 0; q < L.slots.size(); ++q) {
+        const SlotRec &sl = L.slots[q];
+        const SceneHost &S = sl.sc->h;
+        const double *a = items[sl.item].angles;
+        double *o = cs + sl.cs_off;
+        for (int k = 0; k < S.n_nodes; ++k) {
+            const NodeInfo &nd = S.nodes[k];
+            for (int x = 0; x < nd.n_axes; ++x) {
+                const int j = nd.dof_offset + x;
+                int clamped = 0;
+                const double th = clamp_angle(nd, x, a[j], &clamped);
+                o[2 * j] = std::cos(th);
+                o[2 * j + 1] = std::sin(th);
+            }
+        }
+        char *base = Dv + sl.off;
+        ArtJob &J = jobs[q];
+        J.nodes = sl.sc->d_art;
+        J.topo = sl.sc->d_topo;
+        J.cs = reinterpret_cast<const double *>(Dv + L.o_cs) + sl.cs_off;
+        J.inst = reinterpret_cast<Inst *>(base + sl.L.inst);
+        J.tlas = reinterpret_cast<BNode4 *>(base + sl.L.tlas);
+        J.xf = reinterpret_cast<double *>(base + sl.L.xf);
+        J.axw = reinterpret_cast<double *>(base + sl.L.axw);
+        J.dof_node = reinterpret_cast<int32_t *>(base + sl.L.dof_node);
+        J.pad = S.pad;
+        J.n_nodes = S.n_nodes;
+        J.n_tlas = (int32_t)S.tlas_topo.size();
+    }
     for (int64_t k = 0; k < n; ++k) {
         const srp_batch_item &it = items[k];
         const srp_scene *sc = it.scene;
@@ -561,19 +631,9 @@ void staging_fill(const Layout &L, const srp_batch_item *items, const BatchOut &
         D.mats = sc->d_mats;
         D.wpts = sc->d_wpts;
         D.n_wpts = (int64_t)sc->h.wpts.size();
-        const char *slot_base;
-        SlotLayout SL;
-        uint32_t root;
-        if (L.item_slot[k] >= 0) {
-            const SlotRec &s = L.slots[L.item_slot[k]];
-            slot_base = Dv + s.off;
-            SL = s.L;
-            root = s.s.root_ref;
-        } else {
-            slot_base = sc->d_slot;
-            SL = sc->slot_L;
-            root = sc->cur.root_ref;
-        }
+        const char *slot_base = (L.item_slot[k] >= 0) ? Dv + L.slots[L.item_slot[k]].off : sc->d_slot;
+        const SlotLayout &SL = sc->slot_L;
+        const uint32_t root = sc->h.tlas_root;   // every pose shares the topology
         D.inst = reinterpret_cast<const Inst *>(slot_base + SL.inst);
         D.tlas = reinterpret_cast<const BNode4 *>(slot_base + SL.tlas);
         D.xf = reinterpret_cast<const double *>(slot_base + SL.xf);
@@ -608,6 +668,7 @@ void staging_fill(const Layout &L, const srp_batch_item *items, const BatchOut &
         D.grad_n = L.grad ? L.grad_n[k] : 0;   // the per-chunk size the partials were allocated with
         D.grad_part = L.grad ? reinterpret_cast<double *>(Dv + L.gpart_off[k]) : nullptr;
         D.n_slices = L.n_slices[k];
+        D.slice_base = L.slice_base[k];
         D.pslice = reinterpret_cast<SliceOut *>(Dv + L.pslice_off[k]);
         D.gslice = L.grad ? reinterpret_cast<double *>(Dv + L.gslice_off[k]) : nullptr;
         D.grad_out = (L.grad && bo.d_grad) ? bo.d_grad + k * bo.grad_stride : nullptr;
@@ -621,6 +682,10 @@ int enqueue(const Layout &L, char *Dv, const char *H, size_t copy_bytes, const B
             bool profile, hipEvent_t copied = nullptr) {
     HIPCHK(hipMemcpyAsync(Dv, H, copy_bytes, hipMemcpyHostToDevice, stream));
     if (copied) HIPCHK(hipEventRecord(copied, stream));
+    if (!L.slots.empty()) {
+        int e = launch_articulate(reinterpret_cast<const ArtJob *>(Dv + L.o_jobs), (int)L.slots.size(), stream);
+        if (e) return fail(SRP_ERR_DEVICE, std::string("articulation kernel: ") + hipGetErrorString((hipError_t)e));
+    }
     const EvalDesc *d_desc = reinterpret_cast<const EvalDesc *>(Dv + L.o_desc);
     const int64_t *d_cbase = reinterpret_cast<const int64_t *>(Dv + L.o_cbase);
     uint64_t *d_win = reinterpret_cast<uint64_t *>(Dv + L.o_win);
@@ -656,8 +721,8 @@ int enqueue(const Layout &L, char *Dv, const char *H, size_t copy_bytes, const B
         HIPCHK(hipEventRecord(ev.second, stream));
         g_prof.pairs.push_back(ev);
     }
-    e = launch_reduce(d_desc, (int)L.n, d_win, d_patches, d_counts, d_fan_out, d_fan_counts, L.count, L.grad, bo.d_out,
-                      stream);
+    e = launch_reduce(d_desc, (int)L.n, d_win, d_patches, d_counts, d_fan_out, d_fan_counts, L.count, L.grad,
+                      reinterpret_cast<const uint32_t *>(Dv + L.o_seval), L.slice_base[L.n], bo.d_out, stream);
     if (e) return fail(SRP_ERR_DEVICE, std::string("reduce kernel: ") + hipGetErrorString((hipError_t)e));
     if (bo.h_copy) HIPCHK(hipMemcpyAsync(bo.h_copy, bo.d_out, sizeof(srp_result) * L.n, hipMemcpyDeviceToHost, stream));
     return SRP_OK;
@@ -816,8 +881,11 @@ int plan_refill(PlanImpl *P, const srp_batch_item *items, int64_t n, bool *compa
         L2.fan_claim != L.fan_claim || L2.fan_parts != L.fan_parts || L2.fans_inline != L.fans_inline ||
         L2.emit_off != L.emit_off ||
         L2.o_emask != L.o_emask || L2.o_fanout != L.o_fanout || L2.o_fancnt != L.o_fancnt ||
-        L2.o_queue != L.o_queue || L2.o_spill != L.o_spill)
+        L2.o_queue != L.o_queue || L2.o_spill != L.o_spill || L2.slots.size() != L.slots.size() ||
+        L2.o_jobs != L.o_jobs || L2.o_cs != L.o_cs || L2.o_slots != L.o_slots)
         return SRP_OK;
+    for (size_t q = 0; q < L.slots.size(); ++q)
+        if (L2.slots[q].off != L.slots[q].off || L2.slots[q].sc != L.slots[q].sc) return SRP_OK;
     if (P->pending) HIPCHK(hipEventSynchronize(P->done));
     P->pending = false;
     P->L = std::move(L2);
@@ -844,6 +912,8 @@ void free_scene(srp_scene *sc) {
     (void)hipFree(sc->d_mats);
     (void)hipFree(sc->d_wpts);
     (void)hipFree(sc->d_parent);
+    (void)hipFree(sc->d_art);
+    (void)hipFree(sc->d_topo);
     (void)hipFree(sc->d_slot);
     delete sc;
 }
@@ -897,10 +967,11 @@ int srp_build_scene(const double *verts, int64_t n_verts, const int32_t *tris, i
     if ((rc = ws_init())) { free_scene(sc); return rc; }
     sc->device = g_ws.device;
     sc->angles.assign(sc->h.n_dof, 0.0);
-    sc->slot_L = slot_layout(sc->h.n_nodes, std::max(sc->h.n_nodes, 1), sc->h.n_dof);
+    sc->slot_L = slot_layout(sc->h.n_nodes, std::max((int)sc->h.tlas_topo.size(), 1), sc->h.n_dof);
     if ((rc = dev_upload(&sc->d_tris, sc->h.tris)) || (rc = dev_upload(&sc->d_blas, sc->h.blas)) ||
         (rc = dev_upload(&sc->d_mats, sc->h.mats)) || (rc = dev_upload(&sc->d_wpts, sc->h.wpts)) ||
-        (rc = dev_upload(&sc->d_parent, sc->h.parent))) {
+        (rc = dev_upload(&sc->d_parent, sc->h.parent)) || (rc = dev_upload(&sc->d_art, art_nodes(sc->h))) ||
+        (rc = dev_upload(&sc->d_topo, sc->h.tlas_topo))) {
         free_scene(sc);
         return rc;
     }

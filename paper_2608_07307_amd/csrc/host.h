@@ -14,7 +14,8 @@ struct NodeInfo {
     int32_t is_panel = 0;
     double pivot[3] = {0, 0, 0};
     int32_t n_axes = 0;
-    double axis[3][3] = {{0}};
+    double axis[3][3] = {{0}};       // unit axes (world hinge axes are R_parent times these)
+    double unit[3][3] = {{0}};       // the same axes renormalised, as the rotation matrices use them
     double lo[3] = {0}, hi[3] = {0};
     int32_t dof_offset = 0;
     uint32_t blas_root = REF_NONE;   // REF_NONE when the node has no triangles
@@ -64,6 +65,13 @@ struct SceneHost {
     std::vector<PlateLocal> plates; // N-plate model, in the order of each plate's first triangle
     double pad = 0;                 // box padding (metres)
     int max_blas_depth = 0;
+    // top level: 4-wide nodes over the non-empty nodes' instances, built once over
+    // the rest pose; a slot copies the references and refits the boxes (children
+    // follow their parent in this array)
+    std::vector<BNode4> tlas_topo;
+    uint32_t tlas_root = REF_NONE;
+    int tlas_depth = 0;
+    int stack_worst = 0;            // most traversal-stack entries a ray can hold (any pose)
 };
 
 // Validates the inputs and builds the host image.  Returns SRP_OK or an
@@ -77,8 +85,14 @@ int validate_materials(const srp_material *mats, int32_t n_mats, std::string *er
 
 // Composes the node transforms for `angles` (NULL = all zero), clamping each
 // angle to its interval (Sec. 4.4.2 step 4), and builds the instances, the
-// top-level hierarchy and the world hinge axes.
+// world hinge axes and the top level refitted to the instances' world boxes.
 int slot_build(const SceneHost &S, const double *angles, SlotHost *out, std::string *err);
+
+// Angle `th` of axis a of node nd clamped to its interval; *clamped counts a clamp.
+double clamp_angle(const NodeInfo &nd, int a, double th, int *clamped);
+
+// The articulation kernel's view of the scene's nodes (same order).
+std::vector<ArtNode> art_nodes(const SceneHost &S);
 
 // Fills S->plates from S->tris (which the library frees once they are on the
 // device).

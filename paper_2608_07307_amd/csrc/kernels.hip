@@ -19,8 +19,9 @@
 //             visibility.
 //   k_fans    small diffuse batches: the patches' fan passes as a separate
 //             persistent launch, each patch split into several work units.
-//   k_slices  per evaluation, up to 16 blocks each summing a contiguous range of
-//             its patch, fan-pass and gradient partials in a fixed order.
+//   k_slices  one block per range sum (up to 16 per evaluation, numbered
+//             through the batch), summing a contiguous range of its evaluation's
+//             patch, fan-pass and gradient partials in a fixed order.
 //   k_reduce  per evaluation, adds the ranges in order, scales by P * A_pix and
 //             writes the srp_result (and assembles the gradients).
 //
@@ -829,14 +830,16 @@ constexpr int RBLOCK = 1024;   // threads per block of the reduction kernels
 // batch around it.
 template <bool COUNT, bool GRAD>
 __global__ __launch_bounds__(RBLOCK) void k_slices(const EvalDesc *__restrict__ descs,
+                                                const uint32_t *__restrict__ slice_eval,
                                                 const PatchOut *__restrict__ patches,
                                                 const uint64_t *__restrict__ counts,
                                                 const PatchOut *__restrict__ fan_out,
                                                 const uint64_t *__restrict__ fan_counts) {
-    const int q = blockIdx.x, e = blockIdx.y, tid = threadIdx.x, lane = tid & (WAVE - 1), wid = tid >> 6;
+    const int64_t b = blockIdx.x;
+    const int e = (int)slice_eval[b], tid = threadIdx.x, lane = tid & (WAVE - 1), wid = tid >> 6;
     const EvalDesc &D = descs[e];
-    const int Q = D.n_slices;
-    if (q >= Q) return;
+    const int Q = D.n_slices, q = (int)(b - D.slice_base);
+    if (q < 0 || q >= Q) return;
     double f[6] = {0, 0, 0, 0, 0, 0};
     unsigned long long cn[5] = {0, 0, 0, 0, 0};
     uint32_t st = 0;
@@ -1082,14 +1085,15 @@ int launch_fans(const EvalDesc *d_desc, const int64_t *d_unit_base, int n_evals,
 
 int launch_reduce(const EvalDesc *d_desc, int n_evals, const uint64_t *d_win, const PatchOut *d_patches,
                   const uint64_t *d_counts, const PatchOut *d_fan_out, const uint64_t *d_fan_counts, bool count,
-                  bool grad, void *d_out, void *stream) {
+                  bool grad, const uint32_t *d_slice_eval, int64_t total_slices, void *d_out, void *stream) {
     if (n_evals <= 0) return 0;
+    if (total_slices < n_evals || total_slices > INT32_MAX) return (int)hipErrorInvalidValue;
     hipStream_t s = (hipStream_t)stream;
     srp_result *out = (srp_result *)d_out;
 #define SRP_LAUNCH_REDUCE(C, G)                                                                                 \
     do {                                                                                                        \
-        hipLaunchKernelGGL((k_slices<C, G>), dim3(MAX_SLICES, n_evals), dim3(RBLOCK), 0, s, d_desc, d_patches,  \
-                           d_counts, d_fan_out, d_fan_counts);                                                  \
+        hipLaunchKernelGGL((k_slices<C, G>), dim3((uint32_t)total_slices), dim3(RBLOCK), 0, s, d_desc,          \
+                           d_slice_eval, d_patches, d_counts, d_fan_out, d_fan_counts);                         \
         hipLaunchKernelGGL((k_reduce<C, G>), dim3(n_evals), dim3(RBLOCK), 0, s, d_desc, d_win, out);            \
     } while (0)
     if (count && grad) SRP_LAUNCH_REDUCE(true, true);

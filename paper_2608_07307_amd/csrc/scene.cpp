@@ -1,19 +1,25 @@
 // Scene construction on the host: input validation, one bounding-volume
 // hierarchy per kinematic-tree node in rest-pose coordinates, the window
-// point set, and the per-angle articulation slot (instance transforms and a
-// top-level hierarchy over the nodes).
+// point set, the top-level topology, and the per-angle articulation slot
+// (instance transforms and the top level refitted to them).
 //
 // The paper moves the triangles of each articulated subtree on the CPU before
 // every evaluation (Sec. 4.4.2, step 5).  Here each node's triangles stay in
 // their rest pose inside their own hierarchy; a hinge rotation only changes
-// the node's rigid transform, so an angle update rebuilds nothing but a
-// top-level hierarchy of at most SRP_MAX_NODES boxes.
+// the node's rigid transform, so an angle update builds nothing: it refits
+// the boxes of a top level of at most SRP_MAX_NODES instances whose topology
+// was built once, over the rest pose.  The articulation kernel
+// (articulate.hip) does the same for a batch's angle vectors with the same
+// separately rounded FP64 operations, so both give the same bits; floating-
+// point contraction stays off in both files for that reason.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <numeric>
 
 #include "host.h"
+
+#pragma clang fp contract(off)
 
 namespace srp {
 
@@ -261,10 +267,9 @@ struct Collapser {
     }
 };
 
-void rot_axis_angle(const double *a_in, double th, double *R) {
-    double n = std::sqrt(a_in[0] * a_in[0] + a_in[1] * a_in[1] + a_in[2] * a_in[2]);
-    double x = a_in[0] / n, y = a_in[1] / n, z = a_in[2] / n;
-    double c = std::cos(th), s = std::sin(th), C = 1 - c;
+// Rotation by the angle of cosine c and sine s about the unit axis u (Rodrigues).
+void rot_unit(const double *u, double c, double s, double *R) {
+    const double x = u[0], y = u[1], z = u[2], C = 1 - c;
     double M[9] = {c + x * x * C,     x * y * C - z * s, x * z * C + y * s,
                    y * x * C + z * s, c + y * y * C,     y * z * C - x * s,
                    z * x * C - y * s, z * y * C + x * s, c + z * z * C};
@@ -301,6 +306,10 @@ int validate_materials(const srp_material *mats, int32_t n_mats, std::string *er
         }
     }
     return SRP_OK;
+}
+
+namespace {
+int tlas_topology(SceneHost *S, std::string *err);
 }
 
 int scene_build(const double *verts, int64_t n_verts, const int32_t *tris, int64_t n_tris,
@@ -349,6 +358,9 @@ int scene_build(const double *verts, int64_t n_verts, const int32_t *tris, int64
                 return SRP_ERR_ARG;
             }
             for (int c = 0; c < 3; ++c) o.axis[a][c] = in.axis[a][c] / nrm;
+            const double *ax = o.axis[a];
+            const double n2 = std::sqrt(ax[0] * ax[0] + ax[1] * ax[1] + ax[2] * ax[2]);
+            for (int c = 0; c < 3; ++c) o.unit[a][c] = ax[c] / n2;
             o.lo[a] = in.lo[a];
             o.hi[a] = in.hi[a];
         }
@@ -451,7 +463,7 @@ int scene_build(const double *verts, int64_t n_verts, const int32_t *tris, int64
         const double *p = verts + 3 * (int64_t)vn[i].second;
         S->wpts[i] = WPoint{p[0], p[1], p[2], vn[i].first, 0};
     }
-    return SRP_OK;
+    return tlas_topology(S, err);
 }
 
 SlotLayout slot_layout(int n_nodes, int n_tlas, int n_dof) {
@@ -474,7 +486,111 @@ void slot_pack(const SlotHost &s, const SlotLayout &L, char *dst) {
     if (!s.dof_node.empty()) std::memcpy(dst + L.dof_node, s.dof_node.data(), sizeof(int32_t) * s.dof_node.size());
 }
 
+double clamp_angle(const NodeInfo &nd, int a, double th, int *clamped) {
+    if (th < nd.lo[a]) { th = nd.lo[a]; ++*clamped; }
+    if (th > nd.hi[a]) { th = nd.hi[a]; ++*clamped; }
+    return th;
+}
+
+std::vector<ArtNode> art_nodes(const SceneHost &S) {
+    std::vector<ArtNode> v(S.n_nodes);
+    for (int k = 0; k < S.n_nodes; ++k) {
+        const NodeInfo &nd = S.nodes[k];
+        ArtNode &a = v[k];
+        std::memset(&a, 0, sizeof a);
+        std::memcpy(a.pivot, nd.pivot, sizeof a.pivot);
+        std::memcpy(a.axis, nd.axis, sizeof a.axis);
+        std::memcpy(a.unit, nd.unit, sizeof a.unit);
+        std::memcpy(a.blo, nd.blo, sizeof a.blo);
+        std::memcpy(a.bhi, nd.bhi, sizeof a.bhi);
+        a.parent = nd.parent;
+        a.n_axes = nd.n_axes;
+        a.dof_offset = nd.dof_offset;
+        a.blas_root = nd.blas_root;
+    }
+    return v;
+}
+
 namespace {
+
+// Node transforms, instances and world hinge axes for `angles` (NULL = all
+// zero), each angle clamped to its interval.  Node k's transform is its
+// parent's times the local x -> R_l (x - p) + p, with R_l the product of the
+// axis rotations in axis order.
+int slot_compose(const SceneHost &S, const double *angles, SlotHost *out, std::string *err) {
+    const int K = S.n_nodes, J = S.n_dof;
+    out->inst.assign(K, Inst{});
+    out->xf.assign(12 * (size_t)K, 0.0);
+    out->axw.assign(3 * (size_t)J, 0.0);
+    out->dof_node.assign(J, 0);
+    out->n_clamped = 0;
+    for (int k = 0; k < K; ++k) {
+        const NodeInfo &nd = S.nodes[k];
+        double *X = &out->xf[12 * (size_t)k];
+        if (k == 0) {
+            double I[12] = {1, 0, 0, 0, 1, 0, 0, 0, 1, 0, 0, 0};
+            std::memcpy(X, I, sizeof I);
+        } else {
+            const double *Pm = &out->xf[12 * (size_t)nd.parent];
+            double prefix[9];
+            std::memcpy(prefix, Pm, sizeof prefix);   // R_parent * R(a_0) ... R(a_{j-1})
+            double Rl[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+            for (int a = 0; a < nd.n_axes; ++a) {
+                int j = nd.dof_offset + a;
+                double th = angles ? angles[j] : 0.0;
+                if (!std::isfinite(th)) { *err = "non-finite hinge angle"; return SRP_ERR_ARG; }
+                th = clamp_angle(nd, a, th, &out->n_clamped);
+                mat3_vec(prefix, nd.axis[a], &out->axw[3 * (size_t)j]);
+                out->dof_node[j] = k;
+                double Ra[9];
+                rot_unit(nd.unit[a], std::cos(th), std::sin(th), Ra);
+                mat3_mul(Rl, Ra, Rl);
+                mat3_mul(prefix, Ra, prefix);
+            }
+            // local: x -> Rl (x - p) + p ; world: R_par * local + t_par
+            double Rp[3], tl[3], tw[3];
+            mat3_vec(Rl, nd.pivot, Rp);
+            for (int c = 0; c < 3; ++c) tl[c] = nd.pivot[c] - Rp[c];
+            mat3_vec(Pm, tl, tw);
+            mat3_mul(Pm, Rl, X);
+            for (int c = 0; c < 3; ++c) X[9 + c] = tw[c] + Pm[9 + c];
+        }
+        Inst &I = out->inst[k];
+        for (int c = 0; c < 9; ++c) I.R[c] = (float)X[c];
+        for (int c = 0; c < 3; ++c) I.t[c] = (float)X[9 + c];
+        I.root = nd.blas_root;
+        I.node = k;
+    }
+    return SRP_OK;
+}
+
+// World box (FP64) of node nd's padded rest-pose box under transform X: the
+// extremes of its eight transformed corners.
+void world_box(const NodeInfo &nd, const double *X, double lo[3], double hi[3]) {
+    for (int a = 0; a < 3; ++a) { lo[a] = INFINITY; hi[a] = -INFINITY; }
+    for (int c = 0; c < 8; ++c) {
+        double p[3] = {(c & 1) ? nd.bhi[0] : nd.blo[0], (c & 2) ? nd.bhi[1] : nd.blo[1], (c & 4) ? nd.bhi[2] : nd.blo[2]};
+        double w[3];
+        mat3_vec(X, p, w);
+        for (int a = 0; a < 3; ++a) {
+            w[a] += X[9 + a];
+            lo[a] = std::min(lo[a], w[a]);
+            hi[a] = std::max(hi[a], w[a]);
+        }
+    }
+}
+
+// The instance's top-level box: the world box grown by the padding and
+// rounded outward to FP32.
+void inst_box(const NodeInfo &nd, const double *X, double pad, float lo[3], float hi[3]) {
+    double l[3], h[3];
+    world_box(nd, X, l, h);
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = std::nextafter((float)(l[a] - pad), -INFINITY);
+        hi[a] = std::nextafter((float)(h[a] + pad), INFINITY);
+    }
+}
+
 struct TItem {
     float lo[3], hi[3];
     double c[3];
@@ -509,99 +625,93 @@ uint32_t tlas_build(std::vector<TItem> &it, int b, int e, std::vector<BNode2> &n
     n.ref[1] = r;
     return make_ref(REF_TLAS_NODE, me);
 }
-}  // namespace
 
-int slot_build(const SceneHost &S, const double *angles, SlotHost *out, std::string *err) {
-    const int K = S.n_nodes, J = S.n_dof;
-    out->inst.assign(K, Inst{});
-    out->xf.assign(12 * (size_t)K, 0.0);
-    out->axw.assign(3 * (size_t)J, 0.0);
-    out->dof_node.assign(J, 0);
-    out->tlas.clear();
-    out->n_clamped = 0;
-    for (int k = 0; k < K; ++k) {
-        const NodeInfo &nd = S.nodes[k];
-        double *X = &out->xf[12 * (size_t)k];
-        if (k == 0) {
-            double I[12] = {1, 0, 0, 0, 1, 0, 0, 0, 1, 0, 0, 0};
-            std::memcpy(X, I, sizeof I);
-        } else {
-            const double *Pm = &out->xf[12 * (size_t)nd.parent];
-            double prefix[9];
-            std::memcpy(prefix, Pm, sizeof prefix);   // R_parent * R(a_0) ... R(a_{j-1})
-            double Rl[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
-            for (int a = 0; a < nd.n_axes; ++a) {
-                int j = nd.dof_offset + a;
-                double th = angles ? angles[j] : 0.0;
-                if (!std::isfinite(th)) { *err = "non-finite hinge angle"; return SRP_ERR_ARG; }
-                if (th < nd.lo[a]) { th = nd.lo[a]; out->n_clamped++; }
-                if (th > nd.hi[a]) { th = nd.hi[a]; out->n_clamped++; }
-                mat3_vec(prefix, nd.axis[a], &out->axw[3 * (size_t)j]);
-                out->dof_node[j] = k;
-                double Ra[9];
-                rot_axis_angle(nd.axis[a], th, Ra);
-                mat3_mul(Rl, Ra, Rl);
-                mat3_mul(prefix, Ra, prefix);
-            }
-            // local: x -> Rl (x - p) + p ; world: R_par * local + t_par
-            double Rp[3], tl[3], tw[3];
-            mat3_vec(Rl, nd.pivot, Rp);
-            for (int c = 0; c < 3; ++c) tl[c] = nd.pivot[c] - Rp[c];
-            mat3_vec(Pm, tl, tw);
-            mat3_mul(Pm, Rl, X);
-            for (int c = 0; c < 3; ++c) X[9 + c] = tw[c] + Pm[9 + c];
-        }
-        Inst &I = out->inst[k];
-        for (int c = 0; c < 9; ++c) I.R[c] = (float)X[c];
-        for (int c = 0; c < 3; ++c) I.t[c] = (float)X[9 + c];
-        I.root = nd.blas_root;
-        I.node = k;
-    }
-    // top-level hierarchy over the non-empty nodes' world boxes
+// The top level over the rest pose: median splits of the non-empty nodes'
+// world-box centres along the widest axis, collapsed to 4-wide nodes.  Its
+// references are kept for every pose; its stack bound holds for every pose
+// (it depends on the references alone).
+int tlas_topology(SceneHost *S, std::string *err) {
+    SlotHost rest;
+    int rc = slot_compose(*S, nullptr, &rest, err);
+    if (rc) return rc;
     std::vector<TItem> items;
-    for (int k = 0; k < K; ++k) {
-        const NodeInfo &nd = S.nodes[k];
+    for (int k = 0; k < S->n_nodes; ++k) {
+        const NodeInfo &nd = S->nodes[k];
         if (nd.blas_root == REF_NONE) continue;
-        const double *X = &out->xf[12 * (size_t)k];
-        double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-        for (int c = 0; c < 8; ++c) {
-            double p[3] = {(c & 1) ? nd.bhi[0] : nd.blo[0], (c & 2) ? nd.bhi[1] : nd.blo[1], (c & 4) ? nd.bhi[2] : nd.blo[2]};
-            double w[3];
-            mat3_vec(X, p, w);
-            for (int a = 0; a < 3; ++a) {
-                w[a] += X[9 + a];
-                lo[a] = std::min(lo[a], w[a]);
-                hi[a] = std::max(hi[a], w[a]);
-            }
-        }
+        const double *X = &rest.xf[12 * (size_t)k];
+        double lo[3], hi[3];
+        world_box(nd, X, lo, hi);
         TItem ti;
-        for (int a = 0; a < 3; ++a) {
-            ti.lo[a] = std::nextafter((float)(lo[a] - S.pad), -INFINITY);
-            ti.hi[a] = std::nextafter((float)(hi[a] + S.pad), INFINITY);
-            ti.c[a] = 0.5 * (lo[a] + hi[a]);
-        }
+        inst_box(nd, X, S->pad, ti.lo, ti.hi);
+        for (int a = 0; a < 3; ++a) ti.c[a] = 0.5 * (lo[a] + hi[a]);
         ti.inst = k;
         items.push_back(ti);
     }
-    out->tlas_depth = 0;
-    out->stack_worst = 0;
-    if (items.empty()) {
-        out->root_ref = REF_NONE;
-    } else {
+    S->tlas_topo.clear();
+    S->tlas_root = REF_NONE;
+    S->tlas_depth = 0;
+    S->stack_worst = 0;
+    if (!items.empty()) {
         float lo[3], hi[3];
         std::vector<BNode2> bin;
         int bdepth = 0;
         const uint32_t broot = tlas_build(items, 0, (int)items.size(), bin, 0, bdepth, lo, hi);
-        Collapser Cl{bin, out->tlas, REF_TLAS_NODE};
-        Cl.leaf_info = &S.nodes;
-        out->root_ref = Cl.root(broot);
-        out->tlas_depth = Cl.max_depth;
-        out->stack_worst = Cl.worst;
+        Collapser Cl{bin, S->tlas_topo, REF_TLAS_NODE};
+        Cl.leaf_info = &S->nodes;
+        S->tlas_root = Cl.root(broot);
+        S->tlas_depth = Cl.max_depth;
+        S->stack_worst = Cl.worst;
     }
-    if (out->stack_worst > STACK_DEPTH) {
+    if (S->stack_worst > STACK_DEPTH) {
         *err = "hierarchy depth exceeds the traversal stack";
         return SRP_ERR_DEPTH;
     }
+    // the refit visits nodes last to first: every child must follow its parent
+    for (size_t i = 0; i < S->tlas_topo.size(); ++i)
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t r = S->tlas_topo[i].ref[k];
+            if (r != REF_NONE && ref_type(r) == REF_TLAS_NODE && ref_index(r) <= i) {
+                *err = "top level: a child precedes its parent";
+                return SRP_ERR_ARG;
+            }
+        }
+    return SRP_OK;
+}
+
+}  // namespace
+
+int slot_build(const SceneHost &S, const double *angles, SlotHost *out, std::string *err) {
+    int rc = slot_compose(S, angles, out, err);
+    if (rc) return rc;
+    // refit the top level, children before parents: an instance leaf takes its
+    // world box, an inner child the union of its node's non-empty boxes
+    out->tlas = S.tlas_topo;
+    for (size_t i = out->tlas.size(); i-- > 0;) {
+        BNode4 &nd = out->tlas[i];
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t r = nd.ref[k];
+            if (r == REF_NONE) continue;
+            float lo[3], hi[3];
+            if (ref_type(r) == REF_TLAS_LEAF) {
+                const uint32_t q = ref_index(r);
+                inst_box(S.nodes[q], &out->xf[12 * (size_t)q], S.pad, lo, hi);
+            } else {
+                const BNode4 &c = out->tlas[ref_index(r)];
+                for (int a = 0; a < 3; ++a) { lo[a] = INFINITY; hi[a] = -INFINITY; }
+                for (int m = 0; m < 4; ++m) {
+                    if (c.ref[m] == REF_NONE) continue;
+                    lo[0] = std::min(lo[0], c.lox[m]); hi[0] = std::max(hi[0], c.hix[m]);
+                    lo[1] = std::min(lo[1], c.loy[m]); hi[1] = std::max(hi[1], c.hiy[m]);
+                    lo[2] = std::min(lo[2], c.loz[m]); hi[2] = std::max(hi[2], c.hiz[m]);
+                }
+            }
+            nd.lox[k] = lo[0]; nd.loy[k] = lo[1]; nd.loz[k] = lo[2];
+            nd.hix[k] = hi[0]; nd.hiy[k] = hi[1]; nd.hiz[k] = hi[2];
+        }
+    }
+    out->root_ref = S.tlas_root;
+    out->tlas_depth = S.tlas_depth;
+    out->stack_worst = S.stack_worst;
     return SRP_OK;
 }
 

@@ -7,9 +7,11 @@
 //   float2  mats[M]   (rho_s, rho_d)
 //   WPoint  wpts[..]  distinct (vertex, tree node) pairs, for the window pass
 // Device memory of an articulation slot (one per distinct hinge-angle vector,
-// Sec. 4.4.2 steps 1, 4, 5 as rigid instance transforms):
+// Sec. 4.4.2 steps 1, 4, 5 as rigid instance transforms; built by the host for
+// a scene's current angles, by k_articulate for a batch's angle vectors):
 //   Inst    inst[K]   local->world transform + bottom-level root, 64 B each
-//   BNode4  tlas[..]  top-level hierarchy over the instances' world boxes
+//   BNode4  tlas[..]  the scene's top-level topology refitted to the instances'
+//                     world boxes
 //   double  xf[K][12] FP64 transforms (window pass)
 //   double  axw[J][3] world-frame hinge axes (gradient)
 //   int32   dof_node[J]
@@ -127,6 +129,37 @@ struct alignas(16) SliceOut {
 };
 static_assert(sizeof(SliceOut) == 96, "SliceOut is 96 bytes");
 
+// One kinematic-tree node as the articulation kernel reads it (built once per
+// scene): the edge label (pivot, axes as given and renormalised for the
+// rotation), the padded rest-pose box of the node's triangles and its
+// bottom-level root.
+struct alignas(16) ArtNode {
+    double pivot[3];
+    double axis[3][3];
+    double unit[3][3];
+    double blo[3], bhi[3];
+    int32_t parent, n_axes, dof_offset;
+    uint32_t blas_root;
+};
+static_assert(sizeof(ArtNode) == 240, "ArtNode layout");
+
+// One articulation slot to build on the device: the scene's nodes and top-level
+// topology, the cosine and sine of each clamped hinge angle (2 per degree of
+// freedom), and where the slot's arrays go.
+struct alignas(16) ArtJob {
+    const ArtNode *nodes;
+    const BNode4 *topo;
+    const double *cs;
+    Inst *inst;
+    BNode4 *tlas;
+    double *xf;
+    double *axw;
+    int32_t *dof_node;
+    double pad;
+    int32_t n_nodes, n_tlas;
+};
+static_assert(sizeof(ArtJob) == 80, "ArtJob layout");
+
 // One evaluation, as the kernels see it.
 struct alignas(64) EvalDesc {
     // scene
@@ -173,6 +206,7 @@ struct alignas(64) EvalDesc {
     int64_t fan_base;       // first fan partial slot (n_patches x bounces x ceil(n_diffuse / FAN_SLICE))
     double *gslice;         // gradient: n_slices x grad_n range sums
     SliceOut *pslice;       // n_slices range sums of the patch (and fan) partials
+    int64_t slice_base;     // the batch's number of this evaluation's first range sum
 };
 
 // The host writes these records and the kernels read them: both compilation
@@ -223,6 +257,7 @@ static_assert(offsetof(EvalDesc, n_slices) == 340, "EvalDesc layout");
 static_assert(offsetof(EvalDesc, fan_base) == 344, "EvalDesc layout");
 static_assert(offsetof(EvalDesc, gslice) == 352, "EvalDesc layout");
 static_assert(offsetof(EvalDesc, pslice) == 360, "EvalDesc layout");
+static_assert(offsetof(EvalDesc, slice_base) == 368, "EvalDesc layout");
 static_assert(sizeof(PatchOut) == 64, "PatchOut layout");
 static_assert(offsetof(PatchOut, f) == 0, "PatchOut layout");
 static_assert(offsetof(PatchOut, hits) == 48, "PatchOut layout");
@@ -260,6 +295,9 @@ constexpr int N_QUEUES = 8;
 constexpr int QUEUE_STRIDE = 64;
 int launch_window(const EvalDesc *d_desc, int n_evals, int blocks_x, uint64_t *d_win, uint32_t *d_queue,
                   void *stream);
+// Builds n_jobs articulation slots, one thread each (articulate.hip); the
+// window kernel reads them, so it runs first on the same stream.
+int launch_articulate(const ArtJob *d_jobs, int n_jobs, void *stream);
 // d_spill: grid_blocks * BLOCK * STACK_SPILL words; chunk counts below 2^31.
 // d_fan_out (forward, diffuse rays on): the trace kernel also traces every
 // patch's diffuse fans into their partial slots (no fan launch follows).
@@ -273,9 +311,11 @@ int launch_trace(const EvalDesc *d_desc, const int64_t *d_chunk_base, int n_eval
 int launch_fans(const EvalDesc *d_desc, const int64_t *d_unit_base, int n_evals, const uint64_t *d_win,
                 int64_t total_units, int per_claim, uint32_t *d_queue, uint32_t *d_spill, PatchOut *d_fan_out,
                 uint64_t *d_fan_counts, bool count, int grid_blocks, void *stream);
+// d_slice_eval: the evaluation of each of the batch's total_slices range sums
+// (one block each; an evaluation's are consecutive, from its slice_base).
 int launch_reduce(const EvalDesc *d_desc, int n_evals, const uint64_t *d_win, const PatchOut *d_patches,
                   const uint64_t *d_counts, const PatchOut *d_fan_out, const uint64_t *d_fan_counts, bool count,
-                  bool grad, void *d_out, void *stream);
+                  bool grad, const uint32_t *d_slice_eval, int64_t total_slices, void *d_out, void *stream);
 // Resident blocks per compute unit of the trace kernel variant.
 int trace_blocks_per_cu(bool count, bool grad, bool dir, int lds_grad_doubles);
 // Resident blocks per compute unit of the fan kernel variant.
