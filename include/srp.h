@@ -160,8 +160,9 @@ int srp_set_materials(srp_scene *scene, const srp_material *mats, int32_t n_mats
 
 /* Set the hinge angles (Sec. 4.4.2): angles[n_dof] in node order, then axis
  * order; each is clamped to its interval (not an error).  Only the per-node
- * instance transforms and the top-level hierarchy over the nodes are rebuilt;
- * the per-node hierarchies are untouched.  Returns the number of clamped
+ * instance transforms and the boxes of the top-level hierarchy over the nodes
+ * change (its topology is built once, over the rest pose, and refitted); the
+ * per-node hierarchies are untouched.  Returns the number of clamped
  * angles (>= 0) on success.  Errors: SRP_ERR_ARG (null, n_dof mismatch,
  * non-finite angle). */
 int srp_set_panel_angles(srp_scene *scene, const double *angles, int32_t n_dof);
@@ -184,6 +185,10 @@ int srp_eval(srp_scene *scene, const srp_eval_params *params, srp_result *out,
  * fixed-order reduction).  out_dev: device array of n_items srp_result,
  * written in stream order on hip_stream (a hipStream_t; NULL = null stream).
  * The call returns once the work is queued; host inputs may be reused then.
+ * Items with angles get one articulation slot per distinct angle vector
+ * (equal bits), built on the device from the cosine and sine of each clamped
+ * angle: the same bits as srp_set_panel_angles gives for those angles, so an
+ * item's result equals the single evaluation after srp_set_panel_angles.
  * A batch whose device workspace (about 64 bytes per 8x8-pixel patch, plus
  * gradient partials) would exceed 16 GiB runs as consecutive sub-batches; the
  * call may then block while earlier sub-batches run.  Results are bitwise
