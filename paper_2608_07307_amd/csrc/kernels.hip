@@ -180,20 +180,25 @@ __device__ __forceinline__ void wave_lds_fence() {
 // the geometric normal was flipped.
 __device__ __forceinline__ bool hit_normal(const TraceCtx &TC, const EvalDesc &D, const Hit &h, const float d[3],
                                            float n[3], float &c, float &rs, float &rd, int32_t &id) {
-    const TriRec SRP_GLOBAL &T = TC.tris[h.tri];
+    // the instance's rotation does not depend on the triangle: read it first
     const Inst SRP_GLOBAL &I = TC.inst[h.inst];
+    const float4 Ra = *(const float4 SRP_GLOBAL *)&I.R[0], Rb = *(const float4 SRP_GLOBAL *)&I.R[4];
+    const float R8 = I.R[8];
+    const float IR[9] = {Ra.x, Ra.y, Ra.z, Ra.w, Rb.x, Rb.y, Rb.z, Rb.w, R8};
+    const TriRec SRP_GLOBAL &T = TC.tris[h.tri];
     float e1[3] = {T.v1[0] - T.v0[0], T.v1[1] - T.v0[1], T.v1[2] - T.v0[2]};
     float e2[3] = {T.v2[0] - T.v0[0], T.v2[1] - T.v0[1], T.v2[2] - T.v0[2]};
     float nl[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
-    for (int k = 0; k < 3; ++k) n[k] = I.R[3 * k] * nl[0] + I.R[3 * k + 1] * nl[1] + I.R[3 * k + 2] * nl[2];
+    for (int k = 0; k < 3; ++k) n[k] = IR[3 * k] * nl[0] + IR[3 * k + 1] * nl[1] + IR[3 * k + 2] * nl[2];
     float inv = rsqrtf(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
     const float nd = (n[0] * d[0] + n[1] * d[1] + n[2] * d[2]) * inv;
     const bool flip = nd > 0.0f;
     if (flip) inv = -inv;
     for (int k = 0; k < 3; ++k) n[k] *= inv;
     c = -(n[0] * d[0] + n[1] * d[1] + n[2] * d[2]);
-    rs = D.mats[2 * T.mat];
-    rd = D.mats[2 * T.mat + 1];
+    const float SRP_GLOBAL *mats = (const float SRP_GLOBAL *)D.mats;
+    rs = mats[2 * T.mat];
+    rd = mats[2 * T.mat + 1];
     id = T.id;
     return flip;
 }
@@ -299,7 +304,7 @@ __device__ __forceinline__ void fan_passes(const EvalDesc &D, const TraceCtx &TC
     const int S = (KD + FAN_SLICE - 1) / FAN_SLICE;
     const int PM = B * S;               // pass slots per patch
     const int R = B + 1 + B * KD;
-    const float4 *dset = reinterpret_cast<const float4 *>(D.dset);
+    const float4 SRP_GLOBAL *dset = (const float4 SRP_GLOBAL *)D.dset;
     // emitters packed in generation-then-lane order
     const int c0 = __popcll(m0), c1 = c0 + __popcll(m1), c2 = c1 + __popcll(m2), total = c2 + __popcll(m3);
     const int tasks = total * S;
@@ -341,8 +346,8 @@ __device__ __forceinline__ void fan_passes(const EvalDesc &D, const TraceCtx &TC
                     ++rays;
                     if (D.hit_ids) {
                         const int64_t slot = pix * R + (B + 1 + g * KD + k);
-                        D.hit_ids[slot] = h.tri >= 0 ? h.id : -1;
-                        D.hit_t[slot] = h.tri >= 0 ? h.t : 0.0f;
+                        ((int32_t SRP_GLOBAL *)D.hit_ids)[slot] = h.tri >= 0 ? h.id : -1;
+                        ((float SRP_GLOBAL *)D.hit_t)[slot] = h.tri >= 0 ? h.t : 0.0f;
                     }
                     if (h.tri >= 0) {
                         ++hits;
@@ -467,7 +472,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(GRAD ? SR
         const int B = D.bounces;
         const int KD = GRAD ? 0 : D.n_diffuse;          // diffuse rays per emitting hit
         const int R = B + 1 + B * KD;                   // recorded rays per pixel
-        const float4 *dset = reinterpret_cast<const float4 *>(D.dset);   // KD directions, then their mean
+        const float4 SRP_GLOBAL *dset = (const float4 SRP_GLOBAL *)D.dset;   // KD directions, then their mean
         const TraceCtx TC = trace_ctx(D);
 
         const int gK = D.n_nodes;
@@ -500,8 +505,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(GRAD ? SR
                 uint32_t emitted = 0;                           // generations whose hit emitted a fan
                 if (inside && D.hit_ids) {   // rays that are not traced or miss stay "no hit"
                     for (int s = 0; s < R; ++s) {
-                        D.hit_ids[pix * R + s] = -1;
-                        D.hit_t[pix * R + s] = 0.0f;
+                        ((int32_t SRP_GLOBAL *)D.hit_ids)[pix * R + s] = -1;
+                        ((float SRP_GLOBAL *)D.hit_t)[pix * R + s] = 0.0f;
                     }
                 }
                 if (valid) {
@@ -518,8 +523,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(GRAD ? SR
                             break;
                         }
                         if (D.hit_ids) {
-                            D.hit_ids[pix * R + gen] = h.tri >= 0 ? h.id : -1;
-                            D.hit_t[pix * R + gen] = h.tri >= 0 ? h.t : 0.0f;
+                            ((int32_t SRP_GLOBAL *)D.hit_ids)[pix * R + gen] = h.tri >= 0 ? h.id : -1;
+                            ((float SRP_GLOBAL *)D.hit_t)[pix * R + gen] = h.tri >= 0 ? h.t : 0.0f;
                         }
                         if (h.tri < 0) break;
                         hcnt += gen == 0 ? 1u : (1u << 20);
@@ -573,7 +578,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(GRAD ? SR
                     for (int g = 0; g < SRP_MAX_BOUNCES; ++g) {
                         if (g >= B) break;
                         em[g] = __ballot((emitted >> g) & 1u);
-                        if (lane == 0) D.emit_mask[(size_t)pt * B + g] = em[g];
+                        if (lane == 0) ((uint64_t SRP_GLOBAL *)D.emit_mask)[(size_t)pt * B + g] = em[g];
                     }
                 }
                 if (GRAD) {
@@ -603,7 +608,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(GRAD ? SR
                             float inv = rsqrtf(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
                             if (ew & CHAIN_FLIP) inv = -inv;
                             for (int i = 0; i < 3; ++i) n[i] *= inv;
-                            const float rs = D.mats[2 * T.mat], rd = D.mats[2 * T.mat + 1];
+                            const float SRP_GLOBAL *mats = (const float SRP_GLOBAL *)D.mats;
+                            const float rs = mats[2 * T.mat], rd = mats[2 * T.mat + 1];
                             // (d, w) hold the ray after hit k when hit k spawned one: undo the
                             // reflection and the weight factor to get hit k's incoming ray
                             if (k < K - 1 || cont) {
@@ -710,7 +716,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(GRAD ? SR
         }
         if (GRAD) {
             wave_lds_fence();
-            double *dst = D.grad_part + (size_t)kc * D.grad_n;
+            double SRP_GLOBAL *dst = (double SRP_GLOBAL *)(D.grad_part + (size_t)kc * D.grad_n);
             for (int i = lane; i < D.grad_n; i += WAVE) dst[i] = gw[i];
         }
     }
@@ -767,7 +773,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(SRP_WPE_F
             const int V = D.n_parts, B = D.bounces;
             const int64_t p = u / V;            // the patch
             const int v = (int)(u - p * V);     // which of its parts
-            const uint64_t *em = D.emit_mask + (size_t)p * B;
+            const uint64_t SRP_GLOBAL *em = (const uint64_t SRP_GLOBAL *)(D.emit_mask + (size_t)p * B);
             const uint64_t m0 = em[0], m1 = B > 1 ? em[1] : 0ull, m2 = B > 2 ? em[2] : 0ull, m3 = B > 3 ? em[3] : 0ull;
             fan_passes<COUNT>(D, trace_ctx(D), p, m0, m1, m2, m3, v, V, tmin2, stack, lacc, lane, fan_out, fan_counts);
         }

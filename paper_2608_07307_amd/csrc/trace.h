@@ -340,10 +340,12 @@ SRP_HD inline bool trace_closest(const TraceCtx &C, const float o[3], const floa
             const float4 A = q[0], B = q[1], Cc = q[2];
             const int32_t id = f2i(A.w);
             if (COUNT) ntri++;
-            if (id == exclude_id) continue;
+            // the excluded triangle is tested too and rejected here: skipping it
+            // before the test would hold the third corner's load back until the
+            // id had arrived (two memory round trips per triangle instead of one)
             const float va[3] = {A.x, A.y, A.z}, vb[3] = {B.x, B.y, B.z}, vc[3] = {Cc.x, Cc.y, Cc.z};
             const float t = tri_hit(F, va, vb, vc);
-            if (t > tmin && (t < h.t || (t == h.t && id < h.id))) {
+            if (id != exclude_id && t > tmin && (t < h.t || (t == h.t && id < h.id))) {
                 h.t = t;
                 h.tri = (int32_t)(first + k);
                 h.inst = inst;
