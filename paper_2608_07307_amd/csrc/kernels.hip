@@ -595,21 +595,28 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(GRAD ? SR
                         int node = 0, mat = 0;
                         if (act) {
                             // hit k's normal exactly as the forward pass computed it
+                            // the triangle record in one round trip, then its instance's
+                            // rotation and its material together
                             const uint32_t ew = lchain[k * BLOCK];
-                            const TriRec SRP_GLOBAL &T = TC.tris[ew & ~CHAIN_FLIP];
-                            const Inst SRP_GLOBAL &I = TC.inst[T.node];
-                            float e1[3] = {T.v1[0] - T.v0[0], T.v1[1] - T.v0[1], T.v1[2] - T.v0[2]};
-                            float e2[3] = {T.v2[0] - T.v0[0], T.v2[1] - T.v0[1], T.v2[2] - T.v0[2]};
+                            const float4 SRP_GLOBAL *tq = (const float4 SRP_GLOBAL *)(TC.tris + (ew & ~CHAIN_FLIP));
+                            const float4 T0 = tq[0], T1 = tq[1], T2 = tq[2];
+                            const int tnode = f2i(T2.w), tmat = f2i(T1.w);
+                            const Inst SRP_GLOBAL &I = TC.inst[tnode];
+                            const float4 Ra = *(const float4 SRP_GLOBAL *)&I.R[0], Rb = *(const float4 SRP_GLOBAL *)&I.R[4];
+                            const float R8 = I.R[8];
+                            const float2 rm = ((const float2 SRP_GLOBAL *)D.mats)[tmat];
+                            const float IR[9] = {Ra.x, Ra.y, Ra.z, Ra.w, Rb.x, Rb.y, Rb.z, Rb.w, R8};
+                            float e1[3] = {T1.x - T0.x, T1.y - T0.y, T1.z - T0.z};
+                            float e2[3] = {T2.x - T0.x, T2.y - T0.y, T2.z - T0.z};
                             float nl[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
                                            e1[0] * e2[1] - e1[1] * e2[0]};
                             float n[3];
                             for (int i = 0; i < 3; ++i)
-                                n[i] = I.R[3 * i] * nl[0] + I.R[3 * i + 1] * nl[1] + I.R[3 * i + 2] * nl[2];
+                                n[i] = IR[3 * i] * nl[0] + IR[3 * i + 1] * nl[1] + IR[3 * i + 2] * nl[2];
                             float inv = rsqrtf(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
                             if (ew & CHAIN_FLIP) inv = -inv;
                             for (int i = 0; i < 3; ++i) n[i] *= inv;
-                            const float SRP_GLOBAL *mats = (const float SRP_GLOBAL *)D.mats;
-                            const float rs = mats[2 * T.mat], rd = mats[2 * T.mat + 1];
+                            const float rs = rm.x, rd = rm.y;
                             // (d, w) hold the ray after hit k when hit k spawned one: undo the
                             // reflection and the weight factor to get hit k's incoming ray
                             if (k < K - 1 || cont) {
@@ -662,8 +669,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(GRAD ? SR
                                     A[3 * i + j] = A[3 * i + j] - 2.0f * An[i] * n[j] +
                                                    w * ((i == j ? 1.0f - rs : 0.0f) + 2.0f * rs * n[i] * n[j]);
                             for (int i = 0; i < 3; ++i) Tn[i] = (1.0f - rs) * d[i] - 2.0f * sc * n[i] + rs * Tn[i];
-                            node = T.node;
-                            mat = T.mat;
+                            node = tnode;
+                            mat = tmat;
                         }
                         wave_scatter_add(gw, node, act, Hm, 9, 9);
                         wave_scatter_add(gw + 9 * gK, mat, act, gmat, 6, 6);
