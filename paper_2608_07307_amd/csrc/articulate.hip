@@ -1,13 +1,14 @@
 // Articulation slots on the GPU (Sec. 4.4.2 steps 1, 4 and 5 as rigid
-// instance transforms; Sec. 4.4.1 for the tree): one thread per slot composes
-// the node transforms down the kinematic tree in FP64, writes the instances
-// and world hinge axes, and refits the scene's fixed top-level topology to the
-// instances' world boxes.  The host computes the cosine and sine of every
-// clamped angle (the same library calls as its own slot build); everything
-// after that is the host build's sequence of separately rounded FP64
-// operations (contraction is off in this file and in the host's), so a slot
-// built here holds the same bits as one built on the host for the same
-// angles.
+// instance transforms; Sec. 4.4.1 for the tree): one wave per slot, one lane
+// per tree node.  The nodes are composed level by level down the tree (a node
+// reads its parent's FP64 transform from LDS), then every instance's world box
+// is computed in parallel and the scene's fixed top-level topology is refitted
+// level by level from the bottom.  The host computes the cosine and sine of
+// every clamped angle (the same library calls as its own slot build); every
+// node's and box's arithmetic after that is the host build's sequence of
+// separately rounded FP64 operations (contraction is off in this file and in
+// the host's), so a slot built here holds the same bits as one built on the
+// host for the same angles.
 #include <hip/hip_runtime.h>
 
 #include "srp.h"
@@ -75,76 +76,98 @@ __device__ inline void inst_box(const ArtNode &nd, const double *X, double pad, 
 }
 
 __global__ __launch_bounds__(ART_BLOCK) void k_articulate(const ArtJob *__restrict__ jobs, int n_jobs) {
-    const int j = blockIdx.x * ART_BLOCK + threadIdx.x;
-    if (j >= n_jobs) return;
-    const ArtJob J = jobs[j];
-    // node transforms, parents first (node order is a topological order)
-    for (int k = 0; k < J.n_nodes; ++k) {
-        const ArtNode &nd = J.nodes[k];
-        double X[12];
-        if (k == 0) {
-            for (int c = 0; c < 12; ++c) X[c] = (c == 0 || c == 4 || c == 8) ? 1.0 : 0.0;
-        } else {
-            double Pm[12];
-            for (int c = 0; c < 12; ++c) Pm[c] = J.xf[12 * nd.parent + c];
-            double prefix[9], Rl[9];
-            for (int c = 0; c < 9; ++c) {
-                prefix[c] = Pm[c];   // R_parent * R(a_0) ... R(a_{i-1})
-                Rl[c] = (c == 0 || c == 4 || c == 8) ? 1.0 : 0.0;
-            }
-            for (int a = 0; a < nd.n_axes; ++a) {
-                const int q = nd.dof_offset + a;
-                double w[3];
-                mat3_vec(prefix, nd.axis[a], w);
-                for (int c = 0; c < 3; ++c) J.axw[3 * q + c] = w[c];
-                J.dof_node[q] = k;
-                double Ra[9];
-                rot_unit(nd.unit[a], J.cs[2 * q], J.cs[2 * q + 1], Ra);
-                mat3_mul(Rl, Ra, Rl);
-                mat3_mul(prefix, Ra, prefix);
-            }
-            // local: x -> Rl (x - p) + p ; world: R_par * local + t_par
-            double Rp[3], tl[3], tw[3];
-            mat3_vec(Rl, nd.pivot, Rp);
-            for (int c = 0; c < 3; ++c) tl[c] = nd.pivot[c] - Rp[c];
-            mat3_vec(Pm, tl, tw);
-            mat3_mul(Pm, Rl, X);
-            for (int c = 0; c < 3; ++c) X[9 + c] = tw[c] + Pm[9 + c];
-        }
-        for (int c = 0; c < 12; ++c) J.xf[12 * k + c] = X[c];
-        Inst I;
-        for (int c = 0; c < 9; ++c) I.R[c] = (float)X[c];
-        for (int c = 0; c < 3; ++c) I.t[c] = (float)X[9 + c];
-        I.root = nd.blas_root;
-        I.node = k;
-        I.pad[0] = I.pad[1] = 0.0f;
-        J.inst[k] = I;
-    }
-    // refit, children before parents: an instance leaf takes its world box, an
-    // inner child the union of its node's non-empty boxes
-    for (int i = J.n_tlas - 1; i >= 0; --i) {
-        BNode4 nd = J.topo[i];
-        for (int k = 0; k < 4; ++k) {
-            const uint32_t r = nd.ref[k];
-            if (r == REF_NONE) continue;
-            float lo[3], hi[3];
-            if (ref_type(r) == REF_TLAS_LEAF) {
-                const uint32_t q = ref_index(r);
-                inst_box(J.nodes[q], J.xf + 12 * q, J.pad, lo, hi);
+    __shared__ double sX[SRP_MAX_NODES * 12];   // node transforms
+    __shared__ float sB[SRP_MAX_NODES * 6];     // instance boxes (lo, hi)
+    __shared__ BNode4 sT[SRP_MAX_NODES];        // refitted top-level nodes
+    if ((int)blockIdx.x >= n_jobs) return;
+    const ArtJob J = jobs[blockIdx.x];
+    const int lane = threadIdx.x;
+    // node transforms, one tree level after the other
+    for (int L = 0; L <= J.max_depth; ++L) {
+        for (int k = lane; k < J.n_nodes; k += ART_BLOCK) {
+            const ArtNode &nd = J.nodes[k];
+            if (nd.depth != L) continue;
+            double X[12];
+            if (k == 0) {
+                for (int c = 0; c < 12; ++c) X[c] = (c == 0 || c == 4 || c == 8) ? 1.0 : 0.0;
             } else {
-                const BNode4 &c = J.tlas[ref_index(r)];
-                for (int a = 0; a < 3; ++a) { lo[a] = INFINITY; hi[a] = -INFINITY; }
-                for (int m = 0; m < 4; ++m) {
-                    if (c.ref[m] == REF_NONE) continue;
-                    lo[0] = lmin(lo[0], c.lox[m]); hi[0] = lmax(hi[0], c.hix[m]);
-                    lo[1] = lmin(lo[1], c.loy[m]); hi[1] = lmax(hi[1], c.hiy[m]);
-                    lo[2] = lmin(lo[2], c.loz[m]); hi[2] = lmax(hi[2], c.hiz[m]);
+                double Pm[12];
+                for (int c = 0; c < 12; ++c) Pm[c] = sX[12 * nd.parent + c];
+                double prefix[9], Rl[9];
+                for (int c = 0; c < 9; ++c) {
+                    prefix[c] = Pm[c];   // R_parent * R(a_0) ... R(a_{i-1})
+                    Rl[c] = (c == 0 || c == 4 || c == 8) ? 1.0 : 0.0;
                 }
+                for (int a = 0; a < nd.n_axes; ++a) {
+                    const int q = nd.dof_offset + a;
+                    double w[3];
+                    mat3_vec(prefix, nd.axis[a], w);
+                    for (int c = 0; c < 3; ++c) J.axw[3 * q + c] = w[c];
+                    J.dof_node[q] = k;
+                    double Ra[9];
+                    rot_unit(nd.unit[a], J.cs[2 * q], J.cs[2 * q + 1], Ra);
+                    mat3_mul(Rl, Ra, Rl);
+                    mat3_mul(prefix, Ra, prefix);
+                }
+                // local: x -> Rl (x - p) + p ; world: R_par * local + t_par
+                double Rp[3], tl[3], tw[3];
+                mat3_vec(Rl, nd.pivot, Rp);
+                for (int c = 0; c < 3; ++c) tl[c] = nd.pivot[c] - Rp[c];
+                mat3_vec(Pm, tl, tw);
+                mat3_mul(Pm, Rl, X);
+                for (int c = 0; c < 3; ++c) X[9 + c] = tw[c] + Pm[9 + c];
             }
-            nd.lox[k] = lo[0]; nd.loy[k] = lo[1]; nd.loz[k] = lo[2];
-            nd.hix[k] = hi[0]; nd.hiy[k] = hi[1]; nd.hiz[k] = hi[2];
+            for (int c = 0; c < 12; ++c) {
+                sX[12 * k + c] = X[c];
+                J.xf[12 * k + c] = X[c];
+            }
+            Inst I;
+            for (int c = 0; c < 9; ++c) I.R[c] = (float)X[c];
+            for (int c = 0; c < 3; ++c) I.t[c] = (float)X[9 + c];
+            I.root = nd.blas_root;
+            I.node = k;
+            I.pad[0] = I.pad[1] = 0.0f;
+            J.inst[k] = I;
         }
-        J.tlas[i] = nd;
+        __syncthreads();
+    }
+    // the instances' world boxes
+    for (int k = lane; k < J.n_nodes; k += ART_BLOCK) {
+        const ArtNode &nd = J.nodes[k];
+        if (nd.blas_root == REF_NONE) continue;
+        inst_box(nd, sX + 12 * k, J.pad, sB + 6 * k, sB + 6 * k + 3);
+    }
+    __syncthreads();
+    // refit, one height after the other: an instance leaf takes its world box,
+    // an inner child the union of its node's non-empty boxes
+    for (int hgt = 0; hgt <= J.max_height; ++hgt) {
+        for (int i = lane; i < J.n_tlas; i += ART_BLOCK) {
+            BNode4 nd = J.topo[i];
+            if ((int)nd.pad[0] != hgt) continue;
+            for (int k = 0; k < 4; ++k) {
+                const uint32_t r = nd.ref[k];
+                if (r == REF_NONE) continue;
+                float lo[3], hi[3];
+                if (ref_type(r) == REF_TLAS_LEAF) {
+                    const uint32_t q = ref_index(r);
+                    for (int a = 0; a < 3; ++a) { lo[a] = sB[6 * q + a]; hi[a] = sB[6 * q + 3 + a]; }
+                } else {
+                    const BNode4 &c = sT[ref_index(r)];
+                    for (int a = 0; a < 3; ++a) { lo[a] = INFINITY; hi[a] = -INFINITY; }
+                    for (int m = 0; m < 4; ++m) {
+                        if (c.ref[m] == REF_NONE) continue;
+                        lo[0] = lmin(lo[0], c.lox[m]); hi[0] = lmax(hi[0], c.hix[m]);
+                        lo[1] = lmin(lo[1], c.loy[m]); hi[1] = lmax(hi[1], c.hiy[m]);
+                        lo[2] = lmin(lo[2], c.loz[m]); hi[2] = lmax(hi[2], c.hiz[m]);
+                    }
+                }
+                nd.lox[k] = lo[0]; nd.loy[k] = lo[1]; nd.loz[k] = lo[2];
+                nd.hix[k] = hi[0]; nd.hiy[k] = hi[1]; nd.hiz[k] = hi[2];
+            }
+            sT[i] = nd;
+            J.tlas[i] = nd;
+        }
+        __syncthreads();
     }
 }
 
@@ -152,8 +175,7 @@ __global__ __launch_bounds__(ART_BLOCK) void k_articulate(const ArtJob *__restri
 
 int launch_articulate(const ArtJob *d_jobs, int n_jobs, void *stream) {
     if (n_jobs <= 0) return 0;
-    hipLaunchKernelGGL(k_articulate, dim3((n_jobs + ART_BLOCK - 1) / ART_BLOCK), dim3(ART_BLOCK), 0,
-                       (hipStream_t)stream, d_jobs, n_jobs);
+    hipLaunchKernelGGL(k_articulate, dim3(n_jobs), dim3(ART_BLOCK), 0, (hipStream_t)stream, d_jobs, n_jobs);
     return (int)hipGetLastError();
 }
 

@@ -620,6 +620,9 @@ void staging_fill(const Layout &L, const srp_batch_item *items, const BatchOut &
         J.pad = S.pad;
         J.n_nodes = S.n_nodes;
         J.n_tlas = (int32_t)S.tlas_topo.size();
+        J.max_depth = S.tree_max_depth;
+        J.max_height = S.tlas_max_height;
+        J.pad_[0] = J.pad_[1] = 0;
     }
     for (int64_t k = 0; k < n; ++k) {
         const srp_batch_item &it = items[k];

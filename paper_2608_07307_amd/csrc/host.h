@@ -68,9 +68,11 @@ struct SceneHost {
     // top level: 4-wide nodes over the non-empty nodes' instances, built once over
     // the rest pose; a slot copies the references and refits the boxes (children
     // follow their parent in this array)
-    std::vector<BNode4> tlas_topo;
+    std::vector<BNode4> tlas_topo;  // pad[0] of each node: its height (inner-node levels below it)
     uint32_t tlas_root = REF_NONE;
     int tlas_depth = 0;
+    int tlas_max_height = 0;
+    int tree_max_depth = 0;         // kinematic tree: most edges from the root
     int stack_worst = 0;            // most traversal-stack entries a ray can hold (any pose)
 };
 

@@ -511,6 +511,7 @@ std::vector<ArtNode> art_nodes(const SceneHost &S) {
         a.n_axes = nd.n_axes;
         a.dof_offset = nd.dof_offset;
         a.blas_root = nd.blas_root;
+        a.depth = k == 0 ? 0 : v[nd.parent].depth + 1;   // parents precede their children
     }
     return v;
 }
@@ -670,6 +671,10 @@ int tlas_topology(SceneHost *S, std::string *err) {
         *err = "hierarchy depth exceeds the traversal stack";
         return SRP_ERR_DEPTH;
     }
+    if (S->tlas_topo.size() > (size_t)SRP_MAX_NODES) {   // (at most 127 for 128 instances)
+        *err = "top level: too many nodes";
+        return SRP_ERR_ARG;
+    }
     // the refit visits nodes last to first: every child must follow its parent
     for (size_t i = 0; i < S->tlas_topo.size(); ++i)
         for (int k = 0; k < 4; ++k) {
@@ -679,6 +684,28 @@ int tlas_topology(SceneHost *S, std::string *err) {
                 return SRP_ERR_ARG;
             }
         }
+    // each node's height (inner-node levels below it) in pad[0]: the device refit
+    // runs level by level from height 0 up
+    S->tlas_max_height = 0;
+    for (size_t i = S->tlas_topo.size(); i-- > 0;) {
+        BNode4 &nd = S->tlas_topo[i];
+        uint32_t hgt = 0;
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t r = nd.ref[k];
+            if (r != REF_NONE && ref_type(r) == REF_TLAS_NODE)
+                hgt = std::max(hgt, S->tlas_topo[ref_index(r)].pad[0] + 1);
+        }
+        nd.pad[0] = hgt;
+        S->tlas_max_height = std::max(S->tlas_max_height, (int)hgt);
+    }
+    S->tree_max_depth = 0;
+    {
+        std::vector<int> depth(S->n_nodes, 0);
+        for (int k = 1; k < S->n_nodes; ++k) {
+            depth[k] = depth[S->nodes[k].parent] + 1;
+            S->tree_max_depth = std::max(S->tree_max_depth, depth[k]);
+        }
+    }
     return SRP_OK;
 }
 

@@ -140,11 +140,14 @@ struct alignas(16) ArtNode {
     double blo[3], bhi[3];
     int32_t parent, n_axes, dof_offset;
     uint32_t blas_root;
+    int32_t depth;      // edges from the root
+    int32_t pad_;
 };
 static_assert(sizeof(ArtNode) == 240, "ArtNode layout");
 
 // One articulation slot to build on the device: the scene's nodes and top-level
-// topology, the cosine and sine of each clamped hinge angle (2 per degree of
+// topology (each node's height, the most inner-node levels below it, in
+// pad[0]), the cosine and sine of each clamped hinge angle (2 per degree of
 // freedom), and where the slot's arrays go.
 struct alignas(16) ArtJob {
     const ArtNode *nodes;
@@ -157,8 +160,10 @@ struct alignas(16) ArtJob {
     int32_t *dof_node;
     double pad;
     int32_t n_nodes, n_tlas;
+    int32_t max_depth, max_height;
+    int32_t pad_[2];
 };
-static_assert(sizeof(ArtJob) == 80, "ArtJob layout");
+static_assert(sizeof(ArtJob) == 96, "ArtJob layout");
 
 // One evaluation, as the kernels see it.
 struct alignas(64) EvalDesc {
