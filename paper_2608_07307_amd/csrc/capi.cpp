@@ -942,6 +942,86 @@ int dev_upload(T **dst, const std::vector<T> &src) {
 }  // namespace
 
 namespace srp {
+// One evaluation (srp_eval) with explicit hinge angles for this evaluation
+// only (NULL: the scene's current angles): the item's articulation slot is
+// built by the articulation kernel inside the captured launch, so a caller
+// that changes the angles at every evaluation (a sun-tracking propagation)
+// needs no host slot build and no synchronous upload.  The scene's current
+// angles are not changed.
+int eval_single(srp_scene *scene, const srp_eval_params *params, const double *angles, srp_result *out,
+                int32_t *hit_ids, float *hit_t) {
+    if (!scene || !params || !out) return fail(SRP_ERR_ARG, "null scene, params or out");
+    int rc = check_params(params);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(g_ws.mu);
+    if ((rc = ws_init())) return rc;
+    srp_batch_item it{scene, angles, *params};
+    if ((rc = check_items(&it, 1, false, BatchOut()))) return rc;
+    if (!scene->d_res) {
+        if (hipMalloc(&scene->d_res, sizeof(srp_result)) != hipSuccess) { (void)hipGetLastError(); return fail(SRP_ERR_OOM, "result allocation failed"); }
+        if (hipHostMalloc(&scene->h_res, sizeof(srp_result), hipHostMallocDefault) != hipSuccess) { (void)hipGetLastError(); return fail(SRP_ERR_OOM, "pinned result allocation failed"); }
+    }
+    const size_t R = (size_t)params->bounces + 1 + (size_t)params->bounces * params->n_diffuse;
+    size_t nrec = (hit_ids || hit_t) ? (size_t)params->n * params->n * R : 0;
+    if (nrec) {
+        // recorded evaluations (tests, fixed-visibility checks) take the direct path
+        static char *d_rec = nullptr;
+        static size_t rec_cap = 0;
+        if (nrec * 8 > rec_cap) {
+            if ((rc = ws_wait())) return rc;
+            if (d_rec) HIPCHK(hipFree(d_rec));
+            d_rec = nullptr;
+            if (hipMalloc(&d_rec, nrec * 8) != hipSuccess) {
+                (void)hipGetLastError();
+                rec_cap = 0;
+                return fail(SRP_ERR_OOM, "record buffer allocation failed");
+            }
+            rec_cap = nrec * 8;
+        }
+        BatchOut bo;
+        bo.d_out = scene->d_res;
+        bo.h_copy = scene->h_res;
+        bo.d_hit_ids = reinterpret_cast<int32_t *>(d_rec);
+        bo.d_hit_t = reinterpret_cast<float *>(d_rec + nrec * 4);
+        if ((rc = run_batch(&it, 1, false, bo, g_ws.stream))) return rc;
+        HIPCHK(hipStreamSynchronize(g_ws.stream));
+        g_ws.pending = false;
+        *out = *scene->h_res;
+        if (hit_ids) HIPCHK(hipMemcpy(hit_ids, d_rec, nrec * 4, hipMemcpyDeviceToHost));
+        if (hit_t) HIPCHK(hipMemcpy(hit_t, d_rec + nrec * 4, nrec * 4, hipMemcpyDeviceToHost));
+    } else {
+        // replay of a captured single-evaluation launch (one graph launch + one sync)
+        uint64_t key = ((uint64_t)params->n << 24) | ((uint64_t)params->n_diffuse << 16) |
+                       ((uint64_t)params->bounces << 8) | params->flags | (angles ? (1ull << 63) : 0);
+        PlanImpl *P = nullptr;
+        auto f = scene->eval_plans.find(key);
+        if (f != scene->eval_plans.end()) {
+            P = f->second;
+            bool ok = false;
+            if ((rc = plan_refill(P, &it, 1, &ok))) return rc;
+            if (!ok) {
+                plan_free(P);
+                scene->eval_plans.erase(f);
+                P = nullptr;
+            }
+        }
+        if (!P) {
+            if ((rc = ws_wait())) return rc;
+            BatchOut bo;
+            bo.d_out = scene->d_res;
+            bo.h_copy = scene->h_res;
+            if ((rc = plan_make(&it, 1, false, bo, &P))) return rc;
+            scene->eval_plans[key] = P;
+        }
+        HIPCHK(hipGraphLaunch(P->exec, g_ws.stream));
+        HIPCHK(hipStreamSynchronize(g_ws.stream));
+        *out = *scene->h_res;
+    }
+    if (out->status & SRP_STATUS_STACK) return fail(SRP_ERR_DEPTH, "traversal stack overflow");
+    return SRP_OK;
+}
+
+
 const SceneHost &scene_host(const srp_scene *sc) { return sc->h; }
 int scene_rest_normal(const srp_scene *sc, int node, double n0[3]) {
     for (int a = 0; a < 3; ++a) n0[a] = sc->h.nodes[node].n0[a];
@@ -1068,74 +1148,7 @@ int srp_nplate_from_scene(srp_scene *scene, const double *angles, srp_plate *pla
 
 int srp_eval(srp_scene *scene, const srp_eval_params *params, srp_result *out, int32_t *hit_ids, float *hit_t) {
     g_err.clear();
-    if (!scene || !params || !out) return fail(SRP_ERR_ARG, "null scene, params or out");
-    int rc = check_params(params);
-    if (rc) return rc;
-    std::lock_guard<std::mutex> lk(g_ws.mu);
-    if ((rc = ws_init())) return rc;
-    srp_batch_item it{scene, nullptr, *params};
-    if (!scene->d_res) {
-        if (hipMalloc(&scene->d_res, sizeof(srp_result)) != hipSuccess) { (void)hipGetLastError(); return fail(SRP_ERR_OOM, "result allocation failed"); }
-        if (hipHostMalloc(&scene->h_res, sizeof(srp_result), hipHostMallocDefault) != hipSuccess) { (void)hipGetLastError(); return fail(SRP_ERR_OOM, "pinned result allocation failed"); }
-    }
-    const size_t R = (size_t)params->bounces + 1 + (size_t)params->bounces * params->n_diffuse;
-    size_t nrec = (hit_ids || hit_t) ? (size_t)params->n * params->n * R : 0;
-    if (nrec) {
-        // recorded evaluations (tests, fixed-visibility checks) take the direct path
-        static char *d_rec = nullptr;
-        static size_t rec_cap = 0;
-        if (nrec * 8 > rec_cap) {
-            if ((rc = ws_wait())) return rc;
-            if (d_rec) HIPCHK(hipFree(d_rec));
-            d_rec = nullptr;
-            if (hipMalloc(&d_rec, nrec * 8) != hipSuccess) {
-                (void)hipGetLastError();
-                rec_cap = 0;
-                return fail(SRP_ERR_OOM, "record buffer allocation failed");
-            }
-            rec_cap = nrec * 8;
-        }
-        BatchOut bo;
-        bo.d_out = scene->d_res;
-        bo.h_copy = scene->h_res;
-        bo.d_hit_ids = reinterpret_cast<int32_t *>(d_rec);
-        bo.d_hit_t = reinterpret_cast<float *>(d_rec + nrec * 4);
-        if ((rc = run_batch(&it, 1, false, bo, g_ws.stream))) return rc;
-        HIPCHK(hipStreamSynchronize(g_ws.stream));
-        g_ws.pending = false;
-        *out = *scene->h_res;
-        if (hit_ids) HIPCHK(hipMemcpy(hit_ids, d_rec, nrec * 4, hipMemcpyDeviceToHost));
-        if (hit_t) HIPCHK(hipMemcpy(hit_t, d_rec + nrec * 4, nrec * 4, hipMemcpyDeviceToHost));
-    } else {
-        // replay of a captured single-evaluation launch (one graph launch + one sync)
-        uint64_t key = ((uint64_t)params->n << 24) | ((uint64_t)params->n_diffuse << 16) |
-                       ((uint64_t)params->bounces << 8) | params->flags;
-        PlanImpl *P = nullptr;
-        auto f = scene->eval_plans.find(key);
-        if (f != scene->eval_plans.end()) {
-            P = f->second;
-            bool ok = false;
-            if ((rc = plan_refill(P, &it, 1, &ok))) return rc;
-            if (!ok) {
-                plan_free(P);
-                scene->eval_plans.erase(f);
-                P = nullptr;
-            }
-        }
-        if (!P) {
-            if ((rc = ws_wait())) return rc;
-            BatchOut bo;
-            bo.d_out = scene->d_res;
-            bo.h_copy = scene->h_res;
-            if ((rc = plan_make(&it, 1, false, bo, &P))) return rc;
-            scene->eval_plans[key] = P;
-        }
-        HIPCHK(hipGraphLaunch(P->exec, g_ws.stream));
-        HIPCHK(hipStreamSynchronize(g_ws.stream));
-        *out = *scene->h_res;
-    }
-    if (out->status & SRP_STATUS_STACK) return fail(SRP_ERR_DEPTH, "traversal stack overflow");
-    return SRP_OK;
+    return eval_single(scene, params, nullptr, out, hit_ids, hit_t);
 }
 
 int srp_eval_batch(const srp_batch_item *items, int64_t n_items, srp_result *out_dev, void *hip_stream) {

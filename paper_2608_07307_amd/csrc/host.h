@@ -96,6 +96,12 @@ double clamp_angle(const NodeInfo &nd, int a, double th, int *clamped);
 // The articulation kernel's view of the scene's nodes (same order).
 std::vector<ArtNode> art_nodes(const SceneHost &S);
 
+// srp_eval with hinge angles for this evaluation only (NULL: the scene's
+// current angles), the slot built on the device inside the captured launch;
+// the scene's current angles are unchanged (capi.cpp).
+int eval_single(srp_scene *scene, const srp_eval_params *params, const double *angles, srp_result *out,
+                int32_t *hit_ids, float *hit_t);
+
 // Fills S->plates from S->tris (which the library frees once they are on the
 // device).
 void plates_build(SceneHost *S);

@@ -315,7 +315,6 @@ int prop_accel(double, const double *r, const double *, double *a, void *user) {
     int rc;
     if (O.track_sun) {
         if ((rc = srp_sun_tracking_angles(C.sc, s, C.angles.data(), (int32_t)C.angles.size()))) return rc;
-        if ((rc = srp_set_panel_angles(C.sc, C.angles.data(), (int32_t)C.angles.size())) < 0) return rc;
     }
     srp_eval_params p;
     std::memset(&p, 0, sizeof p);
@@ -326,7 +325,9 @@ int prop_accel(double, const double *r, const double *, double *a, void *user) {
     p.n_diffuse = O.n_diffuse;
     std::memcpy(p.ref, O.ref, sizeof p.ref);
     srp_result res;
-    if ((rc = srp_eval(C.sc, &p, &res, nullptr, nullptr))) return rc;
+    // tracking: this stage's angles go with the evaluation (the slot is built on the
+    // device inside the captured launch); the scene takes the last ones at the end
+    if ((rc = eval_single(C.sc, &p, O.track_sun ? C.angles.data() : nullptr, &res, nullptr, nullptr))) return rc;
     clock_gettime(CLOCK_MONOTONIC, &t1);
     C.secs += (t1.tv_sec - t0.tv_sec) + 1e-9 * (t1.tv_nsec - t0.tv_nsec);
     C.evals++;
@@ -351,6 +352,10 @@ extern "C" int srp_propagate_rk78(srp_scene *scene, const srp_orbit_params *op, 
     if (rc < 0) return rc;
     rc = srp_rk78(y0, t0, t1, opts, prop_accel, &C, traj, max_rows, n_rows, nullptr);
     if (stats) { stats->n_evals = C.evals; stats->srp_seconds = C.secs; }
+    if (rc == SRP_OK && op->track_sun) {
+        const int r2 = srp_set_panel_angles(scene, C.angles.data(), S.n_dof);   // the last stage's angles
+        if (r2 < 0) return r2;
+    }
     return rc;
 }
 
@@ -368,5 +373,9 @@ extern "C" int srp_propagate(srp_scene *scene, const srp_orbit_params *op, const
     if (rc < 0) return rc;
     rc = srp_rk4(y0, t0, h, n_steps, prop_accel, &C, traj);
     if (stats) { stats->n_evals = C.evals; stats->srp_seconds = C.secs; }
+    if (rc == SRP_OK && op->track_sun) {
+        const int r2 = srp_set_panel_angles(scene, C.angles.data(), S.n_dof);   // the last stage's angles
+        if (r2 < 0) return r2;
+    }
     return rc;
 }
