@@ -978,11 +978,13 @@ __global__ __launch_bounds__(RBLOCK) void k_reduce(const EvalDesc *__restrict__ 
     if (GRAD) {
         const int G = D.grad_n, K = D.n_nodes, M = D.n_mats, J = D.n_dof;
         __shared__ double sg[MAX_GRAD_SLOTS];
+        __shared__ int spar[SRP_MAX_NODES];   // the tree, for the subtree walks below
         for (int j = tid; j < G; j += RBLOCK) {
             double t = 0.0;
             for (int q = 0; q < Q; ++q) t += D.gslice[(size_t)q * G + j];
             sg[j] = t;
         }
+        for (int q = tid; q < K; q += RBLOCK) spar[q] = D.parent[q];
         __syncthreads();
         double *g = D.grad_out;
         if (g) {
@@ -999,7 +1001,7 @@ __global__ __launch_bounds__(RBLOCK) void k_reduce(const EvalDesc *__restrict__ 
                 double S[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
                 for (int q = 0; q < K; ++q) {
                     int a = q;
-                    while (a > p) a = D.parent[a];
+                    while (a > p) a = spar[a];
                     if (a != p) continue;
                     for (int i = 0; i < 9; ++i) S[i] += sg[9 * q + i];
                 }
