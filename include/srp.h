@@ -115,7 +115,10 @@ typedef struct {
     int64_t n_box_tests;       /* ray-box tests (SRP_F_COUNT) */
     int64_t n_tri_tests;       /* ray-triangle tests (SRP_F_COUNT) */
     uint32_t status;           /* 0, or SRP_STATUS_* bits (the evaluation is then invalid) */
-    uint32_t reserved;
+    uint32_t n_clamped;        /* hinge angles of this evaluation that lay outside their
+                                  intervals and were clamped (Sec. 4.4.2; the item's angles,
+                                  or the scene's current ones as srp_set_panel_angles
+                                  counted them); not an error */
 } srp_result;
 
 /* srp_result.status bits */

@@ -108,7 +108,7 @@ class Scene:
 def _result_dict(r) -> dict:
     return dict(force=np.array(r.force[:]), torque=np.array(r.torque[:]), n_rays=r.n_rays,
                 n_hits=r.n_hits, n_secondary=r.n_secondary, n_secondary_hits=r.n_secondary_hits,
-                n_box_tests=r.n_box_tests, n_tri_tests=r.n_tri_tests, status=r.status)
+                n_box_tests=r.n_box_tests, n_tri_tests=r.n_tri_tests, status=r.status, n_clamped=r.n_clamped)
 
 
 def eval(scene: Scene, sun_dir, n, bounces=0, pressure=1.0, ref=(0, 0, 0), count=False,

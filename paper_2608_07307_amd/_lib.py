@@ -48,7 +48,7 @@ class srp_result(C.Structure):
     _fields_ = [("force", C.c_double * 3), ("torque", C.c_double * 3), ("n_rays", C.c_int64),
                 ("n_hits", C.c_int64), ("n_secondary", C.c_int64),
                 ("n_secondary_hits", C.c_int64), ("n_box_tests", C.c_int64),
-                ("n_tri_tests", C.c_int64), ("status", C.c_uint32), ("reserved", C.c_uint32)]
+                ("n_tri_tests", C.c_int64), ("status", C.c_uint32), ("n_clamped", C.c_uint32)]
 
 
 class srp_batch_item(C.Structure):
@@ -86,7 +86,7 @@ ACCEL_FN = C.CFUNCTYPE(C.c_int, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c
 RESULT_DTYPE = np.dtype([("force", "<f8", 3), ("torque", "<f8", 3), ("n_rays", "<i8"),
                          ("n_hits", "<i8"), ("n_secondary", "<i8"), ("n_secondary_hits", "<i8"),
                          ("n_box_tests", "<i8"), ("n_tri_tests", "<i8"), ("status", "<u4"),
-                         ("reserved", "<u4")])
+                         ("n_clamped", "<u4")])
 assert RESULT_DTYPE.itemsize == C.sizeof(srp_result)
 
 _lib = None

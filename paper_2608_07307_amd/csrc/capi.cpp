@@ -598,6 +598,7 @@ void staging_fill(const Layout &L, const srp_batch_item *items, const BatchOut &
         for (int64_t q = L.slice_base[k]; q < L.slice_base[k + 1]; ++q) seval[q] = (uint32_t)k;
     ArtJob *jobs = reinterpret_cast<ArtJob *>(H + L.o_jobs);
     double *cs = reinterpret_cast<double *>(H + L.o_cs);
+    std::vector<int> slot_clamped(L.slots.size(), 0);
     for (size_t q = 0; q < L.slots.size(); ++q) {
         const SlotRec &sl = L.slots[q];
         const SceneHost &S = sl.sc->h;
@@ -607,8 +608,7 @@ void staging_fill(const Layout &L, const srp_batch_item *items, const BatchOut &
             const NodeInfo &nd = S.nodes[k];
             for (int x = 0; x < nd.n_axes; ++x) {
                 const int j = nd.dof_offset + x;
-                int clamped = 0;
-                const double th = clamp_angle(nd, x, a[j], &clamped);
+                const double th = clamp_angle(nd, x, a[j], &slot_clamped[q]);
                 o[2 * j] = std::cos(th);
                 o[2 * j + 1] = std::sin(th);
             }
@@ -678,6 +678,7 @@ void staging_fill(const Layout &L, const srp_batch_item *items, const BatchOut &
         D.grad_part = L.grad ? reinterpret_cast<double *>(Dv + L.gpart_off[k]) : nullptr;
         D.n_slices = L.n_slices[k];
         D.slice_base = L.slice_base[k];
+        D.n_clamped = L.item_slot[k] >= 0 ? slot_clamped[L.item_slot[k]] : sc->cur.n_clamped;
         D.pslice = reinterpret_cast<SliceOut *>(Dv + L.pslice_off[k]);
         D.gslice = L.grad ? reinterpret_cast<double *>(Dv + L.gslice_off[k]) : nullptr;
         D.grad_out = (L.grad && bo.d_grad) ? bo.d_grad + k * bo.grad_stride : nullptr;

@@ -972,7 +972,7 @@ __global__ __launch_bounds__(RBLOCK) void k_reduce(const EvalDesc *__restrict__ 
         r.n_box_tests = COUNT ? (int64_t)N[3] : 0;
         r.n_tri_tests = COUNT ? (int64_t)N[4] : 0;
         r.status = S;
-        r.reserved = 0;
+        r.n_clamped = (uint32_t)D.n_clamped;
         out[e] = r;
     }
     if (GRAD) {

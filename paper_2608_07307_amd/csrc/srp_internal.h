@@ -212,6 +212,8 @@ struct alignas(64) EvalDesc {
     double *gslice;         // gradient: n_slices x grad_n range sums
     SliceOut *pslice;       // n_slices range sums of the patch (and fan) partials
     int64_t slice_base;     // the batch's number of this evaluation's first range sum
+    int32_t n_clamped;      // hinge angles of this evaluation clamped to their intervals
+    int32_t pad_;
 };
 
 // The host writes these records and the kernels read them: both compilation
@@ -263,6 +265,7 @@ static_assert(offsetof(EvalDesc, fan_base) == 344, "EvalDesc layout");
 static_assert(offsetof(EvalDesc, gslice) == 352, "EvalDesc layout");
 static_assert(offsetof(EvalDesc, pslice) == 360, "EvalDesc layout");
 static_assert(offsetof(EvalDesc, slice_base) == 368, "EvalDesc layout");
+static_assert(offsetof(EvalDesc, n_clamped) == 376, "EvalDesc layout");
 static_assert(sizeof(PatchOut) == 64, "PatchOut layout");
 static_assert(offsetof(PatchOut, f) == 0, "PatchOut layout");
 static_assert(offsetof(PatchOut, hits) == 48, "PatchOut layout");

@@ -2,7 +2,8 @@
 batch) against the host's build of the same slot (srp_set_panel_angles):
 both compose the node transforms in FP64 from the same cosines and sines and
 refit the same top-level topology, so results, test counts and gradients
-must be bitwise equal (Sec. 4.4.2 steps 1, 4, 5)."""
+must be bitwise equal (Sec. 4.4.2 steps 1, 4, 5); every result reports how
+many of its angles were clamped to their intervals."""
 import numpy as np
 import pytest
 
@@ -61,13 +62,17 @@ def test_device_slots_equal_host_slots(srp, name):
     print(f"{name}: {mesh.n_tris} tris, {mesh.n_nodes} nodes, {mesh.n_dof} DOF, {E} items", flush=True)
     out = srp.results_to_numpy(srp.eval_batch(entries))
     fields = ("force", "torque", "n_rays", "n_hits", "n_secondary", "n_secondary_hits", "n_box_tests",
-              "n_tri_tests", "status")
+              "n_tri_tests", "status", "n_clamped")
+    lo, hi = _dof_limits(mesh)
     for k in range(E):
-        sc.set_angles(angs[k])
+        n_clamped = sc.set_angles(angs[k])
+        assert n_clamped == int(((angs[k] < lo) | (angs[k] > hi)).sum()), (name, k)
         s = srp.eval(sc, suns[k], n, bounces=B, count=True)
+        assert s["n_clamped"] == n_clamped, (name, k)
         for f in fields:
             assert np.array_equal(np.asarray(out[k][f]), np.asarray(s[f])), (name, k, f, out[k][f], s[f])
     assert out[0]["n_hits"] > 0
+    assert out["n_clamped"].max() > 0
     # gradients (world hinge axes and transforms of the slot enter them); the
     # single evaluation always returns the photon-direction Jacobian too
     gentries = [(sc, angs[k], srp.params(suns[k], n, B, grad_dir=True)) for k in range(E)]
