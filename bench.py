@@ -70,13 +70,15 @@ def _log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def time_config(srp, torch, name, stream, steps):
+def time_config(srp, torch, name, stream, steps, oracle_sample=True):
     """Throughput of one of the other batch workloads: the box-wing at 128^2
     (c1, 1,024 attitudes), the 32,768-evaluation SPAD table at 512^2 (c3), the
     uneven 64-scene batch (c4), the 1M-triangle batch of 256 attitudes at
     2048^2 with the adjoint (c5).  Autotuned, one warm-up call, `steps` timed
     calls (a call runs as consecutive sub-batches when its workspace would
-    pass 16 GiB); ray and test counts from one counting call."""
+    pass 16 GiB); ray and test counts from one counting call.  With
+    oracle_sample, the oracle is timed on a seeded subsample of the items
+    (forward only) and their forces are compared with the batch's."""
     import synth
     grad = False
     if name == "c1":
@@ -87,23 +89,31 @@ def time_config(srp, torch, name, stream, steps):
         rng = np.random.default_rng(1001)
         angles = rng.uniform(-np.pi / 2, np.pi / 2, size=(E, mesh.n_dof))
         items = [(sc, angles[k], dirs[k], n) for k in range(E)]
+        meshes = [mesh] * E
+        sample = list(np.random.default_rng(11).choice(E, 64, replace=False))
         desc = f"box-wing ({mesh.n_tris} tris), {E} attitudes, {n}x{n} rays, B={B}"
     elif name == "c3":
         mesh, dirs, angles, n, B = synth.c3_spad()
         sc = srp.Scene(mesh)
         items = [(sc, angles[k], dirs[k], n) for k in range(len(dirs))]
+        meshes = [mesh] * len(items)
+        sample = list(np.random.default_rng(13).choice(len(items), 64, replace=False))
         desc = f"SPAD table: {mesh.n_tris}-triangle spacecraft, {len(dirs)} attitudes, {n}x{n} rays, B={B}"
     elif name == "c4":
         specs, B = synth.c4_uneven()
         scenes = [srp.Scene(m) for m, _, _, _ in specs]
         items = [(scenes[k], a, s_, n_) for k, (m, a, s_, n_) in enumerate(specs)]
         tris = [m.n_tris for m, _, _, _ in specs]
+        meshes = [m for m, _, _, _ in specs]
+        sample = [k for k in range(len(specs)) if specs[k][3] <= 512]   # every scene at N <= 512
         desc = (f"uneven batch: {len(specs)} scenes of {min(tris)}..{max(tris)} triangles, "
                 f"grids {min(x[3] for x in specs)}..{max(x[3] for x in specs)}, B={B}")
     elif name == "c5":
         mesh, dirs, angles, n, B = synth.c5_batch()
         sc = srp.Scene(mesh)
         items = [(sc, angles[k], dirs[k], n) for k in range(len(dirs))]
+        meshes = [mesh] * len(items)
+        sample = list(np.random.default_rng(15).choice(len(items), 4, replace=False))
         grad = True
         desc = (f"greebled spacecraft ({mesh.n_tris} tris, {mesh.n_dof} hinge DOF), {len(dirs)} attitudes, "
                 f"{n}x{n} rays, B={B}, forward + adjoint")
@@ -159,6 +169,42 @@ def time_config(srp, torch, name, stream, steps):
                lane_op_frac=round(work / kern / PEAK_LANE_OPS, 4),
                tests_per_ray=round((int(cnt["n_box_tests"].sum()) + int(cnt["n_tri_tests"].sum())) / rays, 2),
                schedule={"patches_per_chunk": tune[0], "blocks_per_cu": tune[1]})
+    if oracle_sample:
+        # the FP64 oracle (its own hierarchy) on a seeded subsample of the items, forward
+        # only, timed on the host's cores; then each item's parity by the tests' policy:
+        # its single recorded evaluation (bitwise the batch item) against the oracle's
+        # hits (raw), against oracle physics on the GPU's hits (visibility matched), and
+        # the primary rays whose hits differ outside the edge band
+        import oracle
+        sys.path.insert(0, os.path.join(ROOT, "tests"))
+        from parity import compare_eval
+        t0 = time.perf_counter()
+        o_rays, orcs = 0, []
+        for k in sample:
+            _, a, d, n_ = items[k]
+            o = oracle.eval_srp(meshes[k], d, n_, bounces=B, angles=a, record=True)
+            o_rays += o.n_rays + o.n_secondary
+            orcs.append(o)
+        dt_o = time.perf_counter() - t0
+        f_err, f_vm, outside, band = [], [], 0, []
+        for k, o in zip(sample, orcs):
+            sc_k, a, d, n_ = items[k]
+            sc_k.set_angles(a)
+            single = srp.eval(sc_k, d, n_, bounces=B, record=True)
+            assert np.array_equal(single["force"], res[k]["force"]), (name, k)
+            rep = compare_eval(meshes[k], a, d, n_, B, single, o)
+            f_err.append(rep["f_err"])
+            f_vm.append(rep["f_err_vis_matched"])
+            outside += rep["primary_outside_band"]
+            band.append(rep["edge_band_fraction"])
+        rec["oracle"] = {"evals_per_s": round(len(sample) / dt_o, 4), "grays_per_s": round(o_rays / dt_o / 1e9, 6),
+                         "cores": oracle.threads(), "sample": f"items {sorted(int(k) for k in sample)} of {E}, "
+                         f"forward only (FP64, oracle BVH)",
+                         "max_rel_force_err": max(f_err), "max_rel_force_err_vis_matched": max(f_vm),
+                         "primary_ids_differing_outside_edge_band": outside, "edge_band_fraction": max(band)}
+        _log(f"{name} oracle: {len(sample) / dt_o:.3f} evals/s on {oracle.threads()} threads ({len(sample)} items); "
+             f"max rel force err {max(f_err):.2e}, visibility matched {max(f_vm):.2e}, "
+             f"ids differing outside the edge band {outside}")
     return rec
 
 
@@ -631,7 +677,7 @@ def main():
         "cpu_baseline": cpu,
     }
     if args.configs:
-        line["configs"] = {c: time_config(srp, torch, c, stream, max(1, min(args.steps, 3)))
+        line["configs"] = {c: time_config(srp, torch, c, stream, max(1, min(args.steps, 3)), args.cpu_samples > 0)
                            for c in args.configs.split(",") if c}
     print(json.dumps(line), flush=True)
 
