@@ -111,7 +111,8 @@ static_assert(sizeof(FanRec) == 32, "FanRec is 32 bytes");
 
 // Diffuse rays per fan task: the fan kernel's lane task is one emitter times
 // one slice of FAN_SLICE consecutive fan-ray indices.
-constexpr int FAN_SLICE = 4;
+constexpr int FAN_SLICE = 2;   // (4 and 1 measured: 2 gives single evaluations at the paper's
+                                //  setting 3 % with batches unchanged; 1 costs batches 2 %)
 static_assert(SRP_MAX_BOUNCES == 4, "fan emitter masks: four generations");
 // Most work units per patch of the fan kernel.
 // Most range sums per evaluation in the reduction's first stage (separate
