@@ -719,7 +719,7 @@ int enqueue(const Layout &L, char *Dv, const char *H, size_t copy_bytes, const B
     }
     e = launch_trace(d_desc, d_cbase, (int)L.n, d_win, L.total_chunks, d_queue, d_spill, d_patches, d_counts, L.count,
                      L.grad, L.dir, L.grid, L.max_grad_n, L.fans_inline ? d_fan_out : nullptr,
-                     L.fans_inline ? d_fan_counts : nullptr, stream);
+                     L.fans_inline ? d_fan_counts : nullptr, L.sch.bpc, stream);
     if (e) return fail(SRP_ERR_DEVICE, std::string("trace kernel: ") + hipGetErrorString((hipError_t)e));
     if (L.total_units > 0) {
         const int64_t *d_ubase = reinterpret_cast<const int64_t *>(Dv + L.o_ubase);

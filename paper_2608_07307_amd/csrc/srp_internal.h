@@ -310,10 +310,13 @@ int launch_articulate(const ArtJob *d_jobs, int n_jobs, void *stream);
 // d_spill: grid_blocks * BLOCK * STACK_SPILL words; chunk counts below 2^31.
 // d_fan_out (forward, diffuse rays on): the trace kernel also traces every
 // patch's diffuse fans into their partial slots (no fan launch follows).
+// blocks_per_cu <= 2 (grid_blocks = that times the CU count) launches the
+// kernel compiled for 2 waves per SIMD.
 int launch_trace(const EvalDesc *d_desc, const int64_t *d_chunk_base, int n_evals,
                  const uint64_t *d_win, int64_t total_chunks, uint32_t *d_queue, uint32_t *d_spill,
                  PatchOut *d_patches, uint64_t *d_counts, bool count, bool grad, bool dir, int grid_blocks,
-                 int lds_grad_doubles, PatchOut *d_fan_out, uint64_t *d_fan_counts, void *stream);
+                 int lds_grad_doubles, PatchOut *d_fan_out, uint64_t *d_fan_counts, int blocks_per_cu,
+                 void *stream);
 // Diffuse fans of the recorded emitters: one work unit per patch and fan slice
 // (d_unit_base: first unit of every evaluation, then the total); uses the
 // second set of queue counters and the same spill area as the trace kernel.

@@ -84,13 +84,19 @@ SRP_HD inline void frame_setup(const float o[3], const float d[3], Frame &F) {
 }
 
 // Slab test of one box against [tmin, tmax] with its planes already ordered
-// per axis (near, far); returns the entry distance or T_INF.
-SRP_HD inline float box_enter(float nx, float ny, float nz, float fx, float fy, float fz,
-                              float ix, float iy, float iz, float oix, float oiy, float oiz,
-                              float tmin, float tmax) {
+// per axis (near, far): returns 1 when the ray enters the box, with t = the
+// entry distance (at most tmax, which never exceeds T_INF), else 0 with
+// t = +infinity, so that sorting puts every entered child before every other.
+// (A node visit counts its hit children from these flags, so the compiler
+// needs the full sort of the children only when a lane has two or more.)
+SRP_HD inline int box_enter(float nx, float ny, float nz, float fx, float fy, float fz,
+                            float ix, float iy, float iz, float oix, float oiy, float oiz,
+                            float tmin, float tmax, float &t) {
     float tn = fmaxf(fmaxf(fmaf(nx, ix, -oix), fmaf(ny, iy, -oiy)), fmaxf(fmaf(nz, iz, -oiz), tmin));
     float tf = fminf(fminf(fmaf(fx, ix, -oix), fmaf(fy, iy, -oiy)), fminf(fmaf(fz, iz, -oiz), tmax));
-    return tn <= tf ? tn : T_INF;
+    const bool in = tn <= tf;
+    t = in ? tn : INFINITY;
+    return in ? 1 : 0;
 }
 
 SRP_HD inline float xf_dot(const float m[3], float c, const float v[3]) {
@@ -278,15 +284,14 @@ SRP_HD inline bool trace_closest(const TraceCtx &C, const float o[3], const floa
                 const float4 FX = q[F.nx ^ 3], FY = q[F.ny ^ 5], FZ = q[F.nz ^ 7];
                 const uint4 NR = ((const uint4 SRP_GLOBAL *)q)[6];
                 const float ix = F.ix, iy = F.iy, iz = F.iz, oix = F.oix, oiy = F.oiy, oiz = F.oiz;
-                float t[4] = {
-                    box_enter(NX.x, NY.x, NZ.x, FX.x, FY.x, FZ.x, ix, iy, iz, oix, oiy, oiz, tmin, h.t),
-                    box_enter(NX.y, NY.y, NZ.y, FX.y, FY.y, FZ.y, ix, iy, iz, oix, oiy, oiz, tmin, h.t),
-                    box_enter(NX.z, NY.z, NZ.z, FX.z, FY.z, FZ.z, ix, iy, iz, oix, oiy, oiz, tmin, h.t),
-                    box_enter(NX.w, NY.w, NZ.w, FX.w, FY.w, FZ.w, ix, iy, iz, oix, oiy, oiz, tmin, h.t)};
+                float t[4];
+                const int hits = box_enter(NX.x, NY.x, NZ.x, FX.x, FY.x, FZ.x, ix, iy, iz, oix, oiy, oiz, tmin, h.t, t[0]) +
+                                 box_enter(NX.y, NY.y, NZ.y, FX.y, FY.y, FZ.y, ix, iy, iz, oix, oiy, oiz, tmin, h.t, t[1]) +
+                                 box_enter(NX.z, NY.z, NZ.z, FX.z, FY.z, FZ.z, ix, iy, iz, oix, oiy, oiz, tmin, h.t, t[2]) +
+                                 box_enter(NX.w, NY.w, NZ.w, FX.w, FY.w, FZ.w, ix, iy, iz, oix, oiy, oiz, tmin, h.t, t[3]);
                 uint32_t r[4] = {NR.x, NR.y, NR.z, NR.w};
                 if (COUNT) nbox += (r[0] != REF_NONE) + (r[1] != REF_NONE) + (r[2] != REF_NONE) + (r[3] != REF_NONE);
-                sort4(t, r);
-                const int hits = (t[0] != T_INF) + (t[1] != T_INF) + (t[2] != T_INF) + (t[3] != T_INF);
+                sort4(t, r);   // the hit children first, nearest first
                 if (hits > 1) {
                     // push the other hit children far to near: afterwards the ring holds
                     // ..., old top (entry sp - 1), r[np], ..., r[2] and r[1] is the top
