@@ -310,6 +310,10 @@ struct Layout {
     std::vector<int> item_ppc;   // patches per chunk of each item (the adjoint: its gradient group)
     int grid = 1, fan_grid = 0, fan_claim = 1, fan_parts = 0, wb = 1;
     bool fans_inline = false;   // the trace kernel traces the fans itself (no fan launch)
+    // captured forward plans of one patch per chunk: the patch order of the next
+    // launch and the per-patch costs it is made from (layout_add_order)
+    bool ordered = false;
+    size_t o_order = 0, o_cost = 0;
 };
 
 // Gradient partial slots per chunk: 9 per node (rotation sensitivities), 6
@@ -585,6 +589,22 @@ int layout_build(const srp_batch_item *items, int64_t n, bool grad, Schedule for
     return SRP_OK;
 }
 
+// Gives a captured forward launch of one patch per chunk its patch order and
+// cost arrays (one 32-bit word per patch each, after the rest of the device
+// workspace): each launch traces the patches heaviest first by the costs the
+// previous launch measured, which shortens the launch's tail when consecutive
+// launches see similar images (a propagation's stages; replays of one batch).
+// The results do not depend on the order.
+void layout_add_order(Layout &L) {
+    if (L.grad || L.total_patches <= 0) return;
+    for (int64_t k = 0; k < L.n; ++k)
+        if (L.item_ppc[k] != 1) return;
+    L.ordered = true;
+    L.o_order = align_up(L.dev_bytes);
+    L.o_cost = align_up(L.o_order + sizeof(uint32_t) * (size_t)L.total_patches);
+    L.dev_bytes = align_up(L.o_cost + sizeof(uint32_t) * (size_t)L.total_patches);
+}
+
 // Writes the per-launch staging image for device buffer Dv.
 void staging_fill(const Layout &L, const srp_batch_item *items, const BatchOut &bo, char *H, char *Dv) {
     const int64_t n = L.n;
@@ -684,6 +704,8 @@ void staging_fill(const Layout &L, const srp_batch_item *items, const BatchOut &
         D.grad_out = (L.grad && bo.d_grad) ? bo.d_grad + k * bo.grad_stride : nullptr;
         D.hit_ids = (n == 1) ? bo.d_hit_ids : nullptr;
         D.hit_t = (n == 1) ? bo.d_hit_t : nullptr;
+        D.order = L.ordered ? reinterpret_cast<uint32_t *>(Dv + L.o_order) + D.patch_base : nullptr;
+        D.cost = L.ordered ? reinterpret_cast<uint32_t *>(Dv + L.o_cost) + D.patch_base : nullptr;
     }
 }
 
@@ -840,10 +862,26 @@ int plan_make(const srp_batch_item *items, int64_t n, bool grad, const BatchOut 
     if (!P) return fail(SRP_ERR_OOM, "host allocation failed");
     P->bo = bo;
     if ((rc = layout_build(items, n, grad, Schedule(), &P->L))) { plan_free(P); return rc; }
+    layout_add_order(P->L);
     if (hipMalloc(&P->d_buf, std::max<size_t>(P->L.dev_bytes, 256)) != hipSuccess) {
         (void)hipGetLastError();
         plan_free(P);
         return fail(SRP_ERR_OOM, "plan device allocation failed");
+    }
+    if (P->L.ordered) {
+        // the first launch traces every evaluation's patches in image order
+        std::vector<uint32_t> ident((size_t)P->L.total_patches);
+        for (int64_t k = 0; k < n; ++k)
+            for (int64_t q = P->L.patch_base[k]; q < P->L.patch_base[k + 1]; ++q)
+                ident[(size_t)q] = (uint32_t)(q - P->L.patch_base[k]);
+        hipError_t e1 = hipMemcpy(P->d_buf + P->L.o_order, ident.data(), sizeof(uint32_t) * ident.size(),
+                                  hipMemcpyHostToDevice);
+        hipError_t e2 = hipMemset(P->d_buf + P->L.o_cost, 0, sizeof(uint32_t) * ident.size());
+        if (e1 != hipSuccess || e2 != hipSuccess) {
+            plan_free(P);
+            return fail(SRP_ERR_DEVICE, std::string("plan order setup: ") +
+                                            hipGetErrorString(e1 != hipSuccess ? e1 : e2));
+        }
     }
     if (hipHostMalloc(&P->h_stage, std::max<size_t>(P->L.stage_bytes, 256), hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
@@ -882,6 +920,7 @@ int plan_refill(PlanImpl *P, const srp_batch_item *items, int64_t n, bool *compa
     if (rc) return rc;
     Layout L2;
     if ((rc = layout_build(items, n, P->L.grad, P->L.sch, &L2))) return rc;
+    if (P->L.ordered) layout_add_order(L2);
     const Layout &L = P->L;
     if (L2.n != L.n || L2.stage_bytes != L.stage_bytes || L2.dev_bytes > L.dev_bytes || L2.grid != L.grid ||
         L2.wb != L.wb || L2.count != L.count || L2.dir != L.dir || L2.max_grad_n != L.max_grad_n ||
@@ -892,7 +931,8 @@ int plan_refill(PlanImpl *P, const srp_batch_item *items, int64_t n, bool *compa
         L2.emit_off != L.emit_off ||
         L2.o_emask != L.o_emask || L2.o_fanout != L.o_fanout || L2.o_fancnt != L.o_fancnt ||
         L2.o_queue != L.o_queue || L2.o_spill != L.o_spill || L2.slots.size() != L.slots.size() ||
-        L2.o_jobs != L.o_jobs || L2.o_cs != L.o_cs || L2.o_slots != L.o_slots)
+        L2.o_jobs != L.o_jobs || L2.o_cs != L.o_cs || L2.o_slots != L.o_slots || L2.ordered != L.ordered ||
+        L2.o_order != L.o_order || L2.o_cost != L.o_cost)
         return SRP_OK;
     for (size_t q = 0; q < L.slots.size(); ++q)
         if (L2.slots[q].off != L.slots[q].off || L2.slots[q].sc != L.slots[q].sc) return SRP_OK;

@@ -471,7 +471,14 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE ? WPE
         const int64_t kc = c - D.chunk_base;
         const int N = D.n;
 
-        const int64_t p0 = kc * D.ppc, p1 = min(p0 + D.ppc, D.n_patches);
+        int64_t p0 = kc * D.ppc, p1 = min(p0 + D.ppc, D.n_patches);
+        if (!GRAD && D.order) {
+            // a captured forward plan of one patch per chunk hands out its patches
+            // heaviest first, in the order its previous launch measured; any order
+            // gives the same result, since every patch writes its own partial slot
+            p0 = ((const uint32_t SRP_GLOBAL *)D.order)[kc];
+            p1 = p0 < D.n_patches ? p0 + 1 : p0;
+        }
         const int B = D.bounces;
         const int KD = GRAD ? 0 : D.n_diffuse;          // diffuse rays per emitting hit
         const int R = B + 1 + B * KD;                   // recorded rays per pixel
@@ -492,6 +499,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE ? WPE
             const int tile = (int)(pt >> 2), q = (int)(pt & 3);
             const int px = (tile % D.tiles_x) * TILE + (q & 1) * PATCH + (lane & 7);
             const int py = (tile / D.tiles_x) * TILE + (q >> 1) * PATCH + (lane >> 3);
+            const uint64_t clock0 = (!GRAD && D.cost) ? wall_clock64() : 0;
             for (int k = 0; k < 6; ++k) lacc[k * BLOCK] = 0.0;
             // hit counts packed in 10-bit fields (primary hits, specular secondary rays and
             // their hits; a patch sums at most 64 * SRP_MAX_BOUNCES of each), the status
@@ -723,6 +731,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE ? WPE
                 fan_passes<COUNT>(D, TC, pt, em[0], em[1], em[2], em[3], 0, 1, tmin2, stack, lacc, lane, fan_out,
                                   fan_counts);
             }
+            if (!GRAD && D.cost && lane == 0) {
+                const uint64_t dt = wall_clock64() - clock0;
+                ((uint32_t SRP_GLOBAL *)D.cost)[pt] = dt < 0xFFFFFFFFull ? (uint32_t)dt : 0xFFFFFFFFu;
+            }
         }
         if (GRAD) {
             wave_lds_fence();
@@ -938,9 +950,40 @@ __global__ __launch_bounds__(RBLOCK) void k_slices(const EvalDesc *__restrict__ 
     }
 }
 
+// Heaviest-first patch order for the next launch of a captured forward plan
+// (run by the reduction's block of the evaluation, all RBLOCK threads): the
+// patches grouped by the bit length of their measured cost (trace time on
+// the constant-rate clock, so groups differ by factors of two), groups in
+// decreasing cost.  Positions inside a group come from LDS atomics and may
+// differ between launches; that changes which wave traces a patch and when,
+// never the result.  Every count is exact, so the positions form a
+// permutation of the evaluation's patches.
+__device__ void patch_order(const EvalDesc &D, int tid) {
+    uint32_t SRP_GLOBAL *ord = (uint32_t SRP_GLOBAL *)D.order;
+    const uint32_t SRP_GLOBAL *cost = (const uint32_t SRP_GLOBAL *)D.cost;
+    const int64_t n = D.n_patches;
+    constexpr int NG = 33;   // bit lengths 0..32
+    __shared__ uint32_t cnt[NG];
+    if (tid < NG) cnt[tid] = 0;
+    __syncthreads();
+    for (int64_t i = tid; i < n; i += RBLOCK) atomicAdd(&cnt[32 - __clz(cost[i])], 1u);
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t run = 0;
+        for (int g = NG - 1; g >= 0; --g) {
+            const uint32_t c = cnt[g];
+            cnt[g] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+    for (int64_t i = tid; i < n; i += RBLOCK) ord[atomicAdd(&cnt[32 - __clz(cost[i])], 1u)] = (uint32_t)i;
+}
+
 // Reduction, second stage (one block per evaluation): the first stage's
 // range sums added in order, scaled to newtons; with GRAD the gradient range
-// sums likewise, then assembled per material and hinge DOF.
+// sums likewise, then assembled per material and hinge DOF.  A captured
+// forward plan's block also orders the patches for the plan's next launch.
 template <bool COUNT, bool GRAD>
 __global__ __launch_bounds__(RBLOCK) void k_reduce(const EvalDesc *__restrict__ descs,
                                                 const uint64_t *__restrict__ win, srp_result *out) {
@@ -978,6 +1021,7 @@ __global__ __launch_bounds__(RBLOCK) void k_reduce(const EvalDesc *__restrict__ 
         r.n_clamped = (uint32_t)D.n_clamped;
         out[e] = r;
     }
+    if (!GRAD && D.order && D.cost) patch_order(D, tid);   // (the same for the whole block)
     if (GRAD) {
         const int G = D.grad_n, K = D.n_nodes, M = D.n_mats, J = D.n_dof;
         __shared__ double sg[MAX_GRAD_SLOTS];

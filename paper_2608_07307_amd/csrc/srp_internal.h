@@ -215,11 +215,17 @@ struct alignas(64) EvalDesc {
     int64_t slice_base;     // the batch's number of this evaluation's first range sum
     int32_t n_clamped;      // hinge angles of this evaluation clamped to their intervals
     int32_t pad_;
+    // captured forward launches of one patch per chunk (else null): chunk c
+    // traces patch order[c] (a permutation of the evaluation's patches),
+    // cost[p] receives patch p's trace time (constant-rate clock ticks), and
+    // the reduction rewrites order from cost for the next launch
+    uint32_t *order;
+    uint32_t *cost;
 };
 
 // The host writes these records and the kernels read them: both compilation
 // passes (host and gfx950) must agree on every offset.
-static_assert(sizeof(EvalDesc) == 384, "EvalDesc layout");
+static_assert(sizeof(EvalDesc) == 448, "EvalDesc layout");
 static_assert(offsetof(EvalDesc, tris) == 0, "EvalDesc layout");
 static_assert(offsetof(EvalDesc, blas) == 8, "EvalDesc layout");
 static_assert(offsetof(EvalDesc, mats) == 16, "EvalDesc layout");
@@ -267,6 +273,8 @@ static_assert(offsetof(EvalDesc, gslice) == 352, "EvalDesc layout");
 static_assert(offsetof(EvalDesc, pslice) == 360, "EvalDesc layout");
 static_assert(offsetof(EvalDesc, slice_base) == 368, "EvalDesc layout");
 static_assert(offsetof(EvalDesc, n_clamped) == 376, "EvalDesc layout");
+static_assert(offsetof(EvalDesc, order) == 384, "EvalDesc layout");
+static_assert(offsetof(EvalDesc, cost) == 392, "EvalDesc layout");
 static_assert(sizeof(PatchOut) == 64, "PatchOut layout");
 static_assert(offsetof(PatchOut, f) == 0, "PatchOut layout");
 static_assert(offsetof(PatchOut, hits) == 48, "PatchOut layout");
