@@ -75,6 +75,85 @@ __device__ inline void inst_box(const ArtNode &nd, const double *X, double pad, 
     }
 }
 
+// Node k's world transform X (rotation row-major, then translation) from its
+// parent's in sX, with its axes' cosines and sines cs; writes the world hinge
+// axes, the DOF-to-node map, X (LDS and the slot) and the instance.
+__device__ inline void compose(const ArtJob &J, int k, const ArtNode &nd, const double *cs, double *sX) {
+    double X[12];
+    if (k == 0) {
+        for (int c = 0; c < 12; ++c) X[c] = (c == 0 || c == 4 || c == 8) ? 1.0 : 0.0;
+    } else {
+        double Pm[12];
+        for (int c = 0; c < 12; ++c) Pm[c] = sX[12 * nd.parent + c];
+        double prefix[9], Rl[9];
+        for (int c = 0; c < 9; ++c) {
+            prefix[c] = Pm[c];   // R_parent * R(a_0) ... R(a_{i-1})
+            Rl[c] = (c == 0 || c == 4 || c == 8) ? 1.0 : 0.0;
+        }
+        #pragma unroll
+        for (int a = 0; a < 3; ++a) {   // (unrolled: the node stays in registers)
+            if (a >= nd.n_axes) break;
+            const int q = nd.dof_offset + a;
+            double w[3];
+            mat3_vec(prefix, nd.axis[a], w);
+            for (int c = 0; c < 3; ++c) J.axw[3 * q + c] = w[c];
+            J.dof_node[q] = k;
+            double Ra[9];
+            rot_unit(nd.unit[a], cs[2 * a], cs[2 * a + 1], Ra);
+            mat3_mul(Rl, Ra, Rl);
+            mat3_mul(prefix, Ra, prefix);
+        }
+        // local: x -> Rl (x - p) + p ; world: R_par * local + t_par
+        double Rp[3], tl[3], tw[3];
+        mat3_vec(Rl, nd.pivot, Rp);
+        for (int c = 0; c < 3; ++c) tl[c] = nd.pivot[c] - Rp[c];
+        mat3_vec(Pm, tl, tw);
+        mat3_mul(Pm, Rl, X);
+        for (int c = 0; c < 3; ++c) X[9 + c] = tw[c] + Pm[9 + c];
+    }
+    for (int c = 0; c < 12; ++c) {
+        sX[12 * k + c] = X[c];
+        J.xf[12 * k + c] = X[c];
+    }
+    Inst I;
+    for (int c = 0; c < 9; ++c) I.R[c] = (float)X[c];
+    for (int c = 0; c < 3; ++c) I.t[c] = (float)X[9 + c];
+    I.root = nd.blas_root;
+    I.node = k;
+    I.pad[0] = I.pad[1] = 0.0f;
+    J.inst[k] = I;
+}
+
+// Top-level node tp refitted from the instance boxes sB and the already
+// refitted nodes sT: an instance leaf takes its world box, an inner child
+// the union of its node's non-empty boxes.
+__device__ inline void refit(BNode4 nd, int i, const ArtJob &J, const float *sB, BNode4 *sT) {
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t r = nd.ref[k];
+        if (r == REF_NONE) continue;
+        float lo[3], hi[3];
+        if (ref_type(r) == REF_TLAS_LEAF) {
+            const uint32_t q = ref_index(r);
+            for (int a = 0; a < 3; ++a) { lo[a] = sB[6 * q + a]; hi[a] = sB[6 * q + 3 + a]; }
+        } else {
+            const BNode4 &c = sT[ref_index(r)];
+            for (int a = 0; a < 3; ++a) { lo[a] = INFINITY; hi[a] = -INFINITY; }
+            for (int m = 0; m < 4; ++m) {
+                if (c.ref[m] == REF_NONE) continue;
+                lo[0] = lmin(lo[0], c.lox[m]); hi[0] = lmax(hi[0], c.hix[m]);
+                lo[1] = lmin(lo[1], c.loy[m]); hi[1] = lmax(hi[1], c.hiy[m]);
+                lo[2] = lmin(lo[2], c.loz[m]); hi[2] = lmax(hi[2], c.hiz[m]);
+            }
+        }
+        nd.lox[k] = lo[0]; nd.loy[k] = lo[1]; nd.loz[k] = lo[2];
+        nd.hix[k] = hi[0]; nd.hiy[k] = hi[1]; nd.hiz[k] = hi[2];
+    }
+    sT[i] = nd;
+    J.tlas[i] = nd;
+}
+
+static_assert(SRP_MAX_NODES <= 2 * ART_BLOCK, "at most two tree nodes and two top-level nodes per lane");
+
 __global__ __launch_bounds__(ART_BLOCK) void k_articulate(const ArtJob *__restrict__ jobs, int n_jobs) {
     __shared__ double sX[SRP_MAX_NODES * 12];   // node transforms
     __shared__ float sB[SRP_MAX_NODES * 6];     // instance boxes (lo, hi)
@@ -82,90 +161,50 @@ __global__ __launch_bounds__(ART_BLOCK) void k_articulate(const ArtJob *__restri
     if ((int)blockIdx.x >= n_jobs) return;
     const ArtJob J = jobs[blockIdx.x];
     const int lane = threadIdx.x;
+    // Each lane's tree nodes (lane and lane + ART_BLOCK), their axes' cosines
+    // and sines, and its top-level nodes, read once: the level loops below then
+    // wait on LDS only, not on a memory round trip per level.
+    ArtNode nd[2];
+    double cs[2][6];
+    BNode4 tp[2];
+    #pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const int k = lane + s * ART_BLOCK;
+        if (k < J.n_nodes) nd[s] = J.nodes[k];
+        if (k < J.n_tlas) tp[s] = J.topo[k];
+    }
+    #pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const int k = lane + s * ART_BLOCK;
+        #pragma unroll
+        for (int a = 0; a < 3; ++a)
+            if (k < J.n_nodes && a < nd[s].n_axes) {
+                cs[s][2 * a] = J.cs[2 * (nd[s].dof_offset + a)];
+                cs[s][2 * a + 1] = J.cs[2 * (nd[s].dof_offset + a) + 1];
+            }
+    }
     // node transforms, one tree level after the other
     for (int L = 0; L <= J.max_depth; ++L) {
-        for (int k = lane; k < J.n_nodes; k += ART_BLOCK) {
-            const ArtNode &nd = J.nodes[k];
-            if (nd.depth != L) continue;
-            double X[12];
-            if (k == 0) {
-                for (int c = 0; c < 12; ++c) X[c] = (c == 0 || c == 4 || c == 8) ? 1.0 : 0.0;
-            } else {
-                double Pm[12];
-                for (int c = 0; c < 12; ++c) Pm[c] = sX[12 * nd.parent + c];
-                double prefix[9], Rl[9];
-                for (int c = 0; c < 9; ++c) {
-                    prefix[c] = Pm[c];   // R_parent * R(a_0) ... R(a_{i-1})
-                    Rl[c] = (c == 0 || c == 4 || c == 8) ? 1.0 : 0.0;
-                }
-                for (int a = 0; a < nd.n_axes; ++a) {
-                    const int q = nd.dof_offset + a;
-                    double w[3];
-                    mat3_vec(prefix, nd.axis[a], w);
-                    for (int c = 0; c < 3; ++c) J.axw[3 * q + c] = w[c];
-                    J.dof_node[q] = k;
-                    double Ra[9];
-                    rot_unit(nd.unit[a], J.cs[2 * q], J.cs[2 * q + 1], Ra);
-                    mat3_mul(Rl, Ra, Rl);
-                    mat3_mul(prefix, Ra, prefix);
-                }
-                // local: x -> Rl (x - p) + p ; world: R_par * local + t_par
-                double Rp[3], tl[3], tw[3];
-                mat3_vec(Rl, nd.pivot, Rp);
-                for (int c = 0; c < 3; ++c) tl[c] = nd.pivot[c] - Rp[c];
-                mat3_vec(Pm, tl, tw);
-                mat3_mul(Pm, Rl, X);
-                for (int c = 0; c < 3; ++c) X[9 + c] = tw[c] + Pm[9 + c];
-            }
-            for (int c = 0; c < 12; ++c) {
-                sX[12 * k + c] = X[c];
-                J.xf[12 * k + c] = X[c];
-            }
-            Inst I;
-            for (int c = 0; c < 9; ++c) I.R[c] = (float)X[c];
-            for (int c = 0; c < 3; ++c) I.t[c] = (float)X[9 + c];
-            I.root = nd.blas_root;
-            I.node = k;
-            I.pad[0] = I.pad[1] = 0.0f;
-            J.inst[k] = I;
+        #pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const int k = lane + s * ART_BLOCK;
+            if (k < J.n_nodes && nd[s].depth == L) compose(J, k, nd[s], cs[s], sX);
         }
         __syncthreads();
     }
     // the instances' world boxes
-    for (int k = lane; k < J.n_nodes; k += ART_BLOCK) {
-        const ArtNode &nd = J.nodes[k];
-        if (nd.blas_root == REF_NONE) continue;
-        inst_box(nd, sX + 12 * k, J.pad, sB + 6 * k, sB + 6 * k + 3);
+    #pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const int k = lane + s * ART_BLOCK;
+        if (k < J.n_nodes && nd[s].blas_root != REF_NONE) inst_box(nd[s], sX + 12 * k, J.pad, sB + 6 * k, sB + 6 * k + 3);
     }
     __syncthreads();
-    // refit, one height after the other: an instance leaf takes its world box,
-    // an inner child the union of its node's non-empty boxes
+    // refit, one height after the other
     for (int hgt = 0; hgt <= J.max_height; ++hgt) {
-        for (int i = lane; i < J.n_tlas; i += ART_BLOCK) {
-            BNode4 nd = J.topo[i];
-            if ((int)nd.pad[0] != hgt) continue;
-            for (int k = 0; k < 4; ++k) {
-                const uint32_t r = nd.ref[k];
-                if (r == REF_NONE) continue;
-                float lo[3], hi[3];
-                if (ref_type(r) == REF_TLAS_LEAF) {
-                    const uint32_t q = ref_index(r);
-                    for (int a = 0; a < 3; ++a) { lo[a] = sB[6 * q + a]; hi[a] = sB[6 * q + 3 + a]; }
-                } else {
-                    const BNode4 &c = sT[ref_index(r)];
-                    for (int a = 0; a < 3; ++a) { lo[a] = INFINITY; hi[a] = -INFINITY; }
-                    for (int m = 0; m < 4; ++m) {
-                        if (c.ref[m] == REF_NONE) continue;
-                        lo[0] = lmin(lo[0], c.lox[m]); hi[0] = lmax(hi[0], c.hix[m]);
-                        lo[1] = lmin(lo[1], c.loy[m]); hi[1] = lmax(hi[1], c.hiy[m]);
-                        lo[2] = lmin(lo[2], c.loz[m]); hi[2] = lmax(hi[2], c.hiz[m]);
-                    }
-                }
-                nd.lox[k] = lo[0]; nd.loy[k] = lo[1]; nd.loz[k] = lo[2];
-                nd.hix[k] = hi[0]; nd.hiy[k] = hi[1]; nd.hiz[k] = hi[2];
-            }
-            sT[i] = nd;
-            J.tlas[i] = nd;
+        #pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const int i = lane + s * ART_BLOCK;
+            if (i < J.n_tlas && (int)tp[s].pad[0] == hgt) refit(tp[s], i, J, sB, sT);
         }
         __syncthreads();
     }

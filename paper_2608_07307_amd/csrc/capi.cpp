@@ -704,8 +704,6 @@ void staging_fill(const Layout &L, const srp_batch_item *items, const BatchOut &
         D.grad_out = (L.grad && bo.d_grad) ? bo.d_grad + k * bo.grad_stride : nullptr;
         D.hit_ids = (n == 1) ? bo.d_hit_ids : nullptr;
         D.hit_t = (n == 1) ? bo.d_hit_t : nullptr;
-        D.order = L.ordered ? reinterpret_cast<uint32_t *>(Dv + L.o_order) + D.patch_base : nullptr;
-        D.cost = L.ordered ? reinterpret_cast<uint32_t *>(Dv + L.o_cost) + D.patch_base : nullptr;
     }
 }
 
@@ -725,6 +723,8 @@ int enqueue(const Layout &L, char *Dv, const char *H, size_t copy_bytes, const B
     uint64_t *d_counts = L.count ? reinterpret_cast<uint64_t *>(Dv + L.o_counts) : nullptr;
     uint32_t *d_queue = reinterpret_cast<uint32_t *>(Dv + L.o_queue);
     uint32_t *d_spill = reinterpret_cast<uint32_t *>(Dv + L.o_spill);
+    uint32_t *d_order = L.ordered ? reinterpret_cast<uint32_t *>(Dv + L.o_order) : nullptr;
+    uint32_t *d_cost = L.ordered ? reinterpret_cast<uint32_t *>(Dv + L.o_cost) : nullptr;
     int e = launch_window(d_desc, (int)L.n, L.wb, d_win, d_queue, stream);
     if (e) return fail(SRP_ERR_DEVICE, std::string("window kernel: ") + hipGetErrorString((hipError_t)e));
     std::pair<hipEvent_t, hipEvent_t> ev{};
@@ -741,7 +741,7 @@ int enqueue(const Layout &L, char *Dv, const char *H, size_t copy_bytes, const B
     }
     e = launch_trace(d_desc, d_cbase, (int)L.n, d_win, L.total_chunks, d_queue, d_spill, d_patches, d_counts, L.count,
                      L.grad, L.dir, L.grid, L.max_grad_n, L.fans_inline ? d_fan_out : nullptr,
-                     L.fans_inline ? d_fan_counts : nullptr, L.sch.bpc, stream);
+                     L.fans_inline ? d_fan_counts : nullptr, L.sch.bpc, d_order, d_cost, stream);
     if (e) return fail(SRP_ERR_DEVICE, std::string("trace kernel: ") + hipGetErrorString((hipError_t)e));
     if (L.total_units > 0) {
         const int64_t *d_ubase = reinterpret_cast<const int64_t *>(Dv + L.o_ubase);
@@ -754,7 +754,8 @@ int enqueue(const Layout &L, char *Dv, const char *H, size_t copy_bytes, const B
         g_prof.pairs.push_back(ev);
     }
     e = launch_reduce(d_desc, (int)L.n, d_win, d_patches, d_counts, d_fan_out, d_fan_counts, L.count, L.grad,
-                      reinterpret_cast<const uint32_t *>(Dv + L.o_seval), L.slice_base[L.n], bo.d_out, stream);
+                      reinterpret_cast<const uint32_t *>(Dv + L.o_seval), L.slice_base[L.n], bo.d_out, d_order, d_cost,
+                      stream);
     if (e) return fail(SRP_ERR_DEVICE, std::string("reduce kernel: ") + hipGetErrorString((hipError_t)e));
     if (bo.h_copy) HIPCHK(hipMemcpyAsync(bo.h_copy, bo.d_out, sizeof(srp_result) * L.n, hipMemcpyDeviceToHost, stream));
     return SRP_OK;

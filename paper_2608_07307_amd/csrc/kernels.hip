@@ -397,7 +397,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE ? WPE
     const EvalDesc *__restrict__ descs, const int64_t *__restrict__ chunk_base, int n_evals,
     const uint64_t *__restrict__ win, int grid_blocks, int64_t total_chunks, uint32_t *queue, uint32_t *spill,
     PatchOut *__restrict__ patches, uint64_t *__restrict__ counts, int lds_grad_doubles, int fans_inline,
-    PatchOut *__restrict__ fan_out, uint64_t *__restrict__ fan_counts) {
+    PatchOut *__restrict__ fan_out, uint64_t *__restrict__ fan_counts, const uint32_t *__restrict__ order,
+    uint32_t *__restrict__ cost) {
     extern __shared__ char smem[];
     const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid >> 6;
     LaneStack stack;
@@ -472,11 +473,11 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE ? WPE
         const int N = D.n;
 
         int64_t p0 = kc * D.ppc, p1 = min(p0 + D.ppc, D.n_patches);
-        if (!GRAD && D.order) {
+        if (!GRAD && order) {
             // a captured forward plan of one patch per chunk hands out its patches
             // heaviest first, in the order its previous launch measured; any order
             // gives the same result, since every patch writes its own partial slot
-            p0 = ((const uint32_t SRP_GLOBAL *)D.order)[kc];
+            p0 = ((const uint32_t SRP_GLOBAL *)order)[D.patch_base + kc];
             p1 = p0 < D.n_patches ? p0 + 1 : p0;
         }
         const int B = D.bounces;
@@ -499,7 +500,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE ? WPE
             const int tile = (int)(pt >> 2), q = (int)(pt & 3);
             const int px = (tile % D.tiles_x) * TILE + (q & 1) * PATCH + (lane & 7);
             const int py = (tile / D.tiles_x) * TILE + (q >> 1) * PATCH + (lane >> 3);
-            const uint64_t clock0 = (!GRAD && D.cost) ? wall_clock64() : 0;
+            const uint64_t clock0 = (!GRAD && cost) ? wall_clock64() : 0;
             for (int k = 0; k < 6; ++k) lacc[k * BLOCK] = 0.0;
             // hit counts packed in 10-bit fields (primary hits, specular secondary rays and
             // their hits; a patch sums at most 64 * SRP_MAX_BOUNCES of each), the status
@@ -731,9 +732,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE ? WPE
                 fan_passes<COUNT>(D, TC, pt, em[0], em[1], em[2], em[3], 0, 1, tmin2, stack, lacc, lane, fan_out,
                                   fan_counts);
             }
-            if (!GRAD && D.cost && lane == 0) {
+            if (!GRAD && cost && lane == 0) {
                 const uint64_t dt = wall_clock64() - clock0;
-                ((uint32_t SRP_GLOBAL *)D.cost)[pt] = dt < 0xFFFFFFFFull ? (uint32_t)dt : 0xFFFFFFFFu;
+                ((uint32_t SRP_GLOBAL *)cost)[D.patch_base + pt] = dt < 0xFFFFFFFFull ? (uint32_t)dt : 0xFFFFFFFFu;
             }
         }
         if (GRAD) {
@@ -958,9 +959,9 @@ __global__ __launch_bounds__(RBLOCK) void k_slices(const EvalDesc *__restrict__ 
 // differ between launches; that changes which wave traces a patch and when,
 // never the result.  Every count is exact, so the positions form a
 // permutation of the evaluation's patches.
-__device__ void patch_order(const EvalDesc &D, int tid) {
-    uint32_t SRP_GLOBAL *ord = (uint32_t SRP_GLOBAL *)D.order;
-    const uint32_t SRP_GLOBAL *cost = (const uint32_t SRP_GLOBAL *)D.cost;
+__device__ void patch_order(const EvalDesc &D, uint32_t *order_all, const uint32_t *cost_all, int tid) {
+    uint32_t SRP_GLOBAL *ord = (uint32_t SRP_GLOBAL *)order_all + D.patch_base;
+    const uint32_t SRP_GLOBAL *cost = (const uint32_t SRP_GLOBAL *)cost_all + D.patch_base;
     const int64_t n = D.n_patches;
     constexpr int NG = 33;   // bit lengths 0..32
     __shared__ uint32_t cnt[NG];
@@ -986,7 +987,8 @@ __device__ void patch_order(const EvalDesc &D, int tid) {
 // forward plan's block also orders the patches for the plan's next launch.
 template <bool COUNT, bool GRAD>
 __global__ __launch_bounds__(RBLOCK) void k_reduce(const EvalDesc *__restrict__ descs,
-                                                const uint64_t *__restrict__ win, srp_result *out) {
+                                                const uint64_t *__restrict__ win, srp_result *out,
+                                                uint32_t *order, const uint32_t *cost) {
     const int e = blockIdx.x, tid = threadIdx.x;
     const EvalDesc &D = descs[e];
     const int Q = D.n_slices;
@@ -1021,7 +1023,7 @@ __global__ __launch_bounds__(RBLOCK) void k_reduce(const EvalDesc *__restrict__ 
         r.n_clamped = (uint32_t)D.n_clamped;
         out[e] = r;
     }
-    if (!GRAD && D.order && D.cost) patch_order(D, tid);   // (the same for the whole block)
+    if (!GRAD && order && cost) patch_order(D, order, cost, tid);   // (the same for the whole block)
     if (GRAD) {
         const int G = D.grad_n, K = D.n_nodes, M = D.n_mats, J = D.n_dof;
         __shared__ double sg[MAX_GRAD_SLOTS];
@@ -1108,7 +1110,8 @@ size_t trace_lds_bytes(bool grad, int lds_grad_doubles) {
 int launch_trace(const EvalDesc *d_desc, const int64_t *d_chunk_base, int n_evals, const uint64_t *d_win,
                  int64_t total_chunks, uint32_t *d_queue, uint32_t *d_spill, PatchOut *d_chunks,
                  uint64_t *d_counts, bool count, bool grad, bool dir, int grid_blocks, int lds_grad_doubles,
-                 PatchOut *d_fan_out, uint64_t *d_fan_counts, int blocks_per_cu, void *stream) {
+                 PatchOut *d_fan_out, uint64_t *d_fan_counts, int blocks_per_cu, const uint32_t *d_order,
+                 uint32_t *d_cost, void *stream) {
     if (total_chunks <= 0) return 0;
     const size_t lds = trace_lds_bytes(grad, lds_grad_doubles);
     const int lgd = grad ? lds_grad_doubles : 0;
@@ -1117,7 +1120,7 @@ int launch_trace(const EvalDesc *d_desc, const int64_t *d_chunk_base, int n_eval
 #define SRP_LAUNCH_TRACE(C, G, R, W)                                                                              \
     hipLaunchKernelGGL((k_trace<C, G, R, W>), dim3(grid_blocks), dim3(BLOCK), lds, s, d_desc, d_chunk_base, n_evals, \
                        d_win, grid_blocks, total_chunks, d_queue, d_spill, d_chunks, d_counts, lgd, fans_inline,  \
-                       d_fan_out, d_fan_counts)
+                       d_fan_out, d_fan_counts, d_order, d_cost)
     // (the counting variants serve tests and the benchmark's work counts: one
     // instantiation each; both instantiations compute the same bits)
     const bool lean = blocks_per_cu <= 2;
@@ -1153,7 +1156,8 @@ int launch_fans(const EvalDesc *d_desc, const int64_t *d_unit_base, int n_evals,
 
 int launch_reduce(const EvalDesc *d_desc, int n_evals, const uint64_t *d_win, const PatchOut *d_patches,
                   const uint64_t *d_counts, const PatchOut *d_fan_out, const uint64_t *d_fan_counts, bool count,
-                  bool grad, const uint32_t *d_slice_eval, int64_t total_slices, void *d_out, void *stream) {
+                  bool grad, const uint32_t *d_slice_eval, int64_t total_slices, void *d_out, uint32_t *d_order,
+                  const uint32_t *d_cost, void *stream) {
     if (n_evals <= 0) return 0;
     if (total_slices < n_evals || total_slices > INT32_MAX) return (int)hipErrorInvalidValue;
     hipStream_t s = (hipStream_t)stream;
@@ -1162,7 +1166,8 @@ int launch_reduce(const EvalDesc *d_desc, int n_evals, const uint64_t *d_win, co
     do {                                                                                                        \
         hipLaunchKernelGGL((k_slices<C, G>), dim3((uint32_t)total_slices), dim3(RBLOCK), 0, s, d_desc,          \
                            d_slice_eval, d_patches, d_counts, d_fan_out, d_fan_counts);                         \
-        hipLaunchKernelGGL((k_reduce<C, G>), dim3(n_evals), dim3(RBLOCK), 0, s, d_desc, d_win, out);            \
+        hipLaunchKernelGGL((k_reduce<C, G>), dim3(n_evals), dim3(RBLOCK), 0, s, d_desc, d_win, out, d_order,    \
+                           d_cost);                                                                             \
     } while (0)
     if (count && grad) SRP_LAUNCH_REDUCE(true, true);
     else if (count) SRP_LAUNCH_REDUCE(true, false);

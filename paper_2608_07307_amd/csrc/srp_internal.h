@@ -215,17 +215,11 @@ struct alignas(64) EvalDesc {
     int64_t slice_base;     // the batch's number of this evaluation's first range sum
     int32_t n_clamped;      // hinge angles of this evaluation clamped to their intervals
     int32_t pad_;
-    // captured forward launches of one patch per chunk (else null): chunk c
-    // traces patch order[c] (a permutation of the evaluation's patches),
-    // cost[p] receives patch p's trace time (constant-rate clock ticks), and
-    // the reduction rewrites order from cost for the next launch
-    uint32_t *order;
-    uint32_t *cost;
 };
 
 // The host writes these records and the kernels read them: both compilation
 // passes (host and gfx950) must agree on every offset.
-static_assert(sizeof(EvalDesc) == 448, "EvalDesc layout");
+static_assert(sizeof(EvalDesc) == 384, "EvalDesc layout");
 static_assert(offsetof(EvalDesc, tris) == 0, "EvalDesc layout");
 static_assert(offsetof(EvalDesc, blas) == 8, "EvalDesc layout");
 static_assert(offsetof(EvalDesc, mats) == 16, "EvalDesc layout");
@@ -273,8 +267,6 @@ static_assert(offsetof(EvalDesc, gslice) == 352, "EvalDesc layout");
 static_assert(offsetof(EvalDesc, pslice) == 360, "EvalDesc layout");
 static_assert(offsetof(EvalDesc, slice_base) == 368, "EvalDesc layout");
 static_assert(offsetof(EvalDesc, n_clamped) == 376, "EvalDesc layout");
-static_assert(offsetof(EvalDesc, order) == 384, "EvalDesc layout");
-static_assert(offsetof(EvalDesc, cost) == 392, "EvalDesc layout");
 static_assert(sizeof(PatchOut) == 64, "PatchOut layout");
 static_assert(offsetof(PatchOut, f) == 0, "PatchOut layout");
 static_assert(offsetof(PatchOut, hits) == 48, "PatchOut layout");
@@ -319,12 +311,16 @@ int launch_articulate(const ArtJob *d_jobs, int n_jobs, void *stream);
 // d_fan_out (forward, diffuse rays on): the trace kernel also traces every
 // patch's diffuse fans into their partial slots (no fan launch follows).
 // blocks_per_cu <= 2 (grid_blocks = that times the CU count) launches the
-// kernel compiled for 2 waves per SIMD.
+// kernel compiled for 2 waves per SIMD.  d_order, d_cost (forward launches of
+// one patch per chunk, else null): one word per patch of the batch (at each
+// evaluation's patch_base); chunk c of an evaluation traces its patch
+// d_order[c], and d_cost receives every patch's trace time (constant-rate
+// clock ticks).
 int launch_trace(const EvalDesc *d_desc, const int64_t *d_chunk_base, int n_evals,
                  const uint64_t *d_win, int64_t total_chunks, uint32_t *d_queue, uint32_t *d_spill,
                  PatchOut *d_patches, uint64_t *d_counts, bool count, bool grad, bool dir, int grid_blocks,
                  int lds_grad_doubles, PatchOut *d_fan_out, uint64_t *d_fan_counts, int blocks_per_cu,
-                 void *stream);
+                 const uint32_t *d_order, uint32_t *d_cost, void *stream);
 // Diffuse fans of the recorded emitters: one work unit per patch and fan slice
 // (d_unit_base: first unit of every evaluation, then the total); uses the
 // second set of queue counters and the same spill area as the trace kernel.
@@ -333,9 +329,13 @@ int launch_fans(const EvalDesc *d_desc, const int64_t *d_unit_base, int n_evals,
                 uint64_t *d_fan_counts, bool count, int grid_blocks, void *stream);
 // d_slice_eval: the evaluation of each of the batch's total_slices range sums
 // (one block each; an evaluation's are consecutive, from its slice_base).
+// With d_order and d_cost (as for launch_trace) the second stage also
+// rewrites every evaluation's patch order from the costs, heaviest first, for
+// the next launch.
 int launch_reduce(const EvalDesc *d_desc, int n_evals, const uint64_t *d_win, const PatchOut *d_patches,
                   const uint64_t *d_counts, const PatchOut *d_fan_out, const uint64_t *d_fan_counts, bool count,
-                  bool grad, const uint32_t *d_slice_eval, int64_t total_slices, void *d_out, void *stream);
+                  bool grad, const uint32_t *d_slice_eval, int64_t total_slices, void *d_out, uint32_t *d_order,
+                  const uint32_t *d_cost, void *stream);
 // Resident blocks per compute unit of the trace kernel variant.
 int trace_blocks_per_cu(bool count, bool grad, bool dir, int lds_grad_doubles);
 // Resident blocks per compute unit of the fan kernel variant.
