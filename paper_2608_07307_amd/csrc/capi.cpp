@@ -596,7 +596,8 @@ int layout_build(const srp_batch_item *items, int64_t n, bool grad, Schedule for
 // launches see similar images (a propagation's stages; replays of one batch).
 // The results do not depend on the order.
 void layout_add_order(Layout &L) {
-    if (L.grad || L.total_patches <= 0) return;
+    // (launches of at most 2 blocks per CU: the kernel build that orders its work)
+    if (L.grad || L.count || L.sch.bpc > 2 || L.total_patches <= 0) return;
     for (int64_t k = 0; k < L.n; ++k)
         if (L.item_ppc[k] != 1) return;
     L.ordered = true;

@@ -473,7 +473,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE ? WPE
         const int N = D.n;
 
         int64_t p0 = kc * D.ppc, p1 = min(p0 + D.ppc, D.n_patches);
-        if (!GRAD && order) {
+        // (patch order and costs: only in the 2-wave build, which the ordered
+        // launches use, so the batch builds keep their registers)
+        constexpr bool ORDERED = !GRAD && WPE == 2;
+        if (ORDERED && order) {
             // a captured forward plan of one patch per chunk hands out its patches
             // heaviest first, in the order its previous launch measured; any order
             // gives the same result, since every patch writes its own partial slot
@@ -500,7 +503,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE ? WPE
             const int tile = (int)(pt >> 2), q = (int)(pt & 3);
             const int px = (tile % D.tiles_x) * TILE + (q & 1) * PATCH + (lane & 7);
             const int py = (tile / D.tiles_x) * TILE + (q >> 1) * PATCH + (lane >> 3);
-            const uint64_t clock0 = (!GRAD && cost) ? wall_clock64() : 0;
+            const uint64_t clock0 = (ORDERED && cost) ? wall_clock64() : 0;
             for (int k = 0; k < 6; ++k) lacc[k * BLOCK] = 0.0;
             // hit counts packed in 10-bit fields (primary hits, specular secondary rays and
             // their hits; a patch sums at most 64 * SRP_MAX_BOUNCES of each), the status
@@ -732,7 +735,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE ? WPE
                 fan_passes<COUNT>(D, TC, pt, em[0], em[1], em[2], em[3], 0, 1, tmin2, stack, lacc, lane, fan_out,
                                   fan_counts);
             }
-            if (!GRAD && cost && lane == 0) {
+            if (ORDERED && cost && lane == 0) {
                 const uint64_t dt = wall_clock64() - clock0;
                 ((uint32_t SRP_GLOBAL *)cost)[D.patch_base + pt] = dt < 0xFFFFFFFFull ? (uint32_t)dt : 0xFFFFFFFFu;
             }

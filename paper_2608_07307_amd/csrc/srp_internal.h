@@ -311,11 +311,11 @@ int launch_articulate(const ArtJob *d_jobs, int n_jobs, void *stream);
 // d_fan_out (forward, diffuse rays on): the trace kernel also traces every
 // patch's diffuse fans into their partial slots (no fan launch follows).
 // blocks_per_cu <= 2 (grid_blocks = that times the CU count) launches the
-// kernel compiled for 2 waves per SIMD.  d_order, d_cost (forward launches of
-// one patch per chunk, else null): one word per patch of the batch (at each
-// evaluation's patch_base); chunk c of an evaluation traces its patch
-// d_order[c], and d_cost receives every patch's trace time (constant-rate
-// clock ticks).
+// kernel compiled for 2 waves per SIMD.  d_order, d_cost (such forward
+// launches of one patch per chunk, else null; other launches ignore them):
+// one word per patch of the batch (at each evaluation's patch_base); chunk c
+// of an evaluation traces its patch d_order[c], and d_cost receives every
+// patch's trace time (constant-rate clock ticks).
 int launch_trace(const EvalDesc *d_desc, const int64_t *d_chunk_base, int n_evals,
                  const uint64_t *d_win, int64_t total_chunks, uint32_t *d_queue, uint32_t *d_spill,
                  PatchOut *d_patches, uint64_t *d_counts, bool count, bool grad, bool dir, int grid_blocks,
