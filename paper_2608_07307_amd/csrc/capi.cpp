@@ -602,7 +602,7 @@ void layout_add_order(Layout &L) {
         if (L.item_ppc[k] != 1) return;
     L.ordered = true;
     L.o_order = align_up(L.dev_bytes);
-    L.o_cost = align_up(L.o_order + sizeof(uint32_t) * (size_t)L.total_patches);
+    L.o_cost = align_up(L.o_order + sizeof(uint32_t) * (size_t)(L.total_patches + 1));   // (+ launch count)
     L.dev_bytes = align_up(L.o_cost + sizeof(uint32_t) * (size_t)L.total_patches);
 }
 
@@ -756,7 +756,7 @@ int enqueue(const Layout &L, char *Dv, const char *H, size_t copy_bytes, const B
     }
     e = launch_reduce(d_desc, (int)L.n, d_win, d_patches, d_counts, d_fan_out, d_fan_counts, L.count, L.grad,
                       reinterpret_cast<const uint32_t *>(Dv + L.o_seval), L.slice_base[L.n], bo.d_out, d_order, d_cost,
-                      stream);
+                      d_order ? d_order + L.total_patches : nullptr, stream);
     if (e) return fail(SRP_ERR_DEVICE, std::string("reduce kernel: ") + hipGetErrorString((hipError_t)e));
     if (bo.h_copy) HIPCHK(hipMemcpyAsync(bo.h_copy, bo.d_out, sizeof(srp_result) * L.n, hipMemcpyDeviceToHost, stream));
     return SRP_OK;
@@ -871,14 +871,15 @@ int plan_make(const srp_batch_item *items, int64_t n, bool grad, const BatchOut 
         return fail(SRP_ERR_OOM, "plan device allocation failed");
     }
     if (P->L.ordered) {
-        // the first launch traces every evaluation's patches in image order
-        std::vector<uint32_t> ident((size_t)P->L.total_patches);
+        // the first launch traces every evaluation's patches in image order (the
+        // word after the order counts the plan's launches)
+        std::vector<uint32_t> ident((size_t)P->L.total_patches + 1, 0u);
         for (int64_t k = 0; k < n; ++k)
             for (int64_t q = P->L.patch_base[k]; q < P->L.patch_base[k + 1]; ++q)
                 ident[(size_t)q] = (uint32_t)(q - P->L.patch_base[k]);
         hipError_t e1 = hipMemcpy(P->d_buf + P->L.o_order, ident.data(), sizeof(uint32_t) * ident.size(),
                                   hipMemcpyHostToDevice);
-        hipError_t e2 = hipMemset(P->d_buf + P->L.o_cost, 0, sizeof(uint32_t) * ident.size());
+        hipError_t e2 = hipMemset(P->d_buf + P->L.o_cost, 0, sizeof(uint32_t) * (size_t)P->L.total_patches);
         if (e1 != hipSuccess || e2 != hipSuccess) {
             plan_free(P);
             return fail(SRP_ERR_DEVICE, std::string("plan order setup: ") +

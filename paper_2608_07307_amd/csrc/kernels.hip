@@ -849,6 +849,7 @@ __global__ __launch_bounds__(WBLOCK) void k_window(const EvalDesc *__restrict__ 
 }
 
 constexpr int RBLOCK = 1024;   // threads per block of the reduction kernels
+constexpr uint32_t ORDER_EVERY = 8;   // launches of a plan per rebuild of its patch order
 
 // Reduction, first stage: block (q, e) sums the q-th of n_slices contiguous
 // ranges of evaluation e's patch partials (patches np q / Q .. np (q + 1) / Q),
@@ -991,7 +992,7 @@ __device__ void patch_order(const EvalDesc &D, uint32_t *order_all, const uint32
 template <bool COUNT, bool GRAD>
 __global__ __launch_bounds__(RBLOCK) void k_reduce(const EvalDesc *__restrict__ descs,
                                                 const uint64_t *__restrict__ win, srp_result *out,
-                                                uint32_t *order, const uint32_t *cost) {
+                                                uint32_t *order, const uint32_t *cost, uint32_t *order_launch) {
     const int e = blockIdx.x, tid = threadIdx.x;
     const EvalDesc &D = descs[e];
     const int Q = D.n_slices;
@@ -1026,7 +1027,19 @@ __global__ __launch_bounds__(RBLOCK) void k_reduce(const EvalDesc *__restrict__ 
         r.n_clamped = (uint32_t)D.n_clamped;
         out[e] = r;
     }
-    if (!GRAD && order && cost) patch_order(D, order, cost, tid);   // (the same for the whole block)
+    if (!GRAD && order && cost) {   // (the same for the whole block)
+        // rebuilt on every ORDER_EVERY-th launch of the plan: the order stays
+        // useful while consecutive launches see similar images, and the pass
+        // costs as much as the reduction itself (its LDS counters are hot)
+        __shared__ uint32_t s_launch;
+        if (tid == 0) s_launch = *order_launch;
+        __syncthreads();
+        const uint32_t launch = s_launch;
+        if (launch % ORDER_EVERY == 0) patch_order(D, order, cost, tid);
+        // (one increment per launch; another evaluation's block may read either
+        // value, which only moves the launch its order is rebuilt on)
+        if (e == 0 && tid == 0) *order_launch = launch + 1;
+    }
     if (GRAD) {
         const int G = D.grad_n, K = D.n_nodes, M = D.n_mats, J = D.n_dof;
         __shared__ double sg[MAX_GRAD_SLOTS];
@@ -1160,7 +1173,7 @@ int launch_fans(const EvalDesc *d_desc, const int64_t *d_unit_base, int n_evals,
 int launch_reduce(const EvalDesc *d_desc, int n_evals, const uint64_t *d_win, const PatchOut *d_patches,
                   const uint64_t *d_counts, const PatchOut *d_fan_out, const uint64_t *d_fan_counts, bool count,
                   bool grad, const uint32_t *d_slice_eval, int64_t total_slices, void *d_out, uint32_t *d_order,
-                  const uint32_t *d_cost, void *stream) {
+                  const uint32_t *d_cost, uint32_t *d_order_launch, void *stream) {
     if (n_evals <= 0) return 0;
     if (total_slices < n_evals || total_slices > INT32_MAX) return (int)hipErrorInvalidValue;
     hipStream_t s = (hipStream_t)stream;
@@ -1170,7 +1183,7 @@ int launch_reduce(const EvalDesc *d_desc, int n_evals, const uint64_t *d_win, co
         hipLaunchKernelGGL((k_slices<C, G>), dim3((uint32_t)total_slices), dim3(RBLOCK), 0, s, d_desc,          \
                            d_slice_eval, d_patches, d_counts, d_fan_out, d_fan_counts);                         \
         hipLaunchKernelGGL((k_reduce<C, G>), dim3(n_evals), dim3(RBLOCK), 0, s, d_desc, d_win, out, d_order,    \
-                           d_cost);                                                                             \
+                           d_cost, d_order_launch);                                                             \
     } while (0)
     if (count && grad) SRP_LAUNCH_REDUCE(true, true);
     else if (count) SRP_LAUNCH_REDUCE(true, false);

@@ -331,11 +331,11 @@ int launch_fans(const EvalDesc *d_desc, const int64_t *d_unit_base, int n_evals,
 // (one block each; an evaluation's are consecutive, from its slice_base).
 // With d_order and d_cost (as for launch_trace) the second stage also
 // rewrites every evaluation's patch order from the costs, heaviest first, for
-// the next launch.
+// the next launches, on every eighth launch as counted in *d_order_launch.
 int launch_reduce(const EvalDesc *d_desc, int n_evals, const uint64_t *d_win, const PatchOut *d_patches,
                   const uint64_t *d_counts, const PatchOut *d_fan_out, const uint64_t *d_fan_counts, bool count,
                   bool grad, const uint32_t *d_slice_eval, int64_t total_slices, void *d_out, uint32_t *d_order,
-                  const uint32_t *d_cost, void *stream);
+                  const uint32_t *d_cost, uint32_t *d_order_launch, void *stream);
 // Resident blocks per compute unit of the trace kernel variant.
 int trace_blocks_per_cu(bool count, bool grad, bool dir, int lds_grad_doubles);
 // Resident blocks per compute unit of the fan kernel variant.
