@@ -291,16 +291,15 @@ struct Layout {
     bool grad = false, count = false, dir = false;
     Schedule sch;
     std::vector<int64_t> chunk_base, patch_base;
-    std::vector<int64_t> unit_base;   // first fan work unit of every item, then the total
     std::vector<int64_t> fan_base;    // first fan partial slot of every item, then the total
     std::vector<int> tiles_x, tiles_y;
     std::vector<int> item_slot;
     std::vector<SlotRec> slots;
     int max_grad_n = 0;
     int64_t total_chunks = 0, total_patches = 0, max_wpts = 0, total_units = 0, total_fan_slots = 0;
-    size_t o_desc = 0, o_cbase = 0, o_ubase = 0, o_win = 0, o_seval = 0, o_jobs = 0, o_cs = 0, stage_bytes = 0;
+    size_t o_desc = 0, o_cbase = 0, o_win = 0, o_seval = 0, o_jobs = 0, o_cs = 0, stage_bytes = 0;
     size_t o_slots = 0, total_cs = 0;
-    size_t o_patches = 0, o_counts = 0, o_emask = 0, o_fanout = 0, o_fancnt = 0, o_gpart = 0, o_queue = 0;
+    size_t o_patches = 0, o_counts = 0, o_emask = 0, o_fanout = 0, o_fancnt = 0, o_units = 0, o_gpart = 0, o_queue = 0;
     size_t o_spill = 0, dev_bytes = 0;
     std::vector<size_t> gpart_off, gslice_off, pslice_off;
     std::vector<int> n_slices;    // reduction range sums per item (first stage)
@@ -308,7 +307,7 @@ struct Layout {
     std::vector<size_t> emit_off;   // emitter records of each item with diffuse fans (0: none)
     std::vector<int> grad_n;   // gradient partial doubles per chunk of each item (allocation and kernel)
     std::vector<int> item_ppc;   // patches per chunk of each item (the adjoint: its gradient group)
-    int grid = 1, fan_grid = 0, fan_claim = 1, fan_parts = 0, wb = 1;
+    int grid = 1, fan_grid = 0, wb = 1;
     bool fans_inline = false;   // the trace kernel traces the fans itself (no fan launch)
     // captured forward plans of one patch per chunk: the patch order of the next
     // launch and the per-patch costs it is made from (layout_add_order)
@@ -442,9 +441,10 @@ int layout_build(const srp_batch_item *items, int64_t n, bool grad, Schedule for
     L.chunk_base[n] = L.total_chunks;
     // diffuse fans (forward only; emitters are chain hits of generation < bounces).
     // Many patches with fans: the trace kernel traces each patch's fans right after
-    // its chains.  Few: a fan kernel follows, with fan_parts units per patch, doubled
-    // (up to MAX_FAN_PARTS) while the units stay within two per resident wave, so
-    // that a small batch still fills the GPU.  Both give the same bits.
+    // its chains.  Few: the trace kernel lists every patch's non-empty fan passes and
+    // a fan kernel follows with one unit per listed pass, so that a small batch
+    // still fills the GPU and a heavy patch's passes run side by side.  Both give
+    // the same bits.
     int64_t fan_patches = 0;
     for (int64_t k = 0; k < n; ++k)
         if (!grad && items[k].p.bounces > 0 && items[k].p.n_diffuse > 0)
@@ -452,27 +452,22 @@ int layout_build(const srp_batch_item *items, int64_t n, bool grad, Schedule for
     if (fan_patches > 0) {
         const int64_t resident = (int64_t)g_ws.n_cu * fan_blocks_per_cu(L.count) * (BLOCK / 64);
         L.fans_inline = fan_patches >= 2 * resident;
-        if (!L.fans_inline) {
-            L.fan_parts = 1;
-            while (L.fan_parts < MAX_FAN_PARTS && fan_patches * (2 * L.fan_parts) <= 2 * resident) L.fan_parts *= 2;
-        }
     }
     // partial slots: one per pass of 64 tasks (emitter, slice of FAN_SLICE fan rays), at
     // most bounces x ceil(n_diffuse / FAN_SLICE) per patch
-    L.unit_base.assign(n + 1, 0);
     L.fan_base.assign(n + 1, 0);
     for (int64_t k = 0; k < n; ++k) {
-        L.unit_base[k] = L.total_units;
         L.fan_base[k] = L.total_fan_slots;
         const srp_eval_params &p = items[k].p;
         if (!grad && p.bounces > 0 && p.n_diffuse > 0) {
             const int64_t np = L.patch_base[k + 1] - L.patch_base[k];
-            L.total_units += np * L.fan_parts;
             L.total_fan_slots += np * p.bounces * ((p.n_diffuse + FAN_SLICE - 1) / FAN_SLICE);
         }
     }
-    L.unit_base[n] = L.total_units;
     L.fan_base[n] = L.total_fan_slots;
+    // the fan launch's unit list: room for every pass slot (each patch lists at
+    // most its slots)
+    L.total_units = L.fans_inline ? 0 : L.total_fan_slots;
     // the work counters are 32-bit and overshoot their range by at most one per wave
     if (L.total_chunks > ((int64_t)1 << 31))
         return fail(SRP_ERR_ARG, "batch too large: more than 2^31 chunks (split it or raise patches per chunk)");
@@ -517,12 +512,11 @@ int layout_build(const srp_batch_item *items, int64_t n, bool grad, Schedule for
         L.item_slot[k] = found;
     }
 
-    // staging (uploaded every launch): descs | chunk_base | unit_base | win |
+    // staging (uploaded every launch): descs | chunk_base | win |
     // evaluation of every range sum | articulation jobs | their cosines and sines
     L.o_desc = 0;
     L.o_cbase = align_up(sizeof(EvalDesc) * n);
-    L.o_ubase = align_up(L.o_cbase + sizeof(int64_t) * (n + 1));
-    L.o_win = align_up(L.o_ubase + sizeof(int64_t) * (n + 1));
+    L.o_win = align_up(L.o_cbase + sizeof(int64_t) * (n + 1));
     L.o_seval = align_up(L.o_win + sizeof(uint64_t) * WIN_STRIDE * n);
     L.o_jobs = align_up(L.o_seval + sizeof(uint32_t) * L.slice_base[n]);
     L.o_cs = align_up(L.o_jobs + sizeof(ArtJob) * L.slots.size());
@@ -542,7 +536,8 @@ int layout_build(const srp_batch_item *items, int64_t n, bool grad, Schedule for
         // masks: SRP_MAX_BOUNCES per patch of every item (only items with fans use theirs)
         L.o_fanout = align_up(L.o_emask + sizeof(uint64_t) * SRP_MAX_BOUNCES * L.total_patches);
         L.o_fancnt = align_up(L.o_fanout + sizeof(PatchOut) * L.total_fan_slots);
-        eoff = align_up(L.o_fancnt + (L.count ? sizeof(uint64_t) * 2 * L.total_fan_slots : 0));
+        L.o_units = align_up(L.o_fancnt + (L.count ? sizeof(uint64_t) * 2 * L.total_fan_slots : 0));
+        eoff = align_up(L.o_units + sizeof(int4) * (size_t)L.total_units);
         for (int64_t k = 0; k < n; ++k) {
             if (L.fan_base[k + 1] == L.fan_base[k]) continue;
             L.emit_off[k] = eoff;
@@ -572,18 +567,14 @@ int layout_build(const srp_batch_item *items, int64_t n, bool grad, Schedule for
     const int64_t waves = BLOCK / 64;
     L.grid = (int)std::max<int64_t>(1, std::min<int64_t>((L.total_chunks + waves - 1) / waves,
                                                          (int64_t)g_ws.n_cu * L.sch.bpc));
-    if (L.total_units > 0) {
+    if (L.total_units > 0)
         L.fan_grid = (int)std::max<int64_t>(1, std::min<int64_t>((L.total_units + waves - 1) / waves,
                                                                  (int64_t)g_ws.n_cu * fan_blocks_per_cu(L.count)));
-        // units per queue claim: the largest (up to 8) that still leaves >= 16 claims per
-        // resident wave (big batches: fewer counter updates; single evaluations: 1)
-        const int64_t resident = (int64_t)L.fan_grid * waves;
-        while (L.fan_claim < 8 && L.total_units / (2 * L.fan_claim) >= 16 * resident) L.fan_claim *= 2;
-    }
-    // the work counters (trace kernel's, then fan kernel's), then the traversal stacks'
-    // spill area (per thread of the larger grid: the kernels run one after the other)
+    // the work counters (trace kernel's, then fan kernel's, then the count of
+    // listed fan units), then the traversal stacks' spill area (per thread of
+    // the larger grid: the kernels run one after the other)
     L.o_queue = align_up(goff);
-    L.o_spill = align_up(L.o_queue + sizeof(uint32_t) * 2 * N_QUEUES * QUEUE_STRIDE);
+    L.o_spill = align_up(L.o_queue + sizeof(uint32_t) * QUEUE_WORDS);
     L.dev_bytes = align_up(L.o_spill + sizeof(uint32_t) * STACK_SPILL * (size_t)BLOCK * std::max(L.grid, L.fan_grid));
     L.wb = (int)std::min<int64_t>(64, std::max<int64_t>(1, (L.max_wpts + 2047) / 2048));
     return SRP_OK;
@@ -611,7 +602,6 @@ void staging_fill(const Layout &L, const srp_batch_item *items, const BatchOut &
     const int64_t n = L.n;
     EvalDesc *desc = reinterpret_cast<EvalDesc *>(H + L.o_desc);
     std::memcpy(H + L.o_cbase, L.chunk_base.data(), sizeof(int64_t) * (n + 1));
-    std::memcpy(H + L.o_ubase, L.unit_base.data(), sizeof(int64_t) * (n + 1));
     uint64_t *win = reinterpret_cast<uint64_t *>(H + L.o_win);
     for (int64_t k = 0; k < WIN_STRIDE * n; ++k) win[k] = enc_f64(INFINITY);
     uint32_t *seval = reinterpret_cast<uint32_t *>(H + L.o_seval);
@@ -692,8 +682,6 @@ void staging_fill(const Layout &L, const srp_batch_item *items, const BatchOut &
         const bool fans = L.fan_base[k + 1] > L.fan_base[k];
         D.emit = fans ? reinterpret_cast<FanRec *>(Dv + L.emit_off[k]) : nullptr;
         D.emit_mask = fans ? reinterpret_cast<uint64_t *>(Dv + L.o_emask) + SRP_MAX_BOUNCES * D.patch_base : nullptr;
-        D.unit_base = L.unit_base[k];
-        D.n_parts = fans ? L.fan_parts : 0;
         D.fan_base = L.fan_base[k];
         D.grad_n = L.grad ? L.grad_n[k] : 0;   // the per-chunk size the partials were allocated with
         D.grad_part = L.grad ? reinterpret_cast<double *>(Dv + L.gpart_off[k]) : nullptr;
@@ -740,14 +728,14 @@ int enqueue(const Layout &L, char *Dv, const char *H, size_t copy_bytes, const B
         d_fan_out = reinterpret_cast<PatchOut *>(Dv + L.o_fanout);
         d_fan_counts = L.count ? reinterpret_cast<uint64_t *>(Dv + L.o_fancnt) : nullptr;
     }
+    int4 *d_units = L.total_units > 0 ? reinterpret_cast<int4 *>(Dv + L.o_units) : nullptr;
     e = launch_trace(d_desc, d_cbase, (int)L.n, d_win, L.total_chunks, d_queue, d_spill, d_patches, d_counts, L.count,
-                     L.grad, L.dir, L.grid, L.max_grad_n, L.fans_inline ? d_fan_out : nullptr,
-                     L.fans_inline ? d_fan_counts : nullptr, L.sch.bpc, d_order, d_cost, stream);
+                     L.grad, L.dir, L.grid, L.max_grad_n, d_fan_out, d_fan_counts, L.fans_inline, d_units, L.sch.bpc,
+                     d_order, d_cost, stream);
     if (e) return fail(SRP_ERR_DEVICE, std::string("trace kernel: ") + hipGetErrorString((hipError_t)e));
     if (L.total_units > 0) {
-        const int64_t *d_ubase = reinterpret_cast<const int64_t *>(Dv + L.o_ubase);
-        e = launch_fans(d_desc, d_ubase, (int)L.n, d_win, L.total_units, L.fan_claim, d_queue, d_spill, d_fan_out,
-                        d_fan_counts, L.count, L.fan_grid, stream);
+        e = launch_fans(d_desc, d_win, L.total_units, d_queue, d_spill, d_fan_out, d_fan_counts, d_units, L.count,
+                        L.fan_grid, stream);
         if (e) return fail(SRP_ERR_DEVICE, std::string("fan kernel: ") + hipGetErrorString((hipError_t)e));
     }
     if (profile) {   // the ray-tracing kernels: trace, then fans
@@ -814,12 +802,7 @@ int layout_fit(Layout *Lp, size_t cap) {
                                      std::to_string(cap) + " available (split it)");
     const int max_blocks = (int)std::min<size_t>((cap - L.o_spill) / per_block, 1 << 30);
     if (L.grid > max_blocks) L.grid = max_blocks;
-    if (L.fan_grid > max_blocks) {
-        L.fan_grid = max_blocks;
-        const int64_t resident = (int64_t)L.fan_grid * (BLOCK / 64);
-        L.fan_claim = 1;
-        while (L.fan_claim < 8 && L.total_units / (2 * L.fan_claim) >= 16 * resident) L.fan_claim *= 2;
-    }
+    if (L.fan_grid > max_blocks) L.fan_grid = max_blocks;
     L.dev_bytes = align_up(L.o_spill + per_block * (size_t)std::max(L.grid, L.fan_grid));
     return SRP_OK;
 }
@@ -929,8 +912,8 @@ int plan_refill(PlanImpl *P, const srp_batch_item *items, int64_t n, bool *compa
         L2.wb != L.wb || L2.count != L.count || L2.dir != L.dir || L2.max_grad_n != L.max_grad_n ||
         L2.grad_n != L.grad_n || L2.chunk_base != L.chunk_base ||
         L2.patch_base != L.patch_base || L2.o_patches != L.o_patches || L2.o_counts != L.o_counts ||
-        L2.unit_base != L.unit_base || L2.fan_base != L.fan_base || L2.fan_grid != L.fan_grid ||
-        L2.fan_claim != L.fan_claim || L2.fan_parts != L.fan_parts || L2.fans_inline != L.fans_inline ||
+        L2.total_units != L.total_units || L2.fan_base != L.fan_base || L2.fan_grid != L.fan_grid ||
+        L2.o_units != L.o_units || L2.fans_inline != L.fans_inline ||
         L2.emit_off != L.emit_off ||
         L2.o_emask != L.o_emask || L2.o_fanout != L.o_fanout || L2.o_fancnt != L.o_fancnt ||
         L2.o_queue != L.o_queue || L2.o_spill != L.o_spill || L2.slots.size() != L.slots.size() ||

@@ -397,8 +397,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE ? WPE
     const EvalDesc *__restrict__ descs, const int64_t *__restrict__ chunk_base, int n_evals,
     const uint64_t *__restrict__ win, int grid_blocks, int64_t total_chunks, uint32_t *queue, uint32_t *spill,
     PatchOut *__restrict__ patches, uint64_t *__restrict__ counts, int lds_grad_doubles, int fans_inline,
-    PatchOut *__restrict__ fan_out, uint64_t *__restrict__ fan_counts, const uint32_t *__restrict__ order,
-    uint32_t *__restrict__ cost) {
+    PatchOut *__restrict__ fan_out, uint64_t *__restrict__ fan_counts, int4 *__restrict__ fan_units,
+    const uint32_t *__restrict__ order, uint32_t *__restrict__ cost) {
     extern __shared__ char smem[];
     const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid >> 6;
     LaneStack stack;
@@ -734,6 +734,30 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE ? WPE
                 __threadfence_block();
                 fan_passes<COUNT>(D, TC, pt, em[0], em[1], em[2], em[3], 0, 1, tmin2, stack, lacc, lane, fan_out,
                                   fan_counts);
+            } else if (!GRAD && KD > 0 && fan_units) {
+                // a fan launch follows: list the patch's non-empty fan passes as its
+                // work units (one pass each), and write the empty passes' zero
+                // partials here, as a pass with no task writes them
+                const int S = (KD + FAN_SLICE - 1) / FAN_SLICE, PM = B * S;
+                int ne = 0;
+                for (int g = 0; g < B; ++g) ne += __popcll(em[g]);
+                const int np = (ne * S + WAVE - 1) / WAVE;
+                uint32_t ubase = 0;
+                if (lane == 0 && np > 0) ubase = atomicAdd(queue + FAN_UNITS_AT, (uint32_t)np);
+                ubase = (uint32_t)__builtin_amdgcn_readfirstlane((int)ubase);
+                for (int l = lane; l < PM; l += WAVE) {
+                    if (l < np) {
+                        ((int4 SRP_GLOBAL *)fan_units)[ubase + l] = make_int4(cur, (int)pt, l, 0);
+                    } else {
+                        const int64_t slot = D.fan_base + pt * PM + l;
+                        PatchOut co = {};
+                        fan_out[slot] = co;
+                        if (COUNT) {
+                            fan_counts[2 * slot] = 0;
+                            fan_counts[2 * slot + 1] = 0;
+                        }
+                    }
+                }
             }
             if (ORDERED && cost && lane == 0) {
                 const uint64_t dt = wall_clock64() - clock0;
@@ -749,15 +773,16 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE ? WPE
 }
 
 // Fan work of the trace kernel's recorded emitters as a separate launch, for
-// batches too small to fill the GPU with whole patches: unit = one of V parts
-// of a patch (passes v, v + V, ...), V chosen by the host (up to
-// MAX_FAN_PARTS).  Persistent waves and work queues as in k_trace; a claim
-// takes `per_claim` consecutive units.
+// batches too small to fill the GPU with whole patches: one unit per
+// non-empty fan pass, as the trace kernel listed them (evaluation, patch,
+// pass), so that one heavy patch's passes run side by side on as many waves
+// and no wave claims an empty pass.  Persistent waves and work queues as in
+// k_trace.
 template <bool COUNT>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(SRP_WPE_FWD))) void k_fans(
-    const EvalDesc *__restrict__ descs, const int64_t *__restrict__ unit_base, int n_evals,
-    const uint64_t *__restrict__ win, int grid_blocks, int64_t total_units, int per_claim, uint32_t *queue,
-    uint32_t *spill, PatchOut *__restrict__ fan_out, uint64_t *__restrict__ fan_counts) {
+    const EvalDesc *__restrict__ descs, const uint64_t *__restrict__ win, int grid_blocks,
+    const int4 *__restrict__ units, int64_t max_units, uint32_t *queue, uint32_t *spill,
+    PatchOut *__restrict__ fan_out, uint64_t *__restrict__ fan_counts) {
     extern __shared__ char smem[];
     const int tid = threadIdx.x, lane = tid & (WAVE - 1);
     LaneStack stack;
@@ -767,42 +792,33 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(SRP_WPE_F
     stack.sstride = grid_blocks * BLOCK;
     double *lacc = reinterpret_cast<double *>(smem + sizeof(uint32_t) * STACK_LDS * BLOCK) + tid;
 
+    // the units the trace kernel listed (it finished before this launch)
+    const int64_t listed = (int64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)queue[FAN_UNITS_AT]);
+    const int64_t total = min(listed, max_units);
+    uint32_t *fq = queue + N_QUEUES * QUEUE_STRIDE;   // the fan kernel's own counters
     uint32_t r = __builtin_amdgcn_s_getreg((HWREG_XCC_ID << 0) | (0 << 6) | (3 << 11)) & (N_QUEUES - 1);
     int tried = 1;
-    const int64_t n_claims = (total_units + per_claim - 1) / per_claim;
-    int64_t n_r = (n_claims - r + N_QUEUES - 1) / N_QUEUES;
+    int64_t n_r = (total - r + N_QUEUES - 1) / N_QUEUES;
     int cur = -1;
-    int64_t cur_begin = 0, cur_end = -1;
     float tmin2 = 0.0f;
     #pragma unroll 1
     for (;;) {
-        const int64_t b = take_work(queue, r, tried, n_r, n_claims, lane);
-        if (b < 0) break;
-        const int64_t c_end = min((b + 1) * per_claim, total_units);
-        #pragma unroll 1
-        for (int64_t c = b * per_claim; c < c_end; ++c) {
-            if (c < cur_begin || c >= cur_end) {
-                int lo = (cur >= 0 && c >= cur_end) ? cur : 0, hi = n_evals - 1;
-                while (lo < hi) {
-                    int mid = (lo + hi + 1) >> 1;
-                    if (unit_base[mid] <= c) lo = mid; else hi = mid - 1;
-                }
-                cur = lo;
-                cur_begin = unit_base[lo];
-                cur_end = unit_base[lo + 1];
-                const uint64_t *W = win + (size_t)lo * WIN_STRIDE;
-                const double wu = -dec_f64(W[1]) - dec_f64(W[0]), wv_ = -dec_f64(W[3]) - dec_f64(W[2]);
-                tmin2 = uniform_f32((float)(1e-6 * fmax(wu, wv_)));
-            }
-            const EvalDesc &D = descs[cur];
-            const int64_t u = c - D.unit_base;
-            const int V = D.n_parts, B = D.bounces;
-            const int64_t p = u / V;            // the patch
-            const int v = (int)(u - p * V);     // which of its parts
-            const uint64_t SRP_GLOBAL *em = (const uint64_t SRP_GLOBAL *)(D.emit_mask + (size_t)p * B);
-            const uint64_t m0 = em[0], m1 = B > 1 ? em[1] : 0ull, m2 = B > 2 ? em[2] : 0ull, m3 = B > 3 ? em[3] : 0ull;
-            fan_passes<COUNT>(D, trace_ctx(D), p, m0, m1, m2, m3, v, V, tmin2, stack, lacc, lane, fan_out, fan_counts);
+        const int64_t c = take_work(fq, r, tried, n_r, total, lane);
+        if (c < 0) break;
+        const int4 U = ((const int4 SRP_GLOBAL *)units)[c];
+        if (U.x != cur) {
+            cur = U.x;
+            const uint64_t *W = win + (size_t)cur * WIN_STRIDE;
+            const double wu = -dec_f64(W[1]) - dec_f64(W[0]), wv_ = -dec_f64(W[3]) - dec_f64(W[2]);
+            tmin2 = uniform_f32((float)(1e-6 * fmax(wu, wv_)));
         }
+        const EvalDesc &D = descs[cur];
+        const int B = D.bounces, PM = B * ((D.n_diffuse + FAN_SLICE - 1) / FAN_SLICE);
+        const int64_t p = U.y;   // the patch
+        const uint64_t SRP_GLOBAL *em = (const uint64_t SRP_GLOBAL *)(D.emit_mask + (size_t)p * B);
+        const uint64_t m0 = em[0], m1 = B > 1 ? em[1] : 0ull, m2 = B > 2 ? em[2] : 0ull, m3 = B > 3 ? em[3] : 0ull;
+        // exactly pass U.z (a step of PM ends the pass loop after it)
+        fan_passes<COUNT>(D, trace_ctx(D), p, m0, m1, m2, m3, U.z, PM, tmin2, stack, lacc, lane, fan_out, fan_counts);
     }
 }
 
@@ -813,8 +829,9 @@ constexpr int WBLOCK = 256;   // threads per block of the window kernel
 __global__ __launch_bounds__(WBLOCK) void k_window(const EvalDesc *__restrict__ descs, uint64_t *win, int blocks_x,
                                                   uint32_t *queue) {
     const EvalDesc &D = descs[blockIdx.y];
-    // the trace and fan kernels' work counters start at zero
-    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < 2 * N_QUEUES) queue[threadIdx.x * QUEUE_STRIDE] = 0u;
+    // the trace and fan kernels' work counters and the count of listed fan
+    // units start at zero
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x <= 2 * N_QUEUES) queue[threadIdx.x * QUEUE_STRIDE] = 0u;
     double mn[5] = {INFINITY, INFINITY, INFINITY, INFINITY, INFINITY};
     const int64_t stride = (int64_t)blocks_x * WBLOCK;
     for (int64_t i = (int64_t)blockIdx.x * WBLOCK + threadIdx.x; i < D.n_wpts; i += stride) {
@@ -1126,17 +1143,18 @@ size_t trace_lds_bytes(bool grad, int lds_grad_doubles) {
 int launch_trace(const EvalDesc *d_desc, const int64_t *d_chunk_base, int n_evals, const uint64_t *d_win,
                  int64_t total_chunks, uint32_t *d_queue, uint32_t *d_spill, PatchOut *d_chunks,
                  uint64_t *d_counts, bool count, bool grad, bool dir, int grid_blocks, int lds_grad_doubles,
-                 PatchOut *d_fan_out, uint64_t *d_fan_counts, int blocks_per_cu, const uint32_t *d_order,
-                 uint32_t *d_cost, void *stream) {
+                 PatchOut *d_fan_out, uint64_t *d_fan_counts, bool fans_inline_, int4 *d_fan_units,
+                 int blocks_per_cu, const uint32_t *d_order, uint32_t *d_cost, void *stream) {
     if (total_chunks <= 0) return 0;
     const size_t lds = trace_lds_bytes(grad, lds_grad_doubles);
     const int lgd = grad ? lds_grad_doubles : 0;
-    const int fans_inline = (!grad && d_fan_out) ? 1 : 0;
+    const int fans_inline = (!grad && d_fan_out && fans_inline_) ? 1 : 0;
+    int4 *fan_units = (!grad && d_fan_out && !fans_inline_) ? d_fan_units : nullptr;
     hipStream_t s = (hipStream_t)stream;
 #define SRP_LAUNCH_TRACE(C, G, R, W)                                                                              \
     hipLaunchKernelGGL((k_trace<C, G, R, W>), dim3(grid_blocks), dim3(BLOCK), lds, s, d_desc, d_chunk_base, n_evals, \
                        d_win, grid_blocks, total_chunks, d_queue, d_spill, d_chunks, d_counts, lgd, fans_inline,  \
-                       d_fan_out, d_fan_counts, d_order, d_cost)
+                       d_fan_out, d_fan_counts, fan_units, d_order, d_cost)
     // (the counting variants serve tests and the benchmark's work counts: one
     // instantiation each; both instantiations compute the same bits)
     const bool lean = blocks_per_cu <= 2;
@@ -1153,20 +1171,18 @@ int launch_trace(const EvalDesc *d_desc, const int64_t *d_chunk_base, int n_eval
     return check(hipGetLastError());
 }
 
-int launch_fans(const EvalDesc *d_desc, const int64_t *d_unit_base, int n_evals, const uint64_t *d_win,
-                int64_t total_units, int per_claim, uint32_t *d_queue, uint32_t *d_spill, PatchOut *d_fan_out,
-                uint64_t *d_fan_counts, bool count, int grid_blocks, void *stream) {
-    if (total_units <= 0) return 0;
-    if (per_claim < 1) return (int)hipErrorInvalidValue;
+int launch_fans(const EvalDesc *d_desc, const uint64_t *d_win, int64_t max_units, uint32_t *d_queue,
+                uint32_t *d_spill, PatchOut *d_fan_out, uint64_t *d_fan_counts, const int4 *d_fan_units, bool count,
+                int grid_blocks, void *stream) {
+    if (max_units <= 0) return 0;
     const size_t lds = trace_lds_bytes(false, 0);   // the same ring and accumulators as the forward trace
     hipStream_t s = (hipStream_t)stream;
-    uint32_t *q = d_queue + N_QUEUES * QUEUE_STRIDE;   // the fan kernel's own counters
     if (count)
-        hipLaunchKernelGGL((k_fans<true>), dim3(grid_blocks), dim3(BLOCK), lds, s, d_desc, d_unit_base, n_evals, d_win,
-                           grid_blocks, total_units, per_claim, q, d_spill, d_fan_out, d_fan_counts);
+        hipLaunchKernelGGL((k_fans<true>), dim3(grid_blocks), dim3(BLOCK), lds, s, d_desc, d_win, grid_blocks,
+                           d_fan_units, max_units, d_queue, d_spill, d_fan_out, d_fan_counts);
     else
-        hipLaunchKernelGGL((k_fans<false>), dim3(grid_blocks), dim3(BLOCK), lds, s, d_desc, d_unit_base, n_evals, d_win,
-                           grid_blocks, total_units, per_claim, q, d_spill, d_fan_out, d_fan_counts);
+        hipLaunchKernelGGL((k_fans<false>), dim3(grid_blocks), dim3(BLOCK), lds, s, d_desc, d_win, grid_blocks,
+                           d_fan_units, max_units, d_queue, d_spill, d_fan_out, d_fan_counts);
     return check(hipGetLastError());
 }
 

@@ -114,11 +114,9 @@ static_assert(sizeof(FanRec) == 32, "FanRec is 32 bytes");
 constexpr int FAN_SLICE = 2;   // (4 and 1 measured: 2 gives single evaluations at the paper's
                                 //  setting 3 % with batches unchanged; 1 costs batches 2 %)
 static_assert(SRP_MAX_BOUNCES == 4, "fan emitter masks: four generations");
-// Most work units per patch of the fan kernel.
 // Most range sums per evaluation in the reduction's first stage (separate
 // blocks, added in order by the second).
 constexpr int MAX_SLICES = 16;
-constexpr int MAX_FAN_PARTS = 8;
 
 // A range sum of an evaluation's patch (and fan) partials: force and torque
 // (FP64, before scaling), hit and test counts, status flags.
@@ -206,8 +204,6 @@ struct alignas(64) EvalDesc {
     const float *dset;      // n_diffuse > 0: the diffuse set, 4 floats per ray (x, y, z, 0), then its mean
     FanRec *emit;           // n_diffuse > 0, forward: emitter records, n_patches x bounces x 64
     uint64_t *emit_mask;    // which of them are filled: n_patches x bounces masks of 64 lanes
-    int64_t unit_base;      // first fan work unit of this evaluation (n_patches x n_parts units)
-    int32_t n_parts;        // fan work units per patch (V); 0 without fans
     int32_t n_slices;       // reduction: contiguous ranges summed by separate blocks (1..MAX_SLICES)
     int64_t fan_base;       // first fan partial slot (n_patches x bounces x ceil(n_diffuse / FAN_SLICE))
     double *gslice;         // gradient: n_slices x grad_n range sums
@@ -259,14 +255,12 @@ static_assert(offsetof(EvalDesc, grad_out) == 296, "EvalDesc layout");
 static_assert(offsetof(EvalDesc, dset) == 304, "EvalDesc layout");
 static_assert(offsetof(EvalDesc, emit) == 312, "EvalDesc layout");
 static_assert(offsetof(EvalDesc, emit_mask) == 320, "EvalDesc layout");
-static_assert(offsetof(EvalDesc, unit_base) == 328, "EvalDesc layout");
-static_assert(offsetof(EvalDesc, n_parts) == 336, "EvalDesc layout");
-static_assert(offsetof(EvalDesc, n_slices) == 340, "EvalDesc layout");
-static_assert(offsetof(EvalDesc, fan_base) == 344, "EvalDesc layout");
-static_assert(offsetof(EvalDesc, gslice) == 352, "EvalDesc layout");
-static_assert(offsetof(EvalDesc, pslice) == 360, "EvalDesc layout");
-static_assert(offsetof(EvalDesc, slice_base) == 368, "EvalDesc layout");
-static_assert(offsetof(EvalDesc, n_clamped) == 376, "EvalDesc layout");
+static_assert(offsetof(EvalDesc, n_slices) == 328, "EvalDesc layout");
+static_assert(offsetof(EvalDesc, fan_base) == 336, "EvalDesc layout");
+static_assert(offsetof(EvalDesc, gslice) == 344, "EvalDesc layout");
+static_assert(offsetof(EvalDesc, pslice) == 352, "EvalDesc layout");
+static_assert(offsetof(EvalDesc, slice_base) == 360, "EvalDesc layout");
+static_assert(offsetof(EvalDesc, n_clamped) == 368, "EvalDesc layout");
 static_assert(sizeof(PatchOut) == 64, "PatchOut layout");
 static_assert(offsetof(PatchOut, f) == 0, "PatchOut layout");
 static_assert(offsetof(PatchOut, hits) == 48, "PatchOut layout");
@@ -298,19 +292,25 @@ constexpr int WIN_STRIDE = 8;
 
 // Kernel launchers (kernels.hip)
 // Work queues of the trace kernel (and, after them, of the fan kernel): N_QUEUES
-// counters QUEUE_STRIDE words apart
+// counters QUEUE_STRIDE words apart; after both sets, the count of fan units
+// the trace kernel listed (FAN_UNITS_AT)
 // (launch_window zeroes them).
 constexpr int N_QUEUES = 8;
 constexpr int QUEUE_STRIDE = 64;
+constexpr int FAN_UNITS_AT = 2 * N_QUEUES * QUEUE_STRIDE;
+constexpr int QUEUE_WORDS = FAN_UNITS_AT + QUEUE_STRIDE;
 int launch_window(const EvalDesc *d_desc, int n_evals, int blocks_x, uint64_t *d_win, uint32_t *d_queue,
                   void *stream);
 // Builds n_jobs articulation slots, one thread each (articulate.hip); the
 // window kernel reads them, so it runs first on the same stream.
 int launch_articulate(const ArtJob *d_jobs, int n_jobs, void *stream);
 // d_spill: grid_blocks * BLOCK * STACK_SPILL words; chunk counts below 2^31.
-// d_fan_out (forward, diffuse rays on): the trace kernel also traces every
-// patch's diffuse fans into their partial slots (no fan launch follows).
-// blocks_per_cu <= 2 (grid_blocks = that times the CU count) launches the
+// d_fan_out, d_fan_counts (forward, diffuse rays on): the fan pass partial
+// slots.  With fans_inline the trace kernel also traces every patch's diffuse
+// fans into them (no fan launch follows); otherwise it lists each patch's
+// non-empty passes in d_fan_units (capacity: one entry per pass slot; their
+// number at d_queue[FAN_UNITS_AT]) for the fan launch and writes the empty
+// passes' zero partials itself.  blocks_per_cu <= 2 (grid_blocks = that times the CU count) launches the
 // kernel compiled for 2 waves per SIMD.  d_order, d_cost (such forward
 // launches of one patch per chunk, else null; other launches ignore them):
 // one word per patch of the batch (at each evaluation's patch_base); chunk c
@@ -319,14 +319,14 @@ int launch_articulate(const ArtJob *d_jobs, int n_jobs, void *stream);
 int launch_trace(const EvalDesc *d_desc, const int64_t *d_chunk_base, int n_evals,
                  const uint64_t *d_win, int64_t total_chunks, uint32_t *d_queue, uint32_t *d_spill,
                  PatchOut *d_patches, uint64_t *d_counts, bool count, bool grad, bool dir, int grid_blocks,
-                 int lds_grad_doubles, PatchOut *d_fan_out, uint64_t *d_fan_counts, int blocks_per_cu,
-                 const uint32_t *d_order, uint32_t *d_cost, void *stream);
-// Diffuse fans of the recorded emitters: one work unit per patch and fan slice
-// (d_unit_base: first unit of every evaluation, then the total); uses the
+                 int lds_grad_doubles, PatchOut *d_fan_out, uint64_t *d_fan_counts, bool fans_inline,
+                 int4 *d_fan_units, int blocks_per_cu, const uint32_t *d_order, uint32_t *d_cost, void *stream);
+// Diffuse fans of the recorded emitters: one work unit per non-empty fan pass,
+// as the trace kernel listed them in d_fan_units (at most max_units); uses the
 // second set of queue counters and the same spill area as the trace kernel.
-int launch_fans(const EvalDesc *d_desc, const int64_t *d_unit_base, int n_evals, const uint64_t *d_win,
-                int64_t total_units, int per_claim, uint32_t *d_queue, uint32_t *d_spill, PatchOut *d_fan_out,
-                uint64_t *d_fan_counts, bool count, int grid_blocks, void *stream);
+int launch_fans(const EvalDesc *d_desc, const uint64_t *d_win, int64_t max_units, uint32_t *d_queue,
+                uint32_t *d_spill, PatchOut *d_fan_out, uint64_t *d_fan_counts, const int4 *d_fan_units, bool count,
+                int grid_blocks, void *stream);
 // d_slice_eval: the evaluation of each of the batch's total_slices range sums
 // (one block each; an evaluation's are consecutive, from its slice_base).
 // With d_order and d_cost (as for launch_trace) the second stage also
