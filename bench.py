@@ -136,10 +136,12 @@ def time_config(srp, torch, name, stream, steps, oracle_sample=True):
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
     ms, launches = srp.profile_read()
+    launch_ms, _ = srp.profile_read_launch()
     srp.profile(False)
     res = srp.results_to_numpy(out[0] if grad else out)
     assert (res["status"] == 0).all()
     kern = ms / 1e3 / steps   # the ray-tracing kernels of one call (of all its sub-batches)
+    dev = launch_ms / 1e3 / steps   # its whole launches: upload, every kernel, result copy
     rec = {"workload": desc, "evals": E}
     if name == "c4":
         # the uneven batch as a captured graph (upload, window, trace, reduction), replayed
@@ -164,8 +166,11 @@ def time_config(srp, torch, name, stream, steps, oracle_sample=True):
         rec.update(path="srp_eval_grad_batch" if grad else "srp_eval_batch",
                    evals_per_s=round(E / dt, 2), grays_per_s=round(rays / dt / 1e9, 3), ms_per_call=round(dt * 1e3, 3))
     _log(f"{name}: {E / dt:.1f} evals/s, {rays / dt / 1e9:.2f} Grays/s, kernels {kern * 1e3:.2f} ms of "
-        f"{dt * 1e3:.2f} ms per call ({launches // steps} launches)")
+        f"{dt * 1e3:.2f} ms per call ({launches // steps} launches; whole launches {dev * 1e3:.2f} ms)")
     rec.update(rays_per_call=rays, kernel_ms=round(kern * 1e3, 3), launches_per_call=launches // steps,
+               device_ms=round(dev * 1e3, 3), device_share=round(dev / dt, 3),
+               device_ms_definition="HIP events around each launch of a direct call: staging upload, articulation, "
+               "window, trace, reduction kernels and result copy; device_share = device_ms / ms of the direct call",
                lane_op_frac=round(work / kern / PEAK_LANE_OPS, 4),
                tests_per_ray=round((int(cnt["n_box_tests"].sum()) + int(cnt["n_tri_tests"].sum())) / rays, 2),
                schedule={"patches_per_chunk": tune[0], "blocks_per_cu": tune[1]})

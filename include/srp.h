@@ -494,6 +494,12 @@ int srp_propagate_nplate_rk78(const srp_plate *plates, int32_t n_plates, const s
  * launch count since the last reset. */
 int srp_profile(int enable);
 int srp_profile_read(double *trace_ms, int64_t *launches);
+/* The same timing for each whole launch: HIP events on the launch stream
+ * around its staging upload, articulation, window, trace, fan, reduction
+ * kernels and result copy.  Returns the summed milliseconds and the launch
+ * count since the last reset (a host that cannot keep the device fed shows
+ * as wall time above this sum).  SRP_ERR_ARG for a null output. */
+int srp_profile_read_launch(double *launch_ms, int64_t *launches);
 
 /* Thread-local message of the last error ("" if none). */
 /* ---- measurement ---- */

@@ -266,6 +266,14 @@ def profile_read():
     return ms.value, n.value
 
 
+def profile_read_launch():
+    """(summed milliseconds of whole launches: upload, every kernel, result copy; launch count)
+    since the last reset."""
+    ms, n = C.c_double(), C.c_int64()
+    L.check(_load().srp_profile_read_launch(C.byref(ms), C.byref(n)))
+    return ms.value, n.value
+
+
 def sun_tracking_angles(scene: Scene, sun_dir, angles=None) -> np.ndarray:
     """srp_sun_tracking_angles: wing roots turned towards the Sun (host)."""
     a = np.zeros(scene.n_dof) if angles is None else np.array(angles, dtype=np.float64)

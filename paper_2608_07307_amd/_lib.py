@@ -16,7 +16,7 @@ SRP_MAX_N, SRP_MAX_BOUNCES, SRP_MAX_NODES, SRP_MAX_MATS, SRP_MAX_DIFFUSE = 8192,
 EXPORTS = [
     "srp_build_scene", "srp_destroy_scene", "srp_scene_n_dof", "srp_set_materials",
     "srp_set_panel_angles", "srp_eval", "srp_eval_batch", "srp_eval_batch_noalloc", "srp_eval_grad",
-    "srp_eval_grad_batch", "srp_last_error", "srp_profile", "srp_profile_read",
+    "srp_eval_grad_batch", "srp_last_error", "srp_profile", "srp_profile_read", "srp_profile_read_launch",
     "srp_sun_tracking_angles", "srp_rk4", "srp_propagate",
     "srp_plan_create", "srp_plan_update", "srp_plan_launch", "srp_plan_destroy",
     "srp_set_schedule", "srp_autotune", "srp_spad_build", "srp_spad_interp", "srp_propagate_spad",
@@ -130,6 +130,7 @@ def load(path: str | None = None):
     lib.srp_propagate.argtypes = [V, C.POINTER(srp_orbit_params), V, V, C.c_double, C.c_double, I64, V,
                                   C.POINTER(srp_prop_stats)]
     lib.srp_profile_read.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+    lib.srp_profile_read_launch.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     lib.srp_spad_build.argtypes = [V, C.POINTER(srp_eval_params), V, C.POINTER(srp_spad_grid), V]
     lib.srp_rk78.argtypes = [V, C.c_double, C.c_double, C.POINTER(srp_rk78_opts), ACCEL_FN, V, V, I64,
                              C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
@@ -152,7 +153,7 @@ def load(path: str | None = None):
                                        C.c_double, C.c_double, I64, V]
     for f in ("srp_build_scene", "srp_destroy_scene", "srp_set_materials",
               "srp_set_panel_angles", "srp_eval", "srp_eval_batch", "srp_eval_batch_noalloc", "srp_eval_grad",
-              "srp_eval_grad_batch", "srp_profile", "srp_profile_read",
+              "srp_eval_grad_batch", "srp_profile", "srp_profile_read", "srp_profile_read_launch",
               "srp_sun_tracking_angles", "srp_rk4", "srp_propagate", "srp_plan_create",
               "srp_plan_update", "srp_plan_launch", "srp_plan_destroy", "srp_set_schedule",
               "srp_autotune", "srp_spad_build", "srp_spad_interp", "srp_propagate_spad", "srp_rk78",

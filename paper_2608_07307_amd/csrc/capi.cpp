@@ -107,12 +107,14 @@ std::vector<float> diffuse_sets() {
     return t;
 }
 
-// Optional timing of the trace-kernel launches (HIP events on the launch stream).
+// Optional timing of the trace-kernel launches (HIP events on the launch stream),
+// and of each whole launch: from its staging upload through its result copy.
 struct Profile {
     bool on = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pairs;   // recorded, not yet read
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> whole;   // the same for whole launches
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
-    double ms = 0;
+    double ms = 0, whole_ms = 0;
     int64_t launches = 0;
 };
 Profile g_prof;
@@ -138,6 +140,14 @@ int prof_collect() {
         g_prof.pool.push_back(pr);
     }
     g_prof.pairs.clear();
+    for (auto &pr : g_prof.whole) {
+        HIPCHK(hipEventSynchronize(pr.second));
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, pr.first, pr.second));
+        g_prof.whole_ms += ms;
+        g_prof.pool.push_back(pr);
+    }
+    g_prof.whole.clear();
     return SRP_OK;
 }
 
@@ -699,6 +709,12 @@ void staging_fill(const Layout &L, const srp_batch_item *items, const BatchOut &
 // Upload + window + trace + reduce (+ optional result copy) on `stream`.
 int enqueue(const Layout &L, char *Dv, const char *H, size_t copy_bytes, const BatchOut &bo, hipStream_t stream,
             bool profile, hipEvent_t copied = nullptr) {
+    std::pair<hipEvent_t, hipEvent_t> whole{};
+    if (profile) {
+        int rc = prof_event_pair(&whole);
+        if (rc) return rc;
+        HIPCHK(hipEventRecord(whole.first, stream));
+    }
     HIPCHK(hipMemcpyAsync(Dv, H, copy_bytes, hipMemcpyHostToDevice, stream));
     if (copied) HIPCHK(hipEventRecord(copied, stream));
     if (!L.slots.empty()) {
@@ -747,6 +763,10 @@ int enqueue(const Layout &L, char *Dv, const char *H, size_t copy_bytes, const B
                       d_order ? d_order + L.total_patches : nullptr, stream);
     if (e) return fail(SRP_ERR_DEVICE, std::string("reduce kernel: ") + hipGetErrorString((hipError_t)e));
     if (bo.h_copy) HIPCHK(hipMemcpyAsync(bo.h_copy, bo.d_out, sizeof(srp_result) * L.n, hipMemcpyDeviceToHost, stream));
+    if (profile) {
+        HIPCHK(hipEventRecord(whole.second, stream));
+        g_prof.whole.push_back(whole);
+    }
     return SRP_OK;
 }
 
@@ -1445,6 +1465,7 @@ int srp_profile(int enable) {
     if (rc) return rc;
     g_prof.on = enable != 0;
     g_prof.ms = 0;
+    g_prof.whole_ms = 0;
     g_prof.launches = 0;
     return SRP_OK;
 }
@@ -1456,6 +1477,17 @@ int srp_profile_read(double *trace_ms, int64_t *launches) {
     int rc = prof_collect();
     if (rc) return rc;
     *trace_ms = g_prof.ms;
+    *launches = g_prof.launches;
+    return SRP_OK;
+}
+
+int srp_profile_read_launch(double *launch_ms, int64_t *launches) {
+    g_err.clear();
+    if (!launch_ms || !launches) return fail(SRP_ERR_ARG, "null output");
+    std::lock_guard<std::mutex> lk(g_ws.mu);
+    int rc = prof_collect();
+    if (rc) return rc;
+    *launch_ms = g_prof.whole_ms;
     *launches = g_prof.launches;
     return SRP_OK;
 }

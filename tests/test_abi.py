@@ -140,4 +140,6 @@ def test_null_arguments_rejected(lib):
     assert lib.srp_destroy_scene(None) == 0
     assert lib.srp_eval_batch(None, 3, None, None) == -1
     assert lib.srp_eval_grad_batch(None, 2, None, None, 0, None) == -1
+    assert lib.srp_profile_read(None, None) == -1
+    assert lib.srp_profile_read_launch(None, None) == -1
     assert "null" in lib.srp_last_error().decode()
