@@ -478,3 +478,25 @@ def test_autograd_sun_direction_and_attitude(srp):
     err = np.abs(om.grad.cpu().numpy() - fd).max() / np.abs(fd).max()
     print(f"attitude gradient: autograd {om.grad.cpu().numpy()}, oracle FD {fd}, rel err {err:.2e}", flush=True)
     assert err <= 2e-4
+
+
+def test_profile_hooks_time_trace_and_whole_launch(srp):
+    """The measurement hooks: while profiling is on, every batch launch adds one
+    trace-kernel interval and one whole-launch interval (staging upload through
+    result copy), the whole launch lasting at least as long as its trace kernel;
+    once it is off, nothing more is recorded."""
+    m = synth.box_wing()
+    sc = srp.Scene(m)
+    entries = [(sc, np.zeros(m.n_dof), srp.params(synth.random_dirs(3100 + k)[0], 96, 1)) for k in range(8)]
+    srp.eval_batch(entries)
+    srp.profile(True)
+    for _ in range(3):
+        srp.eval_batch(entries)
+    ms_t, n_t = srp.profile_read()
+    ms_l, n_l = srp.profile_read_launch()
+    srp.profile(False)
+    assert n_t == 3 and n_l == 3
+    assert 0.0 < ms_t <= ms_l
+    srp.eval_batch(entries)
+    assert srp.profile_read() == (0.0, 0)
+    assert srp.profile_read_launch() == (0.0, 0)
