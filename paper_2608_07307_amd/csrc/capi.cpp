@@ -550,8 +550,9 @@ int layout_build(const srp_batch_item *items, int64_t n, bool grad, Schedule for
         eoff = align_up(L.o_units + sizeof(int4) * (size_t)L.total_units);
         for (int64_t k = 0; k < n; ++k) {
             if (L.fan_base[k + 1] == L.fan_base[k]) continue;
+            // the records, then one byte per record: the planar instance its rays leave, or -1
             L.emit_off[k] = eoff;
-            eoff = align_up(eoff + sizeof(FanRec) * 64 * (size_t)items[k].p.bounces *
+            eoff = align_up(eoff + (sizeof(FanRec) + 1) * 64 * (size_t)items[k].p.bounces *
                                        (L.patch_base[k + 1] - L.patch_base[k]));
         }
     }
@@ -672,6 +673,8 @@ void staging_fill(const Layout &L, const srp_batch_item *items, const BatchOut &
         D.parent = sc->d_parent;
         D.root_ref = root;
         D.n_nodes = sc->h.n_nodes;
+        for (int32_t j = 0; j < sc->h.n_nodes; ++j)
+            if (sc->h.nodes[j].planar) D.planar[j >> 6] |= 1ull << (j & 63);
         D.n_mats = sc->h.n_mats;
         D.n_dof = sc->h.n_dof;
         basis(it.p.sun_dir, D.u, D.v, D.d);

@@ -23,6 +23,7 @@ struct NodeInfo {
     int32_t blas_worst = 0;          // most traversal-stack entries a ray can hold in this hierarchy
     double blo[3] = {0}, bhi[3] = {0};  // padded rest-pose bounds of the node's triangles
     double n0[3] = {0, 0, 0};           // area-weighted rest-pose normal (unit, or 0 if none)
+    int32_t planar = 0;                 // every triangle within 1e-9 x the mesh scale of one plane
 };
 
 // One plate of the N-plate model in its node's frame: the node's triangles of

@@ -175,6 +175,19 @@ __device__ __forceinline__ void wave_lds_fence() {
     __builtin_amdgcn_wave_barrier();
 }
 
+// Whether every triangle of node k lies in one plane (a ray leaving one of
+// them cannot meet the node again, so its traversal skips the node).
+__device__ __forceinline__ bool planar_node(const EvalDesc &D, int k) {
+    const uint64_t m = k < 64 ? D.planar[0] : D.planar[1];
+    return ((m >> (k & 63)) & 1ull) != 0;
+}
+
+// The byte per emitter record that follows an evaluation's records: the
+// planar instance the record's diffuse rays leave, or -1.
+__device__ __forceinline__ int8_t SRP_GLOBAL *emit_skip(const EvalDesc &D) {
+    return (int8_t SRP_GLOBAL *)(D.emit + (size_t)D.n_patches * D.bounces * WAVE);
+}
+
 // Hit record -> unit normal n facing the incoming direction d, c = -n.d, the
 // material's (rho_s, rho_d) and the original triangle index; returns whether
 // the geometric normal was flipped.
@@ -328,6 +341,7 @@ __device__ __forceinline__ void fan_passes(const EvalDesc &D, const TraceCtx &TC
                 const float4 SRP_GLOBAL *er =
                     (const float4 SRP_GLOBAL *)(D.emit + ((size_t)(p * B + g) * WAVE + bl));
                 const float4 ea = er[0], eb = er[1];
+                const int32_t skip = emit_skip(D)[(size_t)(p * B + g) * WAVE + bl];
                 const float x[3] = {ea.x, ea.y, ea.z}, n[3] = {eb.x, eb.y, eb.z};
                 const float wd = ea.w;
                 const int32_t excl = __float_as_int(eb.w);
@@ -339,7 +353,7 @@ __device__ __forceinline__ void fan_passes(const EvalDesc &D, const TraceCtx &TC
                     float d[3];
                     fan_dir(n, dset[k], d);
                     Hit h;
-                    if (!trace_closest<COUNT>(TC, x, d, tmin2, excl, stack, h, nbox, ntri)) {
+                    if (!trace_closest<COUNT>(TC, x, d, tmin2, excl, skip, stack, h, nbox, ntri)) {
                         status |= SRP_STATUS_STACK;
                         break;
                     }
@@ -528,12 +542,12 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE ? WPE
                     float o[3];
                     for (int k = 0; k < 3; ++k) o[k] = fmaf((float)py, sv[k], fmaf((float)px, su[k], o0[k]));
                     float tmin = 0.0f;
-                    int32_t excl = -1;
+                    int32_t excl = -1, skip = -1;   // the triangle and the planar instance the ray leaves
                     int gen = 0;   // chain generation
                     #pragma unroll 1
                     for (;;) {
                         Hit h;
-                        if (!trace_closest<COUNT>(TC, o, d, tmin, excl, stack, h, nbox, ntri)) {
+                        if (!trace_closest<COUNT>(TC, o, d, tmin, excl, skip, stack, h, nbox, ntri)) {
                             status |= SRP_STATUS_STACK;
                             break;
                         }
@@ -569,6 +583,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE ? WPE
                             float4 SRP_GLOBAL *er = (float4 SRP_GLOBAL *)(D.emit + ((size_t)(pt * B + gen) * WAVE + lane));
                             er[0] = make_float4(x[0], x[1], x[2], w * rd / (float)KD);
                             er[1] = make_float4(n[0], n[1], n[2], __int_as_float(id));
+                            emit_skip(D)[(size_t)(pt * B + gen) * WAVE + lane] =
+                                (int8_t)(planar_node(D, h.inst) ? h.inst : -1);
                             emitted |= 1u << gen;
                         }
                         if (GRAD) lchain[K * BLOCK] = (uint32_t)h.tri | (flip ? CHAIN_FLIP : 0u);
@@ -582,6 +598,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE ? WPE
                         w *= rs;
                         tmin = tmin2;
                         excl = id;
+                        skip = planar_node(D, h.inst) ? h.inst : -1;
                         ++gen;
                         cont = true;
                         hcnt += 1u << 10;

@@ -413,6 +413,24 @@ int scene_build(const double *verts, int64_t n_verts, const int32_t *tris, int64
         double l = std::sqrt(nd.n0[0] * nd.n0[0] + nd.n0[1] * nd.n0[1] + nd.n0[2] * nd.n0[2]);
         for (int a = 0; a < 3; ++a) nd.n0[a] = l > 0 ? nd.n0[a] / l : 0.0;
     }
+    // planar nodes: every vertex of the node's triangles within 1e-9 x scale of
+    // the plane through its first vertex with the unit normal n0 (a flat panel
+    // segment; a ray leaving such a node cannot meet it again)
+    for (int32_t k = 0; k < n_nodes; ++k) {
+        NodeInfo &nd = S->nodes[k];
+        const auto &lst = per_node[k];
+        nd.planar = 0;
+        if (lst.empty() || (nd.n0[0] == 0.0 && nd.n0[1] == 0.0 && nd.n0[2] == 0.0)) continue;
+        const double *q = verts + 3 * (int64_t)tris[3 * lst[0]];
+        double dev = 0.0;
+        for (int32_t t : lst)
+            for (int c = 0; c < 3; ++c) {
+                const double *p = verts + 3 * (int64_t)tris[3 * t + c];
+                dev = std::max(dev, std::fabs(nd.n0[0] * (p[0] - q[0]) + nd.n0[1] * (p[1] - q[1]) +
+                                              nd.n0[2] * (p[2] - q[2])));
+            }
+        nd.planar = dev <= 1e-9 * scale ? 1 : 0;
+    }
 
     // one hierarchy per node
     S->tris.clear();

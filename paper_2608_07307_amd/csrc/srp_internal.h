@@ -202,7 +202,8 @@ struct alignas(64) EvalDesc {
     double *grad_part;      // n_chunks x grad_n (gradient partials)
     double *grad_out;       // 3*(2M+J) final gradient or null
     const float *dset;      // n_diffuse > 0: the diffuse set, 4 floats per ray (x, y, z, 0), then its mean
-    FanRec *emit;           // n_diffuse > 0, forward: emitter records, n_patches x bounces x 64
+    FanRec *emit;           // n_diffuse > 0, forward: emitter records, n_patches x bounces x 64, then as
+                            // many bytes: the planar instance each record's rays leave, or -1
     uint64_t *emit_mask;    // which of them are filled: n_patches x bounces masks of 64 lanes
     int32_t n_slices;       // reduction: contiguous ranges summed by separate blocks (1..MAX_SLICES)
     int64_t fan_base;       // first fan partial slot (n_patches x bounces x ceil(n_diffuse / FAN_SLICE))
@@ -211,11 +212,12 @@ struct alignas(64) EvalDesc {
     int64_t slice_base;     // the batch's number of this evaluation's first range sum
     int32_t n_clamped;      // hinge angles of this evaluation clamped to their intervals
     int32_t pad_;
+    uint64_t planar[2];     // bit k: every triangle of node k lies in one plane (rays leaving it skip it)
 };
 
 // The host writes these records and the kernels read them: both compilation
 // passes (host and gfx950) must agree on every offset.
-static_assert(sizeof(EvalDesc) == 384, "EvalDesc layout");
+static_assert(sizeof(EvalDesc) == 448, "EvalDesc layout");
 static_assert(offsetof(EvalDesc, tris) == 0, "EvalDesc layout");
 static_assert(offsetof(EvalDesc, blas) == 8, "EvalDesc layout");
 static_assert(offsetof(EvalDesc, mats) == 16, "EvalDesc layout");
@@ -261,6 +263,7 @@ static_assert(offsetof(EvalDesc, gslice) == 344, "EvalDesc layout");
 static_assert(offsetof(EvalDesc, pslice) == 352, "EvalDesc layout");
 static_assert(offsetof(EvalDesc, slice_base) == 360, "EvalDesc layout");
 static_assert(offsetof(EvalDesc, n_clamped) == 368, "EvalDesc layout");
+static_assert(offsetof(EvalDesc, planar) == 376, "EvalDesc layout");
 static_assert(sizeof(PatchOut) == 64, "PatchOut layout");
 static_assert(offsetof(PatchOut, f) == 0, "PatchOut layout");
 static_assert(offsetof(PatchOut, hits) == 48, "PatchOut layout");

@@ -215,7 +215,13 @@ SRP_HD inline uint32_t st_load(const LaneStack &S, int e) {
     return v;
 }
 
-// Closest hit along o + t d, t > tmin, skipping triangle `exclude_id`.
+// Closest hit along o + t d, t > tmin, skipping triangle `exclude_id` and,
+// when skip_inst >= 0, the whole instance skip_inst.  A caller passes the
+// instance a ray leaves when every triangle of that instance lies in one
+// plane: the ray then has a nonzero component along the plane's normal, so
+// no point of it beyond its origin lies in that plane and the instance holds
+// no hit for it (the first hit is the same as without the skip, up to the
+// rounding of a grazing ray's origin).
 // Both levels are 4-wide: a node visit tests the four child boxes, descends
 // into the nearest hit child and pushes the other hit children far to near.
 // Top-level nodes are tested in the world frame; a top-level leaf enters its
@@ -233,8 +239,9 @@ SRP_HD inline uint32_t st_load(const LaneStack &S, int e) {
 // leaf visits and the most entries the stack held.)
 template <bool COUNT>
 SRP_HD inline bool trace_closest(const TraceCtx &C, const float o[3], const float d[3], float tmin,
-                                 int32_t exclude_id, const LaneStack &stack, Hit &h, uint32_t &nbox,
-                                 uint32_t &ntri, uint32_t *steps = nullptr, int *deepest = nullptr) {
+                                 int32_t exclude_id, int32_t skip_inst, const LaneStack &stack, Hit &h,
+                                 uint32_t &nbox, uint32_t &ntri, uint32_t *steps = nullptr,
+                                 int *deepest = nullptr) {
     h.t = T_INF;
     h.tri = -1;
     h.inst = -1;
@@ -263,7 +270,18 @@ SRP_HD inline bool trace_closest(const TraceCtx &C, const float o[3], const floa
         while (ref_type(ref) != REF_BLAS_LEAF && ref != REF_NONE && visits < MAX_VISITS) {
             ++visits;
             if (steps) ++*steps;
-            if (ref_type(ref) == REF_TLAS_LEAF) {
+            if (ref_type(ref) == REF_TLAS_LEAF && (int32_t)ref_index(ref) == skip_inst) {
+                // the instance the ray leaves (planar): nothing to enter; the next
+                // entry is popped (always a top-level one: this leaf was on the
+                // top level, so the stack holds no bottom-level entries)
+                if (sp > 0) {
+                    ref = top;
+                    --sp;
+                    top = st_load(stack, sp - 1);
+                } else {
+                    ref = REF_NONE;
+                }
+            } else if (ref_type(ref) == REF_TLAS_LEAF) {
                 // enter the instance: the ray in the node's rest-pose frame
                 inst = (int)ref_index(ref);
                 const Inst SRP_GLOBAL &I = C.inst[inst];

@@ -97,7 +97,7 @@ int main(int argc, char **argv) {
         Hit h;
         uint32_t nbox = 0, ntri = 0;
         int deepest = 0;
-        const bool ok = trace_closest<true>(C, r.o, r.d, r.tmin, r.exclude, st, h, nbox, ntri, nullptr, &deepest);
+        const bool ok = trace_closest<true>(C, r.o, r.d, r.tmin, r.exclude, -1, st, h, nbox, ntri, nullptr, &deepest);
         const int32_t rec[2] = {ok ? 1 : 0, h.tri >= 0 ? h.id : -1};
         const float t = h.tri >= 0 ? h.t : 0.0f;
         const uint32_t cnt[2] = {nbox, ntri};
