@@ -11,9 +11,11 @@
 //   int64 nv, nt; int32 nm, nn, n_dof, n_rays
 //   f64 verts[nv][3]; i32 tris[nt][3]; i32 tri_mat[nt]; i32 tri_node[nt]
 //   srp_material mats[nm]; srp_node nodes[nn]; f64 angles[n_dof]
-//   per ray: f32 o[3], d[3], tmin; i32 exclude (original triangle id or -1)
+//   per ray: f32 o[3], d[3], tmin; i32 exclude (original triangle id or -1);
+//   i32 skip (the instance the ray leaves, skipped whole, or -1)
 // Output: int32 status (0, or the library's error code), int32 stack_worst
-// (the builder's bound for this slot), then per ray:
+// (the builder's bound for this slot), int32 n_nodes, int32 planar[n_nodes]
+// (the builder's flag: every triangle of the node in one plane), then per ray:
 //   i32 ok (1, or 0 when trace_closest reported an overflow), i32 id (-1 =
 //   miss), f32 t, u32 box tests, u32 triangle tests, i32 deepest stack.
 #include <cstdio>
@@ -35,7 +37,7 @@ bool rd(FILE *f, T *p, size_t n) {
 
 struct Ray {
     float o[3], d[3], tmin;
-    int32_t exclude;
+    int32_t exclude, skip;
 };
 
 }  // namespace
@@ -74,6 +76,11 @@ int main(int argc, char **argv) {
     int32_t worst = slot.stack_worst;
     fwrite(&status, sizeof status, 1, g);
     fwrite(&worst, sizeof worst, 1, g);
+    fwrite(&nn, sizeof nn, 1, g);
+    for (int32_t k = 0; k < nn; ++k) {
+        const int32_t pl = (!status && k < (int32_t)S.nodes.size()) ? S.nodes[k].planar : 0;
+        fwrite(&pl, sizeof pl, 1, g);
+    }
     if (status) {
         fprintf(stderr, "scene: %s\n", err.c_str());
         fclose(g);
@@ -97,7 +104,7 @@ int main(int argc, char **argv) {
         Hit h;
         uint32_t nbox = 0, ntri = 0;
         int deepest = 0;
-        const bool ok = trace_closest<true>(C, r.o, r.d, r.tmin, r.exclude, -1, st, h, nbox, ntri, nullptr, &deepest);
+        const bool ok = trace_closest<true>(C, r.o, r.d, r.tmin, r.exclude, r.skip, st, h, nbox, ntri, nullptr, &deepest);
         const int32_t rec[2] = {ok ? 1 : 0, h.tri >= 0 ? h.id : -1};
         const float t = h.tri >= 0 ? h.t : 0.0f;
         const uint32_t cnt[2] = {nbox, ntri};

@@ -59,13 +59,17 @@ def build(tmp_path_factory):
     return make, tmp
 
 
-def _run(exe, tmp, mesh, angles, rays):
-    """rays: (k, 8) float64 rows o(3), d(3), tmin, exclude."""
+def _run(exe, tmp, mesh, angles, rays, skip=None, planar_out=None):
+    """rays: (k, 8) float64 rows o(3), d(3), tmin, exclude; skip: per ray the
+    instance skipped whole (default none).  planar_out (a list) receives the
+    builder's per-node planarity flags."""
     from paper_2608_07307_amd import _mesh_arrays
     verts, tris, tm, tn, mats, nodes = _mesh_arrays(mesh)
     ang = np.zeros(mesh.n_dof) if angles is None else np.asarray(angles, np.float64)
-    rec = np.zeros(len(rays), dtype=[("o", "<f4", 3), ("d", "<f4", 3), ("tmin", "<f4"), ("ex", "<i4")])
+    rec = np.zeros(len(rays), dtype=[("o", "<f4", 3), ("d", "<f4", 3), ("tmin", "<f4"), ("ex", "<i4"),
+                                     ("sk", "<i4")])
     rec["o"], rec["d"], rec["tmin"], rec["ex"] = rays[:, :3], rays[:, 3:6], rays[:, 6], rays[:, 7]
+    rec["sk"] = -1 if skip is None else skip
     inp, out = tmp / "in.bin", tmp / "out.bin"
     with open(inp, "wb") as f:
         f.write(np.array([verts.shape[0], tris.shape[0]], "<i8").tobytes())
@@ -80,8 +84,10 @@ def _run(exe, tmp, mesh, angles, rays):
                        env=dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=0"))
     assert r.returncode == 0, r.stderr[-3000:]
     raw = open(out, "rb").read()
-    status, worst = np.frombuffer(raw[:8], "<i4")
-    res = np.frombuffer(raw[8:], dtype=[("ok", "<i4"), ("id", "<i4"), ("t", "<f4"), ("nbox", "<u4"),
+    status, worst, nn = np.frombuffer(raw[:12], "<i4")
+    if planar_out is not None:
+        planar_out.extend(int(x) for x in np.frombuffer(raw[12:12 + 4 * nn], "<i4"))
+    res = np.frombuffer(raw[12 + 4 * nn:], dtype=[("ok", "<i4"), ("id", "<i4"), ("t", "<f4"), ("nbox", "<u4"),
                                         ("ntri", "<u4"), ("deep", "<i4")])
     return int(status), int(worst), res
 
@@ -150,6 +156,73 @@ def test_secondary_rays_exclude_and_tmin(build):
     print(f"secondary rays: {same:.4f} of {len(sec)} agree with the oracle", flush=True)
     assert same > 0.99
     assert not np.any(res["id"] == o.ids[sec, 0])      # the source triangle is never hit again
+
+
+def _planar_nodes(mesh):
+    """Nodes whose triangles all lie within 1e-9 x the mesh's coordinate scale
+    of the plane through the node's first vertex with its summed normal
+    (numpy, independent of the library's builder)."""
+    from paper_2608_07307_amd import _mesh_arrays
+    verts, tris, _, tn, _, _ = _mesh_arrays(mesh)
+    V, T = verts.reshape(-1, 3), tris.reshape(-1, 3)
+    scale = np.abs(V[T.ravel()]).max()
+    out = []
+    for k in range(len(mesh.parent)):
+        P = V[T[tn == k]]
+        if not len(P):
+            out.append(0)
+            continue
+        nrm = np.cross(P[:, 1] - P[:, 0], P[:, 2] - P[:, 0]).sum(0)
+        nrm /= np.linalg.norm(nrm)
+        out.append(int(np.abs((P.reshape(-1, 3) - P[0, 0]) @ nrm).max() <= 1e-9 * scale))
+    return out, np.asarray(tn)
+
+
+def test_secondary_rays_skip_the_planar_instance_they_leave(build):
+    """A ray leaving a triangle of a node whose triangles lie in one plane
+    cannot meet that node again, so the traversal may skip it whole.  The
+    builder flags exactly the planar nodes (the panel segments here, not the
+    bus or the dish), and first-bounce rays traced with their source node
+    skipped meet the same triangles at the same distances as without the
+    skip, with fewer box tests; the only rays allowed to differ are those
+    whose unskipped hit lies in the node they leave (an FP32 re-hit of the
+    plane next to a grazing origin), and there must be none at this size."""
+    make, tmp = build
+    mesh = synth.procedural_sized(64, 6000)
+    ang = np.linspace(-0.9, 0.7, mesh.n_dof)
+    n = 64
+    expect, node_of = _planar_nodes(mesh)
+    assert 0 < sum(expect) < len(expect)
+    nsec = 0
+    for seed in (7200, 7201, 7202):
+        sun = synth.random_dirs(seed)[0]
+        o = oracle.eval_srp(mesh, sun, n, bounces=1, angles=ang, record=True)
+        src = np.nonzero(o.ids[:, 0] >= 0)[0]
+        world = oracle.articulate(mesh, ang)
+        d = o.grid["d"]
+        x = _primary_rays(o.grid, n)[src, :3] + o.ts[src, 0][:, None] * d
+        W = world[o.ids[src, 0]]
+        nrm = np.cross(W[:, 1] - W[:, 0], W[:, 2] - W[:, 0])
+        nrm /= np.linalg.norm(nrm, axis=1)[:, None]
+        nrm *= -np.sign(nrm @ d)[:, None]
+        r = d + 2 * (-(nrm @ d))[:, None] * nrm
+        rays = np.concatenate([x, r, np.full((len(src), 1), 1e-6 * o.grid["L"]), o.ids[src, 0][:, None]], 1)
+        planar = []
+        status, worst, r0 = _run(make(), tmp, mesh, ang, rays, planar_out=planar)
+        assert status == 0 and planar == expect
+        leave = node_of[o.ids[src, 0]]
+        skip = np.where(np.asarray(planar)[leave] == 1, leave, -1).astype(np.int32)
+        status, worst, r1 = _run(make(), tmp, mesh, ang, rays, skip=skip)
+        assert status == 0 and (r0["ok"] == 1).all() and (r1["ok"] == 1).all()
+        rehit = (skip >= 0) & (r0["id"] >= 0) & (node_of[np.maximum(r0["id"], 0)] == skip)
+        assert not rehit.any()
+        assert np.array_equal(r1["id"], r0["id"]) and np.array_equal(r1["t"], r0["t"])
+        assert (skip >= 0).mean() > 0.3
+        assert r1["nbox"].sum() < 0.9 * r0["nbox"].sum()
+        nsec += len(src)
+        print(f"sun {seed}: {len(src)} rays, {(skip >= 0).mean():.2f} leave a planar node; box tests per ray "
+              f"{r0['nbox'].mean():.1f} -> {r1['nbox'].mean():.1f}", flush=True)
+    assert nsec > 1000
 
 
 def test_deep_hierarchy_and_overflow(build):
