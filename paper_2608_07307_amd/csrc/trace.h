@@ -270,7 +270,9 @@ SRP_HD inline bool trace_closest(const TraceCtx &C, const float o[3], const floa
         while (ref_type(ref) != REF_BLAS_LEAF && ref != REF_NONE && visits < MAX_VISITS) {
             ++visits;
             if (steps) ++*steps;
-            if (ref_type(ref) == REF_TLAS_LEAF && (int32_t)ref_index(ref) == skip_inst) {
+            if (ref_type(ref) == REF_TLAS_LEAF) {
+              inst = (int)ref_index(ref);
+              if (inst == skip_inst) {
                 // the instance the ray leaves (planar): nothing to enter; the next
                 // entry is popped (always a top-level one: this leaf was on the
                 // top level, so the stack holds no bottom-level entries)
@@ -281,9 +283,8 @@ SRP_HD inline bool trace_closest(const TraceCtx &C, const float o[3], const floa
                 } else {
                     ref = REF_NONE;
                 }
-            } else if (ref_type(ref) == REF_TLAS_LEAF) {
+              } else {
                 // enter the instance: the ray in the node's rest-pose frame
-                inst = (int)ref_index(ref);
                 const Inst SRP_GLOBAL &I = C.inst[inst];
                 float lo[3], ld[3];
                 const float r0 = o[0] - I.t[0], r1 = o[1] - I.t[1], r2 = o[2] - I.t[2];
@@ -296,6 +297,7 @@ SRP_HD inline bool trace_closest(const TraceCtx &C, const float o[3], const floa
                 frame_setup(lo, ld, F);
                 nodes = C.blas;
                 ref = I.root;
+              }
             } else {
                 const float4 SRP_GLOBAL *q = (const float4 SRP_GLOBAL *)(nodes + ref_index(ref));
                 const float4 NX = q[F.nx], NY = q[F.ny], NZ = q[F.nz];
